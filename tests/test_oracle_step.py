@@ -1,0 +1,228 @@
+"""Pins of the oracle's REXI step (eq. ``rational-evaluation``) and adjoint.
+
+The oracle's direct-solve step is checked against routes that do not share
+its arithmetic: the DST-I closed-form spectrum of the discrete Laplacian,
+scipy's matrix exponential, dense eigendecomposition, separable
+eigendecomposition, the scalar (Dahlquist) case of Section 3.4, the
+harmonic-oscillator eigenstate phase, and central finite differences for
+the adjoint.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import faber_cf as fcf
+from oracle import hamiltonian as ham
+from oracle import step as ost
+from paper_1912_03312_amd import inputs
+
+
+@pytest.fixture(scope="module")
+def p16():
+    s, b, _ = fcf.faber_cf(16, 32.0)      # A ~ 1.4e4, ||e|| ~ 6.7e-6
+    return s, b, fcf.diagnostics(s, b, 32.0)
+
+
+@pytest.fixture(scope="module")
+def p10():
+    s, b, _ = fcf.faber_cf(10, 10.0)      # ||e|| ~ 8.4e-10
+    return s, b, fcf.diagnostics(s, b, 10.0)
+
+
+@pytest.mark.parametrize("n", [(7,), (5, 6), (3, 4, 5)])
+def test_laplacian_spectrum_dst_closed_form(n):
+    # V = 0: H S = S diag(lam) with S the DST-I vectors and
+    # lam = (hbar^2/2m) sum_a (4/h_a^2) sin^2(k_a pi / (2(n_a+1)))
+    g = inputs.Grid(n, tuple(-1.0 - a for a in range(len(n))), tuple(2.0 + a for a in range(len(n))))
+    hbar, mass = 0.7, 1.9
+    H = ham.hamiltonian(g.n, g.h, np.zeros(g.n), hbar, mass).toarray()
+    for trial in range(3):
+        k = [1 + (trial * 3 + a) % na for a, na in enumerate(n)]
+        vec = np.ones(())
+        lam = 0.0
+        for a, na in enumerate(n):
+            i = np.arange(1, na + 1)
+            vec = np.multiply.outer(vec, np.sin(i * k[a] * np.pi / (na + 1)))
+            lam += hbar ** 2 / (2 * mass) * 4 / g.h[a] ** 2 * np.sin(k[a] * np.pi / (2 * (na + 1))) ** 2
+        v = vec.ravel()
+        assert np.allclose(H @ v, lam * v, atol=1e-12 * abs(lam))
+
+
+def test_harmonic_ground_state_energy():
+    # The 1D workload's H: the lowest eigenvalue tends to hbar omega / 2 = 0.5 (O(h^2))
+    wl = inputs.workload("1d_harmonic")
+    H = ham.hamiltonian(wl.grid.n, wl.grid.h, wl.V).toarray()
+    lam = np.linalg.eigvalsh(H)
+    h = wl.grid.h[0]
+    assert abs(lam[0] - 0.5) < h * h / 8 + 1e-9
+    assert abs(lam[1] - 1.5) < h * h
+    lo, hi = ham.gershgorin(wl.grid.n, wl.grid.h, wl.V)
+    assert lo <= lam[0] and lam[-1] <= hi
+
+
+def test_dahlquist_scalar_step_is_exponential(p10):
+    # a one-point grid: H = lam, the step is r(-i dt lam/hbar) ~ exp(-i dt lam/hbar)
+    s, b, d = p10
+    for lam, dt, hbar in [(3.0, 1.0, 1.0), (-2.5, 2.0, 1.0), (40.0, 0.2, 2.0)]:
+        g = inputs.Grid((1,), (0.0,), (2.0,))        # h = 1
+        c = hbar * hbar / 2.0 * 2.0                  # kinetic diagonal (hbar^2/2m)(2/h^2)
+        V = np.array([lam - c])
+        D = ost.DirectStepper(g.n, g.h, V, s, b, dt, hbar)
+        out = D.step(np.array([1.0 + 0j]))[0]
+        assert abs(out - np.exp(-1j * dt * lam / hbar)) <= 1.5 * d["err_inf"]
+
+
+@pytest.mark.parametrize("n", [(40,), (9, 8), (5, 4, 6)])
+def test_direct_vs_eig_vs_expm(n, p10):
+    s, b, d = p10
+    g = inputs.Grid(n, (-4.0,) * len(n), (4.0,) * len(n))
+    V = 0.3 * sum(x * x for x in g.mesh())
+    psi = inputs.random_state(g.size, 11).reshape(n)
+    lo, hi = ham.gershgorin(g.n, g.h, V)
+    dt = 0.9 * 10.0 / hi                             # accuracy condition dt sr(M) <= R1
+    direct = ost.DirectStepper(g.n, g.h, V, s, b, dt).step(psi)
+    dense = ost.step_dense(g.n, g.h, V, psi, s, b, dt)
+    eig = ost.EigStepper(g.n, g.h, V).step(psi, s, b, dt)
+    H = ham.hamiltonian(g.n, g.h, V).toarray()
+    ex = sla.expm(-1j * dt * H) @ psi.ravel()
+    tol = 50 * d["amplification"] * np.finfo(float).eps
+    assert ost.rel_err(direct, dense) < tol
+    assert ost.rel_err(direct, eig) < tol
+    assert ost.rel_err(direct, ex) <= 1.5 * d["err_inf"]
+
+
+def test_free_particle_dst(p16):
+    s, b, d = p16
+    g = inputs.cube(48, 8.0, 2)
+    psi = inputs.gaussian_packet(g, (-1.0, 0.5), 1.0, (1.0, -0.5))
+    D = ost.DirectStepper(g.n, g.h, np.zeros(g.n), s, b, 0.5)
+    F = ost.FreeParticleStepper(g.n, g.h)
+    assert ost.rel_err(D.step(psi), F.step(psi, s, b, 0.5)) < 50 * d["amplification"] * 2.2e-16
+
+
+def test_separable_kronecker(p16):
+    s, b, d = p16
+    g = inputs.cube(40, 20.0, 2)
+    V = inputs.double_well_2d(g)
+    vx, vy = inputs.double_well_parts(g)
+    psi = inputs.seeded_packet(g, 2, (-4.0, 0.0), 0.5)
+    D = ost.DirectStepper(g.n, g.h, V, s, b, 0.5)
+    S = ost.SeparableStepper(g.n, g.h, [vx, vy])
+    assert ost.rel_err(D.step(psi), S.step(psi, s, b, 0.5)) < 50 * d["amplification"] * 2.2e-16
+
+
+def test_harmonic_eigenstate_phase(p10):
+    # a discrete eigenvector with energy E: psi_n = r(-i dt E)^n psi_0 exactly and
+    # |r(-i dt E)^n - exp(-i n dt E)| <= n ||e||_inf
+    s, b, d = p10
+    wl = inputs.workload("1d_harmonic")
+    E = ost.EigStepper(wl.grid.n, wl.grid.h, wl.V)
+    phi = E.Q[:, 0].astype(np.complex128)
+    dt, nsteps = 0.1, 10
+    D = ost.DirectStepper(wl.grid.n, wl.grid.h, wl.V, s, b, dt)
+    psi = phi.copy()
+    for _ in range(nsteps):
+        psi = D.step(psi).ravel()
+    rn = fcf.r_eval(-1j * dt * E.lam[0], s, b) ** nsteps
+    assert np.linalg.norm(psi - rn * phi) < 2 * nsteps * d["amplification"] * 2.2e-16
+    assert abs(rn - np.exp(-1j * nsteps * dt * E.lam[0])) <= nsteps * d["err_inf"]
+    assert abs(E.lam[0] - 0.5) < 1e-3
+
+
+def test_norm_and_reversibility(p16):
+    s, b, d = p16
+    g = inputs.cube(64, 10.0, 1)
+    V = inputs.harmonic(g)
+    psi = inputs.gaussian_packet(g, (-2.0,), 1.0, (1.0,))
+    lo, hi = ham.gershgorin(g.n, g.h, V)
+    dt = 0.9 * 32.0 / hi
+    fwd = ost.DirectStepper(g.n, g.h, V, s, b, dt)
+    bwd = ost.DirectStepper(g.n, g.h, V, s, b, -dt)
+    p1 = fwd.step(psi)
+    assert abs(np.linalg.norm(p1) / np.linalg.norm(psi) - 1.0) <= d["err_inf"]
+    assert ost.rel_err(bwd.step(p1), psi) <= 2.5 * d["err_inf"]
+
+
+def test_certificate_bounds_the_error(p16):
+    s, b, d = p16
+    g = inputs.cube(30, 5.0, 1)
+    V = inputs.harmonic(g)
+    psi = inputs.random_state(g.size, 3)
+    D = ost.DirectStepper(g.n, g.h, V, s, b, 0.3)
+    lam = ham.gershgorin(g.n, g.h, V)
+    rng = np.random.default_rng(0)
+    for j in range(len(s)):
+        x = D.solve(j, psi)
+        xp = x + 1e-6 * (rng.standard_normal(x.size) + 1j * rng.standard_normal(x.size))
+        rn, bound = ost.certificate(g.n, g.h, V, psi, xp, D.s[j], lam)
+        assert np.linalg.norm(xp - x) <= bound * (1 + 1e-9)
+
+
+def _loss_chain(g, V, psi0, phi, s, b, dt, nsteps):
+    D = ost.DirectStepper(g.n, g.h, V, s, b, dt)
+    psi = psi0
+    traj = [psi]
+    for _ in range(nsteps):
+        psi = D.step(psi)
+        traj.append(psi)
+    ov = g.cell_volume * np.vdot(phi.ravel(), psi.ravel())
+    return abs(ov) ** 2, D, traj, ov
+
+
+def test_adjoint_dot_product_and_finite_differences(p10):
+    s, b, d = p10
+    g = inputs.cube(24, 6.0, 1)
+    V = inputs.harmonic(g)
+    psi0 = inputs.gaussian_packet(g, (-1.0,), 1.0, (1.0,))
+    phi = inputs.gaussian_packet(g, (1.0,), 1.0, (0.0,))
+    dt, nsteps = 0.5, 4
+    D = ost.DirectStepper(g.n, g.h, V, s, b, dt)
+    # dot-product test: <R x, y> = <x, R^H y>
+    x = inputs.random_state(g.size, 1)
+    y = inputs.random_state(g.size, 2)
+    Rx = D.step(x).ravel()
+    RHy, _ = D.adjoint(x, y)
+    assert abs(np.vdot(y, Rx) - np.vdot(RHy.ravel(), x)) < 1e-10
+    # backward pass of L = |<phi, psi_N>_h|^2
+    L0, D, traj, ov = _loss_chain(g, V, psi0, phi, s, b, dt, nsteps)
+    # L = |ov|^2 with ov = h^d phi^H psi_N, so dL/d conj(psi_N) = h^d ov phi
+    gbar = g.cell_volume * ov * phi.ravel()
+    dV = np.zeros(g.size)
+    for n in range(nsteps - 1, -1, -1):
+        gbar, dv = D.adjoint(traj[n], gbar)
+        gbar = gbar.ravel()
+        dV += dv.ravel()
+    rng = np.random.default_rng(52)
+    # FD noise ~ nsteps A u L / hfd, truncation ~ hfd^2: hfd = 1e-4 balances both
+    hfd = 1e-4
+    for _ in range(3):
+        dVdir = rng.standard_normal(g.size)
+        dVdir /= np.linalg.norm(dVdir)
+        Lp = _loss_chain(g, V + hfd * dVdir.reshape(g.n), psi0, phi, s, b, dt, nsteps)[0]
+        Lm = _loss_chain(g, V - hfd * dVdir.reshape(g.n), psi0, phi, s, b, dt, nsteps)[0]
+        fd = (Lp - Lm) / (2 * hfd)
+        an = float(dV @ dVdir)
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-2)
+        dp = rng.standard_normal(g.size) + 1j * rng.standard_normal(g.size)
+        dp /= np.linalg.norm(dp)
+        Lp = _loss_chain(g, V, psi0 + hfd * dp.reshape(g.n), phi, s, b, dt, nsteps)[0]
+        Lm = _loss_chain(g, V, psi0 - hfd * dp.reshape(g.n), phi, s, b, dt, nsteps)[0]
+        fd = (Lp - Lm) / (2 * hfd)
+        an = 2.0 * float(np.real(np.vdot(gbar, dp)))
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-2)
+
+
+def test_cpu_gmres_step_within_certificate(p16):
+    # the oracle's Krylov route agrees with its direct route within the
+    # certified bound sum_j |w_j| ||r_j|| / Im s_j
+    from oracle.krylov import KrylovStepper
+    s, b, d = p16
+    wl = inputs.workload("2d_adjoint", scale=32)
+    g = wl.grid
+    Kst = KrylovStepper(g.n, g.h, wl.V, s, b, wl.dt, tol=1e-13)
+    D = ost.DirectStepper(g.n, g.h, wl.V, s, b, wl.dt)
+    out, its = Kst.step(wl.psi0)
+    ref = D.step(wl.psi0)
+    bound = sum(abs(Kst.w[j]) * 1e-13 / Kst.s[j].imag for j in range(len(s)))
+    assert ost.rel_err(out, ref) <= bound + 50 * d["amplification"] * 2.2e-16
+    assert max(its) < 60
