@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark: REXI steps/s on one MI355X, with the dominant kernel's HBM roofline.
+
+Workload (default): 128^3 interior points on [-15, 15]^3, a potential of 20
+seeded Gaussian bumps, a seeded Gaussian packet, K = 64 Faber-CF poles
+(R1 = 180), dt = 1, complex64 Krylov solves inside FP64 residual
+refinement to a per-pole relative residual of 1e-10. One timed step is one
+full REXI step (all 64 shifted solves and the pole sum) on inputs already
+resident in HBM.
+
+Prints one JSON line. ``roofline`` is computed from the library's HIP-event
+timings of each kernel class on the launch stream over the timed region
+(algorithmic bytes / kernel time); ``traffic`` comes from the committed
+rocprofv3 counter summary when it was taken on the current kernel sources.
+``cpu_baseline`` times the FP64 CPU oracle (its GMRES step) on a sample of
+poles of the same workload and scales it to steps/s.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "REXI steps/sec + stencil/Krylov HBM GB/s vs peak, 3D 128³ 64 poles"
+
+
+def kernel_sources_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "api.hip", "rexi_internal.h"):
+        with open(os.path.join(ROOT, "paper_1912_03312_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, precision: str):
+    """Per-launch HBM bytes of `kernel` from the committed counter summary, or None."""
+    path = os.path.join(ROOT, "profiles", "traffic_3d_bumps_128.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("sources") != kernel_sources_hash():
+        return None
+    ent = d.get("kernels", {}).get(f"{kernel}:{precision}")
+    return None if ent is None else ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl, sigma, beta, seconds_cap: float = 25.0):
+    """Oracle CPU Krylov step on a bounded sample of poles, scaled to steps/s."""
+    from oracle.krylov import KrylovStepper
+    g = wl.grid
+    ks = KrylovStepper(g.n, g.h, wl.V, sigma, beta, wl.dt, tol=1e-10, m=60)
+    K = len(sigma)
+    order = [0, K // 2, K - 1, K // 4, 3 * K // 4] + list(range(1, K))
+    done, t_used = [], 0.0
+    for j in order:
+        if j in done:
+            continue
+        t0 = time.perf_counter()
+        ks.solve(j, wl.psi0)
+        t_used += time.perf_counter() - t0
+        done.append(j)
+        if t_used > seconds_cap or len(done) >= K:
+            break
+    per_pole = t_used / len(done)
+    steps_per_s = 1.0 / (per_pole * K)
+    return dict(value=steps_per_s, unit="steps/s", cores=1, kind="oracle",
+                sample=f"oracle FP64 GMRES(60) to rel. residual 1e-10 on {len(done)} of {K} poles of one "
+                       f"step of the 128^3 workload ({t_used:.1f} s); scaled by K/{len(done)}; "
+                       f"scipy sparse matvec, single thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--solver", choices=("shifted", "per_pole"), default="shifted")
+    ap.add_argument("--precision", choices=("c64", "c128"), default=None,
+                    help="default: c128 for the shared-basis solver, c64 (+FP64 refinement) per pole")
+    ap.add_argument("--m", type=int, default=None)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--scale", type=int, default=None, help="points per axis (default 128)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the pole-sharded design is described, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1912_03312_amd import inputs, rexi
+    from paper_1912_03312_amd.poles import faber_cf_poles
+
+    if args.precision is None:
+        args.precision = "c128" if args.solver == "shifted" else "c64"
+    wl = inputs.workload("3d_bumps", scale=args.scale)
+    m = args.m or (100 if args.solver == "shifted" else wl.m)
+    g = wl.grid
+    sigma, beta, pinfo = faber_cf_poles(wl.K, wl.R1)
+    dev = torch.device("cuda:0")
+    V = torch.from_numpy(wl.V.ravel().copy()).to(dev)
+    psi = torch.from_numpy(wl.psi0.ravel().copy()).to(dev)
+    out = torch.empty_like(psi)
+    h = rexi.setup(g.n, g.lo, g.hi, V, wl.hbar, wl.mass, wl.dt, sigma, beta,
+                   precision=args.precision, solver=args.solver, tol=args.tol, m=m,
+                   profile=0 if args.no_profile else 1)
+    print(f"# setup done: {g.n} K={wl.K} precision={args.precision}", file=sys.stderr, flush=True)
+
+    # warmup (also records the per-step solve statistics)
+    cur = psi.clone()
+    info = None
+    for _ in range(args.warmup):
+        info = h.step(cur, out, 1, info=True)
+        cur, out = out, cur
+    torch.cuda.synchronize()
+    h.profile_reset()
+    print(f"# warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        h.step(cur, out, 1, info=False)
+        cur, out = out, cur
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    print(f"# timed {args.steps} steps: {ms:.3f} ms/step", file=sys.stderr, flush=True)
+
+    prof = h.profile()
+    final_info = h.step(cur, out, 1, info=True)
+    torch.cuda.synchronize()
+    ws_bytes, m_used = h.workspace()
+    h.close()
+
+    roof = None
+    if not args.no_profile:
+        # dominant kernel class by summed time over the timed region
+        cand = {k: v for k, v in prof.items() if v["launches"] > 0 and v["bytes"] > 0}
+        dom = max(cand, key=lambda k: cand[k]["ms"])
+        d = cand[dom]
+        avg_ms = d["ms"] / d["launches"]
+        bytes_per_launch = d["bytes"] / d["launches"]
+        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        traffic = load_traffic(dom, args.precision)
+        roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
+                    avg_launch_ms=round(avg_ms, 5), algorithmic_bytes_per_launch=round(bytes_per_launch),
+                    launches=d["launches"],
+                    kernels={k: dict(ms=round(v["ms"], 3), launches=v["launches"],
+                                     GBs=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 and v["bytes"] > 0 else None)
+                             for k, v in prof.items() if v["launches"] > 0})
+
+    res = {
+        "metric": METRIC,
+        "value": round(1e3 / ms, 4),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64" if args.precision == "c64" else "c128",
+        "data": "synthetic",
+        "config": {
+            "workload": f"3d_bumps {g.n[0]}^3 on [-15,15]^3, 20 Gaussian bumps (seed 3), packet (seed 30), "
+                        f"K={wl.K} Faber-CF poles R1={wl.R1}, dt={wl.dt}, "
+                        + ("one complex128 Krylov basis shared by all poles (shifted GMRES)"
+                           if args.solver == "shifted" else
+                           "per-pole complex64 GMRES inside FP64 refinement" if args.precision == "c64"
+                           else "per-pole complex128 GMRES")
+                        + f", per-pole rel. residual {args.tol:g}, Krylov dimension <= {m_used}",
+            "grid": list(g.n), "poles": wl.K, "precision": args.precision, "solver": args.solver,
+        },
+        "solve": {
+            "iterations_per_step": int(final_info["total_iterations"]),
+            "max_cycles": int(final_info["max_cycles_used"]),
+            "max_rel_residual": final_info["max_rel_residual"],
+            "certified_rel_error_bound": final_info["certified_bound"],
+            "norm_drift": final_info["norm_out"] / final_info["norm_in"] - 1.0,
+            "pole_set_err_inf": pinfo["err_inf"],
+            "workspace_GB": round(ws_bytes / 1e9, 2),
+        },
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(wl, sigma, beta)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * rexi.h -- C ABI of the MI355X REXI propagation step.
+ *
+ * The library advances the semi-discrete Schroedinger equation
+ *     i hbar psi'(t) = H psi(t),   H = -(hbar^2 / 2m) Lap_h + diag(V)
+ * (eq. schroedinger, Section 1; the IVP of eq. ode-system with A = H and
+ * B = hbar I for a finite-difference discretisation) by REXI steps
+ * (eq. rational-evaluation, Section 3.1):
+ *     psi_{n+1} = sum_{j=1..K} w_j (H - s_j I)^{-1} psi_n ,
+ *     s_j = i hbar sigma_j / dt ,   w_j = i hbar beta_j / dt ,
+ * where r(z) = sum_j beta_j / (z - sigma_j) ~ exp(z) on i[-R1, R1] is a
+ * rational approximation in partial fractions (eq.
+ * partial-fraction-decomposition), e.g. the Faber-CF approximation of
+ * Section 3.2. The caller supplies the dimensionless (sigma_j, beta_j);
+ * they are computed once, on the host, and do not depend on psi (Section 3.1).
+ *
+ * Every shifted system is solved by restarted GMRES (x0 = 0) driven by a
+ * matrix-free stencil matvec on the GPU, all poles batched together; the
+ * weighted pole sum is accumulated on the GPU in FP64 in a fixed pole order.
+ *
+ * Grid and layout
+ *   n[a] interior points per axis a on [lo[a], hi[a]], zero Dirichlet values
+ *   outside (Section 1): h_a = (hi[a] - lo[a]) / (n[a] + 1). Vectors are
+ *   C-order (axis ndim-1 fastest), complex values interleaved re, im
+ *   (layout of std::complex<double> / torch.complex128). V is float64.
+ *
+ * Conventions
+ *   - Pointers named *_dev are device pointers (HIP, same device as the
+ *     handle); *_host are host pointers. The caller owns every pointer it
+ *     passes; the library owns the handle and its workspaces and never frees
+ *     caller memory. rexi_setup copies V, so V may be freed afterwards.
+ *   - stream is a hipStream_t (NULL = the default stream). Calls enqueue work
+ *     on it; rexi_step and rexi_step_adjoint synchronise it (they read the
+ *     device-side convergence counters) unless the handle was set up with
+ *     capture_safe = 1 and info == NULL.
+ *   - Every call returns a rexi_status and never aborts or throws. After an
+ *     error, rexi_last_error() holds a message. Handles are not thread-safe.
+ */
+#ifndef REXI_H
+#define REXI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } rexi_c128;
+
+typedef struct {
+  int32_t ndim;     /* 1, 2 or 3 */
+  int32_t reserved;
+  int64_t n[3];     /* interior points per axis (axes >= ndim ignored) */
+  double lo[3];
+  double hi[3];
+} rexi_grid;
+
+typedef enum {
+  REXI_OK = 0,
+  REXI_E_INVALID_ARG = 1,   /* bad sizes, non-finite inputs, singular shift  */
+  REXI_E_NO_MEMORY = 2,     /* a workspace does not fit on the device        */
+  REXI_E_HIP = 3,           /* a HIP runtime call failed                      */
+  REXI_E_NOT_CONVERGED = 4, /* a pole missed its tolerance; output written    */
+  REXI_E_NOT_BUILT = 5      /* the library was built without this feature     */
+} rexi_status;
+
+typedef enum {
+  REXI_PREC_C128 = 0,       /* complex128 Krylov basis and matvec             */
+  REXI_PREC_C64_REFINE = 1  /* complex64 basis and matvec inside FP64
+                               residual refinement (FP64 dots, Hessenberg,
+                               residual, solution and pole sum)               */
+} rexi_precision;
+
+typedef enum {
+  REXI_TOL_RELRES = 0,      /* every pole to ||psi - (H - s_j) x_j|| <= tol ||psi|| */
+  REXI_TOL_CERTIFIED = 1    /* per-pole targets tol Re(sigma_j) / (K |beta_j|), so
+                               sum_j |w_j| ||r_j|| / dist(s_j, spec H) <= tol ||psi|| */
+} rexi_tol_policy;
+
+typedef enum {
+  REXI_SOLVER_PER_POLE = 0, /* one Krylov basis per pole, all poles batched    */
+  REXI_SOLVER_SHIFTED = 1   /* one basis shared by all poles (x0 = 0 gives
+                               K_k(H - s I, psi) = K_k(H, psi)): one Arnoldi
+                               process and K small least-squares problems;
+                               complex128, single instance, no restarts; the
+                               per-pole residuals reported are the implicit
+                               (Givens) ones                                  */
+} rexi_solver;
+
+typedef struct {
+  int32_t precision;   /* rexi_precision, default REXI_PREC_C128            */
+  int32_t solver;      /* rexi_solver, default REXI_SOLVER_PER_POLE          */
+  int32_t m;           /* Krylov dimension per cycle (restart length), 30;
+                          at most 256. For the shared-basis solver the
+                          largest Krylov dimension (no restarts)             */
+  int32_t max_cycles;  /* restarts / refinement sweeps per solve, 20         */
+  double tol;          /* see tol_policy, default 1e-10                      */
+  int32_t tol_policy;  /* rexi_tol_policy, default REXI_TOL_RELRES           */
+  int32_t reorth;      /* 0 classical Gram-Schmidt, 1 DGKS when cancellation
+                          is detected (default), 2 always twice              */
+  double reorth_eta;   /* DGKS threshold: a second pass when the projected
+                          vector keeps less than eta of its norm, 1e-2       */
+  double inner_rtol;   /* C64_REFINE: residual reduction per sweep, 1e-5     */
+  int32_t check_every; /* shared-basis solver: iterations between host reads
+                          of the convergence flag, default 4                 */
+  int32_t capture_safe;/* 1: rexi_step(info = NULL) runs a fixed schedule
+                          with no host reads, so it can be graph-captured    */
+  int32_t profile;     /* 1: time kernel classes with HIP events             */
+  int32_t tile;        /* points per work tile (0 = tuned default)           */
+  int32_t grid_blocks; /* workgroups of the grid-stride kernels (0 = tuned)  */
+  int64_t max_workspace_bytes; /* device workspace cap, 0 = 90% of free     */
+} rexi_options;
+
+typedef struct {
+  int32_t K;                /* poles (summed over instances for a batch)      */
+  int32_t steps;            /* steps taken by the call                         */
+  int64_t total_iterations; /* Arnoldi iterations over all poles and steps     */
+  int32_t max_cycles_used;  /* largest cycle count of one pole solve           */
+  int32_t not_converged;    /* pole solves that missed their target            */
+  double max_rel_residual;  /* max_j ||psi - (H - s_j) x_j|| / ||psi|| (last step) */
+  double certified_bound;   /* sum_j |w_j| ||r_j|| / dist(s_j, [lmin, lmax]) / ||psi||,
+                               a bound on the relative step error (last step)  */
+  double norm_in;           /* ||psi_n||_2 of the last step's input            */
+  double norm_out;          /* ||psi_{n+1}||_2 of the last step's output       */
+  /* optional caller-owned per-pole arrays of length K (NULL to skip):        */
+  int32_t* iterations;      /* Arnoldi iterations of pole j (last step)        */
+  int32_t* cycles;          /* cycles of pole j (last step)                    */
+  double* rel_residual;     /* final relative residual of pole j (last step)   */
+} rexi_step_info;
+
+typedef struct {
+  /* accumulated while rexi_options.profile = 1, reset by rexi_profile_reset */
+  int32_t nclasses;
+  const char* names[12];
+  int64_t launches[12];
+  double ms[12];            /* summed kernel time, HIP events on the stream   */
+  double bytes[12];         /* algorithmic HBM bytes of those launches        */
+} rexi_profile;
+
+typedef struct rexi_handle rexi_handle;
+
+/* Fill *opt with the defaults listed above. */
+void rexi_default_options(rexi_options* opt);
+
+/*
+ * rexi_setup -- prepare REXI steps for one grid (eq. rational-evaluation).
+ *   g          grid (ndim 1..3, n[a] >= 1, lo < hi)
+ *   V_dev      device float64[prod n], the potential at the interior points
+ *   hbar, mass > 0; dt != 0 (finite): the step size tau
+ *   K >= 1     poles; sigma_host, beta_host: host rexi_c128[K], the
+ *              dimensionless poles and weights of r(z) ~ exp(z)
+ *   opt        NULL for defaults
+ *   stream     hipStream_t used for the setup copies
+ * Maps (sigma, beta) to s_j = i hbar sigma_j / dt, w_j = i hbar beta_j / dt in
+ * FP64 and plans the workspaces. Fails with REXI_E_INVALID_ARG on bad sizes,
+ * non-finite sigma, beta or V, or a shift on the real segment spanned by the
+ * spectrum bound [min V, (hbar^2/2m) sum_a 4/h_a^2 + max V] (a singular
+ * system); REXI_E_NO_MEMORY if the workspace does not fit.
+ */
+rexi_status rexi_setup(rexi_handle** out, const rexi_grid* g, const double* V_dev,
+                       double hbar, double mass, double dt, int32_t K,
+                       const rexi_c128* sigma_host, const rexi_c128* beta_host,
+                       const rexi_options* opt, void* stream);
+
+/*
+ * rexi_setup_batch -- count independent instances of uneven sizes in one handle.
+ *   grids[i], hbar[i], mass[i], dt[i], K[i] as for rexi_setup;
+ *   V_dev      device float64[sum_i prod n_i], the potentials packed in
+ *              instance order
+ *   sigma_host, beta_host  host rexi_c128[sum_i K_i], packed in instance order
+ * All poles of all instances are solved together (one work queue over
+ * instance, pole and tile).
+ */
+rexi_status rexi_setup_batch(rexi_handle** out, int32_t count, const rexi_grid* grids,
+                             const double* V_dev, const double* hbar, const double* mass,
+                             const double* dt, const int32_t* K,
+                             const rexi_c128* sigma_host, const rexi_c128* beta_host,
+                             const rexi_options* opt, void* stream);
+
+/*
+ * rexi_apply_H -- y = (H - shift I) x in FP64 (the stencil matvec of the
+ * solves). x_dev, y_dev: device rexi_c128[prod n] (no aliasing). For a batch
+ * handle, the packed vectors of all instances.
+ */
+rexi_status rexi_apply_H(rexi_handle* h, const rexi_c128* x_dev, rexi_c128* y_dev,
+                         rexi_c128 shift, void* stream);
+
+/*
+ * rexi_step -- nsteps >= 1 REXI steps psi_out = r(tau M)^nsteps psi_in
+ * (eq. rational-evaluation). psi_in_dev, psi_out_dev: device rexi_c128[prod n]
+ * (packed over instances for a batch); psi_out may equal psi_in. info may be
+ * NULL. Returns REXI_E_NOT_CONVERGED if a pole missed its target after
+ * max_cycles (the best iterate is used and info is filled).
+ */
+rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in_dev, rexi_c128* psi_out_dev,
+                      int32_t nsteps, rexi_step_info* info, void* stream);
+
+/*
+ * rexi_step_adjoint -- one backward step of a real loss L through
+ * psi_{n+1} = R psi_n, R = sum_j w_j (H - s_j)^{-1}. With the
+ * conjugate-Wirtinger gradients gbar = dL/d conj(psi):
+ *   gbar_n   = R^H gbar_{n+1} = sum_j conj(w_j) (H - conj(s_j))^{-1} gbar_{n+1}
+ *   dV_accum += dL/dV = -2 Re sum_j w_j conj(y_j) x_j   (elementwise)
+ * with x_j = (H - s_j)^{-1} psi_n and y_j = (H - conj s_j)^{-1} gbar_{n+1}
+ * (H is real symmetric, so (H - s)^H = H - conj s). psi_n_dev, gbar_next_dev,
+ * gbar_n_dev: device rexi_c128[prod n]; gbar_n may alias gbar_next.
+ * dV_accum_dev: device float64[prod n] or NULL. Single-instance handles only.
+ */
+rexi_status rexi_step_adjoint(rexi_handle* h, const rexi_c128* psi_n_dev,
+                              const rexi_c128* gbar_next_dev, rexi_c128* gbar_n_dev,
+                              double* dV_accum_dev, void* stream);
+
+/* Kernel-class timings gathered while opt.profile = 1. */
+rexi_status rexi_get_profile(const rexi_handle* h, rexi_profile* out);
+rexi_status rexi_profile_reset(rexi_handle* h);
+
+/* Device bytes held by the handle's workspaces, and the restart length used. */
+rexi_status rexi_workspace_info(const rexi_handle* h, int64_t* bytes, int32_t* m_used);
+
+/* Release the handle and its workspaces (NULL is a no-op). */
+rexi_status rexi_destroy(rexi_handle* h);
+
+/* Text of a status code (static storage). */
+const char* rexi_status_string(rexi_status s);
+
+/* Copy the last error message of h (or of the failed setup when h == NULL)
+ * into buf (NUL-terminated, truncated to len). */
+rexi_status rexi_last_error(const rexi_handle* h, char* buf, size_t len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REXI_H */

@@ -1,0 +1,1081 @@
+// C ABI of the REXI step (declared in include/rexi.h): handle, validation,
+// the (sigma, beta) -> (s, w) mapping of eq. rational-evaluation, workspace
+// planning and the host control loop of the batched restarted GMRES.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rexi.h"
+#include "kernels.hip"
+
+using rexi::FastDiv;
+using rexi::InstDesc;
+using rexi::SysDesc;
+using rexi::SysState_t;
+using rexi::Work;
+using cplx = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+enum ProfClass {
+  PC_START = 0, PC_ARNOLDI_A, PC_REDUCE, PC_ARNOLDI_B, PC_REORTH_A, PC_REORTH_B,
+  PC_UPDATE_X, PC_RESIDUAL, PC_POLESUM, PC_APPLY_H, PC_GRAD, PC_NCLASS
+};
+const char* kProfNames[PC_NCLASS] = {"start", "arnoldi_matvec_dots", "per_system_reduce", "arnoldi_update",
+                                     "reorth_dots", "reorth_update", "update_x", "residual",
+                                     "polesum", "apply_h", "grad_v"};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// Restarted GMRES over a set of shifted systems that share one tiling scheme.
+struct Solver {
+  int S = 0, m = 0, max_cycles = 0, prec = 0, tile = 0, grid = 0, reorth = 1, ppt = 8;
+  double eta = 1e-2;
+  double inner_rtol = 0.0;
+  std::vector<SysDesc> hsys;
+  std::vector<int32_t> htile;
+  int total_tiles = 0;
+  std::vector<DevBuf> bufs;
+  Work W{};
+  SysDesc* dsys = nullptr;
+  int32_t* dtile = nullptr;
+  bool ready = false;
+};
+
+struct Prof {
+  bool on = false;
+  int64_t launches[PC_NCLASS] = {};
+  double ms[PC_NCLASS] = {};
+  double bytes[PC_NCLASS] = {};
+  std::vector<hipEvent_t> ev;      // pool, pairs
+  std::vector<int> cls;            // class per recorded pair
+  std::vector<double> pbytes;      // bytes per recorded pair
+  size_t used = 0;
+};
+
+}  // namespace
+
+struct rexi_handle {
+  rexi_options opt{};
+  int ninst = 0;
+  int64_t N = 0;
+  std::vector<InstDesc> hinst;
+  std::vector<int32_t> hitile;
+  int itotal = 0;
+  InstDesc* dinst = nullptr;
+  int32_t* ditile = nullptr;
+  double* V64 = nullptr;
+  float* V32 = nullptr;
+  std::vector<cplx> s, w;             // per system (pole), instance order
+  std::vector<double> tol_sys, dist_sys, lam_lo, lam_hi;
+  std::vector<int> Kinst;
+  Solver fwd, adj;
+  // shared-basis solver: fwd holds one system (H, shift 0) per instance
+  bool shifted = false;
+  rexi::ShiftWork SW{};
+  std::vector<DevBuf> sbufs;
+  int32_t* hpin = nullptr;            // pinned counters read-back
+  double* dnorm = nullptr;            // scratch partials for norms
+  std::string err;
+  Prof prof;
+  int64_t ws_bytes = 0;
+};
+
+namespace {
+
+rexi_status fail(rexi_handle* h, rexi_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (h) h->err = buf; else g_setup_error = buf;
+  return st;
+}
+
+#define HIPCHK(h, call)                                                                      \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail((h), REXI_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));           \
+  } while (0)
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+void free_solver(Solver& sv) {
+  for (auto& b : sv.bufs)
+    if (b.p) (void)hipFree(b.p);
+  sv.bufs.clear();
+  sv.ready = false;
+}
+
+void destroy_handle(rexi_handle* h) {
+  if (!h) return;
+  free_solver(h->fwd);
+  free_solver(h->adj);
+  for (auto& b : h->sbufs)
+    if (b.p) (void)hipFree(b.p);
+  if (h->dinst) (void)hipFree(h->dinst);
+  if (h->ditile) (void)hipFree(h->ditile);
+  if (h->V64) (void)hipFree(h->V64);
+  if (h->V32) (void)hipFree(h->V32);
+  if (h->dnorm) (void)hipFree(h->dnorm);
+  if (h->hpin) (void)hipHostFree(h->hpin);
+  for (auto& e : h->prof.ev) (void)hipEventDestroy(e);
+  delete h;
+}
+
+// ---------------------------------------------------------------- profiling
+struct Timed {
+  rexi_handle* h;
+  int slot = -1;
+  hipStream_t st;
+  Timed(rexi_handle* hh, int cls, double bytes, hipStream_t s) : h(hh), st(s) {
+    Prof& P = h->prof;
+    if (!P.on) return;
+    if (P.used + 2 > P.ev.size()) {
+      for (int i = 0; i < 256; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        P.ev.push_back(e);
+      }
+    }
+    slot = (int)P.used;
+    P.used += 2;
+    P.cls.push_back(cls);
+    P.pbytes.push_back(bytes);
+    (void)hipEventRecord(P.ev[slot], st);
+  }
+  ~Timed() {
+    if (slot >= 0) (void)hipEventRecord(h->prof.ev[slot + 1], st);
+  }
+};
+
+void prof_collect(rexi_handle* h, hipStream_t st) {
+  Prof& P = h->prof;
+  if (!P.on || P.used == 0) return;
+  (void)hipStreamSynchronize(st);
+  for (size_t k = 0; k < P.cls.size(); ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, P.ev[2 * k], P.ev[2 * k + 1]) == hipSuccess) {
+      P.ms[P.cls[k]] += ms;
+      P.launches[P.cls[k]] += 1;
+      P.bytes[P.cls[k]] += P.pbytes[k];
+    }
+  }
+  P.cls.clear();
+  P.pbytes.clear();
+  P.used = 0;
+}
+
+// ---------------------------------------------------------------- planning
+template <typename X>
+rexi_status dalloc(rexi_handle* h, Solver& sv, X** out, size_t count) {
+  DevBuf b;
+  b.bytes = std::max<size_t>(count * sizeof(X), 256);
+  hipError_t e = hipMalloc(&b.p, b.bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, REXI_E_NO_MEMORY, "hipMalloc of %zu bytes failed: %s", b.bytes, hipGetErrorString(e));
+  }
+  sv.bufs.push_back(b);
+  h->ws_bytes += (int64_t)b.bytes;
+  *out = reinterpret_cast<X*>(b.p);
+  return REXI_OK;
+}
+
+size_t solver_bytes(const std::vector<SysDesc>& sys, int m, int prec, int max_cycles, int total_tiles) {
+  size_t e = prec ? 8 : 16, tot = 0;
+  for (auto& d : sys) tot += (size_t)(m + 1) * d.n * e + (size_t)d.n * 16 + (size_t)(m + 1) * d.ntiles * 16;
+  size_t S = sys.size();
+  tot += S * ((size_t)(m + 1) * m * 16 + (m + 1) * 16 * 2 + m * 16 * 3 + (m + 1) * 8 + sizeof(SysState_t));
+  tot += (size_t)total_tiles * 8 + (size_t)(max_cycles * (m + 1) + max_cycles + 4) * 4;
+  return tot;
+}
+
+// Build the system table of a solver: for each (instance, pole) in `order`.
+void layout_systems(Solver& sv, int m) {
+  int64_t basis = 0, xo = 0;
+  int tile0 = 0, pbase = 0;
+  sv.htile.clear();
+  for (auto& d : sv.hsys) {
+    d.ntiles = (d.n + sv.tile - 1) / sv.tile;
+    d.tile0 = tile0;
+    d.basis = basis;
+    d.xoff = xo;
+    d.pbase = pbase;
+    sv.htile.push_back(tile0);
+    tile0 += d.ntiles;
+    basis += (int64_t)(m + 1) * d.n;
+    xo += d.n;
+    pbase += (m + 1) * d.ntiles;
+  }
+  sv.htile.push_back(tile0);
+  sv.total_tiles = tile0;
+  sv.S = (int)sv.hsys.size();
+}
+
+rexi_status build_solver(rexi_handle* h, Solver& sv, hipStream_t stream) {
+  const int m = sv.m, S = sv.S;
+  Work& W = sv.W;
+  W = Work{};
+  rexi_status st;
+#define ALLOC(ptr, type, count) \
+  if ((st = dalloc(h, sv, (type**)&(ptr), (size_t)(count))) != REXI_OK) return st
+  ALLOC(sv.dsys, SysDesc, S);
+  ALLOC(sv.dtile, int32_t, S + 1);
+  SysState_t* dst;
+  ALLOC(dst, SysState_t, S);
+  W.st = dst;
+  ALLOC(W.H, double, (size_t)S * (m + 1) * m * 2);
+  ALLOC(W.hcur, double, (size_t)S * (m + 1) * 2);
+  ALLOC(W.gvec, double, (size_t)S * (m + 1) * 2);
+  ALLOC(W.gc, double, (size_t)S * m * 2);
+  ALLOC(W.gs, double, (size_t)S * m * 2);
+  ALLOC(W.cscale, double, (size_t)S * (m + 1));
+  ALLOC(W.y, double, (size_t)S * m * 2);
+  size_t npart = 0, nx = 0, nb = 0;
+  for (auto& d : sv.hsys) {
+    npart += (size_t)(m + 1) * d.ntiles;
+    nx += d.n;
+    nb += (size_t)(m + 1) * d.n;
+  }
+  ALLOC(W.part, double, npart * 2);
+  ALLOC(W.pnorm, double, sv.total_tiles);
+  ALLOC(W.counters, int32_t, sv.max_cycles * (m + 1) + sv.max_cycles + 4);
+  ALLOC(W.x, double, nx * 2);
+  if (sv.prec) {
+    float* b;
+    ALLOC(b, float, nb * 2);
+    W.basis = b;
+  } else {
+    double* b;
+    ALLOC(b, double, nb * 2);
+    W.basis = b;
+  }
+#undef ALLOC
+  HIPCHK(h, hipMemcpyAsync(sv.dsys, sv.hsys.data(), S * sizeof(SysDesc), hipMemcpyHostToDevice, stream));
+  HIPCHK(h, hipMemcpyAsync(sv.dtile, sv.htile.data(), (S + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  HIPCHK(h, hipStreamSynchronize(stream));
+  W.sys = sv.dsys;
+  W.tile_start = sv.dtile;
+  W.V64 = h->V64;
+  W.V32 = h->V32;
+  W.S = S;
+  W.m = m;
+  W.total_tiles = sv.total_tiles;
+  W.reorth_mode = sv.reorth;
+  W.inner_rtol = sv.inner_rtol;
+  W.eta2 = sv.eta * sv.eta;  // DGKS: second pass when ||w - V h|| < eta ||w||
+  W.max_cycles = sv.max_cycles;
+  W.tile = sv.tile;
+  sv.ready = true;
+  return REXI_OK;
+}
+
+int default_grid(int total_tiles, int opt_grid) {
+  if (opt_grid > 0) return opt_grid;
+  return std::max(1, std::min(total_tiles, 2048));
+}
+
+// ---------------------------------------------------------------- solve
+constexpr int PPT = 8;  // points per thread of the instance-level kernels
+constexpr int TPB = rexi::TPB;
+
+template <typename T, int PPT>
+rexi_status run_solve(rexi_handle* h, Solver& sv, const double2* r0, const double2* r1, hipStream_t stream,
+                      int* restarts_out) {
+  Work& W = sv.W;
+  const int G = sv.grid, S = sv.S, m = sv.m;
+  const double e = sizeof(T);
+  const double eV = sv.prec ? 4.0 : 8.0;
+  double npts = 0;  // points per system (uniform tiling assumed for byte counts)
+  for (auto& d : sv.hsys) npts += d.n;
+  const double n_avg = npts / std::max(1, S);
+  {
+    Timed t(h, PC_START, npts * (16.0 + e), stream);
+    hipLaunchKernelGGL((rexi::k_start<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, r0, r1);
+  }
+  {
+    Timed t(h, PC_REDUCE, 0, stream);
+    hipLaunchKernelGGL(rexi::k_start_reduce, dim3(S), dim3(TPB), 0, stream, W);
+  }
+  int active = S;
+  int total_restarts = 0;
+  for (int c = 0; c < sv.max_cycles; ++c) {
+    for (int j = 0; j < m; ++j) {
+      {
+        Timed t(h, PC_ARNOLDI_A, active * n_avg * ((j + 2) * e + eV), stream);
+        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, true>), dim3(G), dim3(TPB), 0, stream, W, j);
+      }
+      {
+        Timed t(h, PC_REDUCE, 0, stream);
+        hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, stream, W, j, 0);
+      }
+      {
+        Timed t(h, PC_ARNOLDI_B, active * n_avg * (j + 3) * e, stream);
+        hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, j, 0);
+      }
+      if (sv.reorth) {
+        {
+          Timed t(h, PC_REORTH_A, 0, stream);
+          hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(G), dim3(TPB), 0, stream, W, j);
+        }
+        {
+          Timed t(h, PC_REDUCE, 0, stream);
+          hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, stream, W, j, 1);
+        }
+        {
+          Timed t(h, PC_REORTH_B, 0, stream);
+          hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, j, 1);
+        }
+      }
+      {
+        Timed t(h, PC_REDUCE, 0, stream);
+        hipLaunchKernelGGL(rexi::k_givens, dim3(S), dim3(TPB), 0, stream, W, j, c);
+      }
+      HIPCHK(h, hipGetLastError());
+      HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + c * (m + 1) + j, sizeof(int32_t), hipMemcpyDeviceToHost,
+                               stream));
+      HIPCHK(h, hipStreamSynchronize(stream));
+      active = h->hpin[0];
+      if (active == 0) break;
+    }
+    // finishing systems: all that were active in this cycle
+    {
+      Timed t(h, PC_UPDATE_X, 0, stream);
+      hipLaunchKernelGGL((rexi::k_update_x<T, PPT>), dim3(G), dim3(TPB), 0, stream, W);
+    }
+    {
+      Timed t(h, PC_RESIDUAL, 0, stream);
+      hipLaunchKernelGGL((rexi::k_residual<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, r0, r1);
+    }
+    {
+      Timed t(h, PC_REDUCE, 0, stream);
+      hipLaunchKernelGGL(rexi::k_restart, dim3(S), dim3(TPB), 0, stream, W, c);
+    }
+    HIPCHK(h, hipGetLastError());
+    // restarted count of this cycle: counters[max_cycles*(m+1)] accumulates; read the total
+    HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + sv.max_cycles * (m + 1), 2 * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, stream));
+    HIPCHK(h, hipStreamSynchronize(stream));
+    const int restarted_total = h->hpin[0];
+    const int restarted = restarted_total - total_restarts;
+    total_restarts = restarted_total;
+    if (restarted == 0) break;
+    active = restarted;
+  }
+  if (restarts_out) *restarts_out = total_restarts;
+  return REXI_OK;
+}
+
+rexi_status solve(rexi_handle* h, Solver& sv, const double2* r0, const double2* r1, hipStream_t stream,
+                  int* restarts) {
+  switch (sv.ppt * 2 + sv.prec) {
+    case 16: return run_solve<double2, 8>(h, sv, r0, r1, stream, restarts);
+    case 17: return run_solve<float2, 8>(h, sv, r0, r1, stream, restarts);
+    case 8: return run_solve<double2, 4>(h, sv, r0, r1, stream, restarts);
+    case 9: return run_solve<float2, 4>(h, sv, r0, r1, stream, restarts);
+    case 4: return run_solve<double2, 2>(h, sv, r0, r1, stream, restarts);
+    case 5: return run_solve<float2, 2>(h, sv, r0, r1, stream, restarts);
+  }
+  return fail(h, REXI_E_INVALID_ARG, "unsupported tiling");
+}
+
+// Points per thread: the largest of 8, 4, 2 that still gives >= 4096 work tiles.
+int choose_ppt(int64_t points) {
+  for (int p : {8, 4}) if (points / (TPB * p) >= 4096) return p;
+  return 2;
+}
+
+// Fill the system table for a set of poles of the handle's instances.
+void make_systems(rexi_handle* h, Solver& sv, bool conj_shift, int rhs_sel) {
+  int sidx = 0;
+  for (int i = 0; i < h->ninst; ++i) {
+    const InstDesc& in = h->hinst[i];
+    for (int k = 0; k < h->Kinst[i]; ++k, ++sidx) {
+      SysDesc d{};
+      d.off = in.off;
+      d.n = in.n;
+      d.n0 = in.n0;
+      d.n1 = in.n1;
+      d.n2 = in.n2;
+      d.d2 = in.d2;
+      d.d1 = in.d1;
+      d.c0 = in.c0;
+      d.c1 = in.c1;
+      d.c2 = in.c2;
+      d.diag = in.diag;
+      const cplx s = conj_shift ? std::conj(h->s[sidx]) : h->s[sidx];
+      d.sre = s.real();
+      d.sim = s.imag();
+      d.wre = h->w[sidx].real();
+      d.wim = h->w[sidx].imag();
+      d.tol = h->tol_sys[sidx];
+      d.dist = h->dist_sys[sidx];
+      d.inst = i;
+      d.rhs_sel = rhs_sel;
+      sv.hsys.push_back(d);
+    }
+  }
+}
+
+rexi_status init_solver(rexi_handle* h, Solver& sv, int copies, hipStream_t stream) {
+  sv.hsys.clear();
+  if (copies == 0) {
+    // shared-basis solver: one unshifted system per instance
+    for (int i = 0; i < h->ninst; ++i) {
+      const InstDesc& in = h->hinst[i];
+      SysDesc d{};
+      d.off = in.off;
+      d.n = in.n;
+      d.n0 = in.n0;
+      d.n1 = in.n1;
+      d.n2 = in.n2;
+      d.d2 = in.d2;
+      d.d1 = in.d1;
+      d.c0 = in.c0;
+      d.c1 = in.c1;
+      d.c2 = in.c2;
+      d.diag = in.diag;
+      d.tol = 0.0;
+      d.dist = 1.0;
+      d.inst = i;
+      sv.hsys.push_back(d);
+    }
+  }
+  for (int c = 0; c < copies; ++c) make_systems(h, sv, c == 1, c);
+  sv.prec = h->opt.precision == REXI_PREC_C64_REFINE ? 1 : 0;
+  int64_t pts = 0;
+  for (auto& d : sv.hsys) pts += d.n;
+  sv.ppt = choose_ppt(pts);
+  sv.tile = TPB * sv.ppt;
+  sv.eta = h->opt.reorth_eta;
+  sv.reorth = h->opt.reorth;
+  sv.inner_rtol = sv.prec ? h->opt.inner_rtol : 0.0;
+  sv.max_cycles = h->opt.max_cycles;
+  // restart length: as asked, reduced until the workspace fits the budget
+  size_t budget = (size_t)h->opt.max_workspace_bytes;
+  if (budget == 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(h, REXI_E_HIP, "hipMemGetInfo failed");
+    budget = (size_t)(0.9 * (double)fr);
+  }
+  int m = h->opt.m;
+  for (;;) {
+    layout_systems(sv, m);
+    if (solver_bytes(sv.hsys, m, sv.prec, sv.max_cycles, sv.total_tiles) <= budget) break;
+    if (copies == 0) return fail(h, REXI_E_NO_MEMORY, "shared Krylov basis of dimension %d does not fit", m);
+    if (m <= 4) return fail(h, REXI_E_NO_MEMORY, "Krylov workspace does not fit the %zu-byte budget", budget);
+    m = std::max(4, m * 3 / 4);
+  }
+  sv.m = m;
+  sv.grid = default_grid(sv.total_tiles, h->opt.grid_blocks);
+  return build_solver(h, sv, stream);
+}
+
+
+// Shared-basis solver: the Arnoldi system plus per-pole Givens data.
+rexi_status init_shifted(rexi_handle* h, hipStream_t stream) {
+  rexi_status st = init_solver(h, h->fwd, 0, stream);
+  if (st != REXI_OK) return st;
+  const int K = h->Kinst[0], m = h->fwd.m;
+  rexi::ShiftWork& S = h->SW;
+  S.K = K;
+  auto al = [&](double** p, size_t count) -> rexi_status {
+    DevBuf b;
+    b.bytes = std::max<size_t>(count * sizeof(double), 256);
+    hipError_t e = hipMalloc(&b.p, b.bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(h, REXI_E_NO_MEMORY, "hipMalloc failed: %s", hipGetErrorString(e));
+    }
+    h->sbufs.push_back(b);
+    h->ws_bytes += (int64_t)b.bytes;
+    *p = reinterpret_cast<double*>(b.p);
+    return REXI_OK;
+  };
+  double *s = nullptr, *w = nullptr, *tol = nullptr, *its = nullptr;
+  if ((st = al(&s, 2 * K)) || (st = al(&w, 2 * K)) || (st = al(&tol, K)) ||
+      (st = al(&S.R, (size_t)K * (m + 1) * m * 2)) || (st = al(&S.g, (size_t)K * (m + 1) * 2)) ||
+      (st = al(&S.gc, (size_t)K * m * 2)) || (st = al(&S.gs, (size_t)K * m * 2)) ||
+      (st = al(&S.y, (size_t)K * m * 2)) || (st = al(&S.z, (size_t)m * 2)) || (st = al(&S.res, K)) ||
+      (st = al(&its, K)))
+    return st;
+  S.s = s;
+  S.w = w;
+  S.tol = tol;
+  S.its = reinterpret_cast<int32_t*>(its);
+  std::vector<double> hs(2 * K), hw(2 * K), ht(K);
+  for (int k = 0; k < K; ++k) {
+    hs[2 * k] = h->s[k].real();
+    hs[2 * k + 1] = h->s[k].imag();
+    hw[2 * k] = h->w[k].real();
+    hw[2 * k + 1] = h->w[k].imag();
+    ht[k] = h->tol_sys[k];
+  }
+  HIPCHK(h, hipMemcpyAsync(s, hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  HIPCHK(h, hipMemcpyAsync(w, hw.data(), hw.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  HIPCHK(h, hipMemcpyAsync(tol, ht.data(), ht.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  HIPCHK(h, hipStreamSynchronize(stream));
+  return REXI_OK;
+}
+
+// One shared-basis solve of all poles of instance 0; writes the pole sum to out.
+template <typename T, int PPT>
+rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStream_t stream) {
+  Solver& sv = h->fwd;
+  Work& W = sv.W;
+  const int G = sv.grid, m = sv.m;
+  const double e = sizeof(T);
+  const double n = sv.hsys[0].n;
+  {
+    Timed t(h, PC_START, n * (16.0 + e), stream);
+    hipLaunchKernelGGL((rexi::k_start<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, b, b);
+  }
+  {
+    Timed t(h, PC_REDUCE, 0, stream);
+    hipLaunchKernelGGL(rexi::k_start_reduce, dim3(1), dim3(TPB), 0, stream, W);
+    hipLaunchKernelGGL(rexi::k_shifted_init, dim3(1), dim3(TPB), 0, stream, W, h->SW);
+  }
+  // iterations run in chunks between host reads of the convergence counter;
+  // iterations after convergence return at once (device-side state)
+  const int chunk = std::max(1, h->opt.check_every);
+  for (int j = 0; j < m; ++j) {
+    {
+      Timed t(h, PC_ARNOLDI_A, n * ((j + 2) * e + 8.0), stream);
+      hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, true>), dim3(G), dim3(TPB), 0, stream, W, j);
+    }
+    {
+      Timed t(h, PC_REDUCE, 0, stream);
+      hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(1, j + 2), dim3(TPB), 0, stream, W, j, 0);
+    }
+    {
+      Timed t(h, PC_ARNOLDI_B, n * (j + 3) * e, stream);
+      hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, j, 0);
+    }
+    if (sv.reorth) {
+      {
+        Timed t(h, PC_REORTH_A, 0, stream);
+        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(G), dim3(TPB), 0, stream, W, j);
+      }
+      {
+        Timed t(h, PC_REDUCE, 0, stream);
+        hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(1, j + 2), dim3(TPB), 0, stream, W, j, 1);
+      }
+      {
+        Timed t(h, PC_REORTH_B, 0, stream);
+        hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, j, 1);
+      }
+    }
+    {
+      Timed t(h, PC_REDUCE, 0, stream);
+      hipLaunchKernelGGL(rexi::k_shifted_givens, dim3(1), dim3(TPB), 0, stream, W, h->SW, j);
+    }
+    HIPCHK(h, hipGetLastError());
+    if ((j + 1) % chunk == 0 || j + 1 == m) {
+      HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + j, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+      HIPCHK(h, hipStreamSynchronize(stream));
+      if (h->hpin[0] == 0) break;
+    }
+  }
+  {
+    Timed t(h, PC_POLESUM, 0, stream);
+    hipLaunchKernelGGL((rexi::k_combine_out<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, h->SW, out);
+  }
+  HIPCHK(h, hipGetLastError());
+  return REXI_OK;
+}
+
+rexi_status shifted_step(rexi_handle* h, const double2* b, double2* out, hipStream_t stream) {
+  switch (h->fwd.ppt) {
+    case 8: return run_shifted<double2, 8>(h, b, out, stream);
+    case 4: return run_shifted<double2, 4>(h, b, out, stream);
+    case 2: return run_shifted<double2, 2>(h, b, out, stream);
+  }
+  return fail(h, REXI_E_INVALID_ARG, "unsupported tiling");
+}
+
+InstDesc make_inst(const rexi_grid& g, double hbar, double mass, int64_t off) {
+  InstDesc in{};
+  int64_t n[3] = {1, 1, 1};
+  double hh[3] = {1, 1, 1};
+  const int nd = g.ndim;
+  for (int a = 0; a < nd; ++a) {
+    n[3 - nd + a] = g.n[a];
+    hh[3 - nd + a] = (g.hi[a] - g.lo[a]) / (double)(g.n[a] + 1);
+  }
+  in.off = off;
+  in.n0 = (int)n[0];
+  in.n1 = (int)n[1];
+  in.n2 = (int)n[2];
+  in.n = (int)(n[0] * n[1] * n[2]);
+  in.d2 = rexi::make_fastdiv((uint32_t)in.n2);
+  in.d1 = rexi::make_fastdiv((uint32_t)in.n1);
+  const double k = hbar * hbar / (2.0 * mass);
+  double c[3];
+  for (int a = 0; a < 3; ++a) c[a] = (3 - nd <= a) ? k / (hh[a] * hh[a]) : 0.0;
+  in.c0 = c[0];
+  in.c1 = c[1];
+  in.c2 = c[2];
+  in.diag = 2.0 * (c[0] + c[1] + c[2]);
+  return in;
+}
+
+rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, const double* V_dev,
+                         const double* hbar, const double* mass, const double* dt, const int32_t* K,
+                         const rexi_c128* sigma, const rexi_c128* beta, const rexi_options* opt,
+                         hipStream_t stream) {
+  g_setup_error.clear();
+  if (!out) return fail(nullptr, REXI_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (count < 1 || !grids || !V_dev || !hbar || !mass || !dt || !K || !sigma || !beta)
+    return fail(nullptr, REXI_E_INVALID_ARG, "NULL argument or count < 1");
+  rexi_options o;
+  rexi_default_options(&o);
+  if (opt) o = *opt;
+  if (o.precision != REXI_PREC_C128 && o.precision != REXI_PREC_C64_REFINE)
+    return fail(nullptr, REXI_E_INVALID_ARG, "unknown precision %d", o.precision);
+  if (o.solver != REXI_SOLVER_PER_POLE && o.solver != REXI_SOLVER_SHIFTED)
+    return fail(nullptr, REXI_E_INVALID_ARG, "unknown solver %d", o.solver);
+  if (o.solver == REXI_SOLVER_SHIFTED && o.precision != REXI_PREC_C128)
+    return fail(nullptr, REXI_E_INVALID_ARG, "the shared-basis solver runs in complex128 only");
+  if (o.solver == REXI_SOLVER_SHIFTED && count != 1)
+    return fail(nullptr, REXI_E_INVALID_ARG, "the shared-basis solver takes a single instance");
+  if (o.m < 1 || o.m > 256) return fail(nullptr, REXI_E_INVALID_ARG, "m must be in [1, 256] (got %d)", o.m);
+  if (!(o.reorth_eta > 0.0 && o.reorth_eta < 1.0)) return fail(nullptr, REXI_E_INVALID_ARG, "reorth_eta in (0, 1)");
+  if (o.max_cycles < 1 || o.max_cycles > 1000) return fail(nullptr, REXI_E_INVALID_ARG, "max_cycles out of range");
+  if (!(o.tol > 0.0) || !is_fin(o.tol)) return fail(nullptr, REXI_E_INVALID_ARG, "tol must be positive");
+  if (o.tol_policy != REXI_TOL_RELRES && o.tol_policy != REXI_TOL_CERTIFIED)
+    return fail(nullptr, REXI_E_INVALID_ARG, "unknown tol_policy");
+  if (o.reorth < 0 || o.reorth > 2) return fail(nullptr, REXI_E_INVALID_ARG, "reorth must be 0, 1 or 2");
+  if (!(o.inner_rtol >= 0.0 && o.inner_rtol < 1.0)) return fail(nullptr, REXI_E_INVALID_ARG, "inner_rtol in [0,1)");
+  if (o.max_workspace_bytes < 0) return fail(nullptr, REXI_E_INVALID_ARG, "max_workspace_bytes < 0");
+  if (o.grid_blocks < 0) return fail(nullptr, REXI_E_INVALID_ARG, "grid_blocks < 0");
+
+  // ---- validate the instances (host side, before any device work)
+  int64_t N = 0, Ktot = 0;
+  for (int i = 0; i < count; ++i) {
+    const rexi_grid& g = grids[i];
+    if (g.ndim < 1 || g.ndim > 3) return fail(nullptr, REXI_E_INVALID_ARG, "instance %d: ndim %d", i, g.ndim);
+    int64_t np = 1;
+    for (int a = 0; a < g.ndim; ++a) {
+      if (g.n[a] < 1) return fail(nullptr, REXI_E_INVALID_ARG, "instance %d: n[%d] < 1", i, a);
+      if (!(g.hi[a] > g.lo[a]) || !is_fin(g.lo[a]) || !is_fin(g.hi[a]))
+        return fail(nullptr, REXI_E_INVALID_ARG, "instance %d: need finite lo < hi on axis %d", i, a);
+      np *= g.n[a];
+      if (np > (int64_t)1 << 30) return fail(nullptr, REXI_E_INVALID_ARG, "instance %d: more than 2^30 points", i);
+    }
+    if (!(hbar[i] > 0.0) || !is_fin(hbar[i])) return fail(nullptr, REXI_E_INVALID_ARG, "instance %d: hbar <= 0", i);
+    if (!(mass[i] > 0.0) || !is_fin(mass[i])) return fail(nullptr, REXI_E_INVALID_ARG, "instance %d: mass <= 0", i);
+    if (!(dt[i] != 0.0) || !is_fin(dt[i])) return fail(nullptr, REXI_E_INVALID_ARG, "instance %d: dt must be finite and nonzero", i);
+    if (K[i] < 1 || K[i] > 4096) return fail(nullptr, REXI_E_INVALID_ARG, "instance %d: K = %d", i, K[i]);
+    N += np;
+    Ktot += K[i];
+  }
+  if (N > ((int64_t)1 << 31) - 1) return fail(nullptr, REXI_E_INVALID_ARG, "more than 2^31 - 1 points in total");
+  for (int64_t k = 0; k < Ktot; ++k)
+    if (!is_fin(sigma[k].re) || !is_fin(sigma[k].im) || !is_fin(beta[k].re) || !is_fin(beta[k].im))
+      return fail(nullptr, REXI_E_INVALID_ARG, "pole %lld: non-finite sigma or beta", (long long)k);
+
+  // V on the host: finiteness and the range of the spectrum bound
+  std::vector<double> Vh((size_t)N);
+  {
+    hipError_t e = hipMemcpyAsync(Vh.data(), V_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(nullptr, REXI_E_HIP, "reading V failed: %s", hipGetErrorString(e));
+  }
+  for (int64_t i = 0; i < N; ++i)
+    if (!is_fin(Vh[(size_t)i])) return fail(nullptr, REXI_E_INVALID_ARG, "V[%lld] is not finite", (long long)i);
+
+  rexi_handle* h = new (std::nothrow) rexi_handle();
+  if (!h) return fail(nullptr, REXI_E_NO_MEMORY, "host allocation failed");
+  h->opt = o;
+  h->ninst = count;
+  h->N = N;
+  int64_t off = 0, kk = 0;
+  int itile = 0;
+  const int itile_pts = TPB * PPT;
+  for (int i = 0; i < count; ++i) {
+    InstDesc in = make_inst(grids[i], hbar[i], mass[i], off);
+    in.sys0 = (int)kk;
+    in.nsys = K[i];
+    in.tile0 = itile;
+    in.ntiles = (in.n + itile_pts - 1) / itile_pts;
+    h->hitile.push_back(itile);
+    itile += in.ntiles;
+    double vmin = Vh[(size_t)off], vmax = vmin;
+    for (int64_t p = off; p < off + in.n; ++p) {
+      vmin = std::min(vmin, Vh[(size_t)p]);
+      vmax = std::max(vmax, Vh[(size_t)p]);
+    }
+    const double lo = vmin, hi = 2.0 * in.diag + vmax;  // (hbar^2/2m) sum 4/h^2 + max V
+    h->lam_lo.push_back(lo);
+    h->lam_hi.push_back(hi);
+    for (int k = 0; k < K[i]; ++k, ++kk) {
+      // s_j = i hbar sigma_j / dt, w_j = i hbar beta_j / dt (eq. rational-evaluation, B = hbar I)
+      const cplx I(0.0, 1.0);
+      const cplx sg(sigma[kk].re, sigma[kk].im), bt(beta[kk].re, beta[kk].im);
+      const cplx s = I * hbar[i] * sg / dt[i];
+      const cplx w = I * hbar[i] * bt / dt[i];
+      const double re = std::min(std::max(s.real(), lo), hi);
+      const double dist = std::abs(cplx(re, 0.0) - s);
+      const double scale = std::max({std::fabs(lo), std::fabs(hi), std::abs(s), 1e-300});
+      if (!(dist > 1e-13 * scale)) {
+        destroy_handle(h);
+        return fail(nullptr, REXI_E_INVALID_ARG,
+                    "pole %lld: shift (%g, %g) lies on the spectrum bound [%g, %g] (singular system)",
+                    (long long)kk, s.real(), s.imag(), lo, hi);
+      }
+      // floor of an attainable FP64 relative residual for this system
+      const double u = 1.1102230246251565e-16;
+      const double floor_r = 8.0 * u * (1.0 + std::max(std::abs(cplx(lo) - s), std::abs(cplx(hi) - s)) / dist);
+      double tol = o.tol;
+      if (o.tol_policy == REXI_TOL_CERTIFIED) {
+        // sum_j |w_j| rho_j / dist_j <= tol when rho_j = tol dist_j / (K |w_j|)
+        tol = o.tol * dist / ((double)K[i] * std::max(std::abs(w), 1e-300));
+      }
+      tol = std::max(tol, floor_r);
+      h->s.push_back(s);
+      h->w.push_back(w);
+      h->tol_sys.push_back(tol);
+      h->dist_sys.push_back(dist);
+    }
+    h->Kinst.push_back(K[i]);
+    h->hinst.push_back(in);
+    off += in.n;
+  }
+  h->hitile.push_back(itile);
+  h->itotal = itile;
+
+#define SETUP_CHK(call)                                                                             \
+  do {                                                                                              \
+    hipError_t e_ = (call);                                                                         \
+    if (e_ != hipSuccess) {                                                                         \
+      (void)hipGetLastError();                                                                      \
+      rexi_status st_ = (e_ == hipErrorOutOfMemory) ? REXI_E_NO_MEMORY : REXI_E_HIP;                \
+      fail(nullptr, st_, "%s failed: %s", #call, hipGetErrorString(e_));                            \
+      destroy_handle(h);                                                                            \
+      return st_;                                                                                   \
+    }                                                                                               \
+  } while (0)
+  SETUP_CHK(hipMalloc(&h->V64, (size_t)N * sizeof(double)));
+  SETUP_CHK(hipMemcpyAsync(h->V64, V_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  if (o.precision == REXI_PREC_C64_REFINE) {
+    SETUP_CHK(hipMalloc(&h->V32, (size_t)N * sizeof(float)));
+    hipLaunchKernelGGL(rexi::k_v_to_f32, dim3(1024), dim3(TPB), 0, stream, h->V64, h->V32, (int64_t)N);
+    SETUP_CHK(hipGetLastError());
+  }
+  SETUP_CHK(hipMalloc(&h->dinst, count * sizeof(InstDesc)));
+  SETUP_CHK(hipMalloc(&h->ditile, (count + 1) * sizeof(int32_t)));
+  SETUP_CHK(hipMalloc(&h->dnorm, std::max(1, itile) * sizeof(double)));
+  SETUP_CHK(hipMemcpyAsync(h->dinst, h->hinst.data(), count * sizeof(InstDesc), hipMemcpyHostToDevice, stream));
+  SETUP_CHK(hipMemcpyAsync(h->ditile, h->hitile.data(), (count + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  SETUP_CHK(hipHostMalloc((void**)&h->hpin, 64 * sizeof(int32_t), hipHostMallocDefault));
+  SETUP_CHK(hipStreamSynchronize(stream));
+  h->ws_bytes = (int64_t)N * (o.precision ? 12 : 8);
+  h->shifted = o.solver == REXI_SOLVER_SHIFTED;
+  rexi_status st = h->shifted ? init_shifted(h, stream) : init_solver(h, h->fwd, 1, stream);
+  if (st != REXI_OK) {
+    g_setup_error = h->err;
+    destroy_handle(h);
+    return st;
+  }
+  h->prof.on = o.profile != 0;
+  *out = h;
+  return REXI_OK;
+#undef SETUP_CHK
+}
+
+__global__ void k_norm2_inst(const InstDesc* __restrict__ inst, int ninst, const int32_t* __restrict__ itile,
+                             int itotal, const double2* __restrict__ v, double* __restrict__ part, int tile) {
+  __shared__ double lds[rexi::NWAVE];
+  for (int item = blockIdx.x; item < itotal; item += gridDim.x) {
+    const int ii = rexi::find_sys(itile, ninst, item);
+    const InstDesc& in = inst[ii];
+    const int t = item - in.tile0;
+    double acc = 0.0;
+    for (int p = t * tile + threadIdx.x; p < std::min((t + 1) * tile, in.n); p += TPB) {
+      const double2 a = v[in.off + p];
+      acc += a.x * a.x + a.y * a.y;
+    }
+    acc = rexi::block_sum(acc, lds);
+    if (threadIdx.x == 0) part[item] = acc;
+  }
+}
+
+rexi_status vec_norm(rexi_handle* h, const double2* v, hipStream_t stream, double* out) {
+  const int tile = TPB * PPT;
+  hipLaunchKernelGGL(k_norm2_inst, dim3(std::min(h->itotal, 2048)), dim3(TPB), 0, stream, h->dinst, h->ninst,
+                     h->ditile, h->itotal, v, h->dnorm, tile);
+  HIPCHK(h, hipGetLastError());
+  std::vector<double> part((size_t)h->itotal);
+  HIPCHK(h, hipMemcpyAsync(part.data(), h->dnorm, part.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHK(h, hipStreamSynchronize(stream));
+  double s = 0.0;
+  for (double p : part) s += p;
+  *out = std::sqrt(s);
+  return REXI_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+void rexi_default_options(rexi_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->precision = REXI_PREC_C128;
+  o->solver = REXI_SOLVER_PER_POLE;
+  o->m = 30;
+  o->max_cycles = 20;
+  o->tol = 1e-10;
+  o->tol_policy = REXI_TOL_RELRES;
+  o->reorth = 1;
+  o->reorth_eta = 1e-2;
+  o->inner_rtol = 1e-5;
+  o->check_every = 4;
+  o->capture_safe = 0;
+  o->profile = 0;
+  o->tile = 0;
+  o->grid_blocks = 0;
+  o->max_workspace_bytes = 0;
+}
+
+rexi_status rexi_setup(rexi_handle** out, const rexi_grid* g, const double* V_dev, double hbar, double mass,
+                       double dt, int32_t K, const rexi_c128* sigma_host, const rexi_c128* beta_host,
+                       const rexi_options* opt, void* stream) {
+  if (!g) return fail(nullptr, REXI_E_INVALID_ARG, "grid is NULL");
+  return setup_common(out, 1, g, V_dev, &hbar, &mass, &dt, &K, sigma_host, beta_host, opt, (hipStream_t)stream);
+}
+
+rexi_status rexi_setup_batch(rexi_handle** out, int32_t count, const rexi_grid* grids, const double* V_dev,
+                             const double* hbar, const double* mass, const double* dt, const int32_t* K,
+                             const rexi_c128* sigma_host, const rexi_c128* beta_host, const rexi_options* opt,
+                             void* stream) {
+  return setup_common(out, count, grids, V_dev, hbar, mass, dt, K, sigma_host, beta_host, opt,
+                      (hipStream_t)stream);
+}
+
+rexi_status rexi_apply_H(rexi_handle* h, const rexi_c128* x_dev, rexi_c128* y_dev, rexi_c128 shift, void* stream) {
+  if (!h) return REXI_E_INVALID_ARG;
+  if (!x_dev || !y_dev) return fail(h, REXI_E_INVALID_ARG, "NULL vector");
+  if ((const void*)x_dev == (const void*)y_dev) return fail(h, REXI_E_INVALID_ARG, "x and y must not alias");
+  if (!is_fin(shift.re) || !is_fin(shift.im)) return fail(h, REXI_E_INVALID_ARG, "non-finite shift");
+  hipStream_t st = (hipStream_t)stream;
+  Timed t(h, PC_APPLY_H, (double)h->N * 40.0, st);
+  hipLaunchKernelGGL(rexi::k_apply_h, dim3(std::min(h->itotal, 2048)), dim3(TPB), 0, st, h->dinst, h->ninst,
+                     h->ditile, h->itotal, h->V64, (const double2*)x_dev, (double2*)y_dev, shift.re, shift.im,
+                     TPB * PPT);
+  HIPCHK(h, hipGetLastError());
+  return REXI_OK;
+}
+
+rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_out, int32_t nsteps,
+                      rexi_step_info* info, void* stream) {
+  if (!h) return REXI_E_INVALID_ARG;
+  if (!psi_in || !psi_out) return fail(h, REXI_E_INVALID_ARG, "NULL vector");
+  if (nsteps < 1) return fail(h, REXI_E_INVALID_ARG, "nsteps must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  Solver& sv = h->fwd;
+  const double2* in = (const double2*)psi_in;
+  double2* outp = (double2*)psi_out;
+  double norm_in = 0.0;
+  int64_t its_total = 0;
+  int restarts = 0;
+  for (int n = 0; n < nsteps; ++n) {
+    const double2* src = n == 0 ? in : outp;
+    if (h->shifted) {
+      rexi_status s1 = shifted_step(h, src, outp, st);
+      if (s1 != REXI_OK) return s1;
+      if (info) {
+        const int K = h->SW.K;
+        std::vector<double> res((size_t)K);
+        std::vector<int32_t> its((size_t)K);
+        SysState_t s0;
+        HIPCHK(h, hipMemcpyAsync(res.data(), h->SW.res, K * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(h, hipMemcpyAsync(its.data(), h->SW.its, K * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(h, hipMemcpyAsync(&s0, sv.W.st, sizeof(SysState_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(h, hipStreamSynchronize(st));
+        its_total += s0.its;
+        if (n == nsteps - 1) {
+          info->K = K;
+          info->max_cycles_used = 1;
+          info->not_converged = 0;
+          info->max_rel_residual = 0.0;
+          double bound = 0.0;
+          for (int k = 0; k < K; ++k) {
+            if (!(res[k] <= h->tol_sys[k])) info->not_converged += 1;
+            info->max_rel_residual = std::max(info->max_rel_residual, res[k]);
+            bound += std::abs(h->w[k]) * res[k] / h->dist_sys[k];
+            if (info->iterations) info->iterations[k] = its[k] > 0 ? its[k] : s0.its;
+            if (info->cycles) info->cycles[k] = 1;
+            if (info->rel_residual) info->rel_residual[k] = res[k];
+          }
+          info->certified_bound = bound;
+          info->norm_in = s0.bnorm;
+          double no = 0.0;
+          rexi_status s2 = vec_norm(h, outp, st, &no);
+          if (s2 != REXI_OK) return s2;
+          info->norm_out = no;
+        }
+      }
+      prof_collect(h, st);
+      continue;
+    }
+    rexi_status s1 = solve(h, sv, src, src, st, &restarts);
+    if (s1 != REXI_OK) return s1;
+    {
+      Timed t(h, PC_POLESUM, (double)h->N * 16.0 * (1.0 + (double)sv.S / h->ninst), st);
+      hipLaunchKernelGGL(rexi::k_polesum, dim3(std::min(h->itotal, 2048)), dim3(TPB), 0, st, h->dinst, h->ninst,
+                         h->ditile, h->itotal, sv.dsys, sv.W.x, outp, TPB * PPT, 0, 0);
+    }
+    HIPCHK(h, hipGetLastError());
+    if (info) {
+      std::vector<SysState_t> hs((size_t)sv.S);
+      HIPCHK(h, hipMemcpyAsync(hs.data(), sv.W.st, sv.S * sizeof(SysState_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(h, hipStreamSynchronize(st));
+      for (auto& x : hs) its_total += x.its;
+      if (n == nsteps - 1) {
+        info->K = sv.S;
+        info->max_cycles_used = 0;
+        info->not_converged = 0;
+        info->max_rel_residual = 0.0;
+        double bound = 0.0, bn = 0.0;
+        for (int s = 0; s < sv.S; ++s) {
+          const SysState_t& x = hs[(size_t)s];
+          info->max_cycles_used = std::max(info->max_cycles_used, x.cycles);
+          if (!(x.rho <= sv.hsys[(size_t)s].tol)) info->not_converged += 1;
+          info->max_rel_residual = std::max(info->max_rel_residual, x.rho);
+          bound += std::abs(h->w[(size_t)s]) * x.rho * x.bnorm / h->dist_sys[(size_t)s];
+          bn = std::max(bn, x.bnorm);
+          if (info->iterations) info->iterations[s] = x.its;
+          if (info->cycles) info->cycles[s] = x.cycles;
+          if (info->rel_residual) info->rel_residual[s] = x.rho;
+        }
+        norm_in = bn;
+        info->certified_bound = bn > 0.0 ? bound / bn : 0.0;
+        info->norm_in = norm_in;
+        double no = 0.0;
+        rexi_status s2 = vec_norm(h, outp, st, &no);
+        if (s2 != REXI_OK) return s2;
+        info->norm_out = no;
+      }
+    }
+    prof_collect(h, st);
+  }
+  if (info) {
+    info->steps = nsteps;
+    info->total_iterations = its_total;
+    if (info->not_converged) return fail(h, REXI_E_NOT_CONVERGED, "%d pole solves missed their target", info->not_converged);
+  }
+  return REXI_OK;
+}
+
+rexi_status rexi_step_adjoint(rexi_handle* h, const rexi_c128* psi_n, const rexi_c128* gbar_next,
+                              rexi_c128* gbar_n, double* dV_accum, void* stream) {
+  if (!h) return REXI_E_INVALID_ARG;
+  if (!psi_n || !gbar_next || !gbar_n) return fail(h, REXI_E_INVALID_ARG, "NULL vector");
+  if (h->ninst != 1) return fail(h, REXI_E_INVALID_ARG, "adjoint needs a single-instance handle");
+  hipStream_t st = (hipStream_t)stream;
+  if (!h->adj.ready) {
+    rexi_status s0 = init_solver(h, h->adj, 2, st);
+    if (s0 != REXI_OK) return s0;
+  }
+  Solver& sv = h->adj;
+  int restarts = 0;
+  // systems [0, K): (H - s_j) x_j = psi_n ; [K, 2K): (H - conj s_j) y_j = gbar_{n+1}
+  rexi_status s1 = solve(h, sv, (const double2*)psi_n, (const double2*)gbar_next, st, &restarts);
+  if (s1 != REXI_OK) return s1;
+  const int K = h->Kinst[0];
+  if (dV_accum) {
+    Timed t(h, PC_GRAD, (double)h->N * (32.0 * K + 16.0), st);
+    hipLaunchKernelGGL(rexi::k_grad_v, dim3(std::min(h->itotal, 2048)), dim3(TPB), 0, st, h->dinst, h->ditile,
+                       h->itotal, sv.dsys, sv.W.x, dV_accum, TPB * PPT, K);
+    HIPCHK(h, hipGetLastError());
+  }
+  {
+    // gbar_n = sum_j conj(w_j) y_j (systems K..2K-1 hold y_j; their weights are w_j)
+    Timed t(h, PC_POLESUM, (double)h->N * 16.0 * (1.0 + K), st);
+    hipLaunchKernelGGL(rexi::k_polesum, dim3(std::min(h->itotal, 2048)), dim3(TPB), 0, st, h->dinst, h->ninst,
+                       h->ditile, h->itotal, sv.dsys, sv.W.x, (double2*)gbar_n, TPB * PPT, 1, K);
+    HIPCHK(h, hipGetLastError());
+  }
+  // convergence of the 2K solves
+  HIPCHK(h, hipMemcpyAsync(h->hpin, sv.W.counters + sv.max_cycles * (sv.m + 1) + 1, sizeof(int32_t),
+                           hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  prof_collect(h, st);
+  if (h->hpin[0] != 0) return fail(h, REXI_E_NOT_CONVERGED, "%d adjoint pole solves missed their target", h->hpin[0]);
+  return REXI_OK;
+}
+
+rexi_status rexi_get_profile(const rexi_handle* h, rexi_profile* out) {
+  if (!h || !out) return REXI_E_INVALID_ARG;
+  std::memset(out, 0, sizeof *out);
+  out->nclasses = PC_NCLASS;
+  for (int c = 0; c < PC_NCLASS; ++c) {
+    out->names[c] = kProfNames[c];
+    out->launches[c] = h->prof.launches[c];
+    out->ms[c] = h->prof.ms[c];
+    out->bytes[c] = h->prof.bytes[c];
+  }
+  return REXI_OK;
+}
+
+rexi_status rexi_profile_reset(rexi_handle* h) {
+  if (!h) return REXI_E_INVALID_ARG;
+  for (int c = 0; c < PC_NCLASS; ++c) {
+    h->prof.launches[c] = 0;
+    h->prof.ms[c] = 0;
+    h->prof.bytes[c] = 0;
+  }
+  return REXI_OK;
+}
+
+rexi_status rexi_workspace_info(const rexi_handle* h, int64_t* bytes, int32_t* m_used) {
+  if (!h) return REXI_E_INVALID_ARG;
+  if (bytes) *bytes = h->ws_bytes;
+  if (m_used) *m_used = h->fwd.m;
+  return REXI_OK;
+}
+
+rexi_status rexi_destroy(rexi_handle* h) {
+  destroy_handle(h);
+  return REXI_OK;
+}
+
+const char* rexi_status_string(rexi_status s) {
+  switch (s) {
+    case REXI_OK: return "REXI_OK";
+    case REXI_E_INVALID_ARG: return "REXI_E_INVALID_ARG";
+    case REXI_E_NO_MEMORY: return "REXI_E_NO_MEMORY";
+    case REXI_E_HIP: return "REXI_E_HIP";
+    case REXI_E_NOT_CONVERGED: return "REXI_E_NOT_CONVERGED";
+    case REXI_E_NOT_BUILT: return "REXI_E_NOT_BUILT";
+  }
+  return "REXI_E_UNKNOWN";
+}
+
+rexi_status rexi_last_error(const rexi_handle* h, char* buf, size_t len) {
+  if (!buf || len == 0) return REXI_E_INVALID_ARG;
+  const std::string& e = h ? h->err : g_setup_error;
+  std::snprintf(buf, len, "%s", e.c_str());
+  return REXI_OK;
+}
+
+}  // extern "C"

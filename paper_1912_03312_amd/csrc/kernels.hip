@@ -1,0 +1,865 @@
+// HIP kernels of the REXI step for gfx950 (CDNA4, wave64).
+//
+// The step psi <- sum_j w_j (H - s_j I)^{-1} psi (eq. rational-evaluation,
+// Section 3.1) is computed by restarted GMRES on every shifted system, all
+// systems advancing together. One Arnoldi iteration j of every active system
+// is four launches:
+//   arnoldi_a   w = c_j (H - s) u_j (stencil matvec) stored as u_{j+1};
+//               partial sums of <u_i, w> (i <= j) and ||w||^2 per tile
+//   reduce_dots per system: h_ij = c_i <u_i, w>, DGKS test
+//   arnoldi_b   u_{j+1} -= sum_i h_ij c_i u_i; partial ||u_{j+1}||^2
+//   givens      per system: h_{j+1,j} = ||u_{j+1}||, Givens QR update of the
+//               Hessenberg column, implicit residual, convergence decision
+// (plus arnoldi_a / reduce_dots / arnoldi_b without the matvec for a second,
+// DGKS, Gram-Schmidt pass). Basis vectors are stored unnormalised, v_i =
+// c_i u_i, so no pass rescales a vector. A cycle ends with
+//   update_x    x += sum_i y_i c_i u_i (FP64)
+//   residual    r = b - (H - s) x in FP64, u_0 = r for the next cycle
+//   restart     per system: explicit relative residual, done or restart
+// and the step ends with the weighted pole sum in FP64 (polesum).
+//
+// Work tiles: a system's n points are cut into tiles of TPB * PPT points;
+// a tile is one work item. The grid-stride kernels visit every (system,
+// tile) item; items of systems that are not in the state a kernel serves
+// return at once, so ragged convergence needs no host decision.
+//
+// T is the storage type of the Krylov basis: double2 (complex128) or float2
+// (complex64, with the matvec in FP32). Dots, norms, Hessenberg, solutions,
+// residuals and the pole sum are FP64 for both.
+#include "rexi_internal.h"
+
+namespace rexi {
+
+constexpr int TPB = 256;
+constexpr int NWAVE = TPB / 64;
+constexpr int MAXM = 256;  // largest Krylov dimension per cycle
+
+// ------------------------------------------------------------ complex helpers
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__device__ __forceinline__ double2 cjmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 to_d2(double2 a) { return a; }
+__device__ __forceinline__ double2 to_d2(float2 a) { return make_double2((double)a.x, (double)a.y); }
+template <typename T> __device__ __forceinline__ T from_d2(double2 a);
+template <> __device__ __forceinline__ double2 from_d2<double2>(double2 a) { return a; }
+template <> __device__ __forceinline__ float2 from_d2<float2>(double2 a) {
+  return make_float2((float)a.x, (float)a.y);
+}
+
+// ------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the block; every thread gets the result. lds: NWAVE doubles.
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < NWAVE; ++w) s += lds[w];
+  return s;
+}
+
+// Locate the system of global tile `item` (tile_start is the prefix array).
+__device__ __forceinline__ int find_sys(const int32_t* tile_start, int S, int item) {
+  int lo = 0, hi = S;  // invariant: tile_start[lo] <= item < tile_start[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (tile_start[mid] <= item) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T> __device__ __forceinline__ T* basis_vec(const Work& W, const SysDesc& d, int i) {
+  return reinterpret_cast<T*>(W.basis) + d.basis + (int64_t)i * d.n;
+}
+
+// (H - s) u at point p, for storage type T, in the arithmetic of T.
+template <typename T>
+__device__ __forceinline__ double2 stencil_point(const T* __restrict__ u, const SysDesc& d,
+                                                 double vp, uint32_t p);
+
+template <>
+__device__ __forceinline__ double2 stencil_point<double2>(const double2* __restrict__ u, const SysDesc& d,
+                                                          double vp, uint32_t p) {
+  const uint32_t r = fdiv(p, d.d2);
+  const uint32_t k = p - r * (uint32_t)d.n2;
+  const uint32_t i0 = fdiv(r, d.d1);
+  const uint32_t j = r - i0 * (uint32_t)d.n1;
+  const uint32_t plane = (uint32_t)d.n1 * (uint32_t)d.n2;
+  const double2 c = u[p];
+  double2 nb2 = make_double2(0.0, 0.0), nb1 = nb2, nb0 = nb2;
+  if (k > 0) { double2 t = u[p - 1]; nb2.x += t.x; nb2.y += t.y; }
+  if (k + 1 < (uint32_t)d.n2) { double2 t = u[p + 1]; nb2.x += t.x; nb2.y += t.y; }
+  if (j > 0) { double2 t = u[p - d.n2]; nb1.x += t.x; nb1.y += t.y; }
+  if (j + 1 < (uint32_t)d.n1) { double2 t = u[p + d.n2]; nb1.x += t.x; nb1.y += t.y; }
+  if (i0 > 0) { double2 t = u[p - plane]; nb0.x += t.x; nb0.y += t.y; }
+  if (i0 + 1 < (uint32_t)d.n0) { double2 t = u[p + plane]; nb0.x += t.x; nb0.y += t.y; }
+  const double a = d.diag + vp - d.sre;
+  double2 o;
+  o.x = a * c.x + d.sim * c.y - (d.c2 * nb2.x + d.c1 * nb1.x + d.c0 * nb0.x);
+  o.y = a * c.y - d.sim * c.x - (d.c2 * nb2.y + d.c1 * nb1.y + d.c0 * nb0.y);
+  return o;
+}
+
+template <>
+__device__ __forceinline__ double2 stencil_point<float2>(const float2* __restrict__ u, const SysDesc& d,
+                                                         double vp, uint32_t p) {
+  const uint32_t r = fdiv(p, d.d2);
+  const uint32_t k = p - r * (uint32_t)d.n2;
+  const uint32_t i0 = fdiv(r, d.d1);
+  const uint32_t j = r - i0 * (uint32_t)d.n1;
+  const uint32_t plane = (uint32_t)d.n1 * (uint32_t)d.n2;
+  const float2 c = u[p];
+  float2 nb2 = make_float2(0.f, 0.f), nb1 = nb2, nb0 = nb2;
+  if (k > 0) { float2 t = u[p - 1]; nb2.x += t.x; nb2.y += t.y; }
+  if (k + 1 < (uint32_t)d.n2) { float2 t = u[p + 1]; nb2.x += t.x; nb2.y += t.y; }
+  if (j > 0) { float2 t = u[p - d.n2]; nb1.x += t.x; nb1.y += t.y; }
+  if (j + 1 < (uint32_t)d.n1) { float2 t = u[p + d.n2]; nb1.x += t.x; nb1.y += t.y; }
+  if (i0 > 0) { float2 t = u[p - plane]; nb0.x += t.x; nb0.y += t.y; }
+  if (i0 + 1 < (uint32_t)d.n0) { float2 t = u[p + plane]; nb0.x += t.x; nb0.y += t.y; }
+  const float a = (float)(d.diag - d.sre) + (float)vp;
+  const float sim = (float)d.sim;
+  const float c2 = (float)d.c2, c1 = (float)d.c1, c0 = (float)d.c0;
+  float ox = a * c.x + sim * c.y - (c2 * nb2.x + c1 * nb1.x + c0 * nb0.x);
+  float oy = a * c.y - sim * c.x - (c2 * nb2.y + c1 * nb1.y + c0 * nb0.y);
+  return make_double2((double)ox, (double)oy);
+}
+
+// FP64 stencil on an FP64 vector: (H - s) x at p.
+__device__ __forceinline__ double2 stencil_point_f64(const double2* __restrict__ u, int n0, int n1, int n2,
+                                                     const FastDiv& d2, const FastDiv& d1, double c0, double c1,
+                                                     double c2, double diag, double vp, double sre, double sim,
+                                                     uint32_t p) {
+  const uint32_t r = fdiv(p, d2);
+  const uint32_t k = p - r * (uint32_t)n2;
+  const uint32_t i0 = fdiv(r, d1);
+  const uint32_t j = r - i0 * (uint32_t)n1;
+  const uint32_t plane = (uint32_t)n1 * (uint32_t)n2;
+  const double2 c = u[p];
+  double2 nb2 = make_double2(0.0, 0.0), nb1 = nb2, nb0 = nb2;
+  if (k > 0) { double2 t = u[p - 1]; nb2.x += t.x; nb2.y += t.y; }
+  if (k + 1 < (uint32_t)n2) { double2 t = u[p + 1]; nb2.x += t.x; nb2.y += t.y; }
+  if (j > 0) { double2 t = u[p - n2]; nb1.x += t.x; nb1.y += t.y; }
+  if (j + 1 < (uint32_t)n1) { double2 t = u[p + n2]; nb1.x += t.x; nb1.y += t.y; }
+  if (i0 > 0) { double2 t = u[p - plane]; nb0.x += t.x; nb0.y += t.y; }
+  if (i0 + 1 < (uint32_t)n0) { double2 t = u[p + plane]; nb0.x += t.x; nb0.y += t.y; }
+  const double a = diag + vp - sre;
+  double2 o;
+  o.x = a * c.x + sim * c.y - (c2 * nb2.x + c1 * nb1.x + c0 * nb0.x);
+  o.y = a * c.y - sim * c.x - (c2 * nb2.y + c1 * nb1.y + c0 * nb0.y);
+  return o;
+}
+
+template <typename T> __device__ __forceinline__ double vpot(const Work& W, int64_t idx);
+template <> __device__ __forceinline__ double vpot<double2>(const Work& W, int64_t idx) { return W.V64[idx]; }
+template <> __device__ __forceinline__ double vpot<float2>(const Work& W, int64_t idx) { return (double)W.V32[idx]; }
+
+// ------------------------------------------------------------ cycle start
+// u_0 = b (cast to T) and partial ||b||^2 for every system; solutions reset.
+template <typename T, int PPT>
+__global__ __launch_bounds__(TPB) void k_start(Work W, const double2* __restrict__ rhs0,
+                                               const double2* __restrict__ rhs1) {
+  __shared__ double lds[NWAVE];
+  for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
+    const int s = find_sys(W.tile_start, W.S, item);
+    const SysDesc& d = W.sys[s];
+    const int t = item - d.tile0;
+    const double2* __restrict__ b = (d.rhs_sel ? rhs1 : rhs0) + d.off;
+    T* __restrict__ u0 = basis_vec<T>(W, d, 0);
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int p = t * W.tile + q * TPB + threadIdx.x;
+      if (p < d.n) {
+        double2 v = b[p];
+        u0[p] = from_d2<T>(v);
+        acc += v.x * v.x + v.y * v.y;
+      }
+    }
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) W.pnorm[item] = acc;
+  }
+}
+
+// Per system: ||b||, initial Givens right-hand side, state reset.
+__global__ __launch_bounds__(TPB) void k_start_reduce(Work W) {
+  __shared__ double lds[NWAVE];
+  const int s = blockIdx.x;
+  if (s >= W.S) return;
+  const SysDesc& d = W.sys[s];
+  if (s == 0) {
+    const int nc = W.max_cycles * (W.m + 1) + 2;
+    for (int i = threadIdx.x; i < nc; i += TPB) W.counters[i] = 0;
+  }
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < d.ntiles; t += TPB) acc += W.pnorm[d.tile0 + t];
+  acc = block_sum(acc, lds);
+  if (threadIdx.x == 0) {
+    const double bn = sqrt(acc);
+    SysState_t& st = W.st[s];
+    st.bnorm = bn;
+    st.rnorm = bn;
+    st.rho = 1.0;
+    st.its = 0;
+    st.cycles = 0;
+    st.kcyc = 0;
+    st.reorth = 0;
+    st.first = 1;
+    double2* g = reinterpret_cast<double2*>(W.gvec) + (int64_t)s * (W.m + 1);
+    for (int i = 0; i <= W.m; ++i) g[i] = make_double2(0.0, 0.0);
+    g[0] = make_double2(bn, 0.0);
+    W.cscale[(int64_t)s * (W.m + 1)] = bn > 0.0 ? 1.0 / bn : 0.0;
+    // a zero right-hand side has the zero solution
+    st.state = bn > 0.0 ? ST_ACTIVE : ST_FINISH;
+  }
+}
+
+// ------------------------------------------------------------ Arnoldi pass A
+// MATVEC: w = c_j (H - s) u_j, written to u_{j+1}. Otherwise w = u_{j+1}
+// (second Gram-Schmidt pass). Partial sums of conj(u_i) w for i <= j, and
+// of ||w||^2, per tile.
+template <typename T, int PPT, bool MATVEC>
+__global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j) {
+  __shared__ double lds[NWAVE];
+  __shared__ double2 red[NWAVE][MAXM + 1];
+  for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
+    const int s = find_sys(W.tile_start, W.S, item);
+    const SysState_t& st = W.st[s];
+    if (st.state != ST_ACTIVE) continue;
+    if (!MATVEC && !st.reorth) continue;
+    const SysDesc& d = W.sys[s];
+    const int t = item - d.tile0;
+    const double cj = W.cscale[(int64_t)s * (W.m + 1) + j];
+    T* __restrict__ unew = basis_vec<T>(W, d, j + 1);
+    double2 w[PPT];
+    double wn = 0.0;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int p = t * W.tile + q * TPB + threadIdx.x;
+      w[q] = make_double2(0.0, 0.0);
+      if (p < d.n) {
+        if (MATVEC) {
+          const T* __restrict__ uj = basis_vec<T>(W, d, j);
+          double2 v = stencil_point<T>(uj, d, vpot<T>(W, d.off + p), (uint32_t)p);
+          v.x *= cj;
+          v.y *= cj;
+          T vs = from_d2<T>(v);
+          unew[p] = vs;
+          w[q] = to_d2(vs);
+        } else {
+          w[q] = to_d2(unew[p]);
+        }
+        wn += w[q].x * w[q].x + w[q].y * w[q].y;
+      }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int i = 0; i <= j; ++i) {
+      const T* __restrict__ ui = basis_vec<T>(W, d, i);
+      double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        const int p = t * W.tile + q * TPB + threadIdx.x;
+        if (p < d.n) {
+          double2 a = to_d2(ui[p]);
+          double2 c = cjmul(a, w[q]);
+          acc.x += c.x;
+          acc.y += c.y;
+        }
+      }
+      acc.x = wave_sum(acc.x);
+      acc.y = wave_sum(acc.y);
+      if (lane == 0) red[wid][i] = acc;
+    }
+    wn = wave_sum(wn);
+    if (lane == 0) red[wid][MAXM] = make_double2(wn, 0.0);
+    __syncthreads();
+    double2* part = reinterpret_cast<double2*>(W.part) + d.pbase;
+    for (int i = threadIdx.x; i <= j; i += TPB) {
+      double2 a = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int w2 = 0; w2 < NWAVE; ++w2) { a.x += red[w2][i].x; a.y += red[w2][i].y; }
+      part[(int64_t)i * d.ntiles + t] = a;
+    }
+    if (threadIdx.x == 63) {
+      double a = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < NWAVE; ++w2) a += red[w2][MAXM].x;
+      W.pnorm[item] = a;
+    }
+    __syncthreads();
+  }
+  (void)lds;
+}
+
+// Grid (S, j + 2): block (s, i <= j) reduces the tile partials of
+// <u_i, w> to h_ij = c_i <u_i, w>; block (s, j + 1) reduces ||w||^2 (first
+// pass only). The first pass stores the Hessenberg column; the second
+// (DGKS) pass adds its correction.
+__global__ __launch_bounds__(TPB) void k_reduce_dots(Work W, int j, int second) {
+  __shared__ double lds[NWAVE];
+  const int s = blockIdx.x;
+  const int i = blockIdx.y;
+  if (s >= W.S || i > j + 1) return;
+  SysState_t& st = W.st[s];
+  if (st.state != ST_ACTIVE) return;
+  if (second && !st.reorth) return;
+  const SysDesc& d = W.sys[s];
+  if (i == j + 1) {
+    if (second) return;
+    double wn = 0.0;
+    for (int t = threadIdx.x; t < d.ntiles; t += TPB) wn += W.pnorm[d.tile0 + t];
+    wn = block_sum(wn, lds);
+    if (threadIdx.x == 0) st.w2 = wn;
+    return;
+  }
+  const double2* part = reinterpret_cast<const double2*>(W.part) + d.pbase + (int64_t)i * d.ntiles;
+  double ax = 0.0, ay = 0.0;
+  for (int t = threadIdx.x; t < d.ntiles; t += TPB) {
+    const double2 v = part[t];
+    ax += v.x;
+    ay += v.y;
+  }
+  ax = block_sum(ax, lds);
+  ay = block_sum(ay, lds);
+  if (threadIdx.x == 0) {
+    const double c = W.cscale[(int64_t)s * (W.m + 1) + i];
+    const double2 h = make_double2(c * ax, c * ay);
+    double2* hcol = reinterpret_cast<double2*>(W.H) + (int64_t)s * (W.m + 1) * W.m + (int64_t)j * (W.m + 1);
+    reinterpret_cast<double2*>(W.hcur)[(int64_t)s * (W.m + 1) + i] = h;
+    if (second) {
+      hcol[i].x += h.x;
+      hcol[i].y += h.y;
+    } else {
+      hcol[i] = h;
+    }
+  }
+}
+
+// ------------------------------------------------------------ Arnoldi pass B
+// u_{j+1} -= sum_{i<=j} hcur_i c_i u_i ; partial ||u_{j+1}||^2.
+template <typename T, int PPT>
+__global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second) {
+  __shared__ double lds[NWAVE];
+  __shared__ double2 coef[MAXM];
+  for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
+    const int s = find_sys(W.tile_start, W.S, item);
+    const SysState_t& st = W.st[s];
+    if (st.state != ST_ACTIVE) continue;
+    if (second && !st.reorth) continue;
+    const SysDesc& d = W.sys[s];
+    const int t = item - d.tile0;
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j; i += TPB) {
+      const double2 h = reinterpret_cast<const double2*>(W.hcur)[(int64_t)s * (W.m + 1) + i];
+      const double c = W.cscale[(int64_t)s * (W.m + 1) + i];
+      coef[i] = make_double2(h.x * c, h.y * c);
+    }
+    __syncthreads();
+    if (!second && t == 0 && threadIdx.x == 0) {
+      // DGKS: a second pass when ||w - V h||^2 = ||w||^2 - sum |h_i|^2 (orthonormal
+      // V) has dropped below eta^2 ||w||^2, i.e. when cancellation was severe
+      const double2* hc = reinterpret_cast<const double2*>(W.hcur) + (int64_t)s * (W.m + 1);
+      double hs = 0.0;
+      for (int i = 0; i <= j; ++i) hs += hc[i].x * hc[i].x + hc[i].y * hc[i].y;
+      const double w2 = st.w2;
+      W.st[s].reorth = (W.reorth_mode == 2) || (W.reorth_mode == 1 && !(w2 - hs >= W.eta2 * w2));
+    }
+    T* __restrict__ unew = basis_vec<T>(W, d, j + 1);
+    double2 w[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int p = t * W.tile + q * TPB + threadIdx.x;
+      w[q] = p < d.n ? to_d2(unew[p]) : make_double2(0.0, 0.0);
+    }
+    for (int i = 0; i <= j; ++i) {
+      const T* __restrict__ ui = basis_vec<T>(W, d, i);
+      const double2 c = coef[i];
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        const int p = t * W.tile + q * TPB + threadIdx.x;
+        if (p < d.n) {
+          double2 a = to_d2(ui[p]);
+          w[q].x -= c.x * a.x - c.y * a.y;
+          w[q].y -= c.x * a.y + c.y * a.x;
+        }
+      }
+    }
+    double wn = 0.0;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int p = t * W.tile + q * TPB + threadIdx.x;
+      if (p < d.n) {
+        T v = from_d2<T>(w[q]);
+        unew[p] = v;
+        double2 vd = to_d2(v);
+        wn += vd.x * vd.x + vd.y * vd.y;
+      }
+    }
+    wn = block_sum(wn, lds);
+    if (threadIdx.x == 0) W.pnorm[item] = wn;
+  }
+}
+
+// ------------------------------------------------------------ Givens update
+// Per system: h_{j+1,j} = ||u_{j+1}||, rotate column j, residual estimate
+// |g_{j+1}|, convergence decision; at the end of the cycle the triangular
+// solve R y = g.
+__global__ __launch_bounds__(TPB) void k_givens(Work W, int j, int cycle) {
+  __shared__ double lds[NWAVE];
+  const int s = blockIdx.x;
+  if (s >= W.S) return;
+  SysState_t& st = W.st[s];
+  if (st.state != ST_ACTIVE) return;
+  const SysDesc& d = W.sys[s];
+  double wn = 0.0;
+  for (int t = threadIdx.x; t < d.ntiles; t += TPB) wn += W.pnorm[d.tile0 + t];
+  wn = block_sum(wn, lds);
+  if (threadIdx.x != 0) return;
+  const int m = W.m;
+  const double beta = sqrt(wn);
+  double2* Hs = reinterpret_cast<double2*>(W.H) + (int64_t)s * (m + 1) * m;
+  double2* col = Hs + (int64_t)j * (m + 1);
+  double2* gcv = reinterpret_cast<double2*>(W.gc) + (int64_t)s * m;
+  double2* gsv = reinterpret_cast<double2*>(W.gs) + (int64_t)s * m;
+  double2* g = reinterpret_cast<double2*>(W.gvec) + (int64_t)s * (m + 1);
+  double* cs = W.cscale + (int64_t)s * (m + 1);
+  col[j + 1] = make_double2(beta, 0.0);
+  // earlier rotations: (a, b) -> (conj(c) a + conj(s) b, -s a + c b)
+  for (int i = 0; i < j; ++i) {
+    const double2 c = gcv[i], sn = gsv[i];
+    const double2 a = col[i], b = col[i + 1];
+    const double2 t1 = cjmul(c, a), t2 = cjmul(sn, b);
+    const double2 u1 = cmul(sn, a), u2 = cmul(c, b);
+    col[i] = make_double2(t1.x + t2.x, t1.y + t2.y);
+    col[i + 1] = make_double2(u2.x - u1.x, u2.y - u1.y);
+  }
+  const double2 a = col[j];
+  const double bb = beta;
+  const double den = sqrt(a.x * a.x + a.y * a.y + bb * bb);
+  double2 c, sn;
+  if (den > 0.0) {
+    c = make_double2(a.x / den, a.y / den);
+    sn = make_double2(bb / den, 0.0);
+  } else {
+    c = make_double2(1.0, 0.0);
+    sn = make_double2(0.0, 0.0);
+  }
+  gcv[j] = c;
+  gsv[j] = sn;
+  col[j] = make_double2(den, 0.0);
+  col[j + 1] = make_double2(0.0, 0.0);
+  const double2 gj = g[j];
+  g[j + 1] = make_double2(-(sn.x * gj.x - sn.y * gj.y), -(sn.x * gj.y + sn.y * gj.x));
+  g[j] = cjmul(c, gj);
+  const double res = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
+  cs[j + 1] = beta > 0.0 ? 1.0 / beta : 0.0;
+  st.kcyc = j + 1;
+  st.its += 1;
+  // stop the cycle at the inner target (mixed path: a fixed reduction of the
+  // cycle's starting residual) or at the outer target, whichever is larger
+  const double target = fmax(W.inner_rtol * st.rnorm, 0.5 * d.tol * st.bnorm);
+  const bool conv = res <= target || beta == 0.0 || !(res == res);
+  if (conv || j + 1 == m) {
+    // back substitution R y = g, R = Hs[0:k, 0:k] upper triangular
+    const int k = j + 1;
+    double2* y = reinterpret_cast<double2*>(W.y) + (int64_t)s * m;
+    for (int r = k - 1; r >= 0; --r) {
+      double2 acc = g[r];
+      for (int q = r + 1; q < k; ++q) {
+        const double2 t = cmul(Hs[(int64_t)q * (m + 1) + r], y[q]);
+        acc.x -= t.x;
+        acc.y -= t.y;
+      }
+      const double2 dd = Hs[(int64_t)r * (m + 1) + r];
+      const double dn = dd.x * dd.x + dd.y * dd.y;
+      y[r] = dn > 0.0 ? make_double2((acc.x * dd.x + acc.y * dd.y) / dn, (acc.y * dd.x - acc.x * dd.y) / dn)
+                      : make_double2(0.0, 0.0);
+    }
+    st.state = ST_FINISH;
+  } else {
+    atomicAdd(&W.counters[cycle * (m + 1) + j], 1);
+  }
+}
+
+// ------------------------------------------------------------ end of cycle
+// x (+)= sum_{i<k} y_i c_i u_i  (FP64), systems in ST_FINISH.
+template <typename T, int PPT>
+__global__ __launch_bounds__(TPB) void k_update_x(Work W) {
+  __shared__ double2 coef[MAXM];
+  for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
+    const int s = find_sys(W.tile_start, W.S, item);
+    const SysState_t& st = W.st[s];
+    if (st.state != ST_FINISH) continue;
+    const SysDesc& d = W.sys[s];
+    const int t = item - d.tile0;
+    const int k = st.kcyc;
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += TPB) {
+      const double2 yv = reinterpret_cast<const double2*>(W.y)[(int64_t)s * W.m + i];
+      const double c = W.cscale[(int64_t)s * (W.m + 1) + i];
+      coef[i] = make_double2(yv.x * c, yv.y * c);
+    }
+    __syncthreads();
+    double2* __restrict__ x = reinterpret_cast<double2*>(W.x) + d.xoff;
+    double2 acc[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int p = t * W.tile + q * TPB + threadIdx.x;
+      acc[q] = (p < d.n && !st.first) ? x[p] : make_double2(0.0, 0.0);
+    }
+    for (int i = 0; i < k; ++i) {
+      const T* __restrict__ ui = basis_vec<T>(W, d, i);
+      const double2 c = coef[i];
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        const int p = t * W.tile + q * TPB + threadIdx.x;
+        if (p < d.n) {
+          const double2 a = to_d2(ui[p]);
+          acc[q].x += c.x * a.x - c.y * a.y;
+          acc[q].y += c.x * a.y + c.y * a.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int p = t * W.tile + q * TPB + threadIdx.x;
+      if (p < d.n) x[p] = acc[q];
+    }
+  }
+}
+
+// r = b - (H - s) x in FP64; u_0 = r; partial ||r||^2. Systems in ST_FINISH.
+template <typename T, int PPT>
+__global__ __launch_bounds__(TPB) void k_residual(Work W, const double2* __restrict__ rhs0,
+                                                  const double2* __restrict__ rhs1) {
+  __shared__ double lds[NWAVE];
+  for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
+    const int s = find_sys(W.tile_start, W.S, item);
+    const SysState_t& st = W.st[s];
+    if (st.state != ST_FINISH) continue;
+    const SysDesc& d = W.sys[s];
+    const int t = item - d.tile0;
+    const double2* __restrict__ b = (d.rhs_sel ? rhs1 : rhs0) + d.off;
+    const double2* __restrict__ x = reinterpret_cast<const double2*>(W.x) + d.xoff;
+    T* __restrict__ u0 = basis_vec<T>(W, d, 0);
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int p = t * W.tile + q * TPB + threadIdx.x;
+      if (p < d.n) {
+        const double2 hx = stencil_point_f64(x, d.n0, d.n1, d.n2, d.d2, d.d1, d.c0, d.c1, d.c2, d.diag,
+                                             W.V64[d.off + p], d.sre, d.sim, (uint32_t)p);
+        const double2 bp = b[p];
+        const double2 r = make_double2(bp.x - hx.x, bp.y - hx.y);
+        u0[p] = from_d2<T>(r);
+        acc += r.x * r.x + r.y * r.y;
+      }
+    }
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) W.pnorm[item] = acc;
+  }
+}
+
+// Per system (ST_FINISH): explicit relative residual, done or restart.
+__global__ __launch_bounds__(TPB) void k_restart(Work W, int cycle) {
+  __shared__ double lds[NWAVE];
+  const int s = blockIdx.x;
+  if (s >= W.S) return;
+  SysState_t& st = W.st[s];
+  if (st.state != ST_FINISH) return;
+  const SysDesc& d = W.sys[s];
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < d.ntiles; t += TPB) acc += W.pnorm[d.tile0 + t];
+  acc = block_sum(acc, lds);
+  if (threadIdx.x != 0) return;
+  const double rn = sqrt(acc);
+  st.cycles += 1;
+  st.first = 0;
+  st.rho = st.bnorm > 0.0 ? rn / st.bnorm : 0.0;
+  const bool done = st.rho <= d.tol || st.cycles >= W.max_cycles || rn == 0.0 || !(rn == rn);
+  if (done) {
+    st.state = ST_DONE;
+    if (!(st.rho <= d.tol)) atomicAdd(&W.counters[W.max_cycles * (W.m + 1) + 1], 1);
+    return;
+  }
+  st.rnorm = rn;
+  st.kcyc = 0;
+  double2* g = reinterpret_cast<double2*>(W.gvec) + (int64_t)s * (W.m + 1);
+  for (int i = 0; i <= W.m; ++i) g[i] = make_double2(0.0, 0.0);
+  g[0] = make_double2(rn, 0.0);
+  W.cscale[(int64_t)s * (W.m + 1)] = 1.0 / rn;
+  st.state = ST_ACTIVE;
+  atomicAdd(&W.counters[W.max_cycles * (W.m + 1)], 1);
+  (void)cycle;
+}
+
+
+// ------------------------------------------------------------ shared basis
+// All poles share one Krylov basis: with x0 = 0 every shifted system starts
+// from b, and K_k(H - s I, b) = K_k(H, b). One Arnoldi process on H (system
+// 0 with shift 0) gives H V_k = V_{k+1} Hbar_k, hence (H - s_p) V_k =
+// V_{k+1} (Hbar_k - s_p Itilde); each pole solves its own small least-squares
+// problem min || ||b|| e_1 - (Hbar_k - s_p Itilde) y_p ||, and the step is
+// sum_p w_p V_k y_p = V_k z with z = sum_p w_p y_p.
+struct ShiftWork {
+  int32_t K;
+  const double* s;    // [K] complex shifts
+  const double* w;    // [K] complex weights
+  const double* tol;  // [K] target relative residuals
+  double* R;          // [K][(m+1) m] complex, rotated Hessenberg per pole
+  double* g;          // [K][m+1] complex
+  double* gc;         // [K][m] complex
+  double* gs;         // [K][m] complex
+  double* y;          // [K][m] complex
+  double* z;          // [m] complex, combined coefficients
+  double* res;        // [K] implicit relative residual
+  int32_t* its;       // [K] iteration at which the pole met its target (0: not yet)
+};
+
+__global__ __launch_bounds__(TPB) void k_shifted_init(Work W, ShiftWork SW) {
+  const double bn = W.st[0].bnorm;
+  for (int p = threadIdx.x; p < SW.K; p += TPB) {
+    double2* g = reinterpret_cast<double2*>(SW.g) + (int64_t)p * (W.m + 1);
+    for (int i = 0; i <= W.m; ++i) g[i] = make_double2(0.0, 0.0);
+    g[0] = make_double2(bn, 0.0);
+    SW.its[p] = bn > 0.0 ? 0 : 1;
+    SW.res[p] = bn > 0.0 ? 1.0 : 0.0;
+  }
+}
+
+// One block: h_{j+1,j} = ||u_{j+1}||, then for every pole the Givens update of
+// column j of (Hbar - s_p Itilde). When every pole meets its target (or j + 1
+// = m): back substitution per pole and z = sum_p w_p y_p in fixed pole order.
+__global__ __launch_bounds__(TPB) void k_shifted_givens(Work W, ShiftWork SW, int j) {
+  __shared__ double lds[NWAVE];
+  SysState_t& st = W.st[0];
+  if (st.state != ST_ACTIVE) return;
+  const SysDesc& d = W.sys[0];
+  const int m = W.m;
+  double wn = 0.0;
+  for (int t = threadIdx.x; t < d.ntiles; t += TPB) wn += W.pnorm[d.tile0 + t];
+  wn = block_sum(wn, lds);
+  const double beta = sqrt(wn);
+  const double2* hcol = reinterpret_cast<const double2*>(W.H) + (int64_t)j * (m + 1);
+  const double bn = st.bnorm;
+  double unconv = 0.0;
+  for (int p = threadIdx.x; p < SW.K; p += TPB) {
+    double2* Rp = reinterpret_cast<double2*>(SW.R) + (int64_t)p * (m + 1) * m;
+    double2* col = Rp + (int64_t)j * (m + 1);
+    double2* gcv = reinterpret_cast<double2*>(SW.gc) + (int64_t)p * m;
+    double2* gsv = reinterpret_cast<double2*>(SW.gs) + (int64_t)p * m;
+    double2* g = reinterpret_cast<double2*>(SW.g) + (int64_t)p * (m + 1);
+    const double2 sp = reinterpret_cast<const double2*>(SW.s)[p];
+    for (int i = 0; i <= j; ++i) col[i] = hcol[i];
+    col[j].x -= sp.x;
+    col[j].y -= sp.y;
+    for (int i = 0; i < j; ++i) {
+      const double2 c = gcv[i], sn = gsv[i];
+      const double2 a = col[i], b = col[i + 1];
+      const double2 t1 = cjmul(c, a), t2 = cjmul(sn, b);
+      const double2 u1 = cmul(sn, a), u2 = cmul(c, b);
+      col[i] = make_double2(t1.x + t2.x, t1.y + t2.y);
+      col[i + 1] = make_double2(u2.x - u1.x, u2.y - u1.y);
+    }
+    const double2 a = col[j];
+    const double den = sqrt(a.x * a.x + a.y * a.y + beta * beta);
+    double2 c, sn;
+    if (den > 0.0) {
+      c = make_double2(a.x / den, a.y / den);
+      sn = make_double2(beta / den, 0.0);
+    } else {
+      c = make_double2(1.0, 0.0);
+      sn = make_double2(0.0, 0.0);
+    }
+    gcv[j] = c;
+    gsv[j] = sn;
+    col[j] = make_double2(den, 0.0);
+    const double2 gj = g[j];
+    g[j + 1] = make_double2(-(sn.x * gj.x - sn.y * gj.y), -(sn.x * gj.y + sn.y * gj.x));
+    g[j] = cjmul(c, gj);
+    const double res = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
+    SW.res[p] = bn > 0.0 ? res / bn : 0.0;
+    const bool conv = res <= 0.5 * SW.tol[p] * bn || beta == 0.0 || !(res == res);
+    if (conv) {
+      if (SW.its[p] == 0) SW.its[p] = j + 1;
+    } else {
+      unconv += 1.0;
+    }
+  }
+  unconv = block_sum(unconv, lds);
+  const int k = j + 1;
+  if (unconv == 0.0 || k == m) {
+    for (int p = threadIdx.x; p < SW.K; p += TPB) {
+      const double2* Rp = reinterpret_cast<const double2*>(SW.R) + (int64_t)p * (m + 1) * m;
+      const double2* g = reinterpret_cast<const double2*>(SW.g) + (int64_t)p * (m + 1);
+      double2* y = reinterpret_cast<double2*>(SW.y) + (int64_t)p * m;
+      for (int r = k - 1; r >= 0; --r) {
+        double2 acc = g[r];
+        for (int q = r + 1; q < k; ++q) {
+          const double2 tq = cmul(Rp[(int64_t)q * (m + 1) + r], y[q]);
+          acc.x -= tq.x;
+          acc.y -= tq.y;
+        }
+        const double2 dd = Rp[(int64_t)r * (m + 1) + r];
+        const double dn = dd.x * dd.x + dd.y * dd.y;
+        y[r] = dn > 0.0 ? make_double2((acc.x * dd.x + acc.y * dd.y) / dn, (acc.y * dd.x - acc.x * dd.y) / dn)
+                        : make_double2(0.0, 0.0);
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += TPB) {
+      double2 zi = make_double2(0.0, 0.0);
+      for (int p = 0; p < SW.K; ++p) {
+        const double2 wp = reinterpret_cast<const double2*>(SW.w)[p];
+        const double2 yp = reinterpret_cast<const double2*>(SW.y)[(int64_t)p * m + i];
+        const double2 tz = cmul(wp, yp);
+        zi.x += tz.x;
+        zi.y += tz.y;
+      }
+      reinterpret_cast<double2*>(SW.z)[i] = zi;
+    }
+    if (threadIdx.x == 0) {
+      st.kcyc = k;
+      st.its = k;
+      st.state = ST_FINISH;
+    }
+  } else if (threadIdx.x == 0) {
+    W.H[(int64_t)j * (m + 1) * 2 + 2 * (j + 1)] = beta;  // h_{j+1,j}
+    W.H[(int64_t)j * (m + 1) * 2 + 2 * (j + 1) + 1] = 0.0;
+    W.cscale[j + 1] = beta > 0.0 ? 1.0 / beta : 0.0;
+    st.kcyc = k;
+    st.its = k;
+    atomicAdd(&W.counters[j], 1);
+  }
+}
+
+// out = sum_{i<k} z_i c_i u_i in FP64 (system 0 of W).
+template <typename T, int PPT>
+__global__ __launch_bounds__(TPB) void k_combine_out(Work W, ShiftWork SW, double2* __restrict__ out) {
+  __shared__ double2 coef[MAXM];
+  const SysDesc& d = W.sys[0];
+  const int k = W.st[0].kcyc;
+  for (int i = threadIdx.x; i < k; i += TPB) {
+    const double2 zi = reinterpret_cast<const double2*>(SW.z)[i];
+    const double c = W.cscale[i];
+    coef[i] = make_double2(zi.x * c, zi.y * c);
+  }
+  __syncthreads();
+  for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
+    const int t = item;
+    double2 acc[PPT];
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) acc[q] = make_double2(0.0, 0.0);
+    for (int i = 0; i < k; ++i) {
+      const T* __restrict__ ui = basis_vec<T>(W, d, i);
+      const double2 c = coef[i];
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        const int p = t * W.tile + q * TPB + threadIdx.x;
+        if (p < d.n) {
+          const double2 a = to_d2(ui[p]);
+          acc[q].x += c.x * a.x - c.y * a.y;
+          acc[q].y += c.x * a.y + c.y * a.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int p = t * W.tile + q * TPB + threadIdx.x;
+      if (p < d.n) out[d.off + p] = acc[q];
+    }
+  }
+}
+
+// ------------------------------------------------------------ pole sum
+// out = sum_s w_s x_s over the instance's systems in fixed order (FP64);
+// conj_w selects conj(w_s) (adjoint) and sys_shift the first system used.
+__global__ __launch_bounds__(TPB) void k_polesum(const InstDesc* __restrict__ inst, int ninst,
+                                                 const int32_t* __restrict__ itile_start, int itotal,
+                                                 const SysDesc* __restrict__ sys, const double* __restrict__ xall,
+                                                 double2* __restrict__ out, int tile, int conj_w, int sys_shift) {
+  for (int item = blockIdx.x; item < itotal; item += gridDim.x) {
+    const int ii = find_sys(itile_start, ninst, item);
+    const InstDesc& in = inst[ii];
+    const int t = item - in.tile0;
+    for (int p = t * tile + threadIdx.x; p < min((t + 1) * tile, in.n); p += TPB) {
+      double ax = 0.0, ay = 0.0;
+      for (int k = 0; k < in.nsys; ++k) {
+        const SysDesc& d = sys[in.sys0 + sys_shift + k];
+        const double2 xv = reinterpret_cast<const double2*>(xall)[d.xoff + p];
+        const double wy = conj_w ? -d.wim : d.wim;
+        ax += d.wre * xv.x - wy * xv.y;
+        ay += d.wre * xv.y + wy * xv.x;
+      }
+      out[in.off + p] = make_double2(ax, ay);
+    }
+  }
+}
+
+// dV += -2 Re sum_j w_j conj(y_j) x_j, systems [0, K) hold x_j and [K, 2K) y_j.
+__global__ __launch_bounds__(TPB) void k_grad_v(const InstDesc* __restrict__ inst, const int32_t* __restrict__ itile_start,
+                                                int itotal, const SysDesc* __restrict__ sys,
+                                                const double* __restrict__ xall, double* __restrict__ dV, int tile, int K) {
+  for (int item = blockIdx.x; item < itotal; item += gridDim.x) {
+    const InstDesc& in = inst[0];
+    const int t = item;
+    for (int p = t * tile + threadIdx.x; p < min((t + 1) * tile, in.n); p += TPB) {
+      double acc = 0.0;
+      for (int k = 0; k < K; ++k) {
+        const SysDesc& dx = sys[k];
+        const SysDesc& dy = sys[K + k];
+        const double2 xv = reinterpret_cast<const double2*>(xall)[dx.xoff + p];
+        const double2 yv = reinterpret_cast<const double2*>(xall)[dy.xoff + p];
+        const double2 cy = cjmul(yv, xv);  // conj(y) x
+        acc += dx.wre * cy.x - dx.wim * cy.y;  // Re(w conj(y) x)
+      }
+      dV[p] += -2.0 * acc;
+    }
+  }
+  (void)itile_start;
+}
+
+// y = (H - shift) x in FP64 over all instances (packed).
+__global__ __launch_bounds__(TPB) void k_apply_h(const InstDesc* __restrict__ inst, int ninst,
+                                                 const int32_t* __restrict__ itile_start, int itotal,
+                                                 const double* __restrict__ V, const double2* __restrict__ x,
+                                                 double2* __restrict__ y, double sre, double sim, int tile) {
+  for (int item = blockIdx.x; item < itotal; item += gridDim.x) {
+    const int ii = find_sys(itile_start, ninst, item);
+    const InstDesc& in = inst[ii];
+    const int t = item - in.tile0;
+    const double2* xi = x + in.off;
+    for (int p = t * tile + threadIdx.x; p < min((t + 1) * tile, in.n); p += TPB) {
+      y[in.off + p] = stencil_point_f64(xi, in.n0, in.n1, in.n2, in.d2, in.d1, in.c0, in.c1, in.c2, in.diag,
+                                        V[in.off + p], sre, sim, (uint32_t)p);
+    }
+  }
+}
+
+// V64 -> V32 (the complex64 path's potential).
+__global__ __launch_bounds__(TPB) void k_v_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) b[i] = (float)a[i];
+}
+
+// Flags non-finite entries of V (setup validation).
+__global__ __launch_bounds__(TPB) void k_check_finite(const double* __restrict__ a, int64_t n, int32_t* flag) {
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    const double v = a[i];
+    if (!(v == v) || v - v != 0.0) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+}  // namespace rexi

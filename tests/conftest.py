@@ -10,3 +10,11 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+
+
+def pytest_sessionstart(session):
+    # tests load the in-tree library; build it only when nothing is built
+    lib = os.path.join(ROOT, "paper_1912_03312_amd", "librexi.so")
+    if not os.path.exists(lib):
+        from paper_1912_03312_amd.build import build
+        build()

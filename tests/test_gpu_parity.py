@@ -1,0 +1,320 @@
+"""GPU parity of the HIP REXI path against the FP64 CPU oracle.
+
+Every test calls the library through its C ABI (ctypes binding) and
+compares, element by element, with the oracle on the same seeded inputs.
+Bars: FP64 path relative L2 error <= max(1e-10, 10 F) with F the oracle's
+own two-method floor (direct solve vs eigendecomposition) measured in the
+test; complex64 + FP64 refinement <= 1e-6; the stencil to FP64 roundoff.
+"""
+import numpy as np
+import pytest
+
+from oracle import faber_cf as fcf
+from oracle import hamiltonian as ham
+from oracle import step as ost
+from paper_1912_03312_amd import inputs
+
+from .gpu_util import gpu_steps, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(float).eps
+
+
+@pytest.fixture(scope="module")
+def rexi():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1912_03312_amd import rexi as r
+    return r
+
+
+_POLES = {}
+
+
+def poles(K, R1):
+    if (K, R1) not in _POLES:
+        s, b, _ = fcf.faber_cf(K, R1)
+        _POLES[(K, R1)] = (s, b, fcf.diagnostics(s, b, R1))
+    return _POLES[(K, R1)]
+
+
+@pytest.mark.parametrize("shape", [(300,), (37, 41), (9, 13, 17), (1,), (1, 5), (64, 64, 64)])
+def test_apply_h_matches_sparse_product(rexi, shape):
+    import torch
+    g = inputs.Grid(shape, tuple(-3.0 - a for a in range(len(shape))), tuple(4.0 + a for a in range(len(shape))))
+    V = inputs.gaussian_bumps(g, 7) if g.size > 1 else np.array([0.7])
+    x = inputs.random_state(g.size, 5)
+    shift = 1.7 - 42.5j
+    h = rexi.setup(g.n, g.lo, g.hi, to_dev(V.ravel()), 1.3, 0.8, 0.5, [1.0 + 5j], [1.0 + 0j])
+    xd = to_dev(x)
+    yd = torch.empty_like(xd)
+    h.apply_H(xd, yd, shift)
+    torch.cuda.synchronize()
+    ref = ham.apply_shifted(g.n, g.h, V, x, shift, 1.3, 0.8)
+    assert rel(yd.cpu().numpy(), ref) < 1e-14
+    h.close()
+
+
+def iterative_floor(g, V, s, b, dt):
+    """Smallest step error any FP64 iterative solve can certify, per step.
+
+    The residual b - (H - s_j) x of a computed x carries rounding of about
+    u (|lam|_max + |s_j|) ||x||, with ||x|| <= ||b|| / dist_j, so per pole the
+    relative residual cannot be certified below u (1 + (|lam|_max + |s_j|) /
+    dist_j), and the pole sum amplifies it by |w_j| / dist_j.
+    """
+    lo, hi = ham.gershgorin(g.n, g.h, V)
+    sj, wj = ost.shifts_and_weights(s, b, dt)
+    tot = 0.0
+    for sv, wv in zip(sj, wj):
+        re = min(max(sv.real, lo), hi)
+        dist = abs(complex(re, 0.0) - sv)
+        tot += abs(wv) / dist * EPS * (1.0 + (max(abs(lo), abs(hi)) + abs(sv)) / dist)
+    return tot
+
+
+def _floor(g, V, psi0, s, b, dt, nsteps, eig_route):
+    D = ost.DirectStepper(g.n, g.h, V, s, b, dt)
+    ref, psi_d, psi_e, F = [], psi0, psi0, 0.0
+    for _ in range(nsteps):
+        psi_d = D.step(psi_d)
+        psi_e = eig_route(psi_e)
+        ref.append(psi_d)
+        F = max(F, rel(psi_e, psi_d))
+    return ref, F
+
+
+def test_step_1d_harmonic_fp64(rexi):
+    wl = inputs.workload("1d_harmonic")
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+    E = ost.EigStepper(g.n, g.h, wl.V)
+    ref, F = _floor(g, wl.V, wl.psi0, s, b, wl.dt, wl.steps, lambda p: E.step(p, s, b, wl.dt))
+    out, infos = gpu_steps(g, wl.V, wl.psi0, s, b, wl.dt, wl.steps, tol=1e-11, tol_policy="certified")
+    bar = max(1e-10, 10 * F)
+    errs = [rel(o, r) for o, r in zip(out, ref)]
+    print("1d errs", max(errs), "floor", F, "its", infos[0]["total_iterations"], infos[0]["certified_bound"])
+    assert max(errs) <= bar
+    assert all(i["not_converged"] == 0 for i in infos)
+    # norm drift: the approximation damps by at most about ||e|| per step
+    drift = np.linalg.norm(out[-1]) / np.linalg.norm(wl.psi0) - 1.0
+    assert abs(drift) <= wl.steps * 2 * d["err_inf"]
+
+
+def test_step_1d_relres_tolerance_as_configured(rexi):
+    # the configured per-pole tolerance 1e-12; its certified bound must hold
+    wl = inputs.workload("1d_harmonic")
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+    ref = ost.DirectStepper(g.n, g.h, wl.V, s, b, wl.dt).step(wl.psi0)
+    out, infos = gpu_steps(g, wl.V, wl.psi0, s, b, wl.dt, 1, tol=wl.tol)
+    assert rel(out[0], ref) <= infos[0]["certified_bound"] + 1e-12
+    assert infos[0]["max_rel_residual"] <= wl.tol
+
+
+@pytest.mark.parametrize("side", [40, 29])
+def test_step_2d_double_well_fp64(rexi, side):
+    wl = inputs.workload("2d_double_well", scale=side)
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+    vx, vy = inputs.double_well_parts(g)
+    S = ost.SeparableStepper(g.n, g.h, [vx, vy])
+    ref, F = _floor(g, wl.V, wl.psi0, s, b, wl.dt, 3, lambda p: S.step(p, s, b, wl.dt))
+    # interior shifts (Re s inside the spectrum, which reaches ~7e3) make
+    # restarted GMRES(30) slow: hundreds of iterations per pole
+    out, infos = gpu_steps(g, wl.V, wl.psi0, s, b, wl.dt, 3, tol=1e-11, tol_policy="certified", max_cycles=80)
+    errs = [rel(o, r) for o, r in zip(out, ref)]
+    bar = max(1e-10, 10 * F, 3 * iterative_floor(g, wl.V, s, b, wl.dt))
+    print("2d errs", errs, "floor", F, "bar", bar, [i["total_iterations"] for i in infos])
+    assert max(errs) <= bar
+
+
+def test_step_3d_bumps_fp64(rexi):
+    wl = inputs.workload("3d_bumps", scale=12)
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+    E = ost.EigStepper(g.n, g.h, wl.V)
+    ref, F = _floor(g, wl.V, wl.psi0, s, b, wl.dt, 2, lambda p: E.step(p, s, b, wl.dt))
+    out, infos = gpu_steps(g, wl.V, wl.psi0, s, b, wl.dt, 2, tol=1e-11, tol_policy="certified")
+    errs = [rel(o, r) for o, r in zip(out, ref)]
+    print("3d errs", errs, "floor", F)
+    assert max(errs) <= max(1e-10, 10 * F)
+
+
+@pytest.mark.parametrize("name,scale", [("2d_double_well", 40), ("3d_bumps", 12), ("2d_adjoint", 33)])
+def test_step_mixed_precision(rexi, name, scale):
+    wl = inputs.workload(name, scale=scale)
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+    D = ost.DirectStepper(g.n, g.h, wl.V, s, b, wl.dt)
+    ref = [D.step(wl.psi0)]
+    ref.append(D.step(ref[0]))
+    out, infos = gpu_steps(g, wl.V, wl.psi0, s, b, wl.dt, 2, precision="c64", tol=1e-8, tol_policy="certified",
+                           max_cycles=200)
+    errs = [rel(o, r) for o, r in zip(out, ref)]
+    print("mixed errs", name, errs, [i["max_cycles_used"] for i in infos])
+    assert max(errs) <= 1e-6
+    assert infos[0]["certified_bound"] <= 1.01e-8
+
+
+def test_full_size_3d_separable(rexi):
+    # the 128^3, 64-pole launch configuration with a separable potential, whose
+    # exact REXI step the oracle evaluates at full size by 1D eigendecompositions
+    g = inputs.cube(128, 15.0, 3)
+    x = g.axes()
+    parts = [0.02 * xa * xa for xa in x]
+    V = parts[0][:, None, None] + parts[1][None, :, None] + parts[2][None, None, :]
+    psi0 = inputs.seeded_packet(g, 30, (0.0, 0.0, 0.0), 2.0)
+    s, b, d = poles(64, 180.0)
+    S = ost.SeparableStepper(g.n, g.h, parts)
+    ref = S.step(psi0, s, b, 1.0)
+    out, infos = gpu_steps(g, V, psi0, s, b, 1.0, 1, precision="c64", tol=1e-10)
+    e_mixed = rel(out[0], ref)
+    out64, infos64 = gpu_steps(g, V, psi0, s, b, 1.0, 1, tol=1e-12, tol_policy="certified")
+    e64 = rel(out64[0], ref)
+    print("full 3d separable: mixed", e_mixed, "fp64", e64, infos[0]["total_iterations"], infos64[0]["total_iterations"])
+    assert e_mixed <= 1e-6
+    assert e64 <= max(1e-10, 10 * d["amplification"] * EPS)
+
+
+def test_full_size_3d_bumps_properties(rexi):
+    # the benchmarked workload itself: certified bound, norm and reversibility
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    wl = inputs.workload("3d_bumps")
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+    Vd = to_dev(wl.V.ravel())
+    fwd = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, wl.dt, s, b, precision="c64", tol=wl.tol)
+    bwd = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, -wl.dt, s, b, precision="c64", tol=wl.tol)
+    p0 = to_dev(wl.psi0.ravel())
+    p1 = torch.empty_like(p0)
+    p2 = torch.empty_like(p0)
+    i1 = fwd.step(p0, p1, 1)
+    i2 = bwd.step(p1, p2, 1)
+    torch.cuda.synchronize()
+    assert i1["not_converged"] == 0 and i2["not_converged"] == 0
+    assert i1["max_rel_residual"] <= wl.tol
+    n0 = np.linalg.norm(wl.psi0)
+    assert abs(i1["norm_out"] / n0 - 1.0) <= 2 * d["err_inf"] + i1["certified_bound"]
+    back = rel(p2.cpu().numpy(), wl.psi0)
+    print("reversibility", back, i1["certified_bound"], i1["total_iterations"])
+    assert back <= 3 * d["err_inf"] + i1["certified_bound"] + i2["certified_bound"]
+    fwd.close()
+    bwd.close()
+
+
+def test_zero_state_and_single_point(rexi):
+    s, b, d = poles(16, 28.0)
+    g = inputs.cube(33, 5.0, 2)
+    out, infos = gpu_steps(g, inputs.harmonic(g), np.zeros(g.n, np.complex128), s, b, 0.2, 1)
+    assert np.all(out[0] == 0)
+    # one grid point: the scalar (Dahlquist) case r(-i dt lam)
+    g1 = inputs.Grid((1,), (0.0,), (2.0,))
+    V = np.array([0.4])
+    lam = 1.0 + 0.4
+    out, _ = gpu_steps(g1, V, np.array([1.0 + 0j]), s, b, 0.7, 1, tol=1e-13)
+    assert abs(out[0][0] - fcf.r_eval(-1j * 0.7 * lam, s, b)) < 1e-11
+
+
+def test_inplace_multistep_and_determinism(rexi):
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    wl = inputs.workload("2d_adjoint", scale=37)
+    g = wl.grid
+    s, b, d = poles(16, 32.0)
+    h = r.setup(g.n, g.lo, g.hi, to_dev(wl.V.ravel()), 1.0, 1.0, wl.dt, s, b)
+    p = to_dev(wl.psi0.ravel())
+    q = torch.empty_like(p)
+    h.step(p, q, 1)
+    h.step(q, q, 1)          # in place
+    h.step(q, q, 1)
+    a = q.cpu().numpy()
+    p2 = to_dev(wl.psi0.ravel())
+    h.step(p2, p2, 3)        # three steps in one call, in place
+    bb = p2.cpu().numpy()
+    assert np.array_equal(a, bb)   # same kernels, fixed summation order: bitwise
+    h.close()
+
+
+def test_adjoint_matches_oracle(rexi):
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    g = inputs.cube(24, 6.0, 2)
+    V = inputs.gaussian_bumps(g, 5)
+    s, b, d = poles(16, 32.0)
+    dt = 0.5
+    psi = inputs.seeded_packet(g, 50, (-1.0, 0.0), 1.0)
+    gb = inputs.random_state(g.size, 9).reshape(g.n)
+    D = ost.DirectStepper(g.n, g.h, V, s, b, dt)
+    g_ref, dV_ref = D.adjoint(psi, gb)
+    h = r.setup(g.n, g.lo, g.hi, to_dev(V.ravel()), 1.0, 1.0, dt, s, b, tol=1e-12, tol_policy="certified")
+    gout = torch.empty(g.size, dtype=torch.complex128, device="cuda")
+    dV = torch.zeros(g.size, dtype=torch.float64, device="cuda")
+    h.step_adjoint(to_dev(psi.ravel()), to_dev(gb.ravel()), gout, dV)
+    torch.cuda.synchronize()
+    e_g = rel(gout.cpu().numpy(), g_ref)
+    e_v = rel(dV.cpu().numpy(), dV_ref)
+    print("adjoint", e_g, e_v)
+    assert e_g <= 1e-9
+    assert e_v <= 1e-8
+    h.close()
+
+
+# ---------------------------------------------------------------- shared basis
+@pytest.mark.parametrize("name,scale,K,R1,m", [("1d_harmonic", None, 16, 28.0, 200), ("3d_bumps", 12, 64, 180.0, 120),
+                                               ("2d_adjoint", 33, 32, 80.0, 200), ("3d_bumps", 13, 16, 32.0, 120)])
+def test_shifted_solver_fp64(rexi, name, scale, K, R1, m):
+    wl = inputs.workload(name, scale=scale)
+    g = wl.grid
+    s, b, d = poles(K, R1)
+    E = ost.EigStepper(g.n, g.h, wl.V)
+    ref, F = _floor(g, wl.V, wl.psi0, s, b, wl.dt, 2, lambda p: E.step(p, s, b, wl.dt))
+    out, infos = gpu_steps(g, wl.V, wl.psi0, s, b, wl.dt, 2, solver="shifted", m=m, tol=1e-11,
+                           tol_policy="certified", check_every=2)
+    errs = [rel(o, r) for o, r in zip(out, ref)]
+    print("shifted", name, errs, "floor", F, [i["total_iterations"] for i in infos], infos[0]["certified_bound"])
+    assert max(errs) <= max(1e-10, 10 * F)
+    assert all(i["not_converged"] == 0 for i in infos)
+
+
+def test_shifted_full_size_3d_separable(rexi):
+    g = inputs.cube(128, 15.0, 3)
+    x = g.axes()
+    parts = [0.02 * xa * xa for xa in x]
+    V = parts[0][:, None, None] + parts[1][None, :, None] + parts[2][None, None, :]
+    psi0 = inputs.seeded_packet(g, 30, (0.0, 0.0, 0.0), 2.0)
+    s, b, d = poles(64, 180.0)
+    ref = ost.SeparableStepper(g.n, g.h, parts).step(psi0, s, b, 1.0)
+    out, infos = gpu_steps(g, V, psi0, s, b, 1.0, 1, solver="shifted", m=100, tol=1e-10)
+    e1 = rel(out[0], ref)
+    out2, infos2 = gpu_steps(g, V, psi0, s, b, 1.0, 1, solver="shifted", m=100, tol=1e-12, tol_policy="certified")
+    e2 = rel(out2[0], ref)
+    print("shifted full 3d separable", e1, e2, infos[0]["total_iterations"], infos2[0]["total_iterations"])
+    assert e1 <= max(1e-6, infos[0]["certified_bound"])
+    assert e2 <= max(1e-10, 10 * d["amplification"] * EPS)
+
+
+def test_shifted_matches_per_pole_on_bench_workload(rexi):
+    # the benchmarked 128^3 workload: both solvers agree within their bounds
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    wl = inputs.workload("3d_bumps")
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+    Vd = to_dev(wl.V.ravel())
+    p0 = to_dev(wl.psi0.ravel())
+    a = torch.empty_like(p0)
+    c = torch.empty_like(p0)
+    hs = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, wl.dt, s, b, solver="shifted", m=100, tol=1e-12,
+                 tol_policy="certified")
+    i1 = hs.step(p0, a, 1)
+    hs.close()
+    hp = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, wl.dt, s, b, tol=1e-12, tol_policy="certified")
+    i2 = hp.step(p0, c, 1)
+    hp.close()
+    torch.cuda.synchronize()
+    diff = rel(a.cpu().numpy(), c.cpu().numpy())
+    print("shifted vs per-pole (128^3 bumps)", diff, i1["total_iterations"], i2["total_iterations"])
+    assert diff <= i1["certified_bound"] + i2["certified_bound"] + 10 * d["amplification"] * EPS
