@@ -104,6 +104,9 @@ typedef struct {
   double inner_rtol;   /* C64_REFINE: residual reduction per sweep, 1e-5     */
   int32_t check_every; /* shared-basis solver: iterations between host reads
                           of the convergence flag, default 4                 */
+  int32_t lanczos;     /* shared-basis solver: 1 (default) uses the Hermitian
+                          three-term (Lanczos) recurrence with partial
+                          reorthogonalisation; 0 full Arnoldi + DGKS         */
   int32_t capture_safe;/* 1: rexi_step(info = NULL) runs a fixed schedule
                           with no host reads, so it can be graph-captured    */
   int32_t profile;     /* 1: time kernel classes with HIP events             */

@@ -86,6 +86,7 @@ struct rexi_handle {
   // shared-basis solver: fwd holds one system (H, shift 0) per instance
   bool shifted = false;
   rexi::ShiftWork SW{};
+  rexi::ShiftWork noshift{};          // K = 0: per-pole Givens in pass B
   std::vector<DevBuf> sbufs;
   int32_t* hpin = nullptr;            // pinned counters read-back
   double* dnorm = nullptr;            // scratch partials for norms
@@ -256,6 +257,7 @@ rexi_status build_solver(rexi_handle* h, Solver& sv, hipStream_t stream) {
   ALLOC(W.part, double, npart * 2);
   ALLOC(W.pnorm, double, sv.total_tiles);
   ALLOC(W.counters, int32_t, sv.max_cycles * (m + 1) + sv.max_cycles + 4);
+  ALLOC(W.tick, int32_t, (size_t)S * 4);
   ALLOC(W.x, double, nx * 2);
   if (sv.prec) {
     float* b;
@@ -267,6 +269,8 @@ rexi_status build_solver(rexi_handle* h, Solver& sv, hipStream_t stream) {
     W.basis = b;
   }
 #undef ALLOC
+  // tickets start at zero and every completed pass returns them to zero
+  HIPCHK(h, hipMemsetAsync(W.tick, 0, (size_t)S * 4 * sizeof(int32_t), stream));
   HIPCHK(h, hipMemcpyAsync(sv.dsys, sv.hsys.data(), S * sizeof(SysDesc), hipMemcpyHostToDevice, stream));
   HIPCHK(h, hipMemcpyAsync(sv.dtile, sv.htile.data(), (S + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
   HIPCHK(h, hipStreamSynchronize(stream));
@@ -319,33 +323,37 @@ rexi_status run_solve(rexi_handle* h, Solver& sv, const double2* r0, const doubl
     for (int j = 0; j < m; ++j) {
       {
         Timed t(h, PC_ARNOLDI_A, active * n_avg * ((j + 2) * e + eV), stream);
-        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, true>), dim3(G), dim3(TPB), 0, stream, W, j);
+        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, true>), dim3(G), dim3(TPB), 0, stream, W, j, 0);
       }
       {
         Timed t(h, PC_REDUCE, 0, stream);
-        hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, stream, W, j, 0);
+        hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, stream, W, j, 0, 0);
       }
       {
         Timed t(h, PC_ARNOLDI_B, active * n_avg * (j + 3) * e, stream);
-        hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, j, 0);
+        hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, j, 0, 0);
+      }
+      {
+        Timed t(h, PC_REDUCE, 0, stream);
+        hipLaunchKernelGGL(rexi::k_end_iter, dim3(S), dim3(TPB), 0, stream, W, h->noshift, j, 0, c);
       }
       if (sv.reorth) {
         {
           Timed t(h, PC_REORTH_A, 0, stream);
-          hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(G), dim3(TPB), 0, stream, W, j);
+          hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(G), dim3(TPB), 0, stream, W, j, 0);
         }
         {
           Timed t(h, PC_REDUCE, 0, stream);
-          hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, stream, W, j, 1);
+          hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, stream, W, j, 1, 0);
         }
         {
           Timed t(h, PC_REORTH_B, 0, stream);
-          hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, j, 1);
+          hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, j, 1, 0);
         }
-      }
-      {
-        Timed t(h, PC_REDUCE, 0, stream);
-        hipLaunchKernelGGL(rexi::k_givens, dim3(S), dim3(TPB), 0, stream, W, j, c);
+        {
+          Timed t(h, PC_REDUCE, 0, stream);
+          hipLaunchKernelGGL(rexi::k_end_iter, dim3(S), dim3(TPB), 0, stream, W, h->noshift, j, 1, c);
+        }
       }
       HIPCHK(h, hipGetLastError());
       HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + c * (m + 1) + j, sizeof(int32_t), hipMemcpyDeviceToHost,
@@ -395,9 +403,10 @@ rexi_status solve(rexi_handle* h, Solver& sv, const double2* r0, const double2* 
   return fail(h, REXI_E_INVALID_ARG, "unsupported tiling");
 }
 
-// Points per thread: the largest of 8, 4, 2 that still gives >= 4096 work tiles.
+// Points per thread: the largest of 8, 4, 2 that still gives >= 1024 work
+// tiles (four or more 4-wave blocks per compute unit).
 int choose_ppt(int64_t points) {
-  for (int p : {8, 4}) if (points / (TPB * p) >= 4096) return p;
+  for (int p : {8, 4}) if (points / (TPB * p) >= 1024) return p;
   return 2;
 }
 
@@ -513,8 +522,19 @@ rexi_status init_shifted(rexi_handle* h, hipStream_t stream) {
       (st = al(&S.R, (size_t)K * (m + 1) * m * 2)) || (st = al(&S.g, (size_t)K * (m + 1) * 2)) ||
       (st = al(&S.gc, (size_t)K * m * 2)) || (st = al(&S.gs, (size_t)K * m * 2)) ||
       (st = al(&S.y, (size_t)K * m * 2)) || (st = al(&S.z, (size_t)m * 2)) || (st = al(&S.res, K)) ||
-      (st = al(&its, K)))
+      (st = al(&its, K)) || (st = al(&S.alpha, m)) || (st = al(&S.beta, m + 1)) ||
+      (st = al(&S.omega, 2 * (m + 1))))
     return st;
+  double* flags = nullptr;
+  if ((st = al(&flags, 2))) return st;
+  S.flags = reinterpret_cast<int32_t*>(flags);
+  HIPCHK(h, hipMemsetAsync(flags, 0, 2 * sizeof(double), stream));
+  S.lanczos = h->opt.lanczos ? 1 : 0;
+  S.eps1 = std::sqrt((double)h->fwd.hsys[0].n) * 1.1102230246251565e-16;
+  if (S.lanczos) {
+    // the recurrence decides the second passes; the DGKS test is off
+    h->fwd.W.reorth_mode = 3;
+  }
   S.s = s;
   S.w = w;
   S.tol = tol;
@@ -554,36 +574,44 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
   // iterations run in chunks between host reads of the convergence counter;
   // iterations after convergence return at once (device-side state)
   const int chunk = std::max(1, h->opt.check_every);
+  const bool lz = h->SW.lanczos != 0;
   for (int j = 0; j < m; ++j) {
+    // Lanczos: project on v_{j-1}, v_j only (H is Hermitian); Arnoldi: on all
+    const int i0 = lz ? std::max(0, j - 1) : 0;
+    const int nproj = j + 1 - i0;
     {
-      Timed t(h, PC_ARNOLDI_A, n * ((j + 2) * e + 8.0), stream);
-      hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, true>), dim3(G), dim3(TPB), 0, stream, W, j);
+      Timed t(h, PC_ARNOLDI_A, n * ((nproj + 1) * e + 8.0), stream);
+      hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, true>), dim3(G), dim3(TPB), 0, stream, W, j, i0);
     }
     {
       Timed t(h, PC_REDUCE, 0, stream);
-      hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(1, j + 2), dim3(TPB), 0, stream, W, j, 0);
+      hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(1, j + 2), dim3(TPB), 0, stream, W, j, 0, i0);
     }
     {
-      Timed t(h, PC_ARNOLDI_B, n * (j + 3) * e, stream);
-      hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, j, 0);
+      Timed t(h, PC_ARNOLDI_B, n * (nproj + 2) * e, stream);
+      hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, j, 0, i0);
     }
-    if (sv.reorth) {
+    {
+      Timed t(h, PC_REDUCE, 0, stream);
+      hipLaunchKernelGGL(rexi::k_end_iter, dim3(1), dim3(TPB), 0, stream, W, h->SW, j, 0, 0);
+    }
+    if (sv.reorth || lz) {
       {
         Timed t(h, PC_REORTH_A, 0, stream);
-        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(G), dim3(TPB), 0, stream, W, j);
+        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(G), dim3(TPB), 0, stream, W, j, 0);
       }
       {
         Timed t(h, PC_REDUCE, 0, stream);
-        hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(1, j + 2), dim3(TPB), 0, stream, W, j, 1);
+        hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(1, j + 2), dim3(TPB), 0, stream, W, j, 1, 0);
       }
       {
         Timed t(h, PC_REORTH_B, 0, stream);
-        hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, j, 1);
+        hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, j, 1, 0);
       }
-    }
-    {
-      Timed t(h, PC_REDUCE, 0, stream);
-      hipLaunchKernelGGL(rexi::k_shifted_givens, dim3(1), dim3(TPB), 0, stream, W, h->SW, j);
+      {
+        Timed t(h, PC_REDUCE, 0, stream);
+        hipLaunchKernelGGL(rexi::k_end_iter, dim3(1), dim3(TPB), 0, stream, W, h->SW, j, 1, 0);
+      }
     }
     HIPCHK(h, hipGetLastError());
     if ((j + 1) % chunk == 0 || j + 1 == m) {
@@ -591,6 +619,11 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
       HIPCHK(h, hipStreamSynchronize(stream));
       if (h->hpin[0] == 0) break;
     }
+  }
+  {
+    Timed t(h, PC_REDUCE, 0, stream);
+    hipLaunchKernelGGL(rexi::k_shifted_backsub, dim3((h->SW.K + rexi::NWAVE - 1) / rexi::NWAVE), dim3(TPB), 0,
+                       stream, W, h->SW);
   }
   {
     Timed t(h, PC_POLESUM, 0, stream);
@@ -849,6 +882,7 @@ void rexi_default_options(rexi_options* o) {
   o->reorth_eta = 1e-2;
   o->inner_rtol = 1e-5;
   o->check_every = 4;
+  o->lanczos = 1;
   o->capture_safe = 0;
   o->profile = 0;
   o->tile = 0;

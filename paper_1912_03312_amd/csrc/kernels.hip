@@ -225,14 +225,121 @@ __global__ __launch_bounds__(TPB) void k_start_reduce(Work W) {
   }
 }
 
+// ------------------------------------------------------------ shared basis
+// All poles share one Krylov basis: with x0 = 0 every shifted system starts
+// from b, and K_k(H - s I, b) = K_k(H, b). One Arnoldi (or, H being
+// Hermitian, Lanczos) process on H (system 0 with shift 0) gives
+// H V_k = V_{k+1} Hbar_k, hence (H - s_p) V_k = V_{k+1} (Hbar_k - s_p Itilde);
+// each pole solves its own small least-squares problem
+// min || ||b|| e_1 - (Hbar_k - s_p Itilde) y_p ||, and the step is
+// sum_p w_p V_k y_p = V_k z with z = sum_p w_p y_p.
+struct ShiftWork {
+  int32_t K;          // poles sharing the basis (0: per-pole solver)
+  const double* s;    // [K] complex shifts
+  const double* w;    // [K] complex weights
+  const double* tol;  // [K] target relative residuals
+  double* R;          // [K][(m+1) m] complex, rotated Hessenberg per pole
+  double* g;          // [K][m+1] complex
+  double* gc;         // [K][m] complex
+  double* gs;         // [K][m] complex
+  double* y;          // [K][m] complex
+  double* z;          // [m] complex, combined coefficients
+  double* res;        // [K] implicit relative residual
+  int32_t* its;       // [K] iteration at which the pole met its target (0: not yet)
+  // Lanczos with partial reorthogonalisation (three-term recurrence)
+  int32_t lanczos;    // 1: project only on the last two basis vectors
+  double* alpha;      // [m] diagonal of the tridiagonal matrix
+  double* beta;       // [m+1] off-diagonal, beta[j+1] = ||v_{j+1}|| before scaling
+  double* omega;      // [2][m+1] estimated <v_{j}, v_k>, <v_{j+1}, v_k> (rolling)
+  int32_t* flags;     // [0]: reorthogonalise the next vector too; [1]: passes done;
+                      // [2]: back-substitution ticket
+  double eps1;        // local orthogonality level sqrt(n) u
+};
+
+// ------------------------------------------------------------ completion ticket
+// Every block publishes its results, then takes a ticket; the block that
+// takes the last ticket sees all of them (fences on both sides), resets the
+// ticket and returns true. Used where few blocks take part (contention on
+// one counter grows with the number of blocks).
+__device__ __forceinline__ bool last_tile(int32_t* ticket, int ntiles) {
+  __shared__ int flag;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int old = atomicAdd(ticket, 1);
+    flag = old == ntiles - 1;
+  }
+  __syncthreads();
+  const bool last = flag != 0;
+  if (last) {
+    __threadfence();
+    if (threadIdx.x == 0) atomicExch(ticket, 0);
+  }
+  return last;
+}
+
+// Grid (S, j + 2): block (s, i) with lo <= i <= j reduces the tile partials
+// of <u_i, w> to h_ij = c_i <u_i, w> (lo = i0 on the first pass, 0 on the
+// second); blocks i < lo zero the entry (three-term window); block j + 1
+// reduces ||w||^2 (first pass). The first pass stores the Hessenberg column,
+// the second (re-orthogonalisation) pass adds its correction.
+__global__ __launch_bounds__(TPB) void k_reduce_dots(Work W, int j, int second, int i0) {
+  __shared__ double lds[NWAVE];
+  const int s = blockIdx.x;
+  const int i = blockIdx.y;
+  if (s >= W.S || i > j + 1) return;
+  SysState_t& st = W.st[s];
+  if (st.state != ST_ACTIVE) return;
+  if (second && !st.reorth) return;
+  const SysDesc& d = W.sys[s];
+  const int lo = second ? 0 : i0;
+  double2* hcol = reinterpret_cast<double2*>(W.H) + (int64_t)s * (W.m + 1) * W.m + (int64_t)j * (W.m + 1);
+  double2* hc = reinterpret_cast<double2*>(W.hcur) + (int64_t)s * (W.m + 1);
+  if (i == j + 1) {
+    if (second) return;
+    double wn = 0.0;
+    for (int t = threadIdx.x; t < d.ntiles; t += TPB) wn += W.pnorm[d.tile0 + t];
+    wn = block_sum(wn, lds);
+    if (threadIdx.x == 0) st.w2 = wn;
+    return;
+  }
+  if (i < lo) {
+    if (threadIdx.x == 0) {
+      hcol[i] = make_double2(0.0, 0.0);
+      hc[i] = make_double2(0.0, 0.0);
+    }
+    return;
+  }
+  const double2* part = reinterpret_cast<const double2*>(W.part) + d.pbase + (int64_t)i * d.ntiles;
+  double ax = 0.0, ay = 0.0;
+  for (int t = threadIdx.x; t < d.ntiles; t += TPB) {
+    const double2 v = part[t];
+    ax += v.x;
+    ay += v.y;
+  }
+  ax = block_sum(ax, lds);
+  ay = block_sum(ay, lds);
+  if (threadIdx.x == 0) {
+    const double c = W.cscale[(int64_t)s * (W.m + 1) + i];
+    const double2 h = make_double2(c * ax, c * ay);
+    hc[i] = h;
+    if (second) {
+      hcol[i].x += h.x;
+      hcol[i].y += h.y;
+    } else {
+      hcol[i] = h;
+    }
+  }
+}
+
 // ------------------------------------------------------------ Arnoldi pass A
 // MATVEC: w = c_j (H - s) u_j, written to u_{j+1}. Otherwise w = u_{j+1}
-// (second Gram-Schmidt pass). Partial sums of conj(u_i) w for i <= j, and
-// of ||w||^2, per tile.
+// (second Gram-Schmidt pass). Partial sums of conj(u_i) w for lo <= i <= j,
+// and of ||w||^2, per tile.
 template <typename T, int PPT, bool MATVEC>
-__global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j) {
-  __shared__ double lds[NWAVE];
+__global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0) {
   __shared__ double2 red[NWAVE][MAXM + 1];
+  const int lo = MATVEC ? i0 : 0;
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
     const int s = find_sys(W.tile_start, W.S, item);
     const SysState_t& st = W.st[s];
@@ -264,7 +371,7 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j) {
       }
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int i = 0; i <= j; ++i) {
+    for (int i = lo; i <= j; ++i) {
       const T* __restrict__ ui = basis_vec<T>(W, d, i);
       double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
@@ -285,7 +392,7 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j) {
     if (lane == 0) red[wid][MAXM] = make_double2(wn, 0.0);
     __syncthreads();
     double2* part = reinterpret_cast<double2*>(W.part) + d.pbase;
-    for (int i = threadIdx.x; i <= j; i += TPB) {
+    for (int i = lo + threadIdx.x; i <= j; i += TPB) {
       double2 a = make_double2(0.0, 0.0);
 #pragma unroll
       for (int w2 = 0; w2 < NWAVE; ++w2) { a.x += red[w2][i].x; a.y += red[w2][i].y; }
@@ -299,57 +406,195 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j) {
     }
     __syncthreads();
   }
-  (void)lds;
 }
 
-// Grid (S, j + 2): block (s, i <= j) reduces the tile partials of
-// <u_i, w> to h_ij = c_i <u_i, w>; block (s, j + 1) reduces ||w||^2 (first
-// pass only). The first pass stores the Hessenberg column; the second
-// (DGKS) pass adds its correction.
-__global__ __launch_bounds__(TPB) void k_reduce_dots(Work W, int j, int second) {
-  __shared__ double lds[NWAVE];
-  const int s = blockIdx.x;
-  const int i = blockIdx.y;
-  if (s >= W.S || i > j + 1) return;
+// Per-system Givens step (thread 0): h_{j+1,j} = beta, rotate column j,
+// residual estimate |g_{j+1}|, convergence decision; at the end of the cycle
+// the triangular solve R y = g.
+__device__ void givens_per_pole(Work& W, int s, int j, int cycle, double beta) {
   SysState_t& st = W.st[s];
-  if (st.state != ST_ACTIVE) return;
-  if (second && !st.reorth) return;
   const SysDesc& d = W.sys[s];
-  if (i == j + 1) {
-    if (second) return;
-    double wn = 0.0;
-    for (int t = threadIdx.x; t < d.ntiles; t += TPB) wn += W.pnorm[d.tile0 + t];
-    wn = block_sum(wn, lds);
-    if (threadIdx.x == 0) st.w2 = wn;
-    return;
+  const int m = W.m;
+  double2* Hs = reinterpret_cast<double2*>(W.H) + (int64_t)s * (m + 1) * m;
+  double2* col = Hs + (int64_t)j * (m + 1);
+  double2* gcv = reinterpret_cast<double2*>(W.gc) + (int64_t)s * m;
+  double2* gsv = reinterpret_cast<double2*>(W.gs) + (int64_t)s * m;
+  double2* g = reinterpret_cast<double2*>(W.gvec) + (int64_t)s * (m + 1);
+  double* cs = W.cscale + (int64_t)s * (m + 1);
+  col[j + 1] = make_double2(beta, 0.0);
+  // earlier rotations: (a, b) -> (conj(c) a + conj(s) b, -s a + c b)
+  for (int i = 0; i < j; ++i) {
+    const double2 c = gcv[i], sn = gsv[i];
+    const double2 a = col[i], b = col[i + 1];
+    const double2 t1 = cjmul(c, a), t2 = cjmul(sn, b);
+    const double2 u1 = cmul(sn, a), u2 = cmul(c, b);
+    col[i] = make_double2(t1.x + t2.x, t1.y + t2.y);
+    col[i + 1] = make_double2(u2.x - u1.x, u2.y - u1.y);
   }
-  const double2* part = reinterpret_cast<const double2*>(W.part) + d.pbase + (int64_t)i * d.ntiles;
-  double ax = 0.0, ay = 0.0;
-  for (int t = threadIdx.x; t < d.ntiles; t += TPB) {
-    const double2 v = part[t];
-    ax += v.x;
-    ay += v.y;
+  const double2 a = col[j];
+  const double den = sqrt(a.x * a.x + a.y * a.y + beta * beta);
+  double2 c, sn;
+  if (den > 0.0) {
+    c = make_double2(a.x / den, a.y / den);
+    sn = make_double2(beta / den, 0.0);
+  } else {
+    c = make_double2(1.0, 0.0);
+    sn = make_double2(0.0, 0.0);
   }
-  ax = block_sum(ax, lds);
-  ay = block_sum(ay, lds);
-  if (threadIdx.x == 0) {
-    const double c = W.cscale[(int64_t)s * (W.m + 1) + i];
-    const double2 h = make_double2(c * ax, c * ay);
-    double2* hcol = reinterpret_cast<double2*>(W.H) + (int64_t)s * (W.m + 1) * W.m + (int64_t)j * (W.m + 1);
-    reinterpret_cast<double2*>(W.hcur)[(int64_t)s * (W.m + 1) + i] = h;
-    if (second) {
-      hcol[i].x += h.x;
-      hcol[i].y += h.y;
-    } else {
-      hcol[i] = h;
+  gcv[j] = c;
+  gsv[j] = sn;
+  col[j] = make_double2(den, 0.0);
+  col[j + 1] = make_double2(0.0, 0.0);
+  const double2 gj = g[j];
+  g[j + 1] = make_double2(-(sn.x * gj.x - sn.y * gj.y), -(sn.x * gj.y + sn.y * gj.x));
+  g[j] = cjmul(c, gj);
+  const double res = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
+  cs[j + 1] = beta > 0.0 ? 1.0 / beta : 0.0;
+  st.kcyc = j + 1;
+  st.its += 1;
+  // stop the cycle at the inner target (mixed path: a fixed reduction of the
+  // cycle's starting residual) or at the outer target, whichever is larger
+  const double target = fmax(W.inner_rtol * st.rnorm, 0.5 * d.tol * st.bnorm);
+  const bool conv = res <= target || beta == 0.0 || !(res == res);
+  if (conv || j + 1 == m) {
+    const int k = j + 1;
+    double2* y = reinterpret_cast<double2*>(W.y) + (int64_t)s * m;
+    for (int r = k - 1; r >= 0; --r) {
+      double2 acc = g[r];
+      for (int q = r + 1; q < k; ++q) {
+        const double2 tq = cmul(Hs[(int64_t)q * (m + 1) + r], y[q]);
+        acc.x -= tq.x;
+        acc.y -= tq.y;
+      }
+      const double2 dd = Hs[(int64_t)r * (m + 1) + r];
+      const double dn = dd.x * dd.x + dd.y * dd.y;
+      y[r] = dn > 0.0 ? make_double2((acc.x * dd.x + acc.y * dd.y) / dn, (acc.y * dd.x - acc.x * dd.y) / dn)
+                      : make_double2(0.0, 0.0);
     }
+    st.state = ST_FINISH;
+  } else {
+    atomicAdd(&W.counters[cycle * (m + 1) + j], 1);
+  }
+}
+
+// Partial reorthogonalisation (shared-basis Lanczos; thread 0). The three-term
+// recurrence with local orthogonalisation against v_{j-1}, v_j leaves the
+// loss of orthogonality of v_{j+1} against v_k (k < j) to Simon's recurrence
+//   beta_{j+1} w_{j+1,k} = beta_{k+1} w_{j,k+1} + (alpha_k - alpha_j) w_{j,k}
+//                          + beta_k w_{j,k-1} - beta_j w_{j-1,k} + rounding,
+// w_{j,j} = 1, w_{j+1,j} = eps1. When max_k |w_{j+1,k}| exceeds sqrt(u),
+// v_{j+1} (and then v_{j+2}) get a full Gram-Schmidt pass against all earlier
+// vectors, and the estimates of a reorthogonalised vector reset to eps1.
+__device__ bool pro_decide(Work& W, ShiftWork& SW, int j, double bj1) {
+  const int m = W.m;
+  const double u = 1.1102230246251565e-16;
+  const double2 hjj = reinterpret_cast<const double2*>(W.H)[(int64_t)j * (m + 1) + j];
+  SW.alpha[j] = hjj.x;
+  SW.beta[j + 1] = bj1;
+  double* wprev = SW.omega + (int64_t)((j + 1) & 1) * (m + 1);  // row j-1, becomes row j+1
+  double* wcur = SW.omega + (int64_t)(j & 1) * (m + 1);         // row j
+  const int force = SW.flags[0];
+  if (j == 0) wcur[0] = 1.0;
+  const double bj = SW.beta[j];
+  const double aj = SW.alpha[j];
+  double anorm = 0.0;
+  for (int k = 0; k <= j; ++k) anorm = fmax(anorm, fabs(SW.alpha[k]) + SW.beta[k] + SW.beta[k + 1]);
+  double worst = 0.0;
+  for (int k = 0; k < j; ++k) {
+    const double wkp1 = wcur[k + 1];
+    const double wk = wcur[k];
+    const double wkm1 = k > 0 ? wcur[k - 1] : 0.0;
+    const double wold = wprev[k];
+    double v = SW.beta[k + 1] * wkp1 + (SW.alpha[k] - aj) * wk + (k > 0 ? SW.beta[k] * wkm1 : 0.0) - bj * wold;
+    v += copysign(2.0 * u * anorm, v);
+    v = bj1 > 0.0 ? v / bj1 : 1.0;
+    wprev[k] = v;
+    worst = fmax(worst, fabs(v));
+  }
+  wprev[j] = SW.eps1;
+  wprev[j + 1] = 1.0;
+  const bool reo = force || worst > sqrt(u);
+  if (reo) {
+    for (int k = 0; k <= j; ++k) wprev[k] = SW.eps1;
+    SW.flags[0] = force ? 0 : 1;  // the next vector gets a pass as well
+    SW.flags[1] += 1;
+  }
+  return reo;
+}
+
+// Block-level: Givens update of column j of (Hbar - s_p Itilde) for every
+// pole sharing the basis; ends the Arnoldi process when every pole meets its
+// target or j + 1 = m (the back substitution runs in k_shifted_backsub).
+// `banded`: column j has no entries above row j - 1 (no second pass).
+__device__ void givens_shifted(Work& W, ShiftWork& SW, int j, double beta, bool banded) {
+  __shared__ double lds[NWAVE];
+  SysState_t& st = W.st[0];
+  const int m = W.m;
+  const double2* hcol = reinterpret_cast<const double2*>(W.H) + (int64_t)j * (m + 1);
+  const double bn = st.bnorm;
+  const int i_start = banded ? max(0, j - 2) : 0;
+  double unconv = 0.0;
+  for (int p = threadIdx.x; p < SW.K; p += TPB) {
+    double2* Rp = reinterpret_cast<double2*>(SW.R) + (int64_t)p * (m + 1) * m;
+    double2* col = Rp + (int64_t)j * (m + 1);
+    double2* gcv = reinterpret_cast<double2*>(SW.gc) + (int64_t)p * m;
+    double2* gsv = reinterpret_cast<double2*>(SW.gs) + (int64_t)p * m;
+    double2* g = reinterpret_cast<double2*>(SW.g) + (int64_t)p * (m + 1);
+    const double2 sp = reinterpret_cast<const double2*>(SW.s)[p];
+    for (int i = 0; i <= j; ++i) col[i] = hcol[i];
+    col[j].x -= sp.x;
+    col[j].y -= sp.y;
+    for (int i = i_start; i < j; ++i) {
+      const double2 c = gcv[i], sn = gsv[i];
+      const double2 a = col[i], b = col[i + 1];
+      const double2 t1 = cjmul(c, a), t2 = cjmul(sn, b);
+      const double2 u1 = cmul(sn, a), u2 = cmul(c, b);
+      col[i] = make_double2(t1.x + t2.x, t1.y + t2.y);
+      col[i + 1] = make_double2(u2.x - u1.x, u2.y - u1.y);
+    }
+    const double2 a = col[j];
+    const double den = sqrt(a.x * a.x + a.y * a.y + beta * beta);
+    double2 c, sn;
+    if (den > 0.0) {
+      c = make_double2(a.x / den, a.y / den);
+      sn = make_double2(beta / den, 0.0);
+    } else {
+      c = make_double2(1.0, 0.0);
+      sn = make_double2(0.0, 0.0);
+    }
+    gcv[j] = c;
+    gsv[j] = sn;
+    col[j] = make_double2(den, 0.0);
+    const double2 gj = g[j];
+    g[j + 1] = make_double2(-(sn.x * gj.x - sn.y * gj.y), -(sn.x * gj.y + sn.y * gj.x));
+    g[j] = cjmul(c, gj);
+    const double res = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
+    SW.res[p] = bn > 0.0 ? res / bn : 0.0;
+    const bool conv = res <= 0.5 * SW.tol[p] * bn || beta == 0.0 || !(res == res);
+    if (conv) {
+      if (SW.its[p] == 0) SW.its[p] = j + 1;
+    } else {
+      unconv += 1.0;
+    }
+  }
+  unconv = block_sum(unconv, lds);
+  if (threadIdx.x == 0) {
+    const int k = j + 1;
+    W.H[(int64_t)j * (m + 1) * 2 + 2 * (j + 1)] = beta;  // h_{j+1,j}
+    W.H[(int64_t)j * (m + 1) * 2 + 2 * (j + 1) + 1] = 0.0;
+    W.cscale[j + 1] = beta > 0.0 ? 1.0 / beta : 0.0;
+    if (SW.lanczos) SW.beta[j + 1] = beta;  // after any second pass
+    st.kcyc = k;
+    st.its = k;
+    if (unconv == 0.0 || k == m) st.state = ST_FINISH;
+    else atomicAdd(&W.counters[j], 1);
   }
 }
 
 // ------------------------------------------------------------ Arnoldi pass B
-// u_{j+1} -= sum_{i<=j} hcur_i c_i u_i ; partial ||u_{j+1}||^2.
+// u_{j+1} -= sum_{lo<=i<=j} hcur_i c_i u_i ; partial ||u_{j+1}||^2 per tile.
 template <typename T, int PPT>
-__global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second) {
+__global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second, int i0) {
   __shared__ double lds[NWAVE];
   __shared__ double2 coef[MAXM];
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
@@ -359,19 +604,21 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second) {
     if (second && !st.reorth) continue;
     const SysDesc& d = W.sys[s];
     const int t = item - d.tile0;
+    const int lo = second ? 0 : i0;
     __syncthreads();
-    for (int i = threadIdx.x; i <= j; i += TPB) {
+    for (int i = lo + threadIdx.x; i <= j; i += TPB) {
       const double2 h = reinterpret_cast<const double2*>(W.hcur)[(int64_t)s * (W.m + 1) + i];
       const double c = W.cscale[(int64_t)s * (W.m + 1) + i];
       coef[i] = make_double2(h.x * c, h.y * c);
     }
     __syncthreads();
-    if (!second && t == 0 && threadIdx.x == 0) {
+    if (!second && t == 0 && threadIdx.x == 0 && W.reorth_mode <= 2) {
       // DGKS: a second pass when ||w - V h||^2 = ||w||^2 - sum |h_i|^2 (orthonormal
       // V) has dropped below eta^2 ||w||^2, i.e. when cancellation was severe
-      const double2* hc = reinterpret_cast<const double2*>(W.hcur) + (int64_t)s * (W.m + 1);
       double hs = 0.0;
-      for (int i = 0; i <= j; ++i) hs += hc[i].x * hc[i].x + hc[i].y * hc[i].y;
+      const double2* hc = reinterpret_cast<const double2*>(W.hcur) + (int64_t)s * (W.m + 1);
+      hs = 0.0;
+      for (int i = lo; i <= j; ++i) hs += hc[i].x * hc[i].x + hc[i].y * hc[i].y;
       const double w2 = st.w2;
       W.st[s].reorth = (W.reorth_mode == 2) || (W.reorth_mode == 1 && !(w2 - hs >= W.eta2 * w2));
     }
@@ -382,7 +629,7 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second) {
       const int p = t * W.tile + q * TPB + threadIdx.x;
       w[q] = p < d.n ? to_d2(unew[p]) : make_double2(0.0, 0.0);
     }
-    for (int i = 0; i <= j; ++i) {
+    for (int i = lo; i <= j; ++i) {
       const T* __restrict__ ui = basis_vec<T>(W, d, i);
       const double2 c = coef[i];
 #pragma unroll
@@ -411,84 +658,102 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second) {
   }
 }
 
-// ------------------------------------------------------------ Givens update
-// Per system: h_{j+1,j} = ||u_{j+1}||, rotate column j, residual estimate
-// |g_{j+1}|, convergence decision; at the end of the cycle the triangular
-// solve R y = g.
-__global__ __launch_bounds__(TPB) void k_givens(Work W, int j, int cycle) {
+// Grid S: the end of Arnoldi iteration j for system s. Reduces ||u_{j+1}||
+// = h_{j+1,j}; on the first pass decides the second Gram-Schmidt pass
+// (DGKS flag from pass B, or the Lanczos orthogonality estimate); when no
+// second pass is due (or on the second pass), runs the Givens step: per pole,
+// or for all poles of a shared basis.
+__global__ __launch_bounds__(TPB) void k_end_iter(Work W, ShiftWork SW, int j, int second, int cycle) {
   __shared__ double lds[NWAVE];
+  __shared__ int reo_sh;
   const int s = blockIdx.x;
   if (s >= W.S) return;
   SysState_t& st = W.st[s];
   if (st.state != ST_ACTIVE) return;
+  if (second && !st.reorth) return;
   const SysDesc& d = W.sys[s];
-  double wn = 0.0;
-  for (int t = threadIdx.x; t < d.ntiles; t += TPB) wn += W.pnorm[d.tile0 + t];
-  wn = block_sum(wn, lds);
-  if (threadIdx.x != 0) return;
-  const int m = W.m;
-  const double beta = sqrt(wn);
-  double2* Hs = reinterpret_cast<double2*>(W.H) + (int64_t)s * (m + 1) * m;
-  double2* col = Hs + (int64_t)j * (m + 1);
-  double2* gcv = reinterpret_cast<double2*>(W.gc) + (int64_t)s * m;
-  double2* gsv = reinterpret_cast<double2*>(W.gs) + (int64_t)s * m;
-  double2* g = reinterpret_cast<double2*>(W.gvec) + (int64_t)s * (m + 1);
-  double* cs = W.cscale + (int64_t)s * (m + 1);
-  col[j + 1] = make_double2(beta, 0.0);
-  // earlier rotations: (a, b) -> (conj(c) a + conj(s) b, -s a + c b)
-  for (int i = 0; i < j; ++i) {
-    const double2 c = gcv[i], sn = gsv[i];
-    const double2 a = col[i], b = col[i + 1];
-    const double2 t1 = cjmul(c, a), t2 = cjmul(sn, b);
-    const double2 u1 = cmul(sn, a), u2 = cmul(c, b);
-    col[i] = make_double2(t1.x + t2.x, t1.y + t2.y);
-    col[i + 1] = make_double2(u2.x - u1.x, u2.y - u1.y);
-  }
-  const double2 a = col[j];
-  const double bb = beta;
-  const double den = sqrt(a.x * a.x + a.y * a.y + bb * bb);
-  double2 c, sn;
-  if (den > 0.0) {
-    c = make_double2(a.x / den, a.y / den);
-    sn = make_double2(bb / den, 0.0);
-  } else {
-    c = make_double2(1.0, 0.0);
-    sn = make_double2(0.0, 0.0);
-  }
-  gcv[j] = c;
-  gsv[j] = sn;
-  col[j] = make_double2(den, 0.0);
-  col[j + 1] = make_double2(0.0, 0.0);
-  const double2 gj = g[j];
-  g[j + 1] = make_double2(-(sn.x * gj.x - sn.y * gj.y), -(sn.x * gj.y + sn.y * gj.x));
-  g[j] = cjmul(c, gj);
-  const double res = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
-  cs[j + 1] = beta > 0.0 ? 1.0 / beta : 0.0;
-  st.kcyc = j + 1;
-  st.its += 1;
-  // stop the cycle at the inner target (mixed path: a fixed reduction of the
-  // cycle's starting residual) or at the outer target, whichever is larger
-  const double target = fmax(W.inner_rtol * st.rnorm, 0.5 * d.tol * st.bnorm);
-  const bool conv = res <= target || beta == 0.0 || !(res == res);
-  if (conv || j + 1 == m) {
-    // back substitution R y = g, R = Hs[0:k, 0:k] upper triangular
-    const int k = j + 1;
-    double2* y = reinterpret_cast<double2*>(W.y) + (int64_t)s * m;
-    for (int r = k - 1; r >= 0; --r) {
-      double2 acc = g[r];
-      for (int q = r + 1; q < k; ++q) {
-        const double2 t = cmul(Hs[(int64_t)q * (m + 1) + r], y[q]);
-        acc.x -= t.x;
-        acc.y -= t.y;
-      }
-      const double2 dd = Hs[(int64_t)r * (m + 1) + r];
-      const double dn = dd.x * dd.x + dd.y * dd.y;
-      y[r] = dn > 0.0 ? make_double2((acc.x * dd.x + acc.y * dd.y) / dn, (acc.y * dd.x - acc.x * dd.y) / dn)
-                      : make_double2(0.0, 0.0);
+  double bsq = 0.0;
+  for (int tt = threadIdx.x; tt < d.ntiles; tt += TPB) bsq += W.pnorm[d.tile0 + tt];
+  bsq = block_sum(bsq, lds);
+  const double beta = sqrt(bsq);
+  if (threadIdx.x == 0) {
+    int reo = second ? 0 : st.reorth;
+    if (!second && SW.K > 0 && SW.lanczos) {
+      reo = pro_decide(W, SW, j, beta) ? 1 : 0;
+      st.reorth = reo;
     }
-    st.state = ST_FINISH;
-  } else {
-    atomicAdd(&W.counters[cycle * (m + 1) + j], 1);
+    reo_sh = reo;
+  }
+  __syncthreads();
+  if (reo_sh) return;
+  if (SW.K > 0) {
+    givens_shifted(W, SW, j, beta, SW.lanczos && !second);
+  } else if (threadIdx.x == 0) {
+    givens_per_pole(W, s, j, cycle, beta);
+  }
+}
+
+// Shared basis, after the last iteration: back substitution R_p y_p = g_p per
+// pole (one wave per pole, rows in sequence, the row sums across lanes),
+// then, in the block that finishes last, z = sum_p w_p y_p in pole order.
+__global__ __launch_bounds__(TPB) void k_shifted_backsub(Work W, ShiftWork SW) {
+  __shared__ int last;
+  const int m = W.m;
+  const int k = W.st[0].kcyc;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int p = blockIdx.x * NWAVE + wid;
+  if (p < SW.K) {
+    const double2* Rp = reinterpret_cast<const double2*>(SW.R) + (int64_t)p * (m + 1) * m;
+    const double2* g = reinterpret_cast<const double2*>(SW.g) + (int64_t)p * (m + 1);
+    double2* y = reinterpret_cast<double2*>(SW.y) + (int64_t)p * m;
+    for (int r = k - 1; r >= 0; --r) {
+      double ax = 0.0, ay = 0.0;
+      for (int q = r + 1 + lane; q < k; q += 64) {
+        const double2 tq = cmul(Rp[(int64_t)q * (m + 1) + r], y[q]);
+        ax += tq.x;
+        ay += tq.y;
+      }
+      ax = wave_sum(ax);
+      ay = wave_sum(ay);
+      if (lane == 0) {
+        const double2 acc = make_double2(g[r].x - ax, g[r].y - ay);
+        const double2 dd = Rp[(int64_t)r * (m + 1) + r];
+        const double dn = dd.x * dd.x + dd.y * dd.y;
+        y[r] = dn > 0.0 ? make_double2((acc.x * dd.x + acc.y * dd.y) / dn, (acc.y * dd.x - acc.x * dd.y) / dn)
+                        : make_double2(0.0, 0.0);
+      }
+      __threadfence_block();
+    }
+  }
+  if (last_tile(SW.flags + 2, gridDim.x)) {
+    for (int i = threadIdx.x; i < k; i += TPB) {
+      double2 zi = make_double2(0.0, 0.0);
+      for (int q = 0; q < SW.K; ++q) {
+        const double2 wq = reinterpret_cast<const double2*>(SW.w)[q];
+        const double2 yq = reinterpret_cast<const double2*>(SW.y)[(int64_t)q * m + i];
+        const double2 tz = cmul(wq, yq);
+        zi.x += tz.x;
+        zi.y += tz.y;
+      }
+      reinterpret_cast<double2*>(SW.z)[i] = zi;
+    }
+  }
+  (void)last;
+}
+
+__global__ __launch_bounds__(TPB) void k_shifted_init(Work W, ShiftWork SW) {
+  const double bn = W.st[0].bnorm;
+  if (threadIdx.x == 0) {
+    SW.flags[0] = 0;
+    SW.flags[1] = 0;
+    SW.beta[0] = 0.0;
+  }
+  for (int p = threadIdx.x; p < SW.K; p += TPB) {
+    double2* g = reinterpret_cast<double2*>(SW.g) + (int64_t)p * (W.m + 1);
+    for (int i = 0; i <= W.m; ++i) g[i] = make_double2(0.0, 0.0);
+    g[0] = make_double2(bn, 0.0);
+    SW.its[p] = bn > 0.0 ? 0 : 1;
+    SW.res[p] = bn > 0.0 ? 1.0 : 0.0;
   }
 }
 
@@ -604,145 +869,6 @@ __global__ __launch_bounds__(TPB) void k_restart(Work W, int cycle) {
   (void)cycle;
 }
 
-
-// ------------------------------------------------------------ shared basis
-// All poles share one Krylov basis: with x0 = 0 every shifted system starts
-// from b, and K_k(H - s I, b) = K_k(H, b). One Arnoldi process on H (system
-// 0 with shift 0) gives H V_k = V_{k+1} Hbar_k, hence (H - s_p) V_k =
-// V_{k+1} (Hbar_k - s_p Itilde); each pole solves its own small least-squares
-// problem min || ||b|| e_1 - (Hbar_k - s_p Itilde) y_p ||, and the step is
-// sum_p w_p V_k y_p = V_k z with z = sum_p w_p y_p.
-struct ShiftWork {
-  int32_t K;
-  const double* s;    // [K] complex shifts
-  const double* w;    // [K] complex weights
-  const double* tol;  // [K] target relative residuals
-  double* R;          // [K][(m+1) m] complex, rotated Hessenberg per pole
-  double* g;          // [K][m+1] complex
-  double* gc;         // [K][m] complex
-  double* gs;         // [K][m] complex
-  double* y;          // [K][m] complex
-  double* z;          // [m] complex, combined coefficients
-  double* res;        // [K] implicit relative residual
-  int32_t* its;       // [K] iteration at which the pole met its target (0: not yet)
-};
-
-__global__ __launch_bounds__(TPB) void k_shifted_init(Work W, ShiftWork SW) {
-  const double bn = W.st[0].bnorm;
-  for (int p = threadIdx.x; p < SW.K; p += TPB) {
-    double2* g = reinterpret_cast<double2*>(SW.g) + (int64_t)p * (W.m + 1);
-    for (int i = 0; i <= W.m; ++i) g[i] = make_double2(0.0, 0.0);
-    g[0] = make_double2(bn, 0.0);
-    SW.its[p] = bn > 0.0 ? 0 : 1;
-    SW.res[p] = bn > 0.0 ? 1.0 : 0.0;
-  }
-}
-
-// One block: h_{j+1,j} = ||u_{j+1}||, then for every pole the Givens update of
-// column j of (Hbar - s_p Itilde). When every pole meets its target (or j + 1
-// = m): back substitution per pole and z = sum_p w_p y_p in fixed pole order.
-__global__ __launch_bounds__(TPB) void k_shifted_givens(Work W, ShiftWork SW, int j) {
-  __shared__ double lds[NWAVE];
-  SysState_t& st = W.st[0];
-  if (st.state != ST_ACTIVE) return;
-  const SysDesc& d = W.sys[0];
-  const int m = W.m;
-  double wn = 0.0;
-  for (int t = threadIdx.x; t < d.ntiles; t += TPB) wn += W.pnorm[d.tile0 + t];
-  wn = block_sum(wn, lds);
-  const double beta = sqrt(wn);
-  const double2* hcol = reinterpret_cast<const double2*>(W.H) + (int64_t)j * (m + 1);
-  const double bn = st.bnorm;
-  double unconv = 0.0;
-  for (int p = threadIdx.x; p < SW.K; p += TPB) {
-    double2* Rp = reinterpret_cast<double2*>(SW.R) + (int64_t)p * (m + 1) * m;
-    double2* col = Rp + (int64_t)j * (m + 1);
-    double2* gcv = reinterpret_cast<double2*>(SW.gc) + (int64_t)p * m;
-    double2* gsv = reinterpret_cast<double2*>(SW.gs) + (int64_t)p * m;
-    double2* g = reinterpret_cast<double2*>(SW.g) + (int64_t)p * (m + 1);
-    const double2 sp = reinterpret_cast<const double2*>(SW.s)[p];
-    for (int i = 0; i <= j; ++i) col[i] = hcol[i];
-    col[j].x -= sp.x;
-    col[j].y -= sp.y;
-    for (int i = 0; i < j; ++i) {
-      const double2 c = gcv[i], sn = gsv[i];
-      const double2 a = col[i], b = col[i + 1];
-      const double2 t1 = cjmul(c, a), t2 = cjmul(sn, b);
-      const double2 u1 = cmul(sn, a), u2 = cmul(c, b);
-      col[i] = make_double2(t1.x + t2.x, t1.y + t2.y);
-      col[i + 1] = make_double2(u2.x - u1.x, u2.y - u1.y);
-    }
-    const double2 a = col[j];
-    const double den = sqrt(a.x * a.x + a.y * a.y + beta * beta);
-    double2 c, sn;
-    if (den > 0.0) {
-      c = make_double2(a.x / den, a.y / den);
-      sn = make_double2(beta / den, 0.0);
-    } else {
-      c = make_double2(1.0, 0.0);
-      sn = make_double2(0.0, 0.0);
-    }
-    gcv[j] = c;
-    gsv[j] = sn;
-    col[j] = make_double2(den, 0.0);
-    const double2 gj = g[j];
-    g[j + 1] = make_double2(-(sn.x * gj.x - sn.y * gj.y), -(sn.x * gj.y + sn.y * gj.x));
-    g[j] = cjmul(c, gj);
-    const double res = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
-    SW.res[p] = bn > 0.0 ? res / bn : 0.0;
-    const bool conv = res <= 0.5 * SW.tol[p] * bn || beta == 0.0 || !(res == res);
-    if (conv) {
-      if (SW.its[p] == 0) SW.its[p] = j + 1;
-    } else {
-      unconv += 1.0;
-    }
-  }
-  unconv = block_sum(unconv, lds);
-  const int k = j + 1;
-  if (unconv == 0.0 || k == m) {
-    for (int p = threadIdx.x; p < SW.K; p += TPB) {
-      const double2* Rp = reinterpret_cast<const double2*>(SW.R) + (int64_t)p * (m + 1) * m;
-      const double2* g = reinterpret_cast<const double2*>(SW.g) + (int64_t)p * (m + 1);
-      double2* y = reinterpret_cast<double2*>(SW.y) + (int64_t)p * m;
-      for (int r = k - 1; r >= 0; --r) {
-        double2 acc = g[r];
-        for (int q = r + 1; q < k; ++q) {
-          const double2 tq = cmul(Rp[(int64_t)q * (m + 1) + r], y[q]);
-          acc.x -= tq.x;
-          acc.y -= tq.y;
-        }
-        const double2 dd = Rp[(int64_t)r * (m + 1) + r];
-        const double dn = dd.x * dd.x + dd.y * dd.y;
-        y[r] = dn > 0.0 ? make_double2((acc.x * dd.x + acc.y * dd.y) / dn, (acc.y * dd.x - acc.x * dd.y) / dn)
-                        : make_double2(0.0, 0.0);
-      }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < k; i += TPB) {
-      double2 zi = make_double2(0.0, 0.0);
-      for (int p = 0; p < SW.K; ++p) {
-        const double2 wp = reinterpret_cast<const double2*>(SW.w)[p];
-        const double2 yp = reinterpret_cast<const double2*>(SW.y)[(int64_t)p * m + i];
-        const double2 tz = cmul(wp, yp);
-        zi.x += tz.x;
-        zi.y += tz.y;
-      }
-      reinterpret_cast<double2*>(SW.z)[i] = zi;
-    }
-    if (threadIdx.x == 0) {
-      st.kcyc = k;
-      st.its = k;
-      st.state = ST_FINISH;
-    }
-  } else if (threadIdx.x == 0) {
-    W.H[(int64_t)j * (m + 1) * 2 + 2 * (j + 1)] = beta;  // h_{j+1,j}
-    W.H[(int64_t)j * (m + 1) * 2 + 2 * (j + 1) + 1] = 0.0;
-    W.cscale[j + 1] = beta > 0.0 ? 1.0 / beta : 0.0;
-    st.kcyc = k;
-    st.its = k;
-    atomicAdd(&W.counters[j], 1);
-  }
-}
 
 // out = sum_{i<k} z_i c_i u_i in FP64 (system 0 of W).
 template <typename T, int PPT>

@@ -102,6 +102,7 @@ struct Work {
   double* part;     // complex partial sums [pbase + slot * ntiles + t]
   double* pnorm;    // real partial sums [tile]
   int32_t* counters;// [max_cycles * (m + 1) + 2]
+  int32_t* tick;    // [S][4] completion tickets of the passes A, B, A', B'
   double* x;        // FP64 solutions [xoff + i]
   void* basis;      // Krylov bases (complex double or float)
   const double* V64;

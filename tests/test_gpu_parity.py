@@ -263,20 +263,40 @@ def test_adjoint_matches_oracle(rexi):
 
 
 # ---------------------------------------------------------------- shared basis
-@pytest.mark.parametrize("name,scale,K,R1,m", [("1d_harmonic", None, 16, 28.0, 200), ("3d_bumps", 12, 64, 180.0, 120),
-                                               ("2d_adjoint", 33, 32, 80.0, 200), ("3d_bumps", 13, 16, 32.0, 120)])
-def test_shifted_solver_fp64(rexi, name, scale, K, R1, m):
+@pytest.mark.parametrize("name,scale,K,R1,m,lz", [("1d_harmonic", None, 16, 28.0, 200, 1),
+                                                  ("1d_harmonic", None, 16, 28.0, 200, 0),
+                                                  ("3d_bumps", 12, 64, 180.0, 120, 1),
+                                                  ("3d_bumps", 12, 64, 180.0, 120, 0),
+                                                  ("2d_adjoint", 33, 32, 80.0, 200, 1),
+                                                  ("3d_bumps", 13, 16, 32.0, 120, 1)])
+def test_shifted_solver_fp64(rexi, name, scale, K, R1, m, lz):
     wl = inputs.workload(name, scale=scale)
     g = wl.grid
     s, b, d = poles(K, R1)
     E = ost.EigStepper(g.n, g.h, wl.V)
     ref, F = _floor(g, wl.V, wl.psi0, s, b, wl.dt, 2, lambda p: E.step(p, s, b, wl.dt))
     out, infos = gpu_steps(g, wl.V, wl.psi0, s, b, wl.dt, 2, solver="shifted", m=m, tol=1e-11,
-                           tol_policy="certified", check_every=2)
+                           tol_policy="certified", check_every=2, lanczos=lz)
     errs = [rel(o, r) for o, r in zip(out, ref)]
-    print("shifted", name, errs, "floor", F, [i["total_iterations"] for i in infos], infos[0]["certified_bound"])
-    assert max(errs) <= max(1e-10, 10 * F)
+    bar = max(1e-10, 10 * F, 3 * iterative_floor(g, wl.V, s, b, wl.dt))
+    print("shifted", name, "lanczos", lz, errs, "floor", F, "bar", bar, [i["total_iterations"] for i in infos],
+          infos[0]["certified_bound"])
+    assert max(errs) <= bar
     assert all(i["not_converged"] == 0 for i in infos)
+
+
+def test_shifted_solver_double_well_within_certificate(rexi):
+    # interior shifts need long Krylov spaces; unrestarted, the shared basis
+    # reaches a looser per-pole target within its 256-vector limit
+    wl = inputs.workload("2d_double_well", scale=40)
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+    ref = ost.DirectStepper(g.n, g.h, wl.V, s, b, wl.dt).step(wl.psi0)
+    out, infos = gpu_steps(g, wl.V, wl.psi0, s, b, wl.dt, 1, solver="shifted", m=256, tol=1e-9)
+    e = rel(out[0], ref)
+    print("shifted double well", e, infos[0]["certified_bound"], infos[0]["total_iterations"])
+    assert infos[0]["not_converged"] == 0
+    assert e <= infos[0]["certified_bound"] + 3 * iterative_floor(g, wl.V, s, b, wl.dt)
 
 
 def test_shifted_full_size_3d_separable(rexi):
