@@ -86,10 +86,12 @@ def main():
     ap.add_argument("--precision", choices=("c64", "c128"), default=None,
                     help="default: c128 for the shared-basis solver, c64 (+FP64 refinement) per pole")
     ap.add_argument("--m", type=int, default=None)
+    ap.add_argument("--capture", action="store_true", help="replay each step as one captured HIP graph")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--scale", type=int, default=None, help="points per axis (default 128)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--no-profile", action="store_true", help="skip the instrumented kernel region")
+    ap.add_argument("--calib-copy", action="store_true", help="end with 3 copies of 256 MiB (counter scaling)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -113,21 +115,24 @@ def main():
     V = torch.from_numpy(wl.V.ravel().copy()).to(dev)
     psi = torch.from_numpy(wl.psi0.ravel().copy()).to(dev)
     out = torch.empty_like(psi)
-    h = rexi.setup(g.n, g.lo, g.hi, V, wl.hbar, wl.mass, wl.dt, sigma, beta,
-                   precision=args.precision, solver=args.solver, tol=args.tol, m=m,
-                   profile=0 if args.no_profile else 1)
-    print(f"# setup done: {g.n} K={wl.K} precision={args.precision}", file=sys.stderr, flush=True)
+    opts = dict(precision=args.precision, solver=args.solver, tol=args.tol, m=m)
+    h = rexi.setup(g.n, g.lo, g.hi, V, wl.hbar, wl.mass, wl.dt, sigma, beta, profile=0,
+                   capture_safe=1 if args.capture else 0, **opts)
+    print(f"# setup done: {g.n} K={wl.K} precision={args.precision} solver={args.solver}",
+          file=sys.stderr, flush=True)
 
-    # warmup (also records the per-step solve statistics)
     cur = psi.clone()
-    info = None
     for _ in range(args.warmup):
-        info = h.step(cur, out, 1, info=True)
+        h.step(cur, out, 1, info=True)
         cur, out = out, cur
+    if args.capture:
+        for _ in range(2):  # record the graphs of both buffer orders
+            h.step(cur, out, 1, info=False)
+            cur, out = out, cur
     torch.cuda.synchronize()
-    h.profile_reset()
     print(f"# warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
 
+    # timed region: whole REXI steps, inputs resident in HBM, no instrumentation
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -137,15 +142,40 @@ def main():
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
     print(f"# timed {args.steps} steps: {ms:.3f} ms/step", file=sys.stderr, flush=True)
-
-    prof = h.profile()
     final_info = h.step(cur, out, 1, info=True)
     torch.cuda.synchronize()
     ws_bytes, m_used = h.workspace()
     h.close()
 
-    roof = None
+    # kernel region: the same steps with HIP events around every kernel launch
+    # (on the launch stream), for per-kernel durations and achieved bandwidth
+    prof = None
+    prof_ms = None
     if not args.no_profile:
+        hp = rexi.setup(g.n, g.lo, g.hi, V, wl.hbar, wl.mass, wl.dt, sigma, beta, profile=1, **opts)
+        cur2 = psi.clone()
+        hp.step(cur2, out, 1, info=False)
+        hp.profile_reset()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(args.steps):
+            hp.step(cur2, out, 1, info=False)
+            cur2, out = out, cur2
+        torch.cuda.synchronize()
+        prof_ms = (time.perf_counter() - t2) * 1e3 / args.steps
+        prof = hp.profile()
+        hp.close()
+        print(f"# kernel region {args.steps} steps: {prof_ms:.3f} ms/step", file=sys.stderr, flush=True)
+    if args.calib_copy:
+        # plain copy of known size, for scaling the HBM byte counters of a profiler run
+        xa = torch.empty(256 * 1024 * 1024 // 8, dtype=torch.complex64, device=dev)
+        ya = torch.empty_like(xa)
+        for _ in range(3):
+            ya.copy_(xa)
+        torch.cuda.synchronize()
+
+    roof = None
+    if prof is not None:
         # dominant kernel class by summed time over the timed region
         cand = {k: v for k, v in prof.items() if v["launches"] > 0 and v["bytes"] > 0}
         dom = max(cand, key=lambda k: cand[k]["ms"])
@@ -156,6 +186,7 @@ def main():
         traffic = load_traffic(dom, args.precision)
         roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
+                    instrumented_ms_per_step=round(prof_ms, 4),
                     avg_launch_ms=round(avg_ms, 5), algorithmic_bytes_per_launch=round(bytes_per_launch),
                     launches=d["launches"],
                     kernels={k: dict(ms=round(v["ms"], 3), launches=v["launches"],
@@ -184,6 +215,7 @@ def main():
                            else "per-pole complex128 GMRES")
                         + f", per-pole rel. residual {args.tol:g}, Krylov dimension <= {m_used}",
             "grid": list(g.n), "poles": wl.K, "precision": args.precision, "solver": args.solver,
+            "graph_replay": bool(args.capture),
         },
         "solve": {
             "iterations_per_step": int(final_info["total_iterations"]),

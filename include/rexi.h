@@ -32,7 +32,10 @@
  *   - stream is a hipStream_t (NULL = the default stream). Calls enqueue work
  *     on it; rexi_step and rexi_step_adjoint synchronise it (they read the
  *     device-side convergence counters) unless the handle was set up with
- *     capture_safe = 1 and info == NULL.
+ *     capture_safe = 1 and info == NULL, in which case rexi_step is
+ *     asynchronous and enqueues no host reads. A pole that misses its target
+ *     within that fixed schedule leaves its best iterate in the sum;
+ *     rexi_step with info reports convergence.
  *   - Every call returns a rexi_status and never aborts or throws. After an
  *     error, rexi_last_error() holds a message. Handles are not thread-safe.
  */
@@ -108,7 +111,13 @@ typedef struct {
                           three-term (Lanczos) recurrence with partial
                           reorthogonalisation; 0 full Arnoldi + DGKS         */
   int32_t capture_safe;/* 1: rexi_step(info = NULL) runs a fixed schedule
-                          with no host reads, so it can be graph-captured    */
+                          with no host reads (all m iterations; per-pole:
+                          capture_cycles cycles), finished poles skipped on
+                          the device. Captured once per (psi_in, psi_out,
+                          nsteps) into a HIP graph that is replayed on the
+                          stream; if the stream is itself being captured,
+                          the schedule is enqueued into the caller's graph  */
+  int32_t capture_cycles; /* per-pole solver, capture_safe: cycles, 4       */
   int32_t profile;     /* 1: time kernel classes with HIP events             */
   int32_t tile;        /* points per work tile (0 = tuned default)           */
   int32_t grid_blocks; /* workgroups of the grid-stride kernels (0 = tuned)  */

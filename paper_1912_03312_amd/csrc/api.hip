@@ -89,6 +89,16 @@ struct rexi_handle {
   rexi::ShiftWork noshift{};          // K = 0: per-pole Givens in pass B
   std::vector<DevBuf> sbufs;
   int32_t* hpin = nullptr;            // pinned counters read-back
+  // capture-safe steps: no host reads, fixed schedule (set while launching one)
+  bool syncfree = false;
+  hipStream_t cap_stream = nullptr;   // internal stream for graph capture
+  struct GraphEntry {
+    const void* in;
+    void* out;
+    int nsteps;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
   double* dnorm = nullptr;            // scratch partials for norms
   std::string err;
   Prof prof;
@@ -135,6 +145,8 @@ void destroy_handle(rexi_handle* h) {
   if (h->V32) (void)hipFree(h->V32);
   if (h->dnorm) (void)hipFree(h->dnorm);
   if (h->hpin) (void)hipHostFree(h->hpin);
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (auto& e : h->prof.ev) (void)hipEventDestroy(e);
   delete h;
 }
@@ -146,7 +158,7 @@ struct Timed {
   hipStream_t st;
   Timed(rexi_handle* hh, int cls, double bytes, hipStream_t s) : h(hh), st(s) {
     Prof& P = h->prof;
-    if (!P.on) return;
+    if (!P.on || h->syncfree) return;
     if (P.used + 2 > P.ev.size()) {
       for (int i = 0; i < 256; ++i) {
         hipEvent_t e;
@@ -356,6 +368,7 @@ rexi_status run_solve(rexi_handle* h, Solver& sv, const double2* r0, const doubl
         }
       }
       HIPCHK(h, hipGetLastError());
+      if (h->syncfree) continue;  // fixed schedule: finished systems skip on the device
       HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + c * (m + 1) + j, sizeof(int32_t), hipMemcpyDeviceToHost,
                                stream));
       HIPCHK(h, hipStreamSynchronize(stream));
@@ -376,6 +389,10 @@ rexi_status run_solve(rexi_handle* h, Solver& sv, const double2* r0, const doubl
       hipLaunchKernelGGL(rexi::k_restart, dim3(S), dim3(TPB), 0, stream, W, c);
     }
     HIPCHK(h, hipGetLastError());
+    if (h->syncfree) {
+      if (c + 1 >= std::max(1, h->opt.capture_cycles)) break;
+      continue;
+    }
     // restarted count of this cycle: counters[max_cycles*(m+1)] accumulates; read the total
     HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + sv.max_cycles * (m + 1), 2 * sizeof(int32_t),
                              hipMemcpyDeviceToHost, stream));
@@ -526,9 +543,12 @@ rexi_status init_shifted(rexi_handle* h, hipStream_t stream) {
       (st = al(&S.omega, 2 * (m + 1))))
     return st;
   double* flags = nullptr;
-  if ((st = al(&flags, 2))) return st;
+  double* full = nullptr;
+  if ((st = al(&flags, 2)) || (st = al(&full, (m + 1) / 2 + 1))) return st;
   S.flags = reinterpret_cast<int32_t*>(flags);
+  S.full = reinterpret_cast<int32_t*>(full);
   HIPCHK(h, hipMemsetAsync(flags, 0, 2 * sizeof(double), stream));
+  HIPCHK(h, hipMemsetAsync(full, 0, ((m + 1) / 2 + 1) * sizeof(double), stream));
   S.lanczos = h->opt.lanczos ? 1 : 0;
   S.eps1 = std::sqrt((double)h->fwd.hsys[0].n) * 1.1102230246251565e-16;
   if (S.lanczos) {
@@ -575,6 +595,9 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
   // iterations after convergence return at once (device-side state)
   const int chunk = std::max(1, h->opt.check_every);
   const bool lz = h->SW.lanczos != 0;
+  // second Gram-Schmidt passes are rare with the Lanczos estimate: a quarter
+  // of the grid keeps their (mostly empty) launches short
+  const int G2 = lz ? std::max(1, G / 4) : G;
   for (int j = 0; j < m; ++j) {
     // Lanczos: project on v_{j-1}, v_j only (H is Hermitian); Arnoldi: on all
     const int i0 = lz ? std::max(0, j - 1) : 0;
@@ -598,7 +621,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
     if (sv.reorth || lz) {
       {
         Timed t(h, PC_REORTH_A, 0, stream);
-        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(G), dim3(TPB), 0, stream, W, j, 0);
+        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(G2), dim3(TPB), 0, stream, W, j, 0);
       }
       {
         Timed t(h, PC_REDUCE, 0, stream);
@@ -606,7 +629,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
       }
       {
         Timed t(h, PC_REORTH_B, 0, stream);
-        hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, j, 1, 0);
+        hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G2), dim3(TPB), 0, stream, W, j, 1, 0);
       }
       {
         Timed t(h, PC_REDUCE, 0, stream);
@@ -614,7 +637,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
       }
     }
     HIPCHK(h, hipGetLastError());
-    if ((j + 1) % chunk == 0 || j + 1 == m) {
+    if (!h->syncfree && ((j + 1) % chunk == 0 || j + 1 == m)) {
       HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + j, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
       HIPCHK(h, hipStreamSynchronize(stream));
       if (h->hpin[0] == 0) break;
@@ -883,6 +906,7 @@ void rexi_default_options(rexi_options* o) {
   o->inner_rtol = 1e-5;
   o->check_every = 4;
   o->lanczos = 1;
+  o->capture_cycles = 4;
   o->capture_safe = 0;
   o->profile = 0;
   o->tile = 0;
@@ -925,6 +949,46 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
   if (!psi_in || !psi_out) return fail(h, REXI_E_INVALID_ARG, "NULL vector");
   if (nsteps < 1) return fail(h, REXI_E_INVALID_ARG, "nsteps must be >= 1");
   hipStream_t st = (hipStream_t)stream;
+  if (h->opt.capture_safe && !info && !h->syncfree) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHK(h, hipStreamIsCapturing(st, &cs));
+    if (cs == hipStreamCaptureStatusActive) {
+      // the caller is capturing: enqueue the fixed, read-free schedule into it
+      h->syncfree = true;
+      rexi_status r = rexi_step(h, psi_in, psi_out, nsteps, nullptr, stream);
+      h->syncfree = false;
+      return r;
+    }
+    // replay (or first capture) of a graph of the whole call on the caller's stream
+    for (auto& g : h->graphs)
+      if (g.in == psi_in && g.out == psi_out && g.nsteps == nsteps) {
+        HIPCHK(h, hipGraphLaunch(g.exec, st));
+        return REXI_OK;
+      }
+    if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    h->syncfree = true;
+    rexi_status r = rexi_step(h, psi_in, psi_out, nsteps, nullptr, h->cap_stream);
+    h->syncfree = false;
+    hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
+    if (r != REXI_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return r;
+    }
+    if (ec != hipSuccess) return fail(h, REXI_E_HIP, "stream capture failed: %s", hipGetErrorString(ec));
+    hipGraphExec_t exec = nullptr;
+    hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return fail(h, REXI_E_HIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+    if (h->graphs.size() >= 4) {
+      (void)hipGraphExecDestroy(h->graphs.front().exec);
+      h->graphs.erase(h->graphs.begin());
+    }
+    h->graphs.push_back({psi_in, psi_out, nsteps, exec});
+    HIPCHK(h, hipGraphLaunch(exec, st));
+    return REXI_OK;
+  }
   Solver& sv = h->fwd;
   const double2* in = (const double2*)psi_in;
   double2* outp = (double2*)psi_out;
@@ -968,7 +1032,7 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
           info->norm_out = no;
         }
       }
-      prof_collect(h, st);
+      if (!h->syncfree) prof_collect(h, st);
       continue;
     }
     rexi_status s1 = solve(h, sv, src, src, st, &restarts);
@@ -1010,7 +1074,7 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
         info->norm_out = no;
       }
     }
-    prof_collect(h, st);
+    if (!h->syncfree) prof_collect(h, st);
   }
   if (info) {
     info->steps = nsteps;

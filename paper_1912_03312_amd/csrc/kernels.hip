@@ -253,6 +253,7 @@ struct ShiftWork {
   double* omega;      // [2][m+1] estimated <v_{j}, v_k>, <v_{j+1}, v_k> (rolling)
   int32_t* flags;     // [0]: reorthogonalise the next vector too; [1]: passes done;
                       // [2]: back-substitution ticket
+  int32_t* full;      // [m] 1 if column j of Hbar has entries above row j - 1
   double eps1;        // local orthogonality level sqrt(n) u
 };
 
@@ -486,21 +487,37 @@ __device__ void givens_per_pole(Work& W, int s, int j, int cycle, double beta) {
 // v_{j+1} (and then v_{j+2}) get a full Gram-Schmidt pass against all earlier
 // vectors, and the estimates of a reorthogonalised vector reset to eps1.
 __device__ bool pro_decide(Work& W, ShiftWork& SW, int j, double bj1) {
+  // block-level: the estimates of row j+1 are independent across k
+  __shared__ double lds[NWAVE];
+  __shared__ int reo_sh;
   const int m = W.m;
   const double u = 1.1102230246251565e-16;
-  const double2 hjj = reinterpret_cast<const double2*>(W.H)[(int64_t)j * (m + 1) + j];
-  SW.alpha[j] = hjj.x;
-  SW.beta[j + 1] = bj1;
   double* wprev = SW.omega + (int64_t)((j + 1) & 1) * (m + 1);  // row j-1, becomes row j+1
   double* wcur = SW.omega + (int64_t)(j & 1) * (m + 1);         // row j
-  const int force = SW.flags[0];
-  if (j == 0) wcur[0] = 1.0;
+  if (threadIdx.x == 0) {
+    const double2 hjj = reinterpret_cast<const double2*>(W.H)[(int64_t)j * (m + 1) + j];
+    SW.alpha[j] = hjj.x;
+    SW.beta[j + 1] = bj1;
+    if (j == 0) wcur[0] = 1.0;
+  }
+  __syncthreads();
+  double an = 0.0;
+  for (int k = threadIdx.x; k <= j; k += TPB) an = fmax(an, fabs(SW.alpha[k]) + SW.beta[k] + SW.beta[k + 1]);
+  // block max via the sum of a one-hot: reuse block_sum on squared maxima is
+  // not exact, so take the max through LDS
+  __shared__ double mx[NWAVE];
+  for (int o = 32; o >= 1; o >>= 1) an = fmax(an, __shfl_xor(an, o, 64));
+  if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = an;
+  __syncthreads();
+  double anorm = 0.0;
+#pragma unroll
+  for (int q = 0; q < NWAVE; ++q) anorm = fmax(anorm, mx[q]);
   const double bj = SW.beta[j];
   const double aj = SW.alpha[j];
-  double anorm = 0.0;
-  for (int k = 0; k <= j; ++k) anorm = fmax(anorm, fabs(SW.alpha[k]) + SW.beta[k] + SW.beta[k + 1]);
   double worst = 0.0;
-  for (int k = 0; k < j; ++k) {
+  double vals[4];
+  int cnt = 0;
+  for (int k = threadIdx.x; k < j; k += TPB) {
     const double wkp1 = wcur[k + 1];
     const double wk = wcur[k];
     const double wkm1 = k > 0 ? wcur[k - 1] : 0.0;
@@ -508,17 +525,35 @@ __device__ bool pro_decide(Work& W, ShiftWork& SW, int j, double bj1) {
     double v = SW.beta[k + 1] * wkp1 + (SW.alpha[k] - aj) * wk + (k > 0 ? SW.beta[k] * wkm1 : 0.0) - bj * wold;
     v += copysign(2.0 * u * anorm, v);
     v = bj1 > 0.0 ? v / bj1 : 1.0;
-    wprev[k] = v;
+    vals[cnt++ & 3] = v;
     worst = fmax(worst, fabs(v));
   }
-  wprev[j] = SW.eps1;
-  wprev[j + 1] = 1.0;
-  const bool reo = force || worst > sqrt(u);
-  if (reo) {
-    for (int k = 0; k <= j; ++k) wprev[k] = SW.eps1;
-    SW.flags[0] = force ? 0 : 1;  // the next vector gets a pass as well
-    SW.flags[1] += 1;
+  __syncthreads();  // every read of row j-1 precedes the writes of row j+1
+  cnt = 0;
+  for (int k = threadIdx.x; k < j; k += TPB) wprev[k] = vals[cnt++ & 3];
+  for (int o = 32; o >= 1; o >>= 1) worst = fmax(worst, __shfl_xor(worst, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = worst;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double wmax = 0.0;
+#pragma unroll
+    for (int q = 0; q < NWAVE; ++q) wmax = fmax(wmax, mx[q]);
+    wprev[j] = SW.eps1;
+    wprev[j + 1] = 1.0;
+    const int force = SW.flags[0];
+    const bool reo = force || wmax > sqrt(u);
+    if (reo) {
+      SW.flags[0] = force ? 0 : 1;  // the next vector gets a pass as well
+      SW.flags[1] += 1;
+    }
+    reo_sh = reo ? 1 : 0;
   }
+  __syncthreads();
+  const bool reo = reo_sh != 0;
+  if (reo)
+    for (int k = threadIdx.x; k <= j; k += TPB) wprev[k] = SW.eps1;
+  (void)lds;
   return reo;
 }
 
@@ -541,7 +576,7 @@ __device__ void givens_shifted(Work& W, ShiftWork& SW, int j, double beta, bool 
     double2* gsv = reinterpret_cast<double2*>(SW.gs) + (int64_t)p * m;
     double2* g = reinterpret_cast<double2*>(SW.g) + (int64_t)p * (m + 1);
     const double2 sp = reinterpret_cast<const double2*>(SW.s)[p];
-    for (int i = 0; i <= j; ++i) col[i] = hcol[i];
+    for (int i = i_start; i <= j; ++i) col[i] = hcol[i];
     col[j].x -= sp.x;
     col[j].y -= sp.y;
     for (int i = i_start; i < j; ++i) {
@@ -580,6 +615,7 @@ __device__ void givens_shifted(Work& W, ShiftWork& SW, int j, double beta, bool 
   unconv = block_sum(unconv, lds);
   if (threadIdx.x == 0) {
     const int k = j + 1;
+    SW.full[j] = banded ? 0 : 1;
     W.H[(int64_t)j * (m + 1) * 2 + 2 * (j + 1)] = beta;  // h_{j+1,j}
     W.H[(int64_t)j * (m + 1) * 2 + 2 * (j + 1) + 1] = 0.0;
     W.cscale[j + 1] = beta > 0.0 ? 1.0 / beta : 0.0;
@@ -676,13 +712,14 @@ __global__ __launch_bounds__(TPB) void k_end_iter(Work W, ShiftWork SW, int j, i
   for (int tt = threadIdx.x; tt < d.ntiles; tt += TPB) bsq += W.pnorm[d.tile0 + tt];
   bsq = block_sum(bsq, lds);
   const double beta = sqrt(bsq);
-  if (threadIdx.x == 0) {
-    int reo = second ? 0 : st.reorth;
-    if (!second && SW.K > 0 && SW.lanczos) {
-      reo = pro_decide(W, SW, j, beta) ? 1 : 0;
-      st.reorth = reo;
+  if (!second && SW.K > 0 && SW.lanczos) {
+    const bool reo = pro_decide(W, SW, j, beta);
+    if (threadIdx.x == 0) {
+      st.reorth = reo ? 1 : 0;
+      reo_sh = reo ? 1 : 0;
     }
-    reo_sh = reo;
+  } else if (threadIdx.x == 0) {
+    reo_sh = second ? 0 : st.reorth;
   }
   __syncthreads();
   if (reo_sh) return;
@@ -709,6 +746,8 @@ __global__ __launch_bounds__(TPB) void k_shifted_backsub(Work W, ShiftWork SW) {
     for (int r = k - 1; r >= 0; --r) {
       double ax = 0.0, ay = 0.0;
       for (int q = r + 1 + lane; q < k; q += 64) {
+        // a banded column q holds R entries in rows q-2..q only
+        if (q > r + 2 && !SW.full[q]) continue;
         const double2 tq = cmul(Rp[(int64_t)q * (m + 1) + r], y[q]);
         ax += tq.x;
         ay += tq.y;

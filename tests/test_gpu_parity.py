@@ -338,3 +338,68 @@ def test_shifted_matches_per_pole_on_bench_workload(rexi):
     diff = rel(a.cpu().numpy(), c.cpu().numpy())
     print("shifted vs per-pole (128^3 bumps)", diff, i1["total_iterations"], i2["total_iterations"])
     assert diff <= i1["certified_bound"] + i2["certified_bound"] + 10 * d["amplification"] * EPS
+
+
+# ---------------------------------------------------------------- graph capture
+@pytest.mark.parametrize("solver,prec", [("shifted", "c128"), ("per_pole", "c64"), ("per_pole", "c128")])
+def test_graph_replays_match_eager(rexi, solver, prec):
+    # a capture-safe step is recorded once into a HIP graph and replayed; every
+    # replay, with eager work and synchronisation in between, must equal the
+    # eager step with host-side convergence checks
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    wl = inputs.workload("3d_bumps", scale=20)
+    g = wl.grid
+    s, b, d = poles(32, 80.0)
+    Vd = to_dev(wl.V.ravel())
+    kw = dict(solver=solver, precision=prec, tol=1e-10, m=100 if solver == "shifted" else 30)
+    he = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, wl.dt, s, b, **kw)
+    hg = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, wl.dt, s, b, capture_safe=1, capture_cycles=6, **kw)
+    p0 = to_dev(wl.psi0.ravel())
+    ref = torch.empty_like(p0)
+    he.step(p0, ref, 1)
+    out = torch.empty_like(p0)
+    for rep in range(4):
+        out.zero_()
+        hg.step(p0, out, 1, info=False)       # first call captures, later calls replay
+        junk = torch.randn(1000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        e = rel(out.cpu().numpy(), ref.cpu().numpy())
+        assert e <= 1e-13, (rep, e)
+    # the same handle also steps eagerly with info (host checks) and agrees
+    i2 = hg.step(p0, out, 1)
+    assert rel(out.cpu().numpy(), ref.cpu().numpy()) <= 1e-13 and i2["not_converged"] == 0
+    he.close()
+    hg.close()
+
+
+def test_step_inside_caller_graph_capture(rexi):
+    # the caller captures rexi_step into its own torch CUDA graph
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    wl = inputs.workload("2d_adjoint", scale=48)
+    g = wl.grid
+    s, b, d = poles(16, 32.0)
+    Vd = to_dev(wl.V.ravel())
+    h = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, wl.dt, s, b, solver="shifted", m=80, tol=1e-11, capture_safe=1)
+    he = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, wl.dt, s, b, solver="shifted", m=80, tol=1e-11)
+    p0 = to_dev(wl.psi0.ravel())
+    ref = torch.empty_like(p0)
+    he.step(p0, ref, 1)
+    src = p0.clone()
+    dst = torch.empty_like(p0)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            h.step(src, dst, 1, info=False)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        dst.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert rel(dst.cpu().numpy(), ref.cpu().numpy()) <= 1e-13, rep
+    h.close()
+    he.close()
