@@ -77,6 +77,74 @@ def cpu_baseline(wl, sigma, beta, seconds_cap: float = 25.0):
                        f"scipy sparse matvec, single thread")
 
 
+def bench_batch(args):
+    """The uneven-size batch: independent 2D instances of sides 64..512, each
+    with its own potential, packet, dt in U(0.2, 1) and K in {16, 24, 32, 48},
+    all stepped by one handle."""
+    import numpy as np
+    import torch
+
+    from paper_1912_03312_amd import inputs, rexi
+    from paper_1912_03312_amd.poles import faber_cf_poles
+
+    t0 = time.perf_counter()
+    insts = inputs.batch_instances(count=args.batch_count)
+    print(f"# {len(insts)} instances built in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    cache = {}
+    grids, Vs, psis, dts, Ks, sig, bet = [], [], [], [], [], [], []
+    for it in insts:
+        K = it["K"]
+        if K not in cache:
+            cache[K] = faber_cf_poles(K, inputs.R1_PARITY[K])
+        s, b, _ = cache[K]
+        g = it["grid"]
+        grids.append((g.n, g.lo, g.hi))
+        Vs.append(it["V"].ravel())
+        psis.append(it["psi0"].ravel())
+        dts.append(it["dt"])
+        Ks.append(K)
+        sig.append(s)
+        bet.append(b)
+    dev = torch.device("cuda:0")
+    V = torch.from_numpy(np.concatenate(Vs)).to(dev)
+    psi = torch.from_numpy(np.concatenate(psis)).to(dev)
+    out = torch.empty_like(psi)
+    cnt = len(insts)
+    m = args.m or (256 if args.solver == "shifted" else 30)
+    h = rexi.setup_batch(grids, V, [1.0] * cnt, [1.0] * cnt, dts, Ks, np.concatenate(sig), np.concatenate(bet),
+                         solver=args.solver, precision=args.precision, tol=args.tol, m=m,
+                         capture_safe=1 if args.capture else 0, max_cycles=200)
+    cur = psi.clone()
+    info = None
+    for _ in range(args.warmup):
+        info = h.step(cur, out, 1, info=True, raise_on_nc=False)
+        cur, out = out, cur
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        h.step(cur, out, 1, info=False)
+        cur, out = out, cur
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / args.steps
+    info = h.step(cur, out, 1, info=True, raise_on_nc=False)
+    ws, m_used = h.workspace()
+    h.close()
+    npts = int(sum(int(np.prod(g[0])) for g in grids))
+    res = {
+        "metric": "REXI batch steps/sec, uneven 2D batch", "value": round(1e3 / ms, 4), "unit": "steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64+f64" if args.precision == "c64" else "c128", "data": "synthetic",
+        "config": {"workload": f"{cnt} 2D instances, sides 64..512 on [-10,10]^2, 20 bumps each, "
+                               f"dt U(0.2,1), K in {{16,24,32,48}}, {args.solver} solver, tol {args.tol:g}",
+                   "instances": cnt, "points": npts, "poles": int(sum(Ks)), "solver": args.solver,
+                   "graph_replay": bool(args.capture)},
+        "solve": {"iterations_per_step": int(info["total_iterations"]), "not_converged": int(info["not_converged"]),
+                  "max_rel_residual": info["max_rel_residual"], "workspace_GB": round(ws / 1e9, 2), "m": m_used},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +155,9 @@ def main():
                     help="default: c128 for the shared-basis solver, c64 (+FP64 refinement) per pole")
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--capture", action="store_true", help="replay each step as one captured HIP graph")
+    ap.add_argument("--workload", choices=("3d", "batch"), default="3d",
+                    help="3d: the 128^3 64-pole step (default); batch: the uneven 2D batch")
+    ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--scale", type=int, default=None, help="points per axis (default 128)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -107,6 +178,8 @@ def main():
 
     if args.precision is None:
         args.precision = "c128" if args.solver == "shifted" else "c64"
+    if args.workload == "batch":
+        return bench_batch(args)
     wl = inputs.workload("3d_bumps", scale=args.scale)
     m = args.m or (100 if args.solver == "shifted" else wl.m)
     g = wl.grid

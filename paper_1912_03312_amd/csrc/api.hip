@@ -514,16 +514,18 @@ rexi_status init_solver(rexi_handle* h, Solver& sv, int copies, hipStream_t stre
 }
 
 
-// Shared-basis solver: the Arnoldi system plus per-pole Givens data.
+// Shared-basis solver: one Krylov system per instance plus per-pole Givens data.
 rexi_status init_shifted(rexi_handle* h, hipStream_t stream) {
   rexi_status st = init_solver(h, h->fwd, 0, stream);
   if (st != REXI_OK) return st;
-  const int K = h->Kinst[0], m = h->fwd.m;
-  rexi::ShiftWork& S = h->SW;
-  S.K = K;
-  auto al = [&](double** p, size_t count) -> rexi_status {
+  const int S = h->ninst, m = h->fwd.m;
+  int K = 0;
+  for (int i = 0; i < S; ++i) K += h->Kinst[i];
+  rexi::ShiftWork& SW = h->SW;
+  SW.K = K;
+  auto al = [&](void** p, size_t bytes) -> rexi_status {
     DevBuf b;
-    b.bytes = std::max<size_t>(count * sizeof(double), 256);
+    b.bytes = std::max<size_t>(bytes, 256);
     hipError_t e = hipMalloc(&b.p, b.bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -531,35 +533,53 @@ rexi_status init_shifted(rexi_handle* h, hipStream_t stream) {
     }
     h->sbufs.push_back(b);
     h->ws_bytes += (int64_t)b.bytes;
-    *p = reinterpret_cast<double*>(b.p);
+    *p = b.p;
     return REXI_OK;
   };
-  double *s = nullptr, *w = nullptr, *tol = nullptr, *its = nullptr;
-  if ((st = al(&s, 2 * K)) || (st = al(&w, 2 * K)) || (st = al(&tol, K)) ||
-      (st = al(&S.R, (size_t)K * (m + 1) * m * 2)) || (st = al(&S.g, (size_t)K * (m + 1) * 2)) ||
-      (st = al(&S.gc, (size_t)K * m * 2)) || (st = al(&S.gs, (size_t)K * m * 2)) ||
-      (st = al(&S.y, (size_t)K * m * 2)) || (st = al(&S.z, (size_t)m * 2)) || (st = al(&S.res, K)) ||
-      (st = al(&its, K)) || (st = al(&S.alpha, m)) || (st = al(&S.beta, m + 1)) ||
-      (st = al(&S.omega, 2 * (m + 1))))
+  const size_t c16 = 16, d8 = 8, i4 = 4;
+  void *s = nullptr, *w = nullptr, *tol = nullptr, *its = nullptr, *pole0 = nullptr, *pinst = nullptr;
+  void *R = nullptr, *g = nullptr, *gc = nullptr, *gs = nullptr, *y = nullptr, *z = nullptr, *res = nullptr;
+  void *alpha = nullptr, *beta = nullptr, *omega = nullptr, *flags = nullptr, *full = nullptr;
+  if ((st = al(&s, K * c16)) || (st = al(&w, K * c16)) || (st = al(&tol, K * d8)) || (st = al(&its, K * i4)) ||
+      (st = al(&pole0, (S + 1) * i4)) || (st = al(&pinst, K * i4)) ||
+      (st = al(&R, (size_t)K * (m + 1) * m * c16)) || (st = al(&g, (size_t)K * (m + 1) * c16)) ||
+      (st = al(&gc, (size_t)K * m * c16)) || (st = al(&gs, (size_t)K * m * c16)) ||
+      (st = al(&y, (size_t)K * m * c16)) || (st = al(&z, (size_t)S * m * c16)) || (st = al(&res, K * d8)) ||
+      (st = al(&alpha, (size_t)S * m * d8)) || (st = al(&beta, (size_t)S * (m + 1) * d8)) ||
+      (st = al(&omega, (size_t)S * 2 * (m + 1) * d8)) || (st = al(&flags, (size_t)S * 4 * i4)) ||
+      (st = al(&full, (size_t)S * m * i4)))
     return st;
-  double* flags = nullptr;
-  double* full = nullptr;
-  if ((st = al(&flags, 2)) || (st = al(&full, (m + 1) / 2 + 1))) return st;
-  S.flags = reinterpret_cast<int32_t*>(flags);
-  S.full = reinterpret_cast<int32_t*>(full);
-  HIPCHK(h, hipMemsetAsync(flags, 0, 2 * sizeof(double), stream));
-  HIPCHK(h, hipMemsetAsync(full, 0, ((m + 1) / 2 + 1) * sizeof(double), stream));
-  S.lanczos = h->opt.lanczos ? 1 : 0;
-  S.eps1 = std::sqrt((double)h->fwd.hsys[0].n) * 1.1102230246251565e-16;
-  if (S.lanczos) {
-    // the recurrence decides the second passes; the DGKS test is off
+  SW.s = (const double*)s;
+  SW.w = (const double*)w;
+  SW.tol = (const double*)tol;
+  SW.its = (int32_t*)its;
+  SW.pole0 = (const int32_t*)pole0;
+  SW.pinst = (const int32_t*)pinst;
+  SW.R = (double*)R;
+  SW.g = (double*)g;
+  SW.gc = (double*)gc;
+  SW.gs = (double*)gs;
+  SW.y = (double*)y;
+  SW.z = (double*)z;
+  SW.res = (double*)res;
+  SW.alpha = (double*)alpha;
+  SW.beta = (double*)beta;
+  SW.omega = (double*)omega;
+  SW.flags = (int32_t*)flags;
+  SW.full = (int32_t*)full;
+  SW.lanczos = h->opt.lanczos ? 1 : 0;
+  if (SW.lanczos) {
+    // the orthogonality estimate decides the second passes; the DGKS test is off
     h->fwd.W.reorth_mode = 3;
   }
-  S.s = s;
-  S.w = w;
-  S.tol = tol;
-  S.its = reinterpret_cast<int32_t*>(its);
   std::vector<double> hs(2 * K), hw(2 * K), ht(K);
+  std::vector<int32_t> hp0(S + 1), hpi(K);
+  int q = 0;
+  for (int i = 0; i < S; ++i) {
+    hp0[i] = q;
+    for (int k = 0; k < h->Kinst[i]; ++k, ++q) hpi[q] = i;
+  }
+  hp0[S] = q;
   for (int k = 0; k < K; ++k) {
     hs[2 * k] = h->s[k].real();
     hs[2 * k + 1] = h->s[k].imag();
@@ -570,26 +590,32 @@ rexi_status init_shifted(rexi_handle* h, hipStream_t stream) {
   HIPCHK(h, hipMemcpyAsync(s, hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice, stream));
   HIPCHK(h, hipMemcpyAsync(w, hw.data(), hw.size() * sizeof(double), hipMemcpyHostToDevice, stream));
   HIPCHK(h, hipMemcpyAsync(tol, ht.data(), ht.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  HIPCHK(h, hipMemcpyAsync(pole0, hp0.data(), hp0.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  HIPCHK(h, hipMemcpyAsync(pinst, hpi.data(), hpi.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  HIPCHK(h, hipMemsetAsync(flags, 0, (size_t)S * 4 * i4, stream));
+  HIPCHK(h, hipMemsetAsync(full, 0, (size_t)S * m * i4, stream));
   HIPCHK(h, hipStreamSynchronize(stream));
   return REXI_OK;
 }
 
-// One shared-basis solve of all poles of instance 0; writes the pole sum to out.
+// One shared-basis solve of all poles of every instance; writes the pole sums to out.
 template <typename T, int PPT>
 rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStream_t stream) {
   Solver& sv = h->fwd;
   Work& W = sv.W;
   const int G = sv.grid, m = sv.m;
   const double e = sizeof(T);
-  const double n = sv.hsys[0].n;
+  const int S = sv.S;
+  double n = 0.0;  // points over all instances (byte counts assume all active)
+  for (auto& d : sv.hsys) n += d.n;
   {
     Timed t(h, PC_START, n * (16.0 + e), stream);
     hipLaunchKernelGGL((rexi::k_start<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, b, b);
   }
   {
     Timed t(h, PC_REDUCE, 0, stream);
-    hipLaunchKernelGGL(rexi::k_start_reduce, dim3(1), dim3(TPB), 0, stream, W);
-    hipLaunchKernelGGL(rexi::k_shifted_init, dim3(1), dim3(TPB), 0, stream, W, h->SW);
+    hipLaunchKernelGGL(rexi::k_start_reduce, dim3(S), dim3(TPB), 0, stream, W);
+    hipLaunchKernelGGL(rexi::k_shifted_init, dim3(S), dim3(TPB), 0, stream, W, h->SW);
   }
   // iterations run in chunks between host reads of the convergence counter;
   // iterations after convergence return at once (device-side state)
@@ -608,7 +634,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
     }
     {
       Timed t(h, PC_REDUCE, 0, stream);
-      hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(1, j + 2), dim3(TPB), 0, stream, W, j, 0, i0);
+      hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, stream, W, j, 0, i0);
     }
     {
       Timed t(h, PC_ARNOLDI_B, n * (nproj + 2) * e, stream);
@@ -616,7 +642,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
     }
     {
       Timed t(h, PC_REDUCE, 0, stream);
-      hipLaunchKernelGGL(rexi::k_end_iter, dim3(1), dim3(TPB), 0, stream, W, h->SW, j, 0, 0);
+      hipLaunchKernelGGL(rexi::k_end_iter, dim3(S), dim3(TPB), 0, stream, W, h->SW, j, 0, 0);
     }
     if (sv.reorth || lz) {
       {
@@ -625,7 +651,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
       }
       {
         Timed t(h, PC_REDUCE, 0, stream);
-        hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(1, j + 2), dim3(TPB), 0, stream, W, j, 1, 0);
+        hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, stream, W, j, 1, 0);
       }
       {
         Timed t(h, PC_REORTH_B, 0, stream);
@@ -633,7 +659,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
       }
       {
         Timed t(h, PC_REDUCE, 0, stream);
-        hipLaunchKernelGGL(rexi::k_end_iter, dim3(1), dim3(TPB), 0, stream, W, h->SW, j, 1, 0);
+        hipLaunchKernelGGL(rexi::k_end_iter, dim3(S), dim3(TPB), 0, stream, W, h->SW, j, 1, 0);
       }
     }
     HIPCHK(h, hipGetLastError());
@@ -647,6 +673,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
     Timed t(h, PC_REDUCE, 0, stream);
     hipLaunchKernelGGL(rexi::k_shifted_backsub, dim3((h->SW.K + rexi::NWAVE - 1) / rexi::NWAVE), dim3(TPB), 0,
                        stream, W, h->SW);
+    hipLaunchKernelGGL(rexi::k_shifted_z, dim3(S), dim3(TPB), 0, stream, W, h->SW);
   }
   {
     Timed t(h, PC_POLESUM, 0, stream);
@@ -709,8 +736,6 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
     return fail(nullptr, REXI_E_INVALID_ARG, "unknown solver %d", o.solver);
   if (o.solver == REXI_SOLVER_SHIFTED && o.precision != REXI_PREC_C128)
     return fail(nullptr, REXI_E_INVALID_ARG, "the shared-basis solver runs in complex128 only");
-  if (o.solver == REXI_SOLVER_SHIFTED && count != 1)
-    return fail(nullptr, REXI_E_INVALID_ARG, "the shared-basis solver takes a single instance");
   if (o.m < 1 || o.m > 256) return fail(nullptr, REXI_E_INVALID_ARG, "m must be in [1, 256] (got %d)", o.m);
   if (!(o.reorth_eta > 0.0 && o.reorth_eta < 1.0)) return fail(nullptr, REXI_E_INVALID_ARG, "reorth_eta in (0, 1)");
   if (o.max_cycles < 1 || o.max_cycles > 1000) return fail(nullptr, REXI_E_INVALID_ARG, "max_cycles out of range");
@@ -1004,12 +1029,17 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
         const int K = h->SW.K;
         std::vector<double> res((size_t)K);
         std::vector<int32_t> its((size_t)K);
-        SysState_t s0;
+        std::vector<SysState_t> sst((size_t)sv.S);
         HIPCHK(h, hipMemcpyAsync(res.data(), h->SW.res, K * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(h, hipMemcpyAsync(its.data(), h->SW.its, K * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HIPCHK(h, hipMemcpyAsync(&s0, sv.W.st, sizeof(SysState_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(h, hipMemcpyAsync(sst.data(), sv.W.st, sv.S * sizeof(SysState_t), hipMemcpyDeviceToHost, st));
         HIPCHK(h, hipStreamSynchronize(st));
-        its_total += s0.its;
+        SysState_t s0 = sst[0];
+        for (auto& x : sst) {
+          its_total += x.its;
+          s0.its = std::max(s0.its, x.its);
+          s0.bnorm = std::max(s0.bnorm, x.bnorm);
+        }
         if (n == nsteps - 1) {
           info->K = K;
           info->max_cycles_used = 1;

@@ -234,7 +234,9 @@ __global__ __launch_bounds__(TPB) void k_start_reduce(Work W) {
 // min || ||b|| e_1 - (Hbar_k - s_p Itilde) y_p ||, and the step is
 // sum_p w_p V_k y_p = V_k z with z = sum_p w_p y_p.
 struct ShiftWork {
-  int32_t K;          // poles sharing the basis (0: per-pole solver)
+  int32_t K;          // poles over all instances (0: per-pole solver)
+  const int32_t* pole0;  // [S+1] first pole of each instance (system)
+  const int32_t* pinst;  // [K] instance of each pole
   const double* s;    // [K] complex shifts
   const double* w;    // [K] complex weights
   const double* tol;  // [K] target relative residuals
@@ -243,41 +245,17 @@ struct ShiftWork {
   double* gc;         // [K][m] complex
   double* gs;         // [K][m] complex
   double* y;          // [K][m] complex
-  double* z;          // [m] complex, combined coefficients
+  double* z;          // [S][m] complex, combined coefficients per instance
   double* res;        // [K] implicit relative residual
   int32_t* its;       // [K] iteration at which the pole met its target (0: not yet)
   // Lanczos with partial reorthogonalisation (three-term recurrence)
   int32_t lanczos;    // 1: project only on the last two basis vectors
-  double* alpha;      // [m] diagonal of the tridiagonal matrix
-  double* beta;       // [m+1] off-diagonal, beta[j+1] = ||v_{j+1}|| before scaling
-  double* omega;      // [2][m+1] estimated <v_{j}, v_k>, <v_{j+1}, v_k> (rolling)
-  int32_t* flags;     // [0]: reorthogonalise the next vector too; [1]: passes done;
-                      // [2]: back-substitution ticket
-  int32_t* full;      // [m] 1 if column j of Hbar has entries above row j - 1
-  double eps1;        // local orthogonality level sqrt(n) u
+  double* alpha;      // [S][m] diagonal of the tridiagonal matrix
+  double* beta;       // [S][m+1] off-diagonal, beta[j+1] = ||v_{j+1}||
+  double* omega;      // [S][2][m+1] estimated <v_j, v_k>, <v_{j+1}, v_k> (rolling)
+  int32_t* flags;     // [S][4] [0]: reorthogonalise the next vector too; [1]: passes done
+  int32_t* full;      // [S][m] 1 if column j of Hbar has entries above row j - 1
 };
-
-// ------------------------------------------------------------ completion ticket
-// Every block publishes its results, then takes a ticket; the block that
-// takes the last ticket sees all of them (fences on both sides), resets the
-// ticket and returns true. Used where few blocks take part (contention on
-// one counter grows with the number of blocks).
-__device__ __forceinline__ bool last_tile(int32_t* ticket, int ntiles) {
-  __shared__ int flag;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int old = atomicAdd(ticket, 1);
-    flag = old == ntiles - 1;
-  }
-  __syncthreads();
-  const bool last = flag != 0;
-  if (last) {
-    __threadfence();
-    if (threadIdx.x == 0) atomicExch(ticket, 0);
-  }
-  return last;
-}
 
 // Grid (S, j + 2): block (s, i) with lo <= i <= j reduces the tile partials
 // of <u_i, w> to h_ij = c_i <u_i, w> (lo = i0 on the first pass, 0 on the
@@ -486,23 +464,28 @@ __device__ void givens_per_pole(Work& W, int s, int j, int cycle, double beta) {
 // w_{j,j} = 1, w_{j+1,j} = eps1. When max_k |w_{j+1,k}| exceeds sqrt(u),
 // v_{j+1} (and then v_{j+2}) get a full Gram-Schmidt pass against all earlier
 // vectors, and the estimates of a reorthogonalised vector reset to eps1.
-__device__ bool pro_decide(Work& W, ShiftWork& SW, int j, double bj1) {
+__device__ bool pro_decide(Work& W, ShiftWork& SW, int s, int j, double bj1) {
   // block-level: the estimates of row j+1 are independent across k
-  __shared__ double lds[NWAVE];
   __shared__ int reo_sh;
   const int m = W.m;
   const double u = 1.1102230246251565e-16;
-  double* wprev = SW.omega + (int64_t)((j + 1) & 1) * (m + 1);  // row j-1, becomes row j+1
-  double* wcur = SW.omega + (int64_t)(j & 1) * (m + 1);         // row j
+  const double eps1 = sqrt((double)W.sys[s].n) * u;
+  double* alpha = SW.alpha + (int64_t)s * m;
+  double* betav = SW.beta + (int64_t)s * (m + 1);
+  int32_t* flags = SW.flags + 4 * s;
+  double* omega = SW.omega + (int64_t)s * 2 * (m + 1);
+  double* wprev = omega + (int64_t)((j + 1) & 1) * (m + 1);  // row j-1, becomes row j+1
+  double* wcur = omega + (int64_t)(j & 1) * (m + 1);         // row j
   if (threadIdx.x == 0) {
-    const double2 hjj = reinterpret_cast<const double2*>(W.H)[(int64_t)j * (m + 1) + j];
-    SW.alpha[j] = hjj.x;
-    SW.beta[j + 1] = bj1;
+    const double2 hjj =
+        reinterpret_cast<const double2*>(W.H)[(int64_t)s * (m + 1) * m + (int64_t)j * (m + 1) + j];
+    alpha[j] = hjj.x;
+    betav[j + 1] = bj1;
     if (j == 0) wcur[0] = 1.0;
   }
   __syncthreads();
   double an = 0.0;
-  for (int k = threadIdx.x; k <= j; k += TPB) an = fmax(an, fabs(SW.alpha[k]) + SW.beta[k] + SW.beta[k + 1]);
+  for (int k = threadIdx.x; k <= j; k += TPB) an = fmax(an, fabs(alpha[k]) + betav[k] + betav[k + 1]);
   // block max via the sum of a one-hot: reuse block_sum on squared maxima is
   // not exact, so take the max through LDS
   __shared__ double mx[NWAVE];
@@ -512,8 +495,8 @@ __device__ bool pro_decide(Work& W, ShiftWork& SW, int j, double bj1) {
   double anorm = 0.0;
 #pragma unroll
   for (int q = 0; q < NWAVE; ++q) anorm = fmax(anorm, mx[q]);
-  const double bj = SW.beta[j];
-  const double aj = SW.alpha[j];
+  const double bj = betav[j];
+  const double aj = alpha[j];
   double worst = 0.0;
   double vals[4];
   int cnt = 0;
@@ -522,7 +505,7 @@ __device__ bool pro_decide(Work& W, ShiftWork& SW, int j, double bj1) {
     const double wk = wcur[k];
     const double wkm1 = k > 0 ? wcur[k - 1] : 0.0;
     const double wold = wprev[k];
-    double v = SW.beta[k + 1] * wkp1 + (SW.alpha[k] - aj) * wk + (k > 0 ? SW.beta[k] * wkm1 : 0.0) - bj * wold;
+    double v = betav[k + 1] * wkp1 + (alpha[k] - aj) * wk + (k > 0 ? betav[k] * wkm1 : 0.0) - bj * wold;
     v += copysign(2.0 * u * anorm, v);
     v = bj1 > 0.0 ? v / bj1 : 1.0;
     vals[cnt++ & 3] = v;
@@ -539,21 +522,20 @@ __device__ bool pro_decide(Work& W, ShiftWork& SW, int j, double bj1) {
     double wmax = 0.0;
 #pragma unroll
     for (int q = 0; q < NWAVE; ++q) wmax = fmax(wmax, mx[q]);
-    wprev[j] = SW.eps1;
+    wprev[j] = eps1;
     wprev[j + 1] = 1.0;
-    const int force = SW.flags[0];
+    const int force = flags[0];
     const bool reo = force || wmax > sqrt(u);
     if (reo) {
-      SW.flags[0] = force ? 0 : 1;  // the next vector gets a pass as well
-      SW.flags[1] += 1;
+      flags[0] = force ? 0 : 1;  // the next vector gets a pass as well
+      flags[1] += 1;
     }
     reo_sh = reo ? 1 : 0;
   }
   __syncthreads();
   const bool reo = reo_sh != 0;
   if (reo)
-    for (int k = threadIdx.x; k <= j; k += TPB) wprev[k] = SW.eps1;
-  (void)lds;
+    for (int k = threadIdx.x; k <= j; k += TPB) wprev[k] = eps1;
   return reo;
 }
 
@@ -561,15 +543,16 @@ __device__ bool pro_decide(Work& W, ShiftWork& SW, int j, double bj1) {
 // pole sharing the basis; ends the Arnoldi process when every pole meets its
 // target or j + 1 = m (the back substitution runs in k_shifted_backsub).
 // `banded`: column j has no entries above row j - 1 (no second pass).
-__device__ void givens_shifted(Work& W, ShiftWork& SW, int j, double beta, bool banded) {
+__device__ void givens_shifted(Work& W, ShiftWork& SW, int s, int j, double beta, bool banded) {
   __shared__ double lds[NWAVE];
-  SysState_t& st = W.st[0];
+  SysState_t& st = W.st[s];
   const int m = W.m;
-  const double2* hcol = reinterpret_cast<const double2*>(W.H) + (int64_t)j * (m + 1);
+  double* Hs = W.H + (int64_t)s * (m + 1) * m * 2;
+  const double2* hcol = reinterpret_cast<const double2*>(Hs) + (int64_t)j * (m + 1);
   const double bn = st.bnorm;
   const int i_start = banded ? max(0, j - 2) : 0;
   double unconv = 0.0;
-  for (int p = threadIdx.x; p < SW.K; p += TPB) {
+  for (int p = SW.pole0[s] + threadIdx.x; p < SW.pole0[s + 1]; p += TPB) {
     double2* Rp = reinterpret_cast<double2*>(SW.R) + (int64_t)p * (m + 1) * m;
     double2* col = Rp + (int64_t)j * (m + 1);
     double2* gcv = reinterpret_cast<double2*>(SW.gc) + (int64_t)p * m;
@@ -615,11 +598,11 @@ __device__ void givens_shifted(Work& W, ShiftWork& SW, int j, double beta, bool 
   unconv = block_sum(unconv, lds);
   if (threadIdx.x == 0) {
     const int k = j + 1;
-    SW.full[j] = banded ? 0 : 1;
-    W.H[(int64_t)j * (m + 1) * 2 + 2 * (j + 1)] = beta;  // h_{j+1,j}
-    W.H[(int64_t)j * (m + 1) * 2 + 2 * (j + 1) + 1] = 0.0;
-    W.cscale[j + 1] = beta > 0.0 ? 1.0 / beta : 0.0;
-    if (SW.lanczos) SW.beta[j + 1] = beta;  // after any second pass
+    SW.full[(int64_t)s * m + j] = banded ? 0 : 1;
+    Hs[(int64_t)j * (m + 1) * 2 + 2 * (j + 1)] = beta;  // h_{j+1,j}
+    Hs[(int64_t)j * (m + 1) * 2 + 2 * (j + 1) + 1] = 0.0;
+    W.cscale[(int64_t)s * (m + 1) + j + 1] = beta > 0.0 ? 1.0 / beta : 0.0;
+    if (SW.lanczos) SW.beta[(int64_t)s * (m + 1) + j + 1] = beta;  // after any second pass
     st.kcyc = k;
     st.its = k;
     if (unconv == 0.0 || k == m) st.state = ST_FINISH;
@@ -713,7 +696,7 @@ __global__ __launch_bounds__(TPB) void k_end_iter(Work W, ShiftWork SW, int j, i
   bsq = block_sum(bsq, lds);
   const double beta = sqrt(bsq);
   if (!second && SW.K > 0 && SW.lanczos) {
-    const bool reo = pro_decide(W, SW, j, beta);
+    const bool reo = pro_decide(W, SW, s, j, beta);
     if (threadIdx.x == 0) {
       st.reorth = reo ? 1 : 0;
       reo_sh = reo ? 1 : 0;
@@ -724,70 +707,78 @@ __global__ __launch_bounds__(TPB) void k_end_iter(Work W, ShiftWork SW, int j, i
   __syncthreads();
   if (reo_sh) return;
   if (SW.K > 0) {
-    givens_shifted(W, SW, j, beta, SW.lanczos && !second);
+    givens_shifted(W, SW, s, j, beta, SW.lanczos && !second);
   } else if (threadIdx.x == 0) {
     givens_per_pole(W, s, j, cycle, beta);
   }
 }
 
 // Shared basis, after the last iteration: back substitution R_p y_p = g_p per
-// pole (one wave per pole, rows in sequence, the row sums across lanes),
-// then, in the block that finishes last, z = sum_p w_p y_p in pole order.
+// pole (one wave per pole, rows in sequence, the row sums across lanes).
 __global__ __launch_bounds__(TPB) void k_shifted_backsub(Work W, ShiftWork SW) {
-  __shared__ int last;
   const int m = W.m;
-  const int k = W.st[0].kcyc;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int p = blockIdx.x * NWAVE + wid;
-  if (p < SW.K) {
-    const double2* Rp = reinterpret_cast<const double2*>(SW.R) + (int64_t)p * (m + 1) * m;
-    const double2* g = reinterpret_cast<const double2*>(SW.g) + (int64_t)p * (m + 1);
-    double2* y = reinterpret_cast<double2*>(SW.y) + (int64_t)p * m;
-    for (int r = k - 1; r >= 0; --r) {
-      double ax = 0.0, ay = 0.0;
-      for (int q = r + 1 + lane; q < k; q += 64) {
-        // a banded column q holds R entries in rows q-2..q only
-        if (q > r + 2 && !SW.full[q]) continue;
-        const double2 tq = cmul(Rp[(int64_t)q * (m + 1) + r], y[q]);
-        ax += tq.x;
-        ay += tq.y;
-      }
-      ax = wave_sum(ax);
-      ay = wave_sum(ay);
-      if (lane == 0) {
-        const double2 acc = make_double2(g[r].x - ax, g[r].y - ay);
-        const double2 dd = Rp[(int64_t)r * (m + 1) + r];
-        const double dn = dd.x * dd.x + dd.y * dd.y;
-        y[r] = dn > 0.0 ? make_double2((acc.x * dd.x + acc.y * dd.y) / dn, (acc.y * dd.x - acc.x * dd.y) / dn)
-                        : make_double2(0.0, 0.0);
-      }
-      __threadfence_block();
+  if (p >= SW.K) return;
+  const int s = SW.pinst[p];
+  const int k = W.st[s].kcyc;
+  const int32_t* full = SW.full + (int64_t)s * m;
+  const double2* Rp = reinterpret_cast<const double2*>(SW.R) + (int64_t)p * (m + 1) * m;
+  const double2* g = reinterpret_cast<const double2*>(SW.g) + (int64_t)p * (m + 1);
+  double2* y = reinterpret_cast<double2*>(SW.y) + (int64_t)p * m;
+  for (int r = k - 1; r >= 0; --r) {
+    double ax = 0.0, ay = 0.0;
+    for (int q = r + 1 + lane; q < k; q += 64) {
+      // a banded column q holds R entries in rows q-2..q only
+      if (q > r + 2 && !full[q]) continue;
+      const double2 tq = cmul(Rp[(int64_t)q * (m + 1) + r], y[q]);
+      ax += tq.x;
+      ay += tq.y;
     }
-  }
-  if (last_tile(SW.flags + 2, gridDim.x)) {
-    for (int i = threadIdx.x; i < k; i += TPB) {
-      double2 zi = make_double2(0.0, 0.0);
-      for (int q = 0; q < SW.K; ++q) {
-        const double2 wq = reinterpret_cast<const double2*>(SW.w)[q];
-        const double2 yq = reinterpret_cast<const double2*>(SW.y)[(int64_t)q * m + i];
-        const double2 tz = cmul(wq, yq);
-        zi.x += tz.x;
-        zi.y += tz.y;
-      }
-      reinterpret_cast<double2*>(SW.z)[i] = zi;
+    ax = wave_sum(ax);
+    ay = wave_sum(ay);
+    if (lane == 0) {
+      const double2 acc = make_double2(g[r].x - ax, g[r].y - ay);
+      const double2 dd = Rp[(int64_t)r * (m + 1) + r];
+      const double dn = dd.x * dd.x + dd.y * dd.y;
+      y[r] = dn > 0.0 ? make_double2((acc.x * dd.x + acc.y * dd.y) / dn, (acc.y * dd.x - acc.x * dd.y) / dn)
+                      : make_double2(0.0, 0.0);
     }
+    __threadfence_block();
   }
-  (void)last;
 }
 
-__global__ __launch_bounds__(TPB) void k_shifted_init(Work W, ShiftWork SW) {
-  const double bn = W.st[0].bnorm;
-  if (threadIdx.x == 0) {
-    SW.flags[0] = 0;
-    SW.flags[1] = 0;
-    SW.beta[0] = 0.0;
+// Grid S: z_s = sum_{p in s} w_p y_p in pole order.
+__global__ __launch_bounds__(TPB) void k_shifted_z(Work W, ShiftWork SW) {
+  const int s = blockIdx.x;
+  if (s >= W.S) return;
+  const int m = W.m;
+  const int k = W.st[s].kcyc;
+  for (int i = threadIdx.x; i < k; i += TPB) {
+    double2 zi = make_double2(0.0, 0.0);
+    for (int q = SW.pole0[s]; q < SW.pole0[s + 1]; ++q) {
+      const double2 wq = reinterpret_cast<const double2*>(SW.w)[q];
+      const double2 yq = reinterpret_cast<const double2*>(SW.y)[(int64_t)q * m + i];
+      const double2 tz = cmul(wq, yq);
+      zi.x += tz.x;
+      zi.y += tz.y;
+    }
+    reinterpret_cast<double2*>(SW.z)[(int64_t)s * m + i] = zi;
   }
-  for (int p = threadIdx.x; p < SW.K; p += TPB) {
+}
+
+// Grid S: per-instance reset of the pole least-squares data and the
+// reorthogonalisation state.
+__global__ __launch_bounds__(TPB) void k_shifted_init(Work W, ShiftWork SW) {
+  const int s = blockIdx.x;
+  if (s >= W.S) return;
+  const double bn = W.st[s].bnorm;
+  if (threadIdx.x == 0) {
+    SW.flags[4 * s] = 0;
+    SW.flags[4 * s + 1] = 0;
+    SW.beta[(int64_t)s * (W.m + 1)] = 0.0;
+  }
+  for (int p = SW.pole0[s] + threadIdx.x; p < SW.pole0[s + 1]; p += TPB) {
     double2* g = reinterpret_cast<double2*>(SW.g) + (int64_t)p * (W.m + 1);
     for (int i = 0; i <= W.m; ++i) g[i] = make_double2(0.0, 0.0);
     g[0] = make_double2(bn, 0.0);
@@ -909,20 +900,26 @@ __global__ __launch_bounds__(TPB) void k_restart(Work W, int cycle) {
 }
 
 
-// out = sum_{i<k} z_i c_i u_i in FP64 (system 0 of W).
+// out = sum_{i<k} z_i c_i u_i in FP64, per instance (system) of W.
 template <typename T, int PPT>
 __global__ __launch_bounds__(TPB) void k_combine_out(Work W, ShiftWork SW, double2* __restrict__ out) {
   __shared__ double2 coef[MAXM];
-  const SysDesc& d = W.sys[0];
-  const int k = W.st[0].kcyc;
-  for (int i = threadIdx.x; i < k; i += TPB) {
-    const double2 zi = reinterpret_cast<const double2*>(SW.z)[i];
-    const double c = W.cscale[i];
-    coef[i] = make_double2(zi.x * c, zi.y * c);
-  }
-  __syncthreads();
+  int sprev = -1;
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
-    const int t = item;
+    const int s = find_sys(W.tile_start, W.S, item);
+    const SysDesc& d = W.sys[s];
+    const int k = W.st[s].kcyc;
+    if (s != sprev) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < k; i += TPB) {
+        const double2 zi = reinterpret_cast<const double2*>(SW.z)[(int64_t)s * W.m + i];
+        const double c = W.cscale[(int64_t)s * (W.m + 1) + i];
+        coef[i] = make_double2(zi.x * c, zi.y * c);
+      }
+      __syncthreads();
+      sprev = s;
+    }
+    const int t = item - d.tile0;
     double2 acc[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) acc[q] = make_double2(0.0, 0.0);

@@ -403,3 +403,44 @@ def test_step_inside_caller_graph_capture(rexi):
         assert rel(dst.cpu().numpy(), ref.cpu().numpy()) <= 1e-13, rep
     h.close()
     he.close()
+
+
+# ---------------------------------------------------------------- uneven batch
+@pytest.mark.parametrize("solver,prec", [("shifted", "c128"), ("per_pole", "c128"), ("per_pole", "c64")])
+def test_uneven_batch_matches_oracle_per_instance(rexi, solver, prec):
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    insts = inputs.batch_instances(count=6, sides=(12, 17, 24, 31, 40, 47))
+    grids, Vs, psis, dts, Ks, sig, bet = [], [], [], [], [], [], []
+    for it in insts:
+        g = it["grid"]
+        s, b, d = poles(it["K"], inputs.R1_PARITY[it["K"]])
+        grids.append((g.n, g.lo, g.hi))
+        Vs.append(it["V"].ravel())
+        psis.append(it["psi0"].ravel())
+        dts.append(it["dt"])
+        Ks.append(it["K"])
+        sig.append(s)
+        bet.append(b)
+    cnt = len(insts)
+    tol = dict(tol=1e-11, tol_policy="certified") if prec == "c128" else dict(tol=1e-8, tol_policy="certified")
+    h = r.setup_batch(grids, to_dev(np.concatenate(Vs)), [1.0] * cnt, [1.0] * cnt, dts, Ks,
+                      np.concatenate(sig), np.concatenate(bet), solver=solver, precision=prec,
+                      m=256 if solver == "shifted" else 30, max_cycles=200, **tol)
+    p0 = to_dev(np.concatenate(psis))
+    out = torch.empty_like(p0)
+    info = h.step(p0, out, 1)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    off = 0
+    errs = []
+    for i, it in enumerate(insts):
+        g = it["grid"]
+        ref = ost.DirectStepper(g.n, g.h, it["V"], sig[i], bet[i], dts[i]).step(it["psi0"]).ravel()
+        e = rel(res[off:off + g.size], ref)
+        bar = 1e-6 if prec == "c64" else max(1e-10, 3 * iterative_floor(g, it["V"], sig[i], bet[i], dts[i]))
+        errs.append((g.n[0], it["K"], round(dts[i], 3), e, bar))
+        assert e <= bar, errs[-1]
+        off += g.size
+    print("batch", solver, prec, errs, info["total_iterations"])
+    h.close()
