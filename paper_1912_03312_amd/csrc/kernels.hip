@@ -51,10 +51,28 @@ template <> __device__ __forceinline__ float2 from_d2<float2>(double2 a) {
 }
 
 // ------------------------------------------------------------ reductions
+// One DPP move of a double (both 32-bit halves); rows not in ROWMASK read 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave with DPP lane moves (no LDS traffic):
+// quad xor 1 and 2, half-row mirror, row mirror, then the row broadcasts of
+// lanes 15 and 31 leave the total in lane 63, which is read back into every
+// lane. The summation order is fixed, so the result is deterministic.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_d<0xB1, 0xF>(v);   // quad_perm(1,0,3,2)
+  v += dpp_d<0x4E, 0xF>(v);   // quad_perm(2,3,0,1)
+  v += dpp_d<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_d<0x140, 0xF>(v);  // row_mirror
+  v += dpp_d<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // Sum over the block; every thread gets the result. lds: NWAVE doubles.
