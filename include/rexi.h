@@ -118,6 +118,8 @@ typedef struct {
                           stream; if the stream is itself being captured,
                           the schedule is enqueued into the caller's graph  */
   int32_t capture_cycles; /* per-pole solver, capture_safe: cycles, 4       */
+  int32_t graph_chunks;   /* shared-basis solver: replay cached HIP graphs of
+                             iteration chunks between host checks, 1        */
   int32_t profile;     /* 1: time kernel classes with HIP events             */
   int32_t tile;        /* points per work tile (0 = tuned default)           */
   int32_t grid_blocks; /* workgroups of the grid-stride kernels (0 = tuned)  */

@@ -99,6 +99,13 @@ struct rexi_handle {
     hipGraphExec_t exec;
   };
   std::vector<GraphEntry> graphs;
+  // iteration-chunk graphs of the shared-basis loop, keyed by (first, count)
+  struct ChunkGraph {
+    int j0, len;
+    hipGraphExec_t exec;
+  };
+  std::vector<ChunkGraph> chunks;
+  int k_hint = 0;                     // iterations the last shared-basis solve took
   double* dnorm = nullptr;            // scratch partials for norms
   std::string err;
   Prof prof;
@@ -146,6 +153,7 @@ void destroy_handle(rexi_handle* h) {
   if (h->dnorm) (void)hipFree(h->dnorm);
   if (h->hpin) (void)hipHostFree(h->hpin);
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+  for (auto& g : h->chunks) (void)hipGraphExecDestroy(g.exec);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (auto& e : h->prof.ev) (void)hipEventDestroy(e);
   delete h;
@@ -624,49 +632,97 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
   // second Gram-Schmidt passes are rare with the Lanczos estimate: a quarter
   // of the grid keeps their (mostly empty) launches short
   const int G2 = lz ? std::max(1, G / 4) : G;
-  for (int j = 0; j < m; ++j) {
+  auto iteration = [&](int j, hipStream_t strm) {
     // Lanczos: project on v_{j-1}, v_j only (H is Hermitian); Arnoldi: on all
     const int i0 = lz ? std::max(0, j - 1) : 0;
     const int nproj = j + 1 - i0;
     {
-      Timed t(h, PC_ARNOLDI_A, n * ((nproj + 1) * e + 8.0), stream);
-      hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, true>), dim3(G), dim3(TPB), 0, stream, W, j, i0);
+      Timed t(h, PC_ARNOLDI_A, n * ((nproj + 1) * e + 8.0), strm);
+      hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, true>), dim3(G), dim3(TPB), 0, strm, W, j, i0);
     }
     {
-      Timed t(h, PC_REDUCE, 0, stream);
-      hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, stream, W, j, 0, i0);
+      Timed t(h, PC_REDUCE, 0, strm);
+      hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, strm, W, j, 0, i0);
     }
     {
-      Timed t(h, PC_ARNOLDI_B, n * (nproj + 2) * e, stream);
-      hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, j, 0, i0);
+      Timed t(h, PC_ARNOLDI_B, n * (nproj + 2) * e, strm);
+      hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, strm, W, j, 0, i0);
     }
     {
-      Timed t(h, PC_REDUCE, 0, stream);
-      hipLaunchKernelGGL(rexi::k_end_iter, dim3(S), dim3(TPB), 0, stream, W, h->SW, j, 0, 0);
+      Timed t(h, PC_REDUCE, 0, strm);
+      hipLaunchKernelGGL(rexi::k_end_iter, dim3(S), dim3(TPB), 0, strm, W, h->SW, j, 0, 0);
     }
     if (sv.reorth || lz) {
       {
-        Timed t(h, PC_REORTH_A, 0, stream);
-        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(G2), dim3(TPB), 0, stream, W, j, 0);
+        Timed t(h, PC_REORTH_A, 0, strm);
+        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(G2), dim3(TPB), 0, strm, W, j, 0);
       }
       {
-        Timed t(h, PC_REDUCE, 0, stream);
-        hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, stream, W, j, 1, 0);
+        Timed t(h, PC_REDUCE, 0, strm);
+        hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, strm, W, j, 1, 0);
       }
       {
-        Timed t(h, PC_REORTH_B, 0, stream);
-        hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G2), dim3(TPB), 0, stream, W, j, 1, 0);
+        Timed t(h, PC_REORTH_B, 0, strm);
+        hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G2), dim3(TPB), 0, strm, W, j, 1, 0);
       }
       {
-        Timed t(h, PC_REDUCE, 0, stream);
-        hipLaunchKernelGGL(rexi::k_end_iter, dim3(S), dim3(TPB), 0, stream, W, h->SW, j, 1, 0);
+        Timed t(h, PC_REDUCE, 0, strm);
+        hipLaunchKernelGGL(rexi::k_end_iter, dim3(S), dim3(TPB), 0, strm, W, h->SW, j, 1, 0);
       }
     }
-    HIPCHK(h, hipGetLastError());
-    if (!h->syncfree && ((j + 1) % chunk == 0 || j + 1 == m)) {
-      HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + j, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  };
+  const bool use_chunks = !h->syncfree && !h->prof.on && h->opt.graph_chunks;
+  if (use_chunks) {
+    // replay cached graphs of iteration chunks; the first chunk spans as many
+    // iterations as the previous solve needed, later ones check_every each
+    int j = 0;
+    int len = h->k_hint > 0 ? h->k_hint : chunk;
+    while (j < m) {
+      len = std::min(len, m - j);
+      hipGraphExec_t exec = nullptr;
+      for (auto& c : h->chunks)
+        if (c.j0 == j && c.len == len) exec = c.exec;
+      if (!exec) {
+        if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        hipGraph_t graph = nullptr;
+        HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        h->syncfree = true;
+        for (int q = j; q < j + len; ++q) iteration(q, h->cap_stream);
+        h->syncfree = false;
+        hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
+        if (ec != hipSuccess) return fail(h, REXI_E_HIP, "chunk capture failed: %s", hipGetErrorString(ec));
+        hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(h, REXI_E_HIP, "chunk instantiation failed: %s", hipGetErrorString(ei));
+        if (h->chunks.size() >= 64) {
+          (void)hipGraphExecDestroy(h->chunks.front().exec);
+          h->chunks.erase(h->chunks.begin());
+        }
+        h->chunks.push_back({j, len, exec});
+      }
+      HIPCHK(h, hipGraphLaunch(exec, stream));
+      j += len;
+      HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + (j - 1), sizeof(int32_t), hipMemcpyDeviceToHost, stream));
       HIPCHK(h, hipStreamSynchronize(stream));
       if (h->hpin[0] == 0) break;
+      len = chunk;
+    }
+    // the next solve starts with one chunk of this solve's length
+    std::vector<SysState_t> sst((size_t)S);
+    HIPCHK(h, hipMemcpyAsync(sst.data(), W.st, S * sizeof(SysState_t), hipMemcpyDeviceToHost, stream));
+    HIPCHK(h, hipStreamSynchronize(stream));
+    int kmax = 1;
+    for (auto& x : sst) kmax = std::max(kmax, x.kcyc);
+    h->k_hint = kmax;
+  } else {
+    for (int j = 0; j < m; ++j) {
+      iteration(j, stream);
+      HIPCHK(h, hipGetLastError());
+      if (!h->syncfree && ((j + 1) % chunk == 0 || j + 1 == m)) {
+        HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + j, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        HIPCHK(h, hipStreamSynchronize(stream));
+        if (h->hpin[0] == 0) break;
+      }
     }
   }
   {
@@ -932,6 +988,7 @@ void rexi_default_options(rexi_options* o) {
   o->check_every = 4;
   o->lanczos = 1;
   o->capture_cycles = 4;
+  o->graph_chunks = 1;
   o->capture_safe = 0;
   o->profile = 0;
   o->tile = 0;
