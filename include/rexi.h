@@ -121,8 +121,12 @@ typedef struct {
   int32_t graph_chunks;   /* shared-basis solver: replay cached HIP graphs of
                              iteration chunks between host checks, 1        */
   int32_t profile;     /* 1: time kernel classes with HIP events             */
-  int32_t tile;        /* points per work tile (0 = tuned default)           */
+  int32_t tile;        /* points per work tile: 512, 1024, 2048, or 0 (tuned) */
   int32_t grid_blocks; /* workgroups of the grid-stride kernels (0 = tuned)  */
+  int32_t autotune;    /* 1 (default): with tile = grid_blocks = 0, time the
+                          candidate tilings x grid sizes on short runs at
+                          setup and keep the fastest (cached per problem
+                          shape; REXI_TUNE_CACHE names an optional file)     */
   int64_t max_workspace_bytes; /* device workspace cap, 0 = 90% of free     */
 } rexi_options;
 

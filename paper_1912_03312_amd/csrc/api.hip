@@ -249,6 +249,8 @@ void layout_systems(Solver& sv, int m) {
   sv.S = (int)sv.hsys.size();
 }
 
+constexpr int TPB_ = rexi::TPB;
+
 rexi_status build_solver(rexi_handle* h, Solver& sv, hipStream_t stream) {
   const int m = sv.m, S = sv.S;
   Work& W = sv.W;
@@ -268,14 +270,17 @@ rexi_status build_solver(rexi_handle* h, Solver& sv, hipStream_t stream) {
   ALLOC(W.gs, double, (size_t)S * m * 2);
   ALLOC(W.cscale, double, (size_t)S * (m + 1));
   ALLOC(W.y, double, (size_t)S * m * 2);
-  size_t npart = 0, nx = 0, nb = 0;
+  // partial sums sized for the smallest tile, so the tuner may switch tilings
+  size_t npart = 0, nx = 0, nb = 0, ntmax = 0;
   for (auto& d : sv.hsys) {
-    npart += (size_t)(m + 1) * d.ntiles;
+    const size_t nt = (size_t)(d.n + 2 * TPB_ - 1) / (2 * TPB_);
+    npart += (size_t)(m + 1) * nt;
+    ntmax += nt;
     nx += d.n;
     nb += (size_t)(m + 1) * d.n;
   }
   ALLOC(W.part, double, npart * 2);
-  ALLOC(W.pnorm, double, sv.total_tiles);
+  ALLOC(W.pnorm, double, ntmax);
   ALLOC(W.counters, int32_t, sv.max_cycles * (m + 1) + sv.max_cycles + 4);
   ALLOC(W.tick, int32_t, (size_t)S * 4);
   ALLOC(W.x, double, nx * 2);
@@ -496,6 +501,7 @@ rexi_status init_solver(rexi_handle* h, Solver& sv, int copies, hipStream_t stre
   int64_t pts = 0;
   for (auto& d : sv.hsys) pts += d.n;
   sv.ppt = choose_ppt(pts);
+  if (h->opt.tile == 2 * TPB || h->opt.tile == 4 * TPB || h->opt.tile == 8 * TPB) sv.ppt = h->opt.tile / TPB;
   sv.tile = TPB * sv.ppt;
   sv.eta = h->opt.reorth_eta;
   sv.reorth = h->opt.reorth;
@@ -748,6 +754,156 @@ rexi_status shifted_step(rexi_handle* h, const double2* b, double2* out, hipStre
   return fail(h, REXI_E_INVALID_ARG, "unsupported tiling");
 }
 
+
+// ---------------------------------------------------------------- autotuner
+// Candidate tilings (points per thread) and grid sizes are timed on short
+// real runs of the solver (start + a few iterations on a synthetic
+// right-hand side) with HIP events; the fastest is kept. Results are cached
+// per problem shape for the life of the process and, when REXI_TUNE_CACHE
+// names a file, across processes.
+struct TuneKey {
+  std::string key;
+  int ppt, grid;
+};
+std::vector<TuneKey>& tune_cache() {
+  static std::vector<TuneKey> c;
+  return c;
+}
+
+std::string tune_key(const rexi_handle* h, const Solver& sv) {
+  char buf[160];
+  std::string k = h->shifted ? "shifted" : "perpole";
+  snprintf(buf, sizeof buf, "|p%d|S%d|m%d|", sv.prec, sv.S, sv.m);
+  k += buf;
+  size_t cnt = 0;
+  for (auto& d : sv.hsys) {
+    if (cnt++ > 64) break;  // long batches: the first instances identify them
+    snprintf(buf, sizeof buf, "%dx%dx%d,", d.n0, d.n1, d.n2);
+    k += buf;
+  }
+  return k;
+}
+
+void tune_cache_load() {
+  static bool loaded = false;
+  if (loaded) return;
+  loaded = true;
+  const char* f = getenv("REXI_TUNE_CACHE");
+  if (!f) return;
+  FILE* fp = fopen(f, "r");
+  if (!fp) return;
+  char line[4096];
+  while (fgets(line, sizeof line, fp)) {
+    char key[4000];
+    int ppt, grid;
+    if (sscanf(line, "%3999s %d %d", key, &ppt, &grid) == 3) tune_cache().push_back({key, ppt, grid});
+  }
+  fclose(fp);
+}
+
+void tune_cache_store(const std::string& key, int ppt, int grid) {
+  tune_cache().push_back({key, ppt, grid});
+  const char* f = getenv("REXI_TUNE_CACHE");
+  if (!f) return;
+  FILE* fp = fopen(f, "a");
+  if (!fp) return;
+  fprintf(fp, "%s %d %d\n", key.c_str(), ppt, grid);
+  fclose(fp);
+}
+
+rexi_status apply_tiling(rexi_handle* h, Solver& sv, int ppt, int grid, hipStream_t stream) {
+  sv.ppt = ppt;
+  sv.tile = TPB * ppt;
+  layout_systems(sv, sv.m);
+  sv.grid = grid;
+  sv.W.total_tiles = sv.total_tiles;
+  sv.W.tile = sv.tile;
+  HIPCHK(h, hipMemcpyAsync(sv.dsys, sv.hsys.data(), sv.S * sizeof(SysDesc), hipMemcpyHostToDevice, stream));
+  HIPCHK(h, hipMemcpyAsync(sv.dtile, sv.htile.data(), (sv.S + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  HIPCHK(h, hipStreamSynchronize(stream));
+  return REXI_OK;
+}
+
+__global__ void k_tune_rhs(double2* __restrict__ v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    const double x = (double)(i % 9973) * 0.0137;
+    v[i] = make_double2(sin(x) + 0.5, cos(1.7 * x));
+  }
+}
+
+template <typename T, int PPT>
+void tune_launch(rexi_handle* h, Solver& sv, const double2* b, int iters, hipStream_t st) {
+  Work& W = sv.W;
+  const int G = sv.grid, S = sv.S;
+  hipLaunchKernelGGL((rexi::k_start<T, PPT>), dim3(G), dim3(TPB), 0, st, W, b, b);
+  hipLaunchKernelGGL(rexi::k_start_reduce, dim3(S), dim3(TPB), 0, st, W);
+  if (h->shifted) hipLaunchKernelGGL(rexi::k_shifted_init, dim3(S), dim3(TPB), 0, st, W, h->SW);
+  const bool lz = h->shifted && h->SW.lanczos;
+  for (int j = 0; j < iters && j < sv.m; ++j) {
+    const int i0 = lz ? std::max(0, j - 1) : 0;
+    hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, true>), dim3(G), dim3(TPB), 0, st, W, j, i0);
+    hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, st, W, j, 0, i0);
+    hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, st, W, j, 0, i0);
+    hipLaunchKernelGGL(rexi::k_end_iter, dim3(S), dim3(TPB), 0, st, W, h->shifted ? h->SW : h->noshift, j, 0, 0);
+  }
+}
+
+rexi_status autotune(rexi_handle* h, Solver& sv, hipStream_t stream) {
+  tune_cache_load();
+  const std::string key = tune_key(h, sv);
+  for (auto& c : tune_cache())
+    if (c.key == key) return apply_tiling(h, sv, c.ppt, c.grid, stream);
+  double2* rhs = nullptr;
+  if (hipMalloc(&rhs, (size_t)h->N * sizeof(double2)) != hipSuccess) {
+    (void)hipGetLastError();
+    return REXI_OK;  // no room to tune: keep the default tiling
+  }
+  hipLaunchKernelGGL(k_tune_rhs, dim3(1024), dim3(TPB), 0, stream, rhs, h->N);
+  hipEvent_t e0, e1;
+  HIPCHK(h, hipEventCreate(&e0));
+  HIPCHK(h, hipEventCreate(&e1));
+  const int iters = h->shifted ? 4 : 3;
+  int best_ppt = sv.ppt, best_grid = sv.grid;
+  float best = 1e30f;
+  int64_t pts = 0;
+  for (auto& d : sv.hsys) pts += d.n;
+  for (int ppt : {8, 4, 2}) {
+    const int tiles = (int)std::min<int64_t>((pts + TPB * ppt - 1) / (TPB * ppt) + sv.S, 1 << 30);
+    for (int gmul : {1, 2, 4, 8}) {
+      const int grid = std::max(1, std::min(tiles, 256 * gmul));
+      if (gmul > 1 && grid == std::min(tiles, 256 * gmul / 2)) continue;  // same as a smaller candidate
+      if (apply_tiling(h, sv, ppt, grid, stream) != REXI_OK) break;
+      float tmin = 1e30f;
+      for (int rep = 0; rep < 2; ++rep) {
+        HIPCHK(h, hipEventRecord(e0, stream));
+        switch (ppt * 2 + sv.prec) {
+          case 16: tune_launch<double2, 8>(h, sv, rhs, iters, stream); break;
+          case 17: tune_launch<float2, 8>(h, sv, rhs, iters, stream); break;
+          case 8: tune_launch<double2, 4>(h, sv, rhs, iters, stream); break;
+          case 9: tune_launch<float2, 4>(h, sv, rhs, iters, stream); break;
+          case 4: tune_launch<double2, 2>(h, sv, rhs, iters, stream); break;
+          case 5: tune_launch<float2, 2>(h, sv, rhs, iters, stream); break;
+        }
+        HIPCHK(h, hipEventRecord(e1, stream));
+        HIPCHK(h, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+        tmin = std::min(tmin, ms);
+      }
+      if (tmin < best) {
+        best = tmin;
+        best_ppt = ppt;
+        best_grid = grid;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(rhs);
+  tune_cache_store(key, best_ppt, best_grid);
+  return apply_tiling(h, sv, best_ppt, best_grid, stream);
+}
+
 InstDesc make_inst(const rexi_grid& g, double hbar, double mass, int64_t off) {
   InstDesc in{};
   int64_t n[3] = {1, 1, 1};
@@ -802,6 +958,8 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   if (!(o.inner_rtol >= 0.0 && o.inner_rtol < 1.0)) return fail(nullptr, REXI_E_INVALID_ARG, "inner_rtol in [0,1)");
   if (o.max_workspace_bytes < 0) return fail(nullptr, REXI_E_INVALID_ARG, "max_workspace_bytes < 0");
   if (o.grid_blocks < 0) return fail(nullptr, REXI_E_INVALID_ARG, "grid_blocks < 0");
+  if (o.tile != 0 && o.tile != 512 && o.tile != 1024 && o.tile != 2048)
+    return fail(nullptr, REXI_E_INVALID_ARG, "tile must be 0 (tuned), 512, 1024 or 2048 points");
 
   // ---- validate the instances (host side, before any device work)
   int64_t N = 0, Ktot = 0;
@@ -931,6 +1089,14 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
     destroy_handle(h);
     return st;
   }
+  if (o.autotune && o.tile == 0 && o.grid_blocks == 0) {
+    st = autotune(h, h->fwd, stream);
+    if (st != REXI_OK) {
+      g_setup_error = h->err;
+      destroy_handle(h);
+      return st;
+    }
+  }
   h->prof.on = o.profile != 0;
   *out = h;
   return REXI_OK;
@@ -989,6 +1155,7 @@ void rexi_default_options(rexi_options* o) {
   o->lanczos = 1;
   o->capture_cycles = 4;
   o->graph_chunks = 1;
+  o->autotune = 1;
   o->capture_safe = 0;
   o->profile = 0;
   o->tile = 0;

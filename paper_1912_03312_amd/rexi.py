@@ -47,7 +47,7 @@ class Options(C.Structure):
                 ("reorth", C.c_int32), ("reorth_eta", C.c_double), ("inner_rtol", C.c_double),
                 ("check_every", C.c_int32), ("lanczos", C.c_int32), ("capture_safe", C.c_int32),
                 ("capture_cycles", C.c_int32), ("graph_chunks", C.c_int32),
-                ("profile", C.c_int32), ("tile", C.c_int32), ("grid_blocks", C.c_int32),
+                ("profile", C.c_int32), ("tile", C.c_int32), ("grid_blocks", C.c_int32), ("autotune", C.c_int32),
                 ("max_workspace_bytes", C.c_int64)]
 
 

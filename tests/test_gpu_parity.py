@@ -444,3 +444,28 @@ def test_uneven_batch_matches_oracle_per_instance(rexi, solver, prec):
         off += g.size
     print("batch", solver, prec, errs, info["total_iterations"])
     h.close()
+
+
+@pytest.mark.parametrize("solver", ["shifted", "per_pole"])
+def test_tilings_agree(rexi, solver):
+    # every tiling the autotuner may pick computes the same step
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    wl = inputs.workload("3d_bumps", scale=21)
+    g = wl.grid
+    s, b, d = poles(16, 32.0)
+    Vd = to_dev(wl.V.ravel())
+    p0 = to_dev(wl.psi0.ravel())
+    outs, bounds = [], []
+    for tile, grid in [(0, 0), (512, 7), (1024, 64), (2048, 3)]:
+        h = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, wl.dt, s, b, solver=solver, m=100 if solver == "shifted" else 30,
+                    tol=1e-12, tile=tile, grid_blocks=grid)
+        o = torch.empty_like(p0)
+        info = h.step(p0, o, 1)
+        outs.append(o.cpu().numpy())
+        bounds.append(info["certified_bound"])
+        h.close()
+    # different tilings round differently; the iterates agree within their
+    # certified error bounds
+    for o, bd in zip(outs[1:], bounds[1:]):
+        assert rel(o, outs[0]) <= bd + bounds[0] + 1e-13
