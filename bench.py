@@ -293,6 +293,7 @@ def main():
         "solve": {
             "iterations_per_step": int(final_info["total_iterations"]),
             "max_cycles": int(final_info["max_cycles_used"]),
+            "second_gs_passes": int(final_info["reorth_passes"]),
             "max_rel_residual": final_info["max_rel_residual"],
             "certified_rel_error_bound": final_info["certified_bound"],
             "norm_drift": final_info["norm_out"] / final_info["norm_in"] - 1.0,

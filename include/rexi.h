@@ -139,6 +139,9 @@ typedef struct {
   double max_rel_residual;  /* max_j ||psi - (H - s_j) x_j|| / ||psi|| (last step) */
   double certified_bound;   /* sum_j |w_j| ||r_j|| / dist(s_j, [lmin, lmax]) / ||psi||,
                                a bound on the relative step error (last step)  */
+  int32_t reorth_passes;    /* shared-basis Lanczos: second Gram-Schmidt passes
+                               of the last step (single instance)             */
+  int32_t reserved_;
   double norm_in;           /* ||psi_n||_2 of the last step's input            */
   double norm_out;          /* ||psi_{n+1}||_2 of the last step's output       */
   /* optional caller-owned per-pole arrays of length K (NULL to skip):        */

@@ -106,6 +106,7 @@ struct rexi_handle {
   };
   std::vector<ChunkGraph> chunks;
   int k_hint = 0;                     // iterations the last shared-basis solve took
+  int reorth_passes = 0;              // second passes of the last shared-basis solve
   double* dnorm = nullptr;            // scratch partials for norms
   std::string err;
   Prof prof;
@@ -635,9 +636,31 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
   // iterations after convergence return at once (device-side state)
   const int chunk = std::max(1, h->opt.check_every);
   const bool lz = h->SW.lanczos != 0;
-  // second Gram-Schmidt passes are rare with the Lanczos estimate: a quarter
-  // of the grid keeps their (mostly empty) launches short
+  // second Gram-Schmidt passes are rare with the Lanczos estimate: a single
+  // instance solved with host checks pauses for them (the host runs the pass
+  // and resumes); otherwise they are predicated launches on a quarter grid
+  const bool pause_mode = lz && S == 1 && !h->syncfree;
+  rexi::ShiftWork SWl = h->SW;
+  SWl.pause_mode = pause_mode ? 1 : 0;
   const int G2 = lz ? std::max(1, G / 4) : G;
+  auto second_pass = [&](int j, hipStream_t strm, int grid2) {
+    {
+      Timed t(h, PC_REORTH_A, 0, strm);
+      hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(grid2), dim3(TPB), 0, strm, W, j, 0);
+    }
+    {
+      Timed t(h, PC_REDUCE, 0, strm);
+      hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, strm, W, j, 1, 0);
+    }
+    {
+      Timed t(h, PC_REORTH_B, 0, strm);
+      hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(grid2), dim3(TPB), 0, strm, W, j, 1, 0);
+    }
+    {
+      Timed t(h, PC_REDUCE, 0, strm);
+      hipLaunchKernelGGL(rexi::k_end_iter, dim3(S), dim3(TPB), 0, strm, W, SWl, j, 1, 0);
+    }
+  };
   auto iteration = [&](int j, hipStream_t strm) {
     // Lanczos: project on v_{j-1}, v_j only (H is Hermitian); Arnoldi: on all
     const int i0 = lz ? std::max(0, j - 1) : 0;
@@ -656,45 +679,31 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
     }
     {
       Timed t(h, PC_REDUCE, 0, strm);
-      hipLaunchKernelGGL(rexi::k_end_iter, dim3(S), dim3(TPB), 0, strm, W, h->SW, j, 0, 0);
+      hipLaunchKernelGGL(rexi::k_end_iter, dim3(S), dim3(TPB), 0, strm, W, SWl, j, 0, 0);
     }
-    if (sv.reorth || lz) {
-      {
-        Timed t(h, PC_REORTH_A, 0, strm);
-        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(G2), dim3(TPB), 0, strm, W, j, 0);
-      }
-      {
-        Timed t(h, PC_REDUCE, 0, strm);
-        hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, strm, W, j, 1, 0);
-      }
-      {
-        Timed t(h, PC_REORTH_B, 0, strm);
-        hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G2), dim3(TPB), 0, strm, W, j, 1, 0);
-      }
-      {
-        Timed t(h, PC_REDUCE, 0, strm);
-        hipLaunchKernelGGL(rexi::k_end_iter, dim3(S), dim3(TPB), 0, strm, W, h->SW, j, 1, 0);
-      }
-    }
+    if ((sv.reorth || lz) && !pause_mode) second_pass(j, strm, G2);
   };
-  const bool use_chunks = !h->syncfree && !h->prof.on && h->opt.graph_chunks;
-  if (use_chunks) {
-    // replay cached graphs of iteration chunks; the first chunk spans as many
-    // iterations as the previous solve needed, later ones check_every each
-    int j = 0;
-    int len = h->k_hint > 0 ? h->k_hint : chunk;
-    while (j < m) {
-      len = std::min(len, m - j);
+  if (h->syncfree) {
+    for (int j = 0; j < m; ++j) iteration(j, stream);
+  } else {
+    // chunks of iterations between host checks: the first spans as many
+    // iterations as the previous solve needed, later ones check_every each;
+    // a chunk is a cached graph (graph_chunks) or plain launches
+    const bool use_graphs = !h->prof.on && h->opt.graph_chunks;
+    auto launch_chunk = [&](int j0, int len) -> rexi_status {
+      if (!use_graphs) {
+        for (int q = j0; q < j0 + len; ++q) iteration(q, stream);
+        HIPCHK(h, hipGetLastError());
+        return REXI_OK;
+      }
       hipGraphExec_t exec = nullptr;
       for (auto& c : h->chunks)
-        if (c.j0 == j && c.len == len) exec = c.exec;
+        if (c.j0 == j0 && c.len == len) exec = c.exec;
       if (!exec) {
         if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
         HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-        h->syncfree = true;
-        for (int q = j; q < j + len; ++q) iteration(q, h->cap_stream);
-        h->syncfree = false;
+        for (int q = j0; q < j0 + len; ++q) iteration(q, h->cap_stream);
         hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
         if (ec != hipSuccess) return fail(h, REXI_E_HIP, "chunk capture failed: %s", hipGetErrorString(ec));
         hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -704,12 +713,39 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
           (void)hipGraphExecDestroy(h->chunks.front().exec);
           h->chunks.erase(h->chunks.begin());
         }
-        h->chunks.push_back({j, len, exec});
+        h->chunks.push_back({j0, len, exec});
       }
       HIPCHK(h, hipGraphLaunch(exec, stream));
-      j += len;
-      HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + (j - 1), sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+      return REXI_OK;
+    };
+    int j = 0;
+    int len = h->k_hint > 0 ? h->k_hint : chunk;
+    int passes = 0;
+    while (j < m) {
+      len = std::max(1, std::min(len, m - j));
+      rexi_status rs = launch_chunk(j, len);
+      if (rs != REXI_OK) return rs;
+      // [0]: systems still iterating after the chunk's last iteration; [1]: pause
+      HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + (j + len - 1), sizeof(int32_t), hipMemcpyDeviceToHost,
+                               stream));
+      HIPCHK(h, hipMemcpyAsync(h->hpin + 1, h->SW.flags + 2, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
       HIPCHK(h, hipStreamSynchronize(stream));
+      const int paused_at = pause_mode ? h->hpin[1] : -1;
+      if (paused_at >= 0) {
+        // second Gram-Schmidt pass of iteration paused_at, then go on after it
+        hipLaunchKernelGGL(rexi::k_resume, dim3(S), dim3(64), 0, stream, W, h->SW);
+        second_pass(paused_at, stream, G);
+        HIPCHK(h, hipGetLastError());
+        ++passes;
+        j = paused_at + 1;
+        SysState_t s0;
+        HIPCHK(h, hipMemcpyAsync(&s0, W.st, sizeof(SysState_t), hipMemcpyDeviceToHost, stream));
+        HIPCHK(h, hipStreamSynchronize(stream));
+        if (s0.state != rexi::ST_ACTIVE) break;
+        len = std::max(chunk, h->k_hint - j);
+        continue;
+      }
+      j += len;
       if (h->hpin[0] == 0) break;
       len = chunk;
     }
@@ -720,16 +756,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
     int kmax = 1;
     for (auto& x : sst) kmax = std::max(kmax, x.kcyc);
     h->k_hint = kmax;
-  } else {
-    for (int j = 0; j < m; ++j) {
-      iteration(j, stream);
-      HIPCHK(h, hipGetLastError());
-      if (!h->syncfree && ((j + 1) % chunk == 0 || j + 1 == m)) {
-        HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + j, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-        HIPCHK(h, hipStreamSynchronize(stream));
-        if (h->hpin[0] == 0) break;
-      }
-    }
+    h->reorth_passes = passes;
   }
   {
     Timed t(h, PC_REDUCE, 0, stream);
@@ -1279,6 +1306,7 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
             if (info->rel_residual) info->rel_residual[k] = res[k];
           }
           info->certified_bound = bound;
+          info->reorth_passes = h->reorth_passes;
           info->norm_in = s0.bnorm;
           double no = 0.0;
           rexi_status s2 = vec_norm(h, outp, st, &no);

@@ -271,7 +271,9 @@ struct ShiftWork {
   double* alpha;      // [S][m] diagonal of the tridiagonal matrix
   double* beta;       // [S][m+1] off-diagonal, beta[j+1] = ||v_{j+1}||
   double* omega;      // [S][2][m+1] estimated <v_j, v_k>, <v_{j+1}, v_k> (rolling)
-  int32_t* flags;     // [S][4] [0]: reorthogonalise the next vector too; [1]: passes done
+  int32_t* flags;     // [S][4] [0]: reorthogonalise the next vector too; [1]: passes done;
+                      // [2]: iteration at which the solve paused (-1: none)
+  int32_t pause_mode; // 1: pause for a second pass instead of predicated passes
   int32_t* full;      // [S][m] 1 if column j of Hbar has entries above row j - 1
 };
 
@@ -718,6 +720,11 @@ __global__ __launch_bounds__(TPB) void k_end_iter(Work W, ShiftWork SW, int j, i
     if (threadIdx.x == 0) {
       st.reorth = reo ? 1 : 0;
       reo_sh = reo ? 1 : 0;
+      if (reo && SW.pause_mode) {
+        // hand the second pass to the host: later launches of this chunk skip
+        st.state = ST_PAUSED;
+        SW.flags[4 * s + 2] = j;
+      }
     }
   } else if (threadIdx.x == 0) {
     reo_sh = second ? 0 : st.reorth;
@@ -785,6 +792,14 @@ __global__ __launch_bounds__(TPB) void k_shifted_z(Work W, ShiftWork SW) {
   }
 }
 
+// Grid S: a paused solve becomes active again (its second pass follows).
+__global__ __launch_bounds__(64) void k_resume(Work W, ShiftWork SW) {
+  const int s = blockIdx.x;
+  if (s >= W.S || threadIdx.x != 0) return;
+  if (W.st[s].state == ST_PAUSED) W.st[s].state = ST_ACTIVE;
+  SW.flags[4 * s + 2] = -1;
+}
+
 // Grid S: per-instance reset of the pole least-squares data and the
 // reorthogonalisation state.
 __global__ __launch_bounds__(TPB) void k_shifted_init(Work W, ShiftWork SW) {
@@ -794,6 +809,7 @@ __global__ __launch_bounds__(TPB) void k_shifted_init(Work W, ShiftWork SW) {
   if (threadIdx.x == 0) {
     SW.flags[4 * s] = 0;
     SW.flags[4 * s + 1] = 0;
+    SW.flags[4 * s + 2] = -1;
     SW.beta[(int64_t)s * (W.m + 1)] = 0.0;
   }
   for (int p = SW.pole0[s] + threadIdx.x; p < SW.pole0[s + 1]; p += TPB) {

@@ -71,7 +71,7 @@ struct InstDesc {
   int32_t ntiles;
 };
 
-enum SysState : int32_t { ST_ACTIVE = 0, ST_FINISH = 1, ST_DONE = 2 };
+enum SysState : int32_t { ST_ACTIVE = 0, ST_FINISH = 1, ST_DONE = 2, ST_PAUSED = 3 };
 
 // Per-system scalar state on the device.
 struct SysState_t {

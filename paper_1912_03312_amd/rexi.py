@@ -55,6 +55,7 @@ class StepInfo(C.Structure):
     _fields_ = [("K", C.c_int32), ("steps", C.c_int32), ("total_iterations", C.c_int64),
                 ("max_cycles_used", C.c_int32), ("not_converged", C.c_int32),
                 ("max_rel_residual", C.c_double), ("certified_bound", C.c_double),
+                ("reorth_passes", C.c_int32), ("reserved_", C.c_int32),
                 ("norm_in", C.c_double), ("norm_out", C.c_double),
                 ("iterations", C.POINTER(C.c_int32)), ("cycles", C.POINTER(C.c_int32)),
                 ("rel_residual", C.POINTER(C.c_double))]
@@ -199,7 +200,8 @@ class Handle:
         out = dict(K=inf.K, steps=inf.steps, total_iterations=inf.total_iterations,
                    max_cycles_used=inf.max_cycles_used, not_converged=inf.not_converged,
                    max_rel_residual=inf.max_rel_residual, certified_bound=inf.certified_bound,
-                   norm_in=inf.norm_in, norm_out=inf.norm_out, iterations=list(it), cycles=list(cy),
+                   norm_in=inf.norm_in, norm_out=inf.norm_out, reorth_passes=inf.reorth_passes,
+                   iterations=list(it), cycles=list(cy),
                    rel_residual=list(rr), status=st)
         if st != REXI_OK and (st != REXI_E_NOT_CONVERGED or raise_on_nc):
             _check(st, self._h)
