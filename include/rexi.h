@@ -107,9 +107,12 @@ typedef struct {
   double inner_rtol;   /* C64_REFINE: residual reduction per sweep, 1e-5     */
   int32_t check_every; /* shared-basis solver: iterations between host reads
                           of the convergence flag, default 4                 */
-  int32_t lanczos;     /* shared-basis solver: 1 (default) uses the Hermitian
-                          three-term (Lanczos) recurrence with partial
-                          reorthogonalisation; 0 full Arnoldi + DGKS         */
+  int32_t lanczos;     /* shared-basis solver: H is Hermitian, so the basis
+                          follows the three-term (Lanczos) recurrence with
+                          partial reorthogonalisation. 1 (default): one fused
+                          pass per iteration (update of u_{j+1} and the next
+                          matvec together); 2: separate update and matvec
+                          passes; 0: full Arnoldi with DGKS                  */
   int32_t capture_safe;/* 1: rexi_step(info = NULL) runs a fixed schedule
                           with no host reads (all m iterations; per-pole:
                           capture_cycles cycles), finished poles skipped on

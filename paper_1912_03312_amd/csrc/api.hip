@@ -29,11 +29,11 @@ thread_local std::string g_setup_error;
 
 enum ProfClass {
   PC_START = 0, PC_ARNOLDI_A, PC_REDUCE, PC_ARNOLDI_B, PC_REORTH_A, PC_REORTH_B,
-  PC_UPDATE_X, PC_RESIDUAL, PC_POLESUM, PC_APPLY_H, PC_GRAD, PC_NCLASS
+  PC_UPDATE_X, PC_RESIDUAL, PC_POLESUM, PC_APPLY_H, PC_GRAD, PC_LANCZOS, PC_NCLASS
 };
 const char* kProfNames[PC_NCLASS] = {"start", "arnoldi_matvec_dots", "per_system_reduce", "arnoldi_update",
                                      "reorth_dots", "reorth_update", "update_x", "residual",
-                                     "polesum", "apply_h", "grad_v"};
+                                     "polesum", "apply_h", "grad_v", "lanczos_step"};
 
 struct DevBuf {
   void* p = nullptr;
@@ -583,6 +583,15 @@ rexi_status init_shifted(rexi_handle* h, hipStream_t stream) {
   SW.flags = (int32_t*)flags;
   SW.full = (int32_t*)full;
   SW.lanczos = h->opt.lanczos ? 1 : 0;
+  if (h->opt.lanczos == 1) {
+    // pipelined recurrence: two z buffers of all instances' points
+    int64_t tot = 0;
+    for (auto& d : h->fwd.hsys) tot += d.n;
+    void* zb = nullptr;
+    if ((st = al(&zb, (size_t)2 * tot * c16))) return st;
+    SW.zb = (double*)zb;
+    SW.zstride = tot;
+  }
   if (SW.lanczos) {
     // the orthogonality estimate decides the second passes; the DGKS test is off
     h->fwd.W.reorth_mode = 3;
@@ -632,6 +641,17 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
     hipLaunchKernelGGL(rexi::k_start_reduce, dim3(S), dim3(TPB), 0, stream, W);
     hipLaunchKernelGGL(rexi::k_shifted_init, dim3(S), dim3(TPB), 0, stream, W, h->SW);
   }
+  const bool pipe = h->opt.lanczos == 1;
+  if (pipe) {
+    {
+      Timed t(h, PC_START, n * 48.0, stream);
+      hipLaunchKernelGGL((rexi::k_lz_matvec<PPT>), dim3(G), dim3(TPB), 0, stream, W, h->SW, 0, 0, 0);
+    }
+    {
+      Timed t(h, PC_REDUCE, 0, stream);
+      hipLaunchKernelGGL(rexi::k_lz_start, dim3(S), dim3(TPB), 0, stream, W, h->SW);
+    }
+  }
   // iterations run in chunks between host reads of the convergence counter;
   // iterations after convergence return at once (device-side state)
   const int chunk = std::max(1, h->opt.check_every);
@@ -644,6 +664,31 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
   SWl.pause_mode = pause_mode ? 1 : 0;
   const int G2 = lz ? std::max(1, G / 4) : G;
   auto second_pass = [&](int j, hipStream_t strm, int grid2) {
+    if (pipe) {
+      // re-orthogonalise u_{j+1}, recompute z_{j+1} = H u_{j+1}, then the Givens step
+      {
+        Timed t(h, PC_REORTH_A, 0, strm);
+        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(grid2), dim3(TPB), 0, strm, W, j, 0);
+      }
+      {
+        Timed t(h, PC_REDUCE, 0, strm);
+        hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, strm, W, j, 1, 0);
+      }
+      {
+        Timed t(h, PC_REORTH_B, 0, strm);
+        hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(grid2), dim3(TPB), 0, strm, W, j, 1, 0);
+      }
+      {
+        Timed t(h, PC_REORTH_B, 0, strm);
+        hipLaunchKernelGGL((rexi::k_lz_matvec<PPT>), dim3(grid2), dim3(TPB), 0, strm, W, h->SW, j + 1,
+                           (j + 1) & 1, 1);
+      }
+      {
+        Timed t(h, PC_REDUCE, 0, strm);
+        hipLaunchKernelGGL(rexi::k_lz_end, dim3(S), dim3(TPB), 0, strm, W, SWl, j, 1);
+      }
+      return;
+    }
     {
       Timed t(h, PC_REORTH_A, 0, strm);
       hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(grid2), dim3(TPB), 0, strm, W, j, 0);
@@ -662,6 +707,18 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
     }
   };
   auto iteration = [&](int j, hipStream_t strm) {
+    if (pipe) {
+      {
+        Timed t(h, PC_LANCZOS, n * (j > 0 ? 88.0 : 72.0), strm);
+        hipLaunchKernelGGL((rexi::k_lz_step<PPT>), dim3(G), dim3(TPB), 0, strm, W, SWl, j);
+      }
+      {
+        Timed t(h, PC_REDUCE, 0, strm);
+        hipLaunchKernelGGL(rexi::k_lz_end, dim3(S), dim3(TPB), 0, strm, W, SWl, j, 0);
+      }
+      if (!pause_mode) second_pass(j, strm, G2);
+      return;
+    }
     // Lanczos: project on v_{j-1}, v_j only (H is Hermitian); Arnoldi: on all
     const int i0 = lz ? std::max(0, j - 1) : 0;
     const int nproj = j + 1 - i0;
@@ -866,6 +923,15 @@ void tune_launch(rexi_handle* h, Solver& sv, const double2* b, int iters, hipStr
   hipLaunchKernelGGL(rexi::k_start_reduce, dim3(S), dim3(TPB), 0, st, W);
   if (h->shifted) hipLaunchKernelGGL(rexi::k_shifted_init, dim3(S), dim3(TPB), 0, st, W, h->SW);
   const bool lz = h->shifted && h->SW.lanczos;
+  if (h->shifted && h->opt.lanczos == 1) {
+    hipLaunchKernelGGL((rexi::k_lz_matvec<PPT>), dim3(G), dim3(TPB), 0, st, W, h->SW, 0, 0, 0);
+    hipLaunchKernelGGL(rexi::k_lz_start, dim3(S), dim3(TPB), 0, st, W, h->SW);
+    for (int j = 0; j < iters && j < sv.m; ++j) {
+      hipLaunchKernelGGL((rexi::k_lz_step<PPT>), dim3(G), dim3(TPB), 0, st, W, h->SW, j);
+      hipLaunchKernelGGL(rexi::k_lz_end, dim3(S), dim3(TPB), 0, st, W, h->SW, j, 0);
+    }
+    return;
+  }
   for (int j = 0; j < iters && j < sv.m; ++j) {
     const int i0 = lz ? std::max(0, j - 1) : 0;
     hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, true>), dim3(G), dim3(TPB), 0, st, W, j, i0);

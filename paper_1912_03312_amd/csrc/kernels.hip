@@ -275,6 +275,8 @@ struct ShiftWork {
                       // [2]: iteration at which the solve paused (-1: none)
   int32_t pause_mode; // 1: pause for a second pass instead of predicated passes
   int32_t* full;      // [S][m] 1 if column j of Hbar has entries above row j - 1
+  double* zb;         // [2][sum n] complex: z_j = H u_j of the pipelined recurrence
+  int64_t zstride;    // complex elements per z buffer
 };
 
 // Grid (S, j + 2): block (s, i) with lo <= i <= j reduces the tile partials
@@ -736,6 +738,211 @@ __global__ __launch_bounds__(TPB) void k_end_iter(Work W, ShiftWork SW, int j, i
   } else if (threadIdx.x == 0) {
     givens_per_pole(W, s, j, cycle, beta);
   }
+}
+
+
+// ------------------------------------------------------------ pipelined Lanczos
+// The shared basis with H Hermitian, one streaming pass per iteration: the
+// Lanczos vector u_{j+1} = H v_j - alpha_j v_j - beta_j v_{j-1} (unnormalised,
+// v_i = c_i u_i) is formed point by point from z_j = H u_j, u_j and u_{j-1},
+// at each point and at its stencil neighbours, and in the same pass
+// z_{j+1} = H u_{j+1} is applied; the pass writes u_{j+1} and z_{j+1} and the
+// partial sums of ||u_{j+1}||^2, <u_{j+1}, z_{j+1}> and <u_j, u_{j+1}>.
+// alpha_{j+1} = c_{j+1}^2 <u_{j+1}, z_{j+1}> and beta_{j+1} = ||u_{j+1}|| then
+// come from one per-system reduction (k_lz_end), which also runs the
+// orthogonality estimate and the Givens step.
+
+// z_i = H u_i for basis slot i (start of the solve, or after a second
+// Gram-Schmidt pass), with partial <u_i, z_i> (partial slot 0) and ||u_i||^2.
+template <int PPT>
+__global__ __launch_bounds__(TPB) void k_lz_matvec(Work W, ShiftWork SW, int i, int zsel, int after_reorth) {
+  __shared__ double lds[NWAVE];
+  for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
+    const int s = find_sys(W.tile_start, W.S, item);
+    const SysState_t& st = W.st[s];
+    if (st.state != ST_ACTIVE) continue;
+    if (after_reorth && !st.reorth) continue;
+    const SysDesc& d = W.sys[s];
+    const int t = item - d.tile0;
+    const double2* __restrict__ u = basis_vec<double2>(W, d, i);
+    double2* __restrict__ z = reinterpret_cast<double2*>(SW.zb) + zsel * SW.zstride + d.xoff;
+    double uzx = 0.0, uzy = 0.0, nn = 0.0;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int p = t * W.tile + q * TPB + threadIdx.x;
+      if (p < d.n) {
+        const double2 c = u[p];
+        const double2 hz = stencil_point<double2>(u, d, W.V64[d.off + p], (uint32_t)p);
+        z[p] = hz;
+        uzx += c.x * hz.x + c.y * hz.y;
+        uzy += c.x * hz.y - c.y * hz.x;
+        nn += c.x * c.x + c.y * c.y;
+      }
+    }
+    uzx = block_sum(uzx, lds);
+    uzy = block_sum(uzy, lds);
+    nn = block_sum(nn, lds);
+    if (threadIdx.x == 0) {
+      reinterpret_cast<double2*>(W.part)[d.pbase + t] = make_double2(uzx, uzy);
+      W.pnorm[item] = nn;
+    }
+  }
+}
+
+// Grid S: alpha_0 = c_0^2 <u_0, z_0> at the start of the solve.
+__global__ __launch_bounds__(TPB) void k_lz_start(Work W, ShiftWork SW) {
+  __shared__ double lds[NWAVE];
+  const int s = blockIdx.x;
+  if (s >= W.S) return;
+  if (W.st[s].state != ST_ACTIVE) return;
+  const SysDesc& d = W.sys[s];
+  double ax = 0.0;
+  for (int t = threadIdx.x; t < d.ntiles; t += TPB) ax += reinterpret_cast<const double2*>(W.part)[d.pbase + t].x;
+  ax = block_sum(ax, lds);
+  if (threadIdx.x == 0) {
+    const double c0 = W.cscale[(int64_t)s * (W.m + 1)];
+    SW.alpha[(int64_t)s * W.m] = c0 * c0 * ax;
+  }
+}
+
+template <int PPT>
+__global__ __launch_bounds__(TPB) void k_lz_step(Work W, ShiftWork SW, int j) {
+  __shared__ double lds[NWAVE];
+  const int m = W.m;
+  for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
+    const int s = find_sys(W.tile_start, W.S, item);
+    const SysState_t& st = W.st[s];
+    if (st.state != ST_ACTIVE) continue;
+    const SysDesc& d = W.sys[s];
+    const int t = item - d.tile0;
+    const double cj = W.cscale[(int64_t)s * (m + 1) + j];
+    const double cjm = j > 0 ? W.cscale[(int64_t)s * (m + 1) + j - 1] : 0.0;
+    const double ka = SW.alpha[(int64_t)s * m + j] * cj;
+    const double kb = j > 0 ? SW.beta[(int64_t)s * (m + 1) + j] * cjm : 0.0;
+    const double2* __restrict__ z = reinterpret_cast<const double2*>(SW.zb) + (j & 1) * SW.zstride + d.xoff;
+    double2* __restrict__ zn = reinterpret_cast<double2*>(SW.zb) + ((j + 1) & 1) * SW.zstride + d.xoff;
+    const double2* __restrict__ uj = basis_vec<double2>(W, d, j);
+    const double2* __restrict__ ujm = basis_vec<double2>(W, d, j > 0 ? j - 1 : 0);
+    double2* __restrict__ un = basis_vec<double2>(W, d, j + 1);
+    const bool three = j > 0;
+    auto U = [&](uint32_t q) -> double2 {
+      const double2 a = z[q];
+      const double2 b = uj[q];
+      double2 r = make_double2(cj * a.x - ka * b.x, cj * a.y - ka * b.y);
+      if (three) {
+        const double2 c = ujm[q];
+        r.x -= kb * c.x;
+        r.y -= kb * c.y;
+      }
+      return r;
+    };
+    const uint32_t plane = (uint32_t)d.n1 * (uint32_t)d.n2;
+    double uzx = 0.0, uzy = 0.0, oux = 0.0, ouy = 0.0, nn = 0.0;
+#pragma unroll 2
+    for (int q = 0; q < PPT; ++q) {
+      const int pi = t * W.tile + q * TPB + threadIdx.x;
+      if (pi < d.n) {
+        const uint32_t p = (uint32_t)pi;
+        const uint32_t r = fdiv(p, d.d2);
+        const uint32_t k = p - r * (uint32_t)d.n2;
+        const uint32_t i0 = fdiv(r, d.d1);
+        const uint32_t jj = r - i0 * (uint32_t)d.n1;
+        const double2 c = U(p);
+        double2 nb2 = make_double2(0.0, 0.0), nb1 = nb2, nb0 = nb2;
+        if (k > 0) { const double2 v = U(p - 1); nb2.x += v.x; nb2.y += v.y; }
+        if (k + 1 < (uint32_t)d.n2) { const double2 v = U(p + 1); nb2.x += v.x; nb2.y += v.y; }
+        if (jj > 0) { const double2 v = U(p - d.n2); nb1.x += v.x; nb1.y += v.y; }
+        if (jj + 1 < (uint32_t)d.n1) { const double2 v = U(p + d.n2); nb1.x += v.x; nb1.y += v.y; }
+        if (i0 > 0) { const double2 v = U(p - plane); nb0.x += v.x; nb0.y += v.y; }
+        if (i0 + 1 < (uint32_t)d.n0) { const double2 v = U(p + plane); nb0.x += v.x; nb0.y += v.y; }
+        const double a = d.diag + W.V64[d.off + p];
+        double2 hz;
+        hz.x = a * c.x - (d.c2 * nb2.x + d.c1 * nb1.x + d.c0 * nb0.x);
+        hz.y = a * c.y - (d.c2 * nb2.y + d.c1 * nb1.y + d.c0 * nb0.y);
+        un[p] = c;
+        zn[p] = hz;
+        const double2 u0 = uj[p];
+        uzx += c.x * hz.x + c.y * hz.y;
+        uzy += c.x * hz.y - c.y * hz.x;
+        oux += u0.x * c.x + u0.y * c.y;
+        ouy += u0.x * c.y - u0.y * c.x;
+        nn += c.x * c.x + c.y * c.y;
+      }
+    }
+    uzx = block_sum(uzx, lds);
+    uzy = block_sum(uzy, lds);
+    oux = block_sum(oux, lds);
+    ouy = block_sum(ouy, lds);
+    nn = block_sum(nn, lds);
+    if (threadIdx.x == 0) {
+      double2* part = reinterpret_cast<double2*>(W.part) + d.pbase;
+      part[t] = make_double2(uzx, uzy);
+      part[d.ntiles + t] = make_double2(oux, ouy);
+      W.pnorm[item] = nn;
+    }
+  }
+}
+
+// Grid S: end of pipelined iteration j. beta_{j+1} = ||u_{j+1}||,
+// alpha_{j+1} = c_{j+1}^2 Re <u_{j+1}, z_{j+1}>; column j of Hbar is
+// (beta_j, alpha_j, beta_{j+1}) at rows j-1, j, j+1. The orthogonality
+// estimate (and the measured local term c_j c_{j+1} <u_j, u_{j+1}>) decide a
+// second Gram-Schmidt pass; otherwise (or after that pass: second = 1, where
+// z_{j+1} was recomputed) the Givens step of every pole runs.
+__global__ __launch_bounds__(TPB) void k_lz_end(Work W, ShiftWork SW, int j, int second) {
+  __shared__ double lds[NWAVE];
+  __shared__ int reo_sh;
+  const int s = blockIdx.x;
+  if (s >= W.S) return;
+  SysState_t& st = W.st[s];
+  if (st.state != ST_ACTIVE) return;
+  if (second && !st.reorth) return;
+  const SysDesc& d = W.sys[s];
+  const int m = W.m;
+  const double2* part = reinterpret_cast<const double2*>(W.part) + d.pbase;
+  double nn = 0.0, uz = 0.0, oux = 0.0, ouy = 0.0;
+  for (int t = threadIdx.x; t < d.ntiles; t += TPB) {
+    nn += W.pnorm[d.tile0 + t];
+    uz += part[t].x;
+    if (!second) {
+      oux += part[d.ntiles + t].x;
+      ouy += part[d.ntiles + t].y;
+    }
+  }
+  nn = block_sum(nn, lds);
+  uz = block_sum(uz, lds);
+  oux = block_sum(oux, lds);
+  ouy = block_sum(ouy, lds);
+  const double beta1 = sqrt(nn);
+  const double c1 = beta1 > 0.0 ? 1.0 / beta1 : 0.0;
+  double2* hcol = reinterpret_cast<double2*>(W.H) + (int64_t)s * (m + 1) * m + (int64_t)j * (m + 1);
+  if (!second) {
+    for (int i = threadIdx.x; i + 1 < j; i += TPB) hcol[i] = make_double2(0.0, 0.0);
+    if (threadIdx.x == 0) {
+      if (j > 0) hcol[j - 1] = make_double2(SW.beta[(int64_t)s * (m + 1) + j], 0.0);
+      hcol[j] = make_double2(SW.alpha[(int64_t)s * m + j], 0.0);
+    }
+  }
+  __syncthreads();
+  if (!second) {
+    bool reo = false;
+    if (SW.lanczos) reo = pro_decide(W, SW, s, j, beta1);
+    if (threadIdx.x == 0) {
+      const double cj = W.cscale[(int64_t)s * (m + 1) + j];
+      const double loc = cj * c1 * sqrt(oux * oux + ouy * ouy);
+      if (loc > 1.4901161193847656e-08) reo = true;  // local orthogonality lost beyond sqrt(u)
+      st.reorth = reo ? 1 : 0;
+      reo_sh = reo ? 1 : 0;
+      if (reo && SW.pause_mode) {
+        st.state = ST_PAUSED;
+        SW.flags[4 * s + 2] = j;
+      }
+    }
+    __syncthreads();
+    if (reo_sh) return;
+  }
+  if (threadIdx.x == 0 && j + 1 < m) SW.alpha[(int64_t)s * m + j + 1] = c1 * c1 * uz;
+  givens_shifted(W, SW, s, j, beta1, !second);
 }
 
 // Shared basis, after the last iteration: back substitution R_p y_p = g_p per

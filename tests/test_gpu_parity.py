@@ -265,8 +265,10 @@ def test_adjoint_matches_oracle(rexi):
 # ---------------------------------------------------------------- shared basis
 @pytest.mark.parametrize("name,scale,K,R1,m,lz", [("1d_harmonic", None, 16, 28.0, 200, 1),
                                                   ("1d_harmonic", None, 16, 28.0, 200, 0),
+                                                  ("1d_harmonic", None, 16, 28.0, 200, 2),
                                                   ("3d_bumps", 12, 64, 180.0, 120, 1),
                                                   ("3d_bumps", 12, 64, 180.0, 120, 0),
+                                                  ("3d_bumps", 12, 64, 180.0, 120, 2),
                                                   ("2d_adjoint", 33, 32, 80.0, 200, 1),
                                                   ("3d_bumps", 13, 16, 32.0, 120, 1)])
 def test_shifted_solver_fp64(rexi, name, scale, K, R1, m, lz):
