@@ -642,6 +642,9 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
     hipLaunchKernelGGL(rexi::k_shifted_init, dim3(S), dim3(TPB), 0, stream, W, h->SW);
   }
   const bool pipe = h->opt.lanczos == 1;
+  // the LDS-staged pass needs a row (n2 points) of halo on each side in LDS
+  bool lds_ok = true;
+  for (auto& d : sv.hsys) lds_ok = lds_ok && d.n2 <= 512;
   if (pipe) {
     {
       Timed t(h, PC_START, n * 48.0, stream);
@@ -710,7 +713,10 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
     if (pipe) {
       {
         Timed t(h, PC_LANCZOS, n * (j > 0 ? 88.0 : 72.0), strm);
-        hipLaunchKernelGGL((rexi::k_lz_step<PPT>), dim3(G), dim3(TPB), 0, strm, W, SWl, j);
+        if (lds_ok)
+          hipLaunchKernelGGL((rexi::k_lz_step_lds<PPT, 512>), dim3(G), dim3(TPB), 0, strm, W, SWl, j);
+        else
+          hipLaunchKernelGGL((rexi::k_lz_step<PPT>), dim3(G), dim3(TPB), 0, strm, W, SWl, j);
       }
       {
         Timed t(h, PC_REDUCE, 0, strm);
@@ -926,8 +932,13 @@ void tune_launch(rexi_handle* h, Solver& sv, const double2* b, int iters, hipStr
   if (h->shifted && h->opt.lanczos == 1) {
     hipLaunchKernelGGL((rexi::k_lz_matvec<PPT>), dim3(G), dim3(TPB), 0, st, W, h->SW, 0, 0, 0);
     hipLaunchKernelGGL(rexi::k_lz_start, dim3(S), dim3(TPB), 0, st, W, h->SW);
+    bool lds_ok = true;
+    for (auto& d : sv.hsys) lds_ok = lds_ok && d.n2 <= 512;
     for (int j = 0; j < iters && j < sv.m; ++j) {
-      hipLaunchKernelGGL((rexi::k_lz_step<PPT>), dim3(G), dim3(TPB), 0, st, W, h->SW, j);
+      if (lds_ok)
+        hipLaunchKernelGGL((rexi::k_lz_step_lds<PPT, 512>), dim3(G), dim3(TPB), 0, st, W, h->SW, j);
+      else
+        hipLaunchKernelGGL((rexi::k_lz_step<PPT>), dim3(G), dim3(TPB), 0, st, W, h->SW, j);
       hipLaunchKernelGGL(rexi::k_lz_end, dim3(S), dim3(TPB), 0, st, W, h->SW, j, 0);
     }
     return;

@@ -581,18 +581,40 @@ __device__ void givens_shifted(Work& W, ShiftWork& SW, int s, int j, double beta
     double2* gsv = reinterpret_cast<double2*>(SW.gs) + (int64_t)p * m;
     double2* g = reinterpret_cast<double2*>(SW.g) + (int64_t)p * (m + 1);
     const double2 sp = reinterpret_cast<const double2*>(SW.s)[p];
-    for (int i = i_start; i <= j; ++i) col[i] = hcol[i];
-    col[j].x -= sp.x;
-    col[j].y -= sp.y;
-    for (int i = i_start; i < j; ++i) {
-      const double2 c = gcv[i], sn = gsv[i];
-      const double2 a = col[i], b = col[i + 1];
-      const double2 t1 = cjmul(c, a), t2 = cjmul(sn, b);
-      const double2 u1 = cmul(sn, a), u2 = cmul(c, b);
-      col[i] = make_double2(t1.x + t2.x, t1.y + t2.y);
-      col[i + 1] = make_double2(u2.x - u1.x, u2.y - u1.y);
+    double2 a;
+    if (banded) {
+      // column j holds rows j-1 and j only: the rotations j-2 and j-1 act on it,
+      // in registers (rows j-2, j-1 of R receive the results)
+      double2 am1 = j >= 1 ? hcol[j - 1] : make_double2(0.0, 0.0);
+      double2 aj = make_double2(hcol[j].x - sp.x, hcol[j].y - sp.y);
+      if (j >= 2) {
+        const double2 c = gcv[j - 2], sn = gsv[j - 2];
+        // (0, am1) -> (conj(s) am1, c am1)
+        col[j - 2] = cjmul(sn, am1);
+        am1 = cmul(c, am1);
+      }
+      if (j >= 1) {
+        const double2 c = gcv[j - 1], sn = gsv[j - 1];
+        const double2 t1 = cjmul(c, am1), t2 = cjmul(sn, aj);
+        const double2 u1 = cmul(sn, am1), u2 = cmul(c, aj);
+        col[j - 1] = make_double2(t1.x + t2.x, t1.y + t2.y);
+        aj = make_double2(u2.x - u1.x, u2.y - u1.y);
+      }
+      a = aj;
+    } else {
+      for (int i = i_start; i <= j; ++i) col[i] = hcol[i];
+      col[j].x -= sp.x;
+      col[j].y -= sp.y;
+      for (int i = i_start; i < j; ++i) {
+        const double2 c = gcv[i], sn = gsv[i];
+        const double2 aa = col[i], b = col[i + 1];
+        const double2 t1 = cjmul(c, aa), t2 = cjmul(sn, b);
+        const double2 u1 = cmul(sn, aa), u2 = cmul(c, b);
+        col[i] = make_double2(t1.x + t2.x, t1.y + t2.y);
+        col[i + 1] = make_double2(u2.x - u1.x, u2.y - u1.y);
+      }
+      a = col[j];
     }
-    const double2 a = col[j];
     const double den = sqrt(a.x * a.x + a.y * a.y + beta * beta);
     double2 c, sn;
     if (den > 0.0) {
@@ -853,6 +875,97 @@ __global__ __launch_bounds__(TPB) void k_lz_step(Work W, ShiftWork SW, int j) {
         if (k + 1 < (uint32_t)d.n2) { const double2 v = U(p + 1); nb2.x += v.x; nb2.y += v.y; }
         if (jj > 0) { const double2 v = U(p - d.n2); nb1.x += v.x; nb1.y += v.y; }
         if (jj + 1 < (uint32_t)d.n1) { const double2 v = U(p + d.n2); nb1.x += v.x; nb1.y += v.y; }
+        if (i0 > 0) { const double2 v = U(p - plane); nb0.x += v.x; nb0.y += v.y; }
+        if (i0 + 1 < (uint32_t)d.n0) { const double2 v = U(p + plane); nb0.x += v.x; nb0.y += v.y; }
+        const double a = d.diag + W.V64[d.off + p];
+        double2 hz;
+        hz.x = a * c.x - (d.c2 * nb2.x + d.c1 * nb1.x + d.c0 * nb0.x);
+        hz.y = a * c.y - (d.c2 * nb2.y + d.c1 * nb1.y + d.c0 * nb0.y);
+        un[p] = c;
+        zn[p] = hz;
+        const double2 u0 = uj[p];
+        uzx += c.x * hz.x + c.y * hz.y;
+        uzy += c.x * hz.y - c.y * hz.x;
+        oux += u0.x * c.x + u0.y * c.y;
+        ouy += u0.x * c.y - u0.y * c.x;
+        nn += c.x * c.x + c.y * c.y;
+      }
+    }
+    uzx = block_sum(uzx, lds);
+    uzy = block_sum(uzy, lds);
+    oux = block_sum(oux, lds);
+    ouy = block_sum(ouy, lds);
+    nn = block_sum(nn, lds);
+    if (threadIdx.x == 0) {
+      double2* part = reinterpret_cast<double2*>(W.part) + d.pbase;
+      part[t] = make_double2(uzx, uzy);
+      part[d.ntiles + t] = make_double2(oux, ouy);
+      W.pnorm[item] = nn;
+    }
+  }
+}
+
+
+// k_lz_step with u_{j+1} staged in LDS for the tile and a halo of one row
+// (n2 points) on each side, so the in-plane neighbours are read from LDS and
+// only the neighbours in the adjacent planes are formed from global memory.
+// Requires n2 <= HMAX for every system.
+template <int PPT, int HMAX>
+__global__ __launch_bounds__(TPB) void k_lz_step_lds(Work W, ShiftWork SW, int j) {
+  __shared__ double lds[NWAVE];
+  __shared__ double2 ub[TPB * PPT + 2 * HMAX];
+  const int m = W.m;
+  for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
+    const int s = find_sys(W.tile_start, W.S, item);
+    const SysState_t& st = W.st[s];
+    if (st.state != ST_ACTIVE) continue;
+    const SysDesc& d = W.sys[s];
+    const int t = item - d.tile0;
+    const double cj = W.cscale[(int64_t)s * (m + 1) + j];
+    const double cjm = j > 0 ? W.cscale[(int64_t)s * (m + 1) + j - 1] : 0.0;
+    const double ka = SW.alpha[(int64_t)s * m + j] * cj;
+    const double kb = j > 0 ? SW.beta[(int64_t)s * (m + 1) + j] * cjm : 0.0;
+    const double2* __restrict__ z = reinterpret_cast<const double2*>(SW.zb) + (j & 1) * SW.zstride + d.xoff;
+    double2* __restrict__ zn = reinterpret_cast<double2*>(SW.zb) + ((j + 1) & 1) * SW.zstride + d.xoff;
+    const double2* __restrict__ uj = basis_vec<double2>(W, d, j);
+    const double2* __restrict__ ujm = basis_vec<double2>(W, d, j > 0 ? j - 1 : 0);
+    double2* __restrict__ un = basis_vec<double2>(W, d, j + 1);
+    const bool three = j > 0;
+    auto U = [&](uint32_t q) -> double2 {
+      const double2 a = z[q];
+      const double2 b = uj[q];
+      double2 r = make_double2(cj * a.x - ka * b.x, cj * a.y - ka * b.y);
+      if (three) {
+        const double2 c = ujm[q];
+        r.x -= kb * c.x;
+        r.y -= kb * c.y;
+      }
+      return r;
+    };
+    const int T0 = t * W.tile;
+    const int T1 = min(T0 + W.tile, d.n);
+    const int L0 = max(0, T0 - d.n2);
+    const int L1 = min(d.n, T1 + d.n2);
+    __syncthreads();  // ub of the previous item is no longer read
+    for (int q = L0 + (int)threadIdx.x; q < L1; q += TPB) ub[q - L0] = U((uint32_t)q);
+    __syncthreads();
+    const uint32_t plane = (uint32_t)d.n1 * (uint32_t)d.n2;
+    double uzx = 0.0, uzy = 0.0, oux = 0.0, ouy = 0.0, nn = 0.0;
+#pragma unroll 2
+    for (int q = 0; q < PPT; ++q) {
+      const int pi = T0 + q * TPB + threadIdx.x;
+      if (pi < T1) {
+        const uint32_t p = (uint32_t)pi;
+        const uint32_t r = fdiv(p, d.d2);
+        const uint32_t k = p - r * (uint32_t)d.n2;
+        const uint32_t i0 = fdiv(r, d.d1);
+        const uint32_t jj = r - i0 * (uint32_t)d.n1;
+        const double2 c = ub[pi - L0];
+        double2 nb2 = make_double2(0.0, 0.0), nb1 = nb2, nb0 = nb2;
+        if (k > 0) { const double2 v = ub[pi - 1 - L0]; nb2.x += v.x; nb2.y += v.y; }
+        if (k + 1 < (uint32_t)d.n2) { const double2 v = ub[pi + 1 - L0]; nb2.x += v.x; nb2.y += v.y; }
+        if (jj > 0) { const double2 v = ub[pi - d.n2 - L0]; nb1.x += v.x; nb1.y += v.y; }
+        if (jj + 1 < (uint32_t)d.n1) { const double2 v = ub[pi + d.n2 - L0]; nb1.x += v.x; nb1.y += v.y; }
         if (i0 > 0) { const double2 v = U(p - plane); nb0.x += v.x; nb0.y += v.y; }
         if (i0 + 1 < (uint32_t)d.n0) { const double2 v = U(p + plane); nb0.x += v.x; nb0.y += v.y; }
         const double a = d.diag + W.V64[d.off + p];
