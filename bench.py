@@ -218,6 +218,7 @@ def main():
     final_info = h.step(cur, out, 1, info=True)
     torch.cuda.synchronize()
     ws_bytes, m_used = h.workspace()
+    tiling = h.tiling()
     h.close()
 
     # kernel region: the same steps with HIP events around every kernel launch
@@ -288,7 +289,7 @@ def main():
                            else "per-pole complex128 GMRES")
                         + f", per-pole rel. residual {args.tol:g}, Krylov dimension <= {m_used}",
             "grid": list(g.n), "poles": wl.K, "precision": args.precision, "solver": args.solver,
-            "graph_replay": bool(args.capture),
+            "graph_replay": bool(args.capture), "tiling": tiling,
         },
         "solve": {
             "iterations_per_step": int(final_info["total_iterations"]),

@@ -131,6 +131,17 @@ typedef struct {
                           setup and keep the fastest (cached per problem
                           shape; REXI_TUNE_CACHE names an optional file)     */
   int64_t max_workspace_bytes; /* device workspace cap, 0 = 90% of free     */
+  int32_t march_planes; /* fused Lanczos pass of the shared-basis solver
+                           (lanczos = 1): 0 (default) the tuner chooses
+                           between the row-staged pass and the pass that
+                           marches along the slowest grid axis (without
+                           tuning: the row-staged pass); -1 the row-staged
+                           pass; 1..1024 the marching pass with that many
+                           planes per work item (row-staged where a system's
+                           band of rows does not fit)                         */
+  int32_t march_slots;  /* marching pass: points per thread and plane, 3, 5
+                           or 8 (0 = 5); a band holds 256 slots / n2 - 2
+                           rows of the plane                                 */
 } rexi_options;
 
 typedef struct {
@@ -241,6 +252,20 @@ rexi_status rexi_profile_reset(rexi_handle* h);
 
 /* Device bytes held by the handle's workspaces, and the restart length used. */
 rexi_status rexi_workspace_info(const rexi_handle* h, int64_t* bytes, int32_t* m_used);
+
+typedef struct {
+  int32_t tile;          /* points per work tile of the grid-stride passes    */
+  int32_t grid_blocks;   /* workgroups of the grid-stride passes              */
+  int32_t march_slots;   /* fused Lanczos pass: 0 row-staged, else points per
+                            thread and plane of the marching pass             */
+  int32_t march_planes;  /* planes per marching work item (0: row-staged)     */
+  int32_t march_items;   /* marching work items over all instances            */
+  int32_t reserved_;
+} rexi_tiling;
+
+/* The tiling in use (chosen by the tuner or given in the options). Fills
+ * *out; REXI_E_INVALID_ARG for a NULL argument. */
+rexi_status rexi_tiling_info(const rexi_handle* h, rexi_tiling* out);
 
 /* Release the handle and its workspaces (NULL is a no-op). */
 rexi_status rexi_destroy(rexi_handle* h);

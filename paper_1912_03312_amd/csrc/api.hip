@@ -52,6 +52,10 @@ struct Solver {
   Work W{};
   SysDesc* dsys = nullptr;
   int32_t* dtile = nullptr;
+  // column-marching Lanczos pass (0: the row-staged pass)
+  int col_kh = 0, col_L = 0, col_total = 0;
+  std::vector<int32_t> hcol;
+  int32_t* dcol = nullptr;
   bool ready = false;
 };
 
@@ -252,6 +256,40 @@ void layout_systems(Solver& sv, int m) {
 
 constexpr int TPB_ = rexi::TPB;
 
+// Column-marching Lanczos pass: kh slots per thread cover a band of rows of
+// the (i1, i2) plane and one halo row on each side; an item spans L planes.
+// Fills the descriptors and the item prefix; false (nothing changed) if a
+// system's rows do not fit or its items outnumber its partial-sum slots.
+bool plan_columns(Solver& sv, int kh, int L) {
+  struct Plan { int rows, Lc, nr, n; };
+  std::vector<Plan> pl;
+  for (auto& d : sv.hsys) {
+    const int rows = std::min(d.n1, TPB_ * kh / d.n2 - 2);
+    if (rows < 1) return false;
+    const int nb = (d.n1 + rows - 1) / rows;
+    const int Lc = std::min(L, d.n0);
+    const int nr = (d.n0 + Lc - 1) / Lc;
+    if ((int64_t)nb * nr > d.ntiles) return false;
+    pl.push_back({rows, Lc, nr, nb * nr});
+  }
+  sv.hcol.clear();
+  int total = 0;
+  for (size_t i = 0; i < sv.hsys.size(); ++i) {
+    SysDesc& d = sv.hsys[i];
+    d.col_rows = pl[i].rows;
+    d.col_L = pl[i].Lc;
+    d.col_nr = pl[i].nr;
+    d.col_n = pl[i].n;
+    sv.hcol.push_back(total);
+    total += pl[i].n;
+  }
+  sv.hcol.push_back(total);
+  sv.col_total = total;
+  sv.col_kh = kh;
+  sv.col_L = L;
+  return true;
+}
+
 rexi_status build_solver(rexi_handle* h, Solver& sv, hipStream_t stream) {
   const int m = sv.m, S = sv.S;
   Work& W = sv.W;
@@ -261,6 +299,7 @@ rexi_status build_solver(rexi_handle* h, Solver& sv, hipStream_t stream) {
   if ((st = dalloc(h, sv, (type**)&(ptr), (size_t)(count))) != REXI_OK) return st
   ALLOC(sv.dsys, SysDesc, S);
   ALLOC(sv.dtile, int32_t, S + 1);
+  ALLOC(sv.dcol, int32_t, S + 1);
   SysState_t* dst;
   ALLOC(dst, SysState_t, S);
   W.st = dst;
@@ -622,6 +661,26 @@ rexi_status init_shifted(rexi_handle* h, hipStream_t stream) {
   return REXI_OK;
 }
 
+// The fused Lanczos pass of iteration j: the marching pass when a column plan
+// is selected, else the row-staged pass (n2 <= 512) or the plain one.
+template <int PPT>
+void launch_lz_step(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork& SW, int j, hipStream_t strm) {
+  if (sv.col_kh) {
+    const dim3 g(sv.col_total);
+    switch (sv.col_kh) {
+      case 3: hipLaunchKernelGGL((rexi::k_lz_step_col<3>), g, dim3(TPB), 0, strm, W, SW, j); return;
+      case 5: hipLaunchKernelGGL((rexi::k_lz_step_col<5>), g, dim3(TPB), 0, strm, W, SW, j); return;
+      default: hipLaunchKernelGGL((rexi::k_lz_step_col<8>), g, dim3(TPB), 0, strm, W, SW, j); return;
+    }
+  }
+  bool lds_ok = true;  // the row-staged pass keeps a row of halo on each side in LDS
+  for (auto& d : sv.hsys) lds_ok = lds_ok && d.n2 <= 512;
+  if (lds_ok)
+    hipLaunchKernelGGL((rexi::k_lz_step_lds<PPT, 512>), dim3(sv.grid), dim3(TPB), 0, strm, W, SW, j);
+  else
+    hipLaunchKernelGGL((rexi::k_lz_step<PPT>), dim3(sv.grid), dim3(TPB), 0, strm, W, SW, j);
+}
+
 // One shared-basis solve of all poles of every instance; writes the pole sums to out.
 template <typename T, int PPT>
 rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStream_t stream) {
@@ -642,9 +701,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
     hipLaunchKernelGGL(rexi::k_shifted_init, dim3(S), dim3(TPB), 0, stream, W, h->SW);
   }
   const bool pipe = h->opt.lanczos == 1;
-  // the LDS-staged pass needs a row (n2 points) of halo on each side in LDS
-  bool lds_ok = true;
-  for (auto& d : sv.hsys) lds_ok = lds_ok && d.n2 <= 512;
+  const int colparts = sv.col_kh ? 1 : 0;
   if (pipe) {
     {
       Timed t(h, PC_START, n * 48.0, stream);
@@ -688,7 +745,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
       }
       {
         Timed t(h, PC_REDUCE, 0, strm);
-        hipLaunchKernelGGL(rexi::k_lz_end, dim3(S), dim3(TPB), 0, strm, W, SWl, j, 1);
+        hipLaunchKernelGGL(rexi::k_lz_end, dim3(S), dim3(TPB), 0, strm, W, SWl, j, 1, 0);
       }
       return;
     }
@@ -713,14 +770,11 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
     if (pipe) {
       {
         Timed t(h, PC_LANCZOS, n * (j > 0 ? 88.0 : 72.0), strm);
-        if (lds_ok)
-          hipLaunchKernelGGL((rexi::k_lz_step_lds<PPT, 512>), dim3(G), dim3(TPB), 0, strm, W, SWl, j);
-        else
-          hipLaunchKernelGGL((rexi::k_lz_step<PPT>), dim3(G), dim3(TPB), 0, strm, W, SWl, j);
+        launch_lz_step<PPT>(sv, W, SWl, j, strm);
       }
       {
         Timed t(h, PC_REDUCE, 0, strm);
-        hipLaunchKernelGGL(rexi::k_lz_end, dim3(S), dim3(TPB), 0, strm, W, SWl, j, 0);
+        hipLaunchKernelGGL(rexi::k_lz_end, dim3(S), dim3(TPB), 0, strm, W, SWl, j, 0, colparts);
       }
       if (!pause_mode) second_pass(j, strm, G2);
       return;
@@ -854,6 +908,7 @@ rexi_status shifted_step(rexi_handle* h, const double2* b, double2* out, hipStre
 struct TuneKey {
   std::string key;
   int ppt, grid;
+  int kh, L;  // fused Lanczos pass: 0 row-staged, else marching slots and planes
 };
 std::vector<TuneKey>& tune_cache() {
   static std::vector<TuneKey> c;
@@ -885,19 +940,20 @@ void tune_cache_load() {
   char line[4096];
   while (fgets(line, sizeof line, fp)) {
     char key[4000];
-    int ppt, grid;
-    if (sscanf(line, "%3999s %d %d", key, &ppt, &grid) == 3) tune_cache().push_back({key, ppt, grid});
+    int ppt, grid, kh = 0, L = 0;
+    if (sscanf(line, "%3999s %d %d %d %d", key, &ppt, &grid, &kh, &L) >= 3)
+      tune_cache().push_back({key, ppt, grid, kh, L});
   }
   fclose(fp);
 }
 
-void tune_cache_store(const std::string& key, int ppt, int grid) {
-  tune_cache().push_back({key, ppt, grid});
+void tune_cache_store(const std::string& key, int ppt, int grid, int kh, int L) {
+  tune_cache().push_back({key, ppt, grid, kh, L});
   const char* f = getenv("REXI_TUNE_CACHE");
   if (!f) return;
   FILE* fp = fopen(f, "a");
   if (!fp) return;
-  fprintf(fp, "%s %d %d\n", key.c_str(), ppt, grid);
+  fprintf(fp, "%s %d %d %d %d\n", key.c_str(), ppt, grid, kh, L);
   fclose(fp);
 }
 
@@ -911,6 +967,27 @@ rexi_status apply_tiling(rexi_handle* h, Solver& sv, int ppt, int grid, hipStrea
   HIPCHK(h, hipMemcpyAsync(sv.dsys, sv.hsys.data(), sv.S * sizeof(SysDesc), hipMemcpyHostToDevice, stream));
   HIPCHK(h, hipMemcpyAsync(sv.dtile, sv.htile.data(), (sv.S + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
   HIPCHK(h, hipStreamSynchronize(stream));
+  sv.col_kh = 0;  // a new tiling invalidates the column plan
+  if (h->shifted) {
+    h->SW.col_start = nullptr;
+    h->SW.col_total = 0;
+  }
+  return REXI_OK;
+}
+
+// Select the fused Lanczos pass: kh = 0 the row-staged pass, else the
+// marching pass with kh slots and L planes per item. REXI_OK with the
+// row-staged pass when the plan does not fit.
+rexi_status apply_columns(rexi_handle* h, Solver& sv, int kh, int L, hipStream_t stream) {
+  sv.col_kh = 0;
+  h->SW.col_start = nullptr;
+  h->SW.col_total = 0;
+  if (kh == 0 || !plan_columns(sv, kh, L)) return REXI_OK;
+  HIPCHK(h, hipMemcpyAsync(sv.dsys, sv.hsys.data(), sv.S * sizeof(SysDesc), hipMemcpyHostToDevice, stream));
+  HIPCHK(h, hipMemcpyAsync(sv.dcol, sv.hcol.data(), (sv.S + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  HIPCHK(h, hipStreamSynchronize(stream));
+  h->SW.col_start = sv.dcol;
+  h->SW.col_total = sv.col_total;
   return REXI_OK;
 }
 
@@ -932,14 +1009,9 @@ void tune_launch(rexi_handle* h, Solver& sv, const double2* b, int iters, hipStr
   if (h->shifted && h->opt.lanczos == 1) {
     hipLaunchKernelGGL((rexi::k_lz_matvec<PPT>), dim3(G), dim3(TPB), 0, st, W, h->SW, 0, 0, 0);
     hipLaunchKernelGGL(rexi::k_lz_start, dim3(S), dim3(TPB), 0, st, W, h->SW);
-    bool lds_ok = true;
-    for (auto& d : sv.hsys) lds_ok = lds_ok && d.n2 <= 512;
     for (int j = 0; j < iters && j < sv.m; ++j) {
-      if (lds_ok)
-        hipLaunchKernelGGL((rexi::k_lz_step_lds<PPT, 512>), dim3(G), dim3(TPB), 0, st, W, h->SW, j);
-      else
-        hipLaunchKernelGGL((rexi::k_lz_step<PPT>), dim3(G), dim3(TPB), 0, st, W, h->SW, j);
-      hipLaunchKernelGGL(rexi::k_lz_end, dim3(S), dim3(TPB), 0, st, W, h->SW, j, 0);
+      launch_lz_step<PPT>(sv, W, h->SW, j, st);
+      hipLaunchKernelGGL(rexi::k_lz_end, dim3(S), dim3(TPB), 0, st, W, h->SW, j, 0, sv.col_kh ? 1 : 0);
     }
     return;
   }
@@ -955,8 +1027,13 @@ void tune_launch(rexi_handle* h, Solver& sv, const double2* b, int iters, hipStr
 rexi_status autotune(rexi_handle* h, Solver& sv, hipStream_t stream) {
   tune_cache_load();
   const std::string key = tune_key(h, sv);
+  const bool march = h->shifted && h->opt.lanczos == 1 && h->opt.march_planes == 0;
   for (auto& c : tune_cache())
-    if (c.key == key) return apply_tiling(h, sv, c.ppt, c.grid, stream);
+    if (c.key == key) {
+      rexi_status st = apply_tiling(h, sv, c.ppt, c.grid, stream);
+      if (st == REXI_OK && march) st = apply_columns(h, sv, c.kh, c.L, stream);
+      return st;
+    }
   double2* rhs = nullptr;
   if (hipMalloc(&rhs, (size_t)h->N * sizeof(double2)) != hipSuccess) {
     (void)hipGetLastError();
@@ -1001,11 +1078,46 @@ rexi_status autotune(rexi_handle* h, Solver& sv, hipStream_t stream) {
       }
     }
   }
+  rexi_status st = apply_tiling(h, sv, best_ppt, best_grid, stream);
+  // second stage (pipelined Lanczos): the row-staged pass against the
+  // marching pass over slots x planes per item, on the chosen tiling
+  int best_kh = 0, best_L = 0;
+  if (st == REXI_OK && march) {
+    best = 1e30f;
+    for (int kh : {0, 3, 5, 8}) {
+      for (int L : {4, 8, 16}) {
+        if (kh == 0 && L != 4) continue;
+        if ((st = apply_columns(h, sv, kh, L, stream)) != REXI_OK) break;
+        if (sv.col_kh != kh) continue;  // the plan does not fit
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+          HIPCHK(h, hipEventRecord(e0, stream));
+          switch (best_ppt) {
+            case 8: tune_launch<double2, 8>(h, sv, rhs, 3 * iters, stream); break;
+            case 4: tune_launch<double2, 4>(h, sv, rhs, 3 * iters, stream); break;
+            default: tune_launch<double2, 2>(h, sv, rhs, 3 * iters, stream); break;
+          }
+          HIPCHK(h, hipEventRecord(e1, stream));
+          HIPCHK(h, hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+          tmin = std::min(tmin, ms);
+        }
+        if (tmin < best) {
+          best = tmin;
+          best_kh = kh;
+          best_L = L;
+        }
+      }
+      if (st != REXI_OK) break;
+    }
+    if (st == REXI_OK) st = apply_columns(h, sv, best_kh, best_L, stream);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(rhs);
-  tune_cache_store(key, best_ppt, best_grid);
-  return apply_tiling(h, sv, best_ppt, best_grid, stream);
+  if (st == REXI_OK) tune_cache_store(key, best_ppt, best_grid, best_kh, best_L);
+  return st;
 }
 
 InstDesc make_inst(const rexi_grid& g, double hbar, double mass, int64_t off) {
@@ -1064,6 +1176,10 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   if (o.grid_blocks < 0) return fail(nullptr, REXI_E_INVALID_ARG, "grid_blocks < 0");
   if (o.tile != 0 && o.tile != 512 && o.tile != 1024 && o.tile != 2048)
     return fail(nullptr, REXI_E_INVALID_ARG, "tile must be 0 (tuned), 512, 1024 or 2048 points");
+  if (o.march_planes < -1 || o.march_planes > 1024)
+    return fail(nullptr, REXI_E_INVALID_ARG, "march_planes must be in [-1, 1024]");
+  if (o.march_slots != 0 && o.march_slots != 3 && o.march_slots != 5 && o.march_slots != 8)
+    return fail(nullptr, REXI_E_INVALID_ARG, "march_slots must be 0, 3, 5 or 8");
 
   // ---- validate the instances (host side, before any device work)
   int64_t N = 0, Ktot = 0;
@@ -1193,13 +1309,13 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
     destroy_handle(h);
     return st;
   }
-  if (o.autotune && o.tile == 0 && o.grid_blocks == 0) {
-    st = autotune(h, h->fwd, stream);
-    if (st != REXI_OK) {
-      g_setup_error = h->err;
-      destroy_handle(h);
-      return st;
-    }
+  if (o.autotune && o.tile == 0 && o.grid_blocks == 0) st = autotune(h, h->fwd, stream);
+  if (st == REXI_OK && h->shifted && o.lanczos == 1 && o.march_planes > 0)
+    st = apply_columns(h, h->fwd, o.march_slots ? o.march_slots : 5, o.march_planes, stream);
+  if (st != REXI_OK) {
+    g_setup_error = h->err;
+    destroy_handle(h);
+    return st;
   }
   h->prof.on = o.profile != 0;
   *out = h;
@@ -1265,6 +1381,8 @@ void rexi_default_options(rexi_options* o) {
   o->tile = 0;
   o->grid_blocks = 0;
   o->max_workspace_bytes = 0;
+  o->march_planes = 0;
+  o->march_slots = 0;
 }
 
 rexi_status rexi_setup(rexi_handle** out, const rexi_grid* g, const double* V_dev, double hbar, double mass,
@@ -1508,6 +1626,17 @@ rexi_status rexi_workspace_info(const rexi_handle* h, int64_t* bytes, int32_t* m
   if (!h) return REXI_E_INVALID_ARG;
   if (bytes) *bytes = h->ws_bytes;
   if (m_used) *m_used = h->fwd.m;
+  return REXI_OK;
+}
+
+rexi_status rexi_tiling_info(const rexi_handle* h, rexi_tiling* out) {
+  if (!h || !out) return REXI_E_INVALID_ARG;
+  out->tile = h->fwd.tile;
+  out->grid_blocks = h->fwd.grid;
+  out->march_slots = h->fwd.col_kh;
+  out->march_planes = h->fwd.col_kh ? h->fwd.col_L : 0;
+  out->march_items = h->fwd.col_kh ? h->fwd.col_total : 0;
+  out->reserved_ = 0;
   return REXI_OK;
 }
 

@@ -88,6 +88,42 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
   return s;
 }
 
+// Thread-strided sum of p[0..n) with eight independent loads per thread in
+// flight (the partial sums of a pass are written by other compute dies, so
+// every load is a round trip to memory; a load-add chain would serialise them).
+__device__ __forceinline__ double strided_sum(const double* __restrict__ p, int n) {
+  double acc = 0.0;
+  for (int b = 0; b < n; b += 8 * TPB) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = b + u * TPB + (int)threadIdx.x;
+      v[u] = t < n ? p[t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  return acc;
+}
+
+__device__ __forceinline__ double2 strided_sum2(const double2* __restrict__ p, int n) {
+  double ax = 0.0, ay = 0.0;
+  for (int b = 0; b < n; b += 8 * TPB) {
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = b + u * TPB + (int)threadIdx.x;
+      v[u] = t < n ? p[t] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      ax += v[u].x;
+      ay += v[u].y;
+    }
+  }
+  return make_double2(ax, ay);
+}
+
 // Locate the system of global tile `item` (tile_start is the prefix array).
 __device__ __forceinline__ int find_sys(const int32_t* tile_start, int S, int item) {
   int lo = 0, hi = S;  // invariant: tile_start[lo] <= item < tile_start[hi]
@@ -220,8 +256,7 @@ __global__ __launch_bounds__(TPB) void k_start_reduce(Work W) {
     const int nc = W.max_cycles * (W.m + 1) + 2;
     for (int i = threadIdx.x; i < nc; i += TPB) W.counters[i] = 0;
   }
-  double acc = 0.0;
-  for (int t = threadIdx.x; t < d.ntiles; t += TPB) acc += W.pnorm[d.tile0 + t];
+  double acc = strided_sum(W.pnorm + d.tile0, d.ntiles);
   acc = block_sum(acc, lds);
   if (threadIdx.x == 0) {
     const double bn = sqrt(acc);
@@ -277,6 +312,8 @@ struct ShiftWork {
   int32_t* full;      // [S][m] 1 if column j of Hbar has entries above row j - 1
   double* zb;         // [2][sum n] complex: z_j = H u_j of the pipelined recurrence
   int64_t zstride;    // complex elements per z buffer
+  const int32_t* col_start;  // [S+1] prefix of column-marching items (null: unused)
+  int32_t col_total;
 };
 
 // Grid (S, j + 2): block (s, i) with lo <= i <= j reduces the tile partials
@@ -298,8 +335,7 @@ __global__ __launch_bounds__(TPB) void k_reduce_dots(Work W, int j, int second, 
   double2* hc = reinterpret_cast<double2*>(W.hcur) + (int64_t)s * (W.m + 1);
   if (i == j + 1) {
     if (second) return;
-    double wn = 0.0;
-    for (int t = threadIdx.x; t < d.ntiles; t += TPB) wn += W.pnorm[d.tile0 + t];
+    double wn = strided_sum(W.pnorm + d.tile0, d.ntiles);
     wn = block_sum(wn, lds);
     if (threadIdx.x == 0) st.w2 = wn;
     return;
@@ -312,12 +348,8 @@ __global__ __launch_bounds__(TPB) void k_reduce_dots(Work W, int j, int second, 
     return;
   }
   const double2* part = reinterpret_cast<const double2*>(W.part) + d.pbase + (int64_t)i * d.ntiles;
-  double ax = 0.0, ay = 0.0;
-  for (int t = threadIdx.x; t < d.ntiles; t += TPB) {
-    const double2 v = part[t];
-    ax += v.x;
-    ay += v.y;
-  }
+  const double2 av = strided_sum2(part, d.ntiles);
+  double ax = av.x, ay = av.y;
   ax = block_sum(ax, lds);
   ay = block_sum(ay, lds);
   if (threadIdx.x == 0) {
@@ -818,8 +850,7 @@ __global__ __launch_bounds__(TPB) void k_lz_start(Work W, ShiftWork SW) {
   if (s >= W.S) return;
   if (W.st[s].state != ST_ACTIVE) return;
   const SysDesc& d = W.sys[s];
-  double ax = 0.0;
-  for (int t = threadIdx.x; t < d.ntiles; t += TPB) ax += reinterpret_cast<const double2*>(W.part)[d.pbase + t].x;
+  double ax = strided_sum2(reinterpret_cast<const double2*>(W.part) + d.pbase, d.ntiles).x;
   ax = block_sum(ax, lds);
   if (threadIdx.x == 0) {
     const double c0 = W.cscale[(int64_t)s * (W.m + 1)];
@@ -996,13 +1027,185 @@ __global__ __launch_bounds__(TPB) void k_lz_step_lds(Work W, ShiftWork SW, int j
   }
 }
 
+// k_lz_step marching along the slowest axis (2.5D blocking). A work item is
+// a band of col_rows rows (n2 points each) of the (i1, i2) plane over col_L
+// consecutive planes i0. Per plane, u_{j+1} is formed once for the band and
+// one halo row on each side into LDS (two buffers: the plane being applied
+// and the next one); the values of the planes before and after stay in
+// registers. Each input of the item is read once, apart from the halo rows
+// and the two planes bounding the range. Slots: h = threadIdx.x + q TPB over
+// the (col_rows + 2) n2 points of the band with its halo rows.
+// Items are ordered band-major over the plane ranges, so with col_nr a
+// multiple of 8 the bands of one plane range share a compute die (blocks go
+// round-robin over the 8 dies) and the halo rows they share hit its L2.
+template <int KH>
+__global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j) {
+  __shared__ double lds[NWAVE];
+  __shared__ double2 ub[2][TPB * KH];
+  const int m = W.m;
+  for (int item = blockIdx.x; item < SW.col_total; item += gridDim.x) {
+    const int s = find_sys(SW.col_start, W.S, item);
+    const SysState_t& st = W.st[s];
+    if (st.state != ST_ACTIVE) continue;
+    const SysDesc& d = W.sys[s];
+    const int t = item - SW.col_start[s];
+    const int band = t / d.col_nr;
+    const int rng = t - band * d.col_nr;
+    const int r0 = band * d.col_rows;
+    const int r1 = min(d.n1, r0 + d.col_rows);
+    const int ia = rng * d.col_L;
+    const int ib = min(d.n0, ia + d.col_L);
+    const int nslot = (r1 - r0 + 2) * d.n2;
+    const uint32_t plane = (uint32_t)d.n1 * (uint32_t)d.n2;
+    const double cj = W.cscale[(int64_t)s * (m + 1) + j];
+    const double cjm = j > 0 ? W.cscale[(int64_t)s * (m + 1) + j - 1] : 0.0;
+    const double ka = SW.alpha[(int64_t)s * m + j] * cj;
+    const double kb = j > 0 ? SW.beta[(int64_t)s * (m + 1) + j] * cjm : 0.0;
+    const double2* __restrict__ z = reinterpret_cast<const double2*>(SW.zb) + (j & 1) * SW.zstride + d.xoff;
+    double2* __restrict__ zn = reinterpret_cast<double2*>(SW.zb) + ((j + 1) & 1) * SW.zstride + d.xoff;
+    const double2* __restrict__ uj = basis_vec<double2>(W, d, j);
+    const double2* __restrict__ ujm = basis_vec<double2>(W, d, j > 0 ? j - 1 : 0);
+    double2* __restrict__ un = basis_vec<double2>(W, d, j + 1);
+    const double* __restrict__ V = W.V64 + d.off;
+    const bool three = j > 0;
+    // slot geometry: in-plane offset, row, column; valid = row inside the grid,
+    // own = row inside the band
+    uint32_t po[KH];
+    int rw[KH], cl[KH];
+    bool valid[KH], own[KH];
+#pragma unroll
+    for (int q = 0; q < KH; ++q) {
+      const int h = (int)threadIdx.x + q * TPB;
+      const int sr = (int)fdiv((uint32_t)h, d.d2);
+      const int row = r0 - 1 + sr;
+      cl[q] = h - sr * d.n2;
+      rw[q] = row;
+      valid[q] = h < nslot && row >= 0 && row < d.n1;
+      own[q] = valid[q] && row >= r0 && row < r1;
+      po[q] = valid[q] ? (uint32_t)row * (uint32_t)d.n2 + (uint32_t)cl[q] : 0u;
+    }
+    // inputs of one plane in flight (z_j, u_j, u_{j-1} at the slots, V at
+    // the band): loaded one plane ahead of their use
+    double2 rz[KH], ru[KH], rm[KH];
+    double rv[KH];
+    auto fetch = [&](int i, bool halo) {
+      const uint32_t base = (uint32_t)i * plane;
+#pragma unroll
+      for (int q = 0; q < KH; ++q) {
+        rz[q] = make_double2(0.0, 0.0);
+        ru[q] = rz[q];
+        rm[q] = rz[q];
+        rv[q] = 0.0;
+        if (halo ? valid[q] : own[q]) {
+          const uint32_t p = base + po[q];
+          rz[q] = z[p];
+          ru[q] = uj[p];
+          if (three) rm[q] = ujm[p];
+          if (own[q]) rv[q] = V[p];
+        }
+      }
+    };
+    // u_{j+1} = c_j z_j - alpha_j c_j u_j - beta_j c_{j-1} u_{j-1} from the fetched inputs
+    auto form = [&](double2 (&dst)[KH], double2 (&ujv)[KH], double (&vv)[KH]) {
+#pragma unroll
+      for (int q = 0; q < KH; ++q) {
+        dst[q] = make_double2(cj * rz[q].x - ka * ru[q].x - kb * rm[q].x, cj * rz[q].y - ka * ru[q].y - kb * rm[q].y);
+        ujv[q] = ru[q];
+        vv[q] = rv[q];
+      }
+    };
+    double2 prv[KH], cur[KH], nxt[KH], ujc[KH], ujn[KH];
+    double vc[KH], vn[KH];
+    if (ia > 0) {
+      fetch(ia - 1, false);
+      form(prv, ujn, vn);
+    } else {
+#pragma unroll
+      for (int q = 0; q < KH; ++q) prv[q] = make_double2(0.0, 0.0);
+    }
+    fetch(ia, true);
+    __syncthreads();  // ub of the previous item is no longer read
+    form(cur, ujc, vc);
+#pragma unroll
+    for (int q = 0; q < KH; ++q)
+      if (valid[q]) ub[0][threadIdx.x + q * TPB] = cur[q];
+    if (ia + 1 < d.n0) fetch(ia + 1, ia + 1 < ib);
+    __syncthreads();
+    int cb = 0;
+    double uzx = 0.0, uzy = 0.0, oux = 0.0, ouy = 0.0, nn = 0.0;
+    for (int i = ia; i < ib; ++i) {
+      if (i + 1 < d.n0) {
+        // the next plane; with its halo rows when this item applies H to it
+        form(nxt, ujn, vn);
+        if (i + 1 < ib) {
+#pragma unroll
+          for (int q = 0; q < KH; ++q)
+            if (valid[q]) ub[cb ^ 1][threadIdx.x + q * TPB] = nxt[q];
+        }
+        // the plane after it: in flight during this plane's stencil
+        if (i + 2 < d.n0 && i + 2 <= ib) fetch(i + 2, i + 2 < ib);
+      } else {
+#pragma unroll
+        for (int q = 0; q < KH; ++q) nxt[q] = make_double2(0.0, 0.0);
+      }
+      const uint32_t base = (uint32_t)i * plane;
+#pragma unroll
+      for (int q = 0; q < KH; ++q) {
+        if (own[q]) {
+          const int h = (int)threadIdx.x + q * TPB;
+          const double2 c = cur[q];
+          double2 nb2 = make_double2(0.0, 0.0), nb1 = nb2;
+          if (cl[q] > 0) { const double2 v = ub[cb][h - 1]; nb2.x += v.x; nb2.y += v.y; }
+          if (cl[q] + 1 < d.n2) { const double2 v = ub[cb][h + 1]; nb2.x += v.x; nb2.y += v.y; }
+          if (rw[q] > 0) { const double2 v = ub[cb][h - d.n2]; nb1.x += v.x; nb1.y += v.y; }
+          if (rw[q] + 1 < d.n1) { const double2 v = ub[cb][h + d.n2]; nb1.x += v.x; nb1.y += v.y; }
+          const double2 nb0 = make_double2(prv[q].x + nxt[q].x, prv[q].y + nxt[q].y);
+          const uint32_t p = base + po[q];
+          const double a = d.diag + vc[q];
+          double2 hz;
+          hz.x = a * c.x - (d.c2 * nb2.x + d.c1 * nb1.x + d.c0 * nb0.x);
+          hz.y = a * c.y - (d.c2 * nb2.y + d.c1 * nb1.y + d.c0 * nb0.y);
+          un[p] = c;
+          zn[p] = hz;
+          const double2 u0 = ujc[q];
+          uzx += c.x * hz.x + c.y * hz.y;
+          uzy += c.x * hz.y - c.y * hz.x;
+          oux += u0.x * c.x + u0.y * c.y;
+          ouy += u0.x * c.y - u0.y * c.x;
+          nn += c.x * c.x + c.y * c.y;
+        }
+      }
+      __syncthreads();  // buffer cb is read, buffer cb ^ 1 is written
+#pragma unroll
+      for (int q = 0; q < KH; ++q) {
+        prv[q] = cur[q];
+        cur[q] = nxt[q];
+        ujc[q] = ujn[q];
+        vc[q] = vn[q];
+      }
+      cb ^= 1;
+    }
+    uzx = block_sum(uzx, lds);
+    uzy = block_sum(uzy, lds);
+    oux = block_sum(oux, lds);
+    ouy = block_sum(ouy, lds);
+    nn = block_sum(nn, lds);
+    if (threadIdx.x == 0) {
+      double2* part = reinterpret_cast<double2*>(W.part) + d.pbase;
+      part[t] = make_double2(uzx, uzy);
+      part[d.ntiles + t] = make_double2(oux, ouy);
+      W.pnorm[d.tile0 + t] = nn;
+    }
+  }
+}
+
 // Grid S: end of pipelined iteration j. beta_{j+1} = ||u_{j+1}||,
 // alpha_{j+1} = c_{j+1}^2 Re <u_{j+1}, z_{j+1}>; column j of Hbar is
 // (beta_j, alpha_j, beta_{j+1}) at rows j-1, j, j+1. The orthogonality
 // estimate (and the measured local term c_j c_{j+1} <u_j, u_{j+1}>) decide a
 // second Gram-Schmidt pass; otherwise (or after that pass: second = 1, where
 // z_{j+1} was recomputed) the Givens step of every pole runs.
-__global__ __launch_bounds__(TPB) void k_lz_end(Work W, ShiftWork SW, int j, int second) {
+__global__ __launch_bounds__(TPB) void k_lz_end(Work W, ShiftWork SW, int j, int second, int colparts) {
   __shared__ double lds[NWAVE];
   __shared__ int reo_sh;
   const int s = blockIdx.x;
@@ -1013,14 +1216,15 @@ __global__ __launch_bounds__(TPB) void k_lz_end(Work W, ShiftWork SW, int j, int
   const SysDesc& d = W.sys[s];
   const int m = W.m;
   const double2* part = reinterpret_cast<const double2*>(W.part) + d.pbase;
-  double nn = 0.0, uz = 0.0, oux = 0.0, ouy = 0.0;
-  for (int t = threadIdx.x; t < d.ntiles; t += TPB) {
-    nn += W.pnorm[d.tile0 + t];
-    uz += part[t].x;
-    if (!second) {
-      oux += part[d.ntiles + t].x;
-      ouy += part[d.ntiles + t].y;
-    }
+  // partial sums per tile, or per column item after the column-marching pass
+  const int np = colparts ? d.col_n : d.ntiles;
+  double nn = strided_sum(W.pnorm + d.tile0, np);
+  double uz = strided_sum2(part, np).x;
+  double oux = 0.0, ouy = 0.0;
+  if (!second) {
+    const double2 o = strided_sum2(part + d.ntiles, np);
+    oux = o.x;
+    ouy = o.y;
   }
   nn = block_sum(nn, lds);
   uz = block_sum(uz, lds);
@@ -1228,8 +1432,7 @@ __global__ __launch_bounds__(TPB) void k_restart(Work W, int cycle) {
   SysState_t& st = W.st[s];
   if (st.state != ST_FINISH) return;
   const SysDesc& d = W.sys[s];
-  double acc = 0.0;
-  for (int t = threadIdx.x; t < d.ntiles; t += TPB) acc += W.pnorm[d.tile0 + t];
+  double acc = strided_sum(W.pnorm + d.tile0, d.ntiles);
   acc = block_sum(acc, lds);
   if (threadIdx.x != 0) return;
   const double rn = sqrt(acc);

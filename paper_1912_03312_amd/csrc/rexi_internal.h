@@ -55,7 +55,12 @@ struct SysDesc {
   int32_t ntiles;    // work tiles of this system
   int32_t rhs_sel;   // 0 or 1
   int32_t pbase;     // offset of the system's partial-sum block
-  int32_t pad;
+  // column-marching Lanczos pass: items of col_rows rows (n2 points each)
+  // of the (i1, i2) plane over col_L consecutive planes, col_nr plane ranges
+  int32_t col_rows;
+  int32_t col_L;
+  int32_t col_nr;
+  int32_t col_n;     // items of the system (col_n = ceil(n1/col_rows) col_nr)
 };
 
 // Instance descriptor (pole sum, apply_H).

@@ -29,7 +29,7 @@ SOLVER_PER_POLE, SOLVER_SHIFTED = 0, 1
 #: every entry point the header declares
 EXPORTS = ("rexi_default_options", "rexi_setup", "rexi_setup_batch", "rexi_apply_H", "rexi_step",
            "rexi_step_adjoint", "rexi_get_profile", "rexi_profile_reset", "rexi_workspace_info",
-           "rexi_destroy", "rexi_status_string", "rexi_last_error")
+           "rexi_tiling_info", "rexi_destroy", "rexi_status_string", "rexi_last_error")
 
 
 class c128(C.Structure):
@@ -48,7 +48,7 @@ class Options(C.Structure):
                 ("check_every", C.c_int32), ("lanczos", C.c_int32), ("capture_safe", C.c_int32),
                 ("capture_cycles", C.c_int32), ("graph_chunks", C.c_int32),
                 ("profile", C.c_int32), ("tile", C.c_int32), ("grid_blocks", C.c_int32), ("autotune", C.c_int32),
-                ("max_workspace_bytes", C.c_int64)]
+                ("max_workspace_bytes", C.c_int64), ("march_planes", C.c_int32), ("march_slots", C.c_int32)]
 
 
 class StepInfo(C.Structure):
@@ -59,6 +59,11 @@ class StepInfo(C.Structure):
                 ("norm_in", C.c_double), ("norm_out", C.c_double),
                 ("iterations", C.POINTER(C.c_int32)), ("cycles", C.POINTER(C.c_int32)),
                 ("rel_residual", C.POINTER(C.c_double))]
+
+
+class Tiling(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("grid_blocks", C.c_int32), ("march_slots", C.c_int32),
+                ("march_planes", C.c_int32), ("march_items", C.c_int32), ("reserved_", C.c_int32)]
 
 
 class Profile(C.Structure):
@@ -81,6 +86,7 @@ _lib.rexi_step_adjoint.argtypes = [_H, _P, _P, _P, _P, _P]
 _lib.rexi_get_profile.argtypes = [_H, C.POINTER(Profile)]
 _lib.rexi_profile_reset.argtypes = [_H]
 _lib.rexi_workspace_info.argtypes = [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+_lib.rexi_tiling_info.argtypes = [_H, C.POINTER(Tiling)]
 _lib.rexi_destroy.argtypes = [_H]
 _lib.rexi_status_string.argtypes = [C.c_int]
 _lib.rexi_status_string.restype = C.c_char_p
@@ -223,6 +229,12 @@ class Handle:
 
     def profile_reset(self):
         _check(_lib.rexi_profile_reset(self._h), self._h)
+
+    def tiling(self) -> dict:
+        """``rexi_tiling_info``: the tiling and fused Lanczos pass in use."""
+        t = Tiling()
+        _check(_lib.rexi_tiling_info(self._h, C.byref(t)), self._h)
+        return {k: int(getattr(t, k)) for k, _ in Tiling._fields_ if k != "reserved_"}
 
     def workspace(self):
         b = C.c_int64()

@@ -78,7 +78,8 @@ def test_invalid_arguments_are_rejected_without_device(rx, case):
 
 
 @pytest.mark.parametrize("field,value", [("m", 0), ("m", 257), ("reorth_eta", 0.0), ("reorth_eta", 1.0), ("solver", 5), ("max_cycles", 0), ("tol", -1.0),
-                                         ("precision", 7), ("reorth", 3), ("inner_rtol", 1.5)])
+                                         ("precision", 7), ("reorth", 3), ("inner_rtol", 1.5),
+                                         ("march_planes", -2), ("march_planes", 1025), ("march_slots", 4)])
 def test_invalid_options(rx, field, value):
     o = rx.default_options()
     setattr(o, field, value)
@@ -90,6 +91,7 @@ def test_null_pointers(rx):
     assert rx._lib.rexi_setup(None, None, None, 1.0, 1.0, 1.0, 1, None, None, None, None) == rx.REXI_E_INVALID_ARG
     assert rx._lib.rexi_step(None, None, None, 1, None, None) == rx.REXI_E_INVALID_ARG
     assert rx._lib.rexi_destroy(None) == rx.REXI_OK
+    assert rx._lib.rexi_tiling_info(None, None) == rx.REXI_E_INVALID_ARG
 
 
 def test_shifted_solver_option_constraints(rx):

@@ -448,6 +448,81 @@ def test_uneven_batch_matches_oracle_per_instance(rexi, solver, prec):
     h.close()
 
 
+# ---------------------------------------------------------------- marching pass
+def _centred_grid(shape, h=0.25):
+    return inputs.Grid(tuple(shape), tuple(-0.5 * h * (k + 1) for k in shape), tuple(0.5 * h * (k + 1) for k in shape))
+
+
+@pytest.mark.parametrize("shape,planes,slots,fits", [
+    ((7, 23, 60), 4, 3, True),    # bands of 10 rows (10 + 10 + 3), plane ranges 4 + 3
+    ((9, 13, 17), 4, 5, True),    # one band of 13 rows, ranges 4 + 4 + 1
+    ((4, 40, 100), 16, 8, True),  # bands 18 + 18 + 4, one range shorter than the item
+    ((37, 41), 8, 5, True),       # 2D: one plane, bands 29 + 8
+    ((300,), 4, 5, True),         # 1D: one row
+    ((1000,), 4, 3, False),       # a row longer than the slots: row-staged pass
+])
+def test_marching_lanczos_pass(rexi, shape, planes, slots, fits):
+    # the fused Lanczos pass that marches along the slowest axis, over ragged
+    # bands and plane ranges, against the sparse direct oracle (2 steps)
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    g = _centred_grid(shape)
+    V = inputs.gaussian_bumps(g, 7)
+    psi0 = inputs.seeded_packet(g, 30, (0.0,) * g.ndim, 1.0)
+    s, b, d = poles(64, 180.0)
+    dt = 1.0
+    D = ost.DirectStepper(g.n, g.h, V, s, b, dt)
+    ref = [D.step(psi0)]
+    ref.append(D.step(ref[0]))
+    Vd = to_dev(V.ravel())
+    h = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, dt, s, b, solver="shifted", m=200, tol=1e-11,
+                tol_policy="certified", check_every=2, tile=512, march_planes=planes, march_slots=slots)
+    t = h.tiling()
+    assert t["march_slots"] == (slots if fits else 0), t
+    cur = to_dev(psi0.ravel())
+    nxt = torch.empty_like(cur)
+    errs, infos = [], []
+    for k in range(2):
+        infos.append(h.step(cur, nxt, 1))
+        torch.cuda.synchronize()
+        errs.append(rel(nxt.cpu().numpy(), ref[k].ravel()))
+        cur, nxt = nxt, cur
+    h.close()
+    bar = max(1e-10, 3 * iterative_floor(g, V, s, b, dt))
+    print("marching", shape, planes, slots, t, errs, "bar", bar, [i["total_iterations"] for i in infos])
+    assert max(errs) <= bar
+    assert all(i["not_converged"] == 0 for i in infos)
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_marching_matches_row_staged_pass(rexi, n):
+    # at the benchmarked size and below, every marching configuration the
+    # tuner may pick agrees with the row-staged pass within the certified bounds
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    wl = inputs.workload("3d_bumps", scale=n)
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+    Vd = to_dev(wl.V.ravel())
+    p0 = to_dev(wl.psi0.ravel())
+    outs, bounds, tilings = [], [], []
+    for planes, slots in [(-1, 0), (4, 3), (8, 5), (16, 8), (7, 5)]:
+        h = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, wl.dt, s, b, solver="shifted", m=100, tol=1e-12,
+                    tol_policy="certified", tile=1024, march_planes=planes, march_slots=slots)
+        tilings.append(h.tiling())
+        o = torch.empty_like(p0)
+        info = h.step(p0, o, 1)
+        assert info["not_converged"] == 0
+        outs.append(o.cpu().numpy())
+        bounds.append(info["certified_bound"])
+        h.close()
+    print("marching vs row-staged", n, tilings, bounds, [rel(o, outs[0]) for o in outs[1:]])
+    assert tilings[0]["march_slots"] == 0
+    assert all(t["march_slots"] > 0 for t in tilings[1:])
+    for o, bd in zip(outs[1:], bounds[1:]):
+        assert rel(o, outs[0]) <= bd + bounds[0] + 1e-13
+
+
 @pytest.mark.parametrize("solver", ["shifted", "per_pole"])
 def test_tilings_agree(rexi, solver):
     # every tiling the autotuner may pick computes the same step
