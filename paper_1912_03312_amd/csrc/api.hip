@@ -745,7 +745,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
       }
       {
         Timed t(h, PC_REDUCE, 0, strm);
-        hipLaunchKernelGGL(rexi::k_lz_end, dim3(S), dim3(TPB), 0, strm, W, SWl, j, 1, 0);
+        hipLaunchKernelGGL(rexi::k_lz_end_second, dim3(S), dim3(TPB), 0, strm, W, SWl, j);
       }
       return;
     }
@@ -774,7 +774,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
       }
       {
         Timed t(h, PC_REDUCE, 0, strm);
-        hipLaunchKernelGGL(rexi::k_lz_end, dim3(S), dim3(TPB), 0, strm, W, SWl, j, 0, colparts);
+        hipLaunchKernelGGL(rexi::k_lz_end, dim3(S), dim3(TPB), 0, strm, W, SWl, j, colparts);
       }
       if (!pause_mode) second_pass(j, strm, G2);
       return;
@@ -1011,7 +1011,7 @@ void tune_launch(rexi_handle* h, Solver& sv, const double2* b, int iters, hipStr
     hipLaunchKernelGGL(rexi::k_lz_start, dim3(S), dim3(TPB), 0, st, W, h->SW);
     for (int j = 0; j < iters && j < sv.m; ++j) {
       launch_lz_step<PPT>(sv, W, h->SW, j, st);
-      hipLaunchKernelGGL(rexi::k_lz_end, dim3(S), dim3(TPB), 0, st, W, h->SW, j, 0, sv.col_kh ? 1 : 0);
+      hipLaunchKernelGGL(rexi::k_lz_end, dim3(S), dim3(TPB), 0, st, W, h->SW, j, sv.col_kh ? 1 : 0);
     }
     return;
   }

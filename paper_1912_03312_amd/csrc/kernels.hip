@@ -1199,67 +1199,260 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
   }
 }
 
-// Grid S: end of pipelined iteration j. beta_{j+1} = ||u_{j+1}||,
+// Sums of four per-thread values over the block (one LDS exchange).
+__device__ __forceinline__ void block_sum4(double& a, double& b, double& c, double& e, double* l4) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  e = wave_sum(e);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    l4[wid] = a;
+    l4[NWAVE + wid] = b;
+    l4[2 * NWAVE + wid] = c;
+    l4[3 * NWAVE + wid] = e;
+  }
+  __syncthreads();
+  a = b = c = e = 0.0;
+#pragma unroll
+  for (int w = 0; w < NWAVE; ++w) {
+    a += l4[w];
+    b += l4[NWAVE + w];
+    c += l4[2 * NWAVE + w];
+    e += l4[3 * NWAVE + w];
+  }
+}
+
+__device__ __forceinline__ double block_max(double v, double* l) {
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) l[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < NWAVE; ++w) r = fmax(r, l[w]);
+  return r;
+}
+
+// Grid S: end of pipelined iteration j (first pass). beta_{j+1} = ||u_{j+1}||,
 // alpha_{j+1} = c_{j+1}^2 Re <u_{j+1}, z_{j+1}>; column j of Hbar is
 // (beta_j, alpha_j, beta_{j+1}) at rows j-1, j, j+1. The orthogonality
-// estimate (and the measured local term c_j c_{j+1} <u_j, u_{j+1}>) decide a
-// second Gram-Schmidt pass; otherwise (or after that pass: second = 1, where
-// z_{j+1} was recomputed) the Givens step of every pole runs.
-__global__ __launch_bounds__(TPB) void k_lz_end(Work W, ShiftWork SW, int j, int second, int colparts) {
-  __shared__ double lds[NWAVE];
+// estimate (Simon's recurrence, as in pro_decide) and the measured local
+// term c_j c_{j+1} <u_j, u_{j+1}> decide a second Gram-Schmidt pass;
+// otherwise the banded Givens step of every pole runs. A single block with a
+// chain of small dependent steps: every global value the block needs (tile
+// partials, the alpha/beta/omega history, the poles' rotations) is loaded
+// up front, so the chain costs about two memory round trips. Requires
+// poles per instance <= TPB for the register path (others take a loop).
+__global__ __launch_bounds__(TPB) void k_lz_end(Work W, ShiftWork SW, int j, int colparts) {
+  __shared__ double l4[4 * NWAVE];
+  __shared__ double hist[4][MAXM + 2];  // alpha, beta, omega row j, omega row j-1
   __shared__ int reo_sh;
   const int s = blockIdx.x;
   if (s >= W.S) return;
+  const int tid = threadIdx.x;
+  const int m = W.m;
   SysState_t& st = W.st[s];
-  if (st.state != ST_ACTIVE) return;
-  if (second && !st.reorth) return;
+  // round trip 1: state, descriptor, pole range
+  const int state = st.state;
+  const SysDesc& d = W.sys[s];
+  const int ntiles = d.ntiles, pbase = d.pbase, tile0 = d.tile0, np = colparts ? d.col_n : d.ntiles;
+  const int npts = d.n;
+  const int p0 = SW.pole0[s], p1 = SW.pole0[s + 1];
+  if (state != ST_ACTIVE) return;
+  double* alpha = SW.alpha + (int64_t)s * m;
+  double* betav = SW.beta + (int64_t)s * (m + 1);
+  double* omega = SW.omega + (int64_t)s * 2 * (m + 1);
+  double* wprev = omega + (int64_t)((j + 1) & 1) * (m + 1);  // row j-1, becomes row j+1
+  double* wcur = omega + (int64_t)(j & 1) * (m + 1);         // row j
+  if (j == 0 && tid == 0) wcur[0] = 1.0;                     // omega_{0,0}
+  // round trip 2: everything else
+  const double2* part = reinterpret_cast<const double2*>(W.part) + pbase;
+  double nn = strided_sum(W.pnorm + tile0, np);
+  double uz = strided_sum2(part, np).x;
+  const double2 ou = strided_sum2(part + ntiles, np);
+  double oux = ou.x, ouy = ou.y;
+  if (tid <= j) {
+    hist[0][tid] = alpha[tid];
+    hist[1][tid] = betav[tid];
+    hist[2][tid] = j == 0 ? 1.0 : wcur[tid];
+    hist[3][tid] = tid < j ? wprev[tid] : 0.0;
+  }
+  double cj = 0.0;
+  int force = 0;
+  if (tid == 0) {
+    cj = W.cscale[(int64_t)s * (m + 1) + j];
+    force = SW.flags[4 * s];
+  }
+  // the first TPB poles: rotations j-2, j-1 and g_j in registers
+  const int p = p0 + tid;
+  const bool hasp = p < p1;
+  double2 cA = make_double2(1.0, 0.0), sA = make_double2(0.0, 0.0), cB = cA, sB = sA, gj = sA, sp = sA;
+  double tolp = 0.0;
+  int itsp = 1;
+  if (hasp) {
+    const double2* gcv = reinterpret_cast<const double2*>(SW.gc) + (int64_t)p * m;
+    const double2* gsv = reinterpret_cast<const double2*>(SW.gs) + (int64_t)p * m;
+    if (j >= 2) {
+      cA = gcv[j - 2];
+      sA = gsv[j - 2];
+    }
+    if (j >= 1) {
+      cB = gcv[j - 1];
+      sB = gsv[j - 1];
+    }
+    gj = reinterpret_cast<const double2*>(SW.g)[(int64_t)p * (m + 1) + j];
+    sp = reinterpret_cast<const double2*>(SW.s)[p];
+    tolp = SW.tol[p];
+    itsp = SW.its[p];
+  }
+  // partial sums, and max_{k<j} |alpha_k| + beta_k + beta_{k+1} (the k = j
+  // term needs beta_{j+1}) in the same exchange
+  block_sum4(nn, uz, oux, ouy, l4);
+  const double beta1 = sqrt(nn);
+  const double c1 = beta1 > 0.0 ? 1.0 / beta1 : 0.0;
+  const double aj = hist[0][j], bj = hist[1][j];
+  double an = tid < j ? fabs(hist[0][tid]) + hist[1][tid] + hist[1][tid + 1] : 0.0;
+  an = block_max(an, l4);
+  const double anorm = fmax(an, fabs(aj) + bj + beta1);
+  // column j of Hbar (its rows above j - 1 are zero; a second pass adds to them)
+  double2* hcol = reinterpret_cast<double2*>(W.H) + (int64_t)s * (m + 1) * m + (int64_t)j * (m + 1);
+  for (int i = tid; i + 1 < j; i += TPB) hcol[i] = make_double2(0.0, 0.0);
+  if (tid == 0) {
+    if (j > 0) hcol[j - 1] = make_double2(bj, 0.0);
+    hcol[j] = make_double2(aj, 0.0);
+    betav[j + 1] = beta1;
+  }
+  // omega row j+1 from rows j and j-1
+  const double u = 1.1102230246251565e-16;
+  const double eps1 = sqrt((double)npts) * u;
+  double v = 0.0;
+  if (tid < j) {
+    const int k = tid;
+    v = hist[1][k + 1] * hist[2][k + 1] + (hist[0][k] - aj) * hist[2][k] +
+        (k > 0 ? hist[1][k] * hist[2][k - 1] : 0.0) - bj * hist[3][k];
+    v += copysign(2.0 * u * anorm, v);
+    v = beta1 > 0.0 ? v / beta1 : 1.0;
+  }
+  const double wmax = block_max(fabs(v), l4);
+  if (tid == 0) {
+    const bool est = force || wmax > sqrt(u);
+    const double loc = cj * c1 * sqrt(oux * oux + ouy * ouy);  // local loss beyond sqrt(u)
+    const bool reo = est || loc > 1.4901161193847656e-08;
+    if (est) {
+      SW.flags[4 * s] = force ? 0 : 1;  // an estimate-driven pass covers the next vector too
+      SW.flags[4 * s + 1] += 1;
+    }
+    st.reorth = reo ? 1 : 0;
+    if (reo && SW.pause_mode) {
+      st.state = ST_PAUSED;
+      SW.flags[4 * s + 2] = j;
+    }
+    reo_sh = reo ? 1 : 0;
+  }
+  __syncthreads();
+  const bool reo = reo_sh != 0;
+  // a reorthogonalised vector has estimates eps1 against all earlier ones
+  if (tid < j) wprev[tid] = reo ? eps1 : v;
+  if (tid == 0) {
+    wprev[j] = eps1;
+    wprev[j + 1] = 1.0;
+  }
+  if (reo) return;  // the second pass follows, then k_lz_end_second
+  if (tid == 0 && j + 1 < m) alpha[j + 1] = c1 * c1 * uz;
+  // banded Givens step of every pole: column j holds beta_j (row j-1) and
+  // alpha_j - s_p (row j); rotations j-2 and j-1 act on it, then the new
+  // rotation j annihilates beta_{j+1}
+  const double bn = st.bnorm;
+  double unconv = 0.0;
+  for (int q = p; q < p1; q += TPB) {
+    if (q != p) {  // poles beyond the first TPB: load here
+      const double2* gcv = reinterpret_cast<const double2*>(SW.gc) + (int64_t)q * m;
+      const double2* gsv = reinterpret_cast<const double2*>(SW.gs) + (int64_t)q * m;
+      cA = j >= 2 ? gcv[j - 2] : make_double2(1.0, 0.0);
+      sA = j >= 2 ? gsv[j - 2] : make_double2(0.0, 0.0);
+      cB = j >= 1 ? gcv[j - 1] : make_double2(1.0, 0.0);
+      sB = j >= 1 ? gsv[j - 1] : make_double2(0.0, 0.0);
+      gj = reinterpret_cast<const double2*>(SW.g)[(int64_t)q * (m + 1) + j];
+      sp = reinterpret_cast<const double2*>(SW.s)[q];
+      tolp = SW.tol[q];
+      itsp = SW.its[q];
+    }
+    double2* col = reinterpret_cast<double2*>(SW.R) + (int64_t)q * (m + 1) * m + (int64_t)j * (m + 1);
+    double2 am1 = make_double2(j >= 1 ? bj : 0.0, 0.0);
+    double2 a = make_double2(aj - sp.x, -sp.y);
+    if (j >= 2) {
+      col[j - 2] = cjmul(sA, am1);  // (0, am1) -> (conj(s) am1, c am1)
+      am1 = cmul(cA, am1);
+    }
+    if (j >= 1) {
+      const double2 t1 = cjmul(cB, am1), t2 = cjmul(sB, a);
+      const double2 u1 = cmul(sB, am1), u2 = cmul(cB, a);
+      col[j - 1] = make_double2(t1.x + t2.x, t1.y + t2.y);
+      a = make_double2(u2.x - u1.x, u2.y - u1.y);
+    }
+    const double den = sqrt(a.x * a.x + a.y * a.y + beta1 * beta1);
+    double2 c, sn;
+    if (den > 0.0) {
+      c = make_double2(a.x / den, a.y / den);
+      sn = make_double2(beta1 / den, 0.0);
+    } else {
+      c = make_double2(1.0, 0.0);
+      sn = make_double2(0.0, 0.0);
+    }
+    reinterpret_cast<double2*>(SW.gc)[(int64_t)q * m + j] = c;
+    reinterpret_cast<double2*>(SW.gs)[(int64_t)q * m + j] = sn;
+    col[j] = make_double2(den, 0.0);
+    double2* g = reinterpret_cast<double2*>(SW.g) + (int64_t)q * (m + 1);
+    const double2 gn = make_double2(-(sn.x * gj.x - sn.y * gj.y), -(sn.x * gj.y + sn.y * gj.x));
+    g[j + 1] = gn;
+    g[j] = cjmul(c, gj);
+    const double res = sqrt(gn.x * gn.x + gn.y * gn.y);
+    SW.res[q] = bn > 0.0 ? res / bn : 0.0;
+    const bool conv = res <= 0.5 * tolp * bn || beta1 == 0.0 || !(res == res);
+    if (conv) {
+      if (itsp == 0) SW.its[q] = j + 1;
+    } else {
+      unconv += 1.0;
+    }
+  }
+  double z0 = 0.0, z1 = 0.0, z2 = 0.0;
+  block_sum4(unconv, z0, z1, z2, l4);
+  if (tid == 0) {
+    const int k = j + 1;
+    SW.full[(int64_t)s * m + j] = 0;
+    double* Hs = W.H + (int64_t)s * (m + 1) * m * 2;
+    Hs[(int64_t)j * (m + 1) * 2 + 2 * (j + 1)] = beta1;  // h_{j+1,j}
+    Hs[(int64_t)j * (m + 1) * 2 + 2 * (j + 1) + 1] = 0.0;
+    W.cscale[(int64_t)s * (m + 1) + j + 1] = beta1 > 0.0 ? 1.0 / beta1 : 0.0;
+    st.kcyc = k;
+    st.its = k;
+    if (unconv == 0.0 || k == m) st.state = ST_FINISH;
+    else atomicAdd(&W.counters[j], 1);
+  }
+}
+
+// Grid S: end of pipelined iteration j after a second Gram-Schmidt pass
+// (z_{j+1} was recomputed): beta_{j+1}, alpha_{j+1} from the new partials,
+// then the Givens step of every pole on the full column.
+__global__ __launch_bounds__(TPB) void k_lz_end_second(Work W, ShiftWork SW, int j) {
+  __shared__ double lds[NWAVE];
+  const int s = blockIdx.x;
+  if (s >= W.S) return;
+  SysState_t& st = W.st[s];
+  if (st.state != ST_ACTIVE || !st.reorth) return;
   const SysDesc& d = W.sys[s];
   const int m = W.m;
   const double2* part = reinterpret_cast<const double2*>(W.part) + d.pbase;
-  // partial sums per tile, or per column item after the column-marching pass
-  const int np = colparts ? d.col_n : d.ntiles;
-  double nn = strided_sum(W.pnorm + d.tile0, np);
-  double uz = strided_sum2(part, np).x;
-  double oux = 0.0, ouy = 0.0;
-  if (!second) {
-    const double2 o = strided_sum2(part + d.ntiles, np);
-    oux = o.x;
-    ouy = o.y;
-  }
+  double nn = strided_sum(W.pnorm + d.tile0, d.ntiles);
+  double uz = strided_sum2(part, d.ntiles).x;
   nn = block_sum(nn, lds);
   uz = block_sum(uz, lds);
-  oux = block_sum(oux, lds);
-  ouy = block_sum(ouy, lds);
   const double beta1 = sqrt(nn);
   const double c1 = beta1 > 0.0 ? 1.0 / beta1 : 0.0;
-  double2* hcol = reinterpret_cast<double2*>(W.H) + (int64_t)s * (m + 1) * m + (int64_t)j * (m + 1);
-  if (!second) {
-    for (int i = threadIdx.x; i + 1 < j; i += TPB) hcol[i] = make_double2(0.0, 0.0);
-    if (threadIdx.x == 0) {
-      if (j > 0) hcol[j - 1] = make_double2(SW.beta[(int64_t)s * (m + 1) + j], 0.0);
-      hcol[j] = make_double2(SW.alpha[(int64_t)s * m + j], 0.0);
-    }
-  }
-  __syncthreads();
-  if (!second) {
-    bool reo = false;
-    if (SW.lanczos) reo = pro_decide(W, SW, s, j, beta1);
-    if (threadIdx.x == 0) {
-      const double cj = W.cscale[(int64_t)s * (m + 1) + j];
-      const double loc = cj * c1 * sqrt(oux * oux + ouy * ouy);
-      if (loc > 1.4901161193847656e-08) reo = true;  // local orthogonality lost beyond sqrt(u)
-      st.reorth = reo ? 1 : 0;
-      reo_sh = reo ? 1 : 0;
-      if (reo && SW.pause_mode) {
-        st.state = ST_PAUSED;
-        SW.flags[4 * s + 2] = j;
-      }
-    }
-    __syncthreads();
-    if (reo_sh) return;
-  }
   if (threadIdx.x == 0 && j + 1 < m) SW.alpha[(int64_t)s * m + j + 1] = c1 * c1 * uz;
-  givens_shifted(W, SW, s, j, beta1, !second);
+  givens_shifted(W, SW, s, j, beta1, false);
 }
 
 // Shared basis, after the last iteration: back substitution R_p y_p = g_p per
