@@ -1044,29 +1044,39 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
   __shared__ double2 ub[2][TPB * KH];
   const int m = W.m;
   for (int item = blockIdx.x; item < SW.col_total; item += gridDim.x) {
-    const int s = find_sys(SW.col_start, W.S, item);
-    const SysState_t& st = W.st[s];
-    if (st.state != ST_ACTIVE) continue;
-    const SysDesc& d = W.sys[s];
+    // the system index is uniform: its descriptor is read once into scalar
+    // registers (a reference would be re-read after every store, and each
+    // re-read waits for the loads in flight)
+    const int s = __builtin_amdgcn_readfirstlane(find_sys(SW.col_start, W.S, item));
+    if (W.st[s].state != ST_ACTIVE) continue;
+    const SysDesc& dref = W.sys[s];
+    const int n0 = dref.n0, n1 = dref.n1, n2 = dref.n2;
+    const FastDiv d2 = dref.d2;
+    const double c0 = dref.c0, c1 = dref.c1, c2 = dref.c2, diag = dref.diag;
+    const int ntiles = dref.ntiles, tile0 = dref.tile0, pbase = dref.pbase;
+    const int col_nr = dref.col_nr, col_rows = dref.col_rows, col_L = dref.col_L;
+    const int64_t xoff = dref.xoff, voff = dref.off, bas = dref.basis;
+    const int npts = dref.n;
     const int t = item - SW.col_start[s];
-    const int band = t / d.col_nr;
-    const int rng = t - band * d.col_nr;
-    const int r0 = band * d.col_rows;
-    const int r1 = min(d.n1, r0 + d.col_rows);
-    const int ia = rng * d.col_L;
-    const int ib = min(d.n0, ia + d.col_L);
-    const int nslot = (r1 - r0 + 2) * d.n2;
-    const uint32_t plane = (uint32_t)d.n1 * (uint32_t)d.n2;
+    const int band = t / col_nr;
+    const int rng = t - band * col_nr;
+    const int r0 = band * col_rows;
+    const int r1 = min(n1, r0 + col_rows);
+    const int ia = rng * col_L;
+    const int ib = min(n0, ia + col_L);
+    const int nslot = (r1 - r0 + 2) * n2;
+    const uint32_t plane = (uint32_t)n1 * (uint32_t)n2;
     const double cj = W.cscale[(int64_t)s * (m + 1) + j];
     const double cjm = j > 0 ? W.cscale[(int64_t)s * (m + 1) + j - 1] : 0.0;
     const double ka = SW.alpha[(int64_t)s * m + j] * cj;
     const double kb = j > 0 ? SW.beta[(int64_t)s * (m + 1) + j] * cjm : 0.0;
-    const double2* __restrict__ z = reinterpret_cast<const double2*>(SW.zb) + (j & 1) * SW.zstride + d.xoff;
-    double2* __restrict__ zn = reinterpret_cast<double2*>(SW.zb) + ((j + 1) & 1) * SW.zstride + d.xoff;
-    const double2* __restrict__ uj = basis_vec<double2>(W, d, j);
-    const double2* __restrict__ ujm = basis_vec<double2>(W, d, j > 0 ? j - 1 : 0);
-    double2* __restrict__ un = basis_vec<double2>(W, d, j + 1);
-    const double* __restrict__ V = W.V64 + d.off;
+    const double2* __restrict__ z = reinterpret_cast<const double2*>(SW.zb) + (j & 1) * SW.zstride + xoff;
+    double2* __restrict__ zn = reinterpret_cast<double2*>(SW.zb) + ((j + 1) & 1) * SW.zstride + xoff;
+    double2* const bvec = reinterpret_cast<double2*>(W.basis) + bas;
+    const double2* __restrict__ uj = bvec + (int64_t)j * npts;
+    const double2* __restrict__ ujm = bvec + (int64_t)(j > 0 ? j - 1 : 0) * npts;
+    double2* __restrict__ un = bvec + (int64_t)(j + 1) * npts;
+    const double* __restrict__ V = W.V64 + voff;
     const bool three = j > 0;
     // slot geometry: in-plane offset, row, column; valid = row inside the grid,
     // own = row inside the band
@@ -1076,74 +1086,80 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
 #pragma unroll
     for (int q = 0; q < KH; ++q) {
       const int h = (int)threadIdx.x + q * TPB;
-      const int sr = (int)fdiv((uint32_t)h, d.d2);
+      const int sr = (int)fdiv((uint32_t)h, d2);
       const int row = r0 - 1 + sr;
-      cl[q] = h - sr * d.n2;
+      cl[q] = h - sr * n2;
       rw[q] = row;
-      valid[q] = h < nslot && row >= 0 && row < d.n1;
+      valid[q] = h < nslot && row >= 0 && row < n1;
       own[q] = valid[q] && row >= r0 && row < r1;
-      po[q] = valid[q] ? (uint32_t)row * (uint32_t)d.n2 + (uint32_t)cl[q] : 0u;
+      po[q] = valid[q] ? (uint32_t)row * (uint32_t)n2 + (uint32_t)cl[q] : 0u;
     }
     // inputs of one plane in flight (z_j, u_j, u_{j-1} at the slots, V at
-    // the band): loaded one plane ahead of their use
-    double2 rz[KH], ru[KH], rm[KH];
-    double rv[KH];
-    auto fetch = [&](int i, bool halo) {
+    // the band), loaded one plane ahead of their use. Two buffers alternate
+    // (the plane loop is unrolled by two), so loads in flight are never
+    // copied between registers, which would wait for them.
+    struct Raw {
+      double2 z[KH], u[KH], m[KH];
+      double v[KH];
+    };
+    auto fetch = [&](Raw& R, int i, bool halo) {
       const uint32_t base = (uint32_t)i * plane;
 #pragma unroll
       for (int q = 0; q < KH; ++q) {
-        rz[q] = make_double2(0.0, 0.0);
-        ru[q] = rz[q];
-        rm[q] = rz[q];
-        rv[q] = 0.0;
+        R.z[q] = make_double2(0.0, 0.0);
+        R.u[q] = R.z[q];
+        R.m[q] = R.z[q];
+        R.v[q] = 0.0;
         if (halo ? valid[q] : own[q]) {
           const uint32_t p = base + po[q];
-          rz[q] = z[p];
-          ru[q] = uj[p];
-          if (three) rm[q] = ujm[p];
-          if (own[q]) rv[q] = V[p];
+          R.z[q] = z[p];
+          R.u[q] = uj[p];
+          if (three) R.m[q] = ujm[p];
+          if (own[q]) R.v[q] = V[p];
         }
       }
     };
-    // u_{j+1} = c_j z_j - alpha_j c_j u_j - beta_j c_{j-1} u_{j-1} from the fetched inputs
-    auto form = [&](double2 (&dst)[KH], double2 (&ujv)[KH], double (&vv)[KH]) {
+    // u_{j+1} = c_j z_j - alpha_j c_j u_j - beta_j c_{j-1} u_{j-1} from fetched inputs
+    auto form = [&](const Raw& R, double2 (&dst)[KH], double2 (&ujv)[KH], double (&vv)[KH]) {
 #pragma unroll
       for (int q = 0; q < KH; ++q) {
-        dst[q] = make_double2(cj * rz[q].x - ka * ru[q].x - kb * rm[q].x, cj * rz[q].y - ka * ru[q].y - kb * rm[q].y);
-        ujv[q] = ru[q];
-        vv[q] = rv[q];
+        dst[q] = make_double2(cj * R.z[q].x - ka * R.u[q].x - kb * R.m[q].x,
+                              cj * R.z[q].y - ka * R.u[q].y - kb * R.m[q].y);
+        ujv[q] = R.u[q];
+        vv[q] = R.v[q];
       }
     };
     double2 prv[KH], cur[KH], nxt[KH], ujc[KH], ujn[KH];
     double vc[KH], vn[KH];
+    Raw A, B;
     if (ia > 0) {
-      fetch(ia - 1, false);
-      form(prv, ujn, vn);
+      fetch(A, ia - 1, false);
+      form(A, prv, ujn, vn);
     } else {
 #pragma unroll
       for (int q = 0; q < KH; ++q) prv[q] = make_double2(0.0, 0.0);
     }
-    fetch(ia, true);
+    fetch(A, ia, true);
     __syncthreads();  // ub of the previous item is no longer read
-    form(cur, ujc, vc);
+    form(A, cur, ujc, vc);
 #pragma unroll
     for (int q = 0; q < KH; ++q)
       if (valid[q]) ub[0][threadIdx.x + q * TPB] = cur[q];
-    if (ia + 1 < d.n0) fetch(ia + 1, ia + 1 < ib);
+    if (ia + 1 < n0) fetch(B, ia + 1, ia + 1 < ib);
     __syncthreads();
     int cb = 0;
     double uzx = 0.0, uzy = 0.0, oux = 0.0, ouy = 0.0, nn = 0.0;
-    for (int i = ia; i < ib; ++i) {
-      if (i + 1 < d.n0) {
+    // plane i: X holds the inputs of plane i+1 (in flight), Y receives plane i+2
+    auto plane_step = [&](int i, const Raw& X, Raw& Y) {
+      if (i + 1 < n0) {
         // the next plane; with its halo rows when this item applies H to it
-        form(nxt, ujn, vn);
+        form(X, nxt, ujn, vn);
         if (i + 1 < ib) {
 #pragma unroll
           for (int q = 0; q < KH; ++q)
             if (valid[q]) ub[cb ^ 1][threadIdx.x + q * TPB] = nxt[q];
         }
-        // the plane after it: in flight during this plane's stencil
-        if (i + 2 < d.n0 && i + 2 <= ib) fetch(i + 2, i + 2 < ib);
+        if (i + 2 < n0 && i + 2 <= ib) fetch(Y, i + 2, i + 2 < ib);
       } else {
 #pragma unroll
         for (int q = 0; q < KH; ++q) nxt[q] = make_double2(0.0, 0.0);
@@ -1156,15 +1172,15 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
           const double2 c = cur[q];
           double2 nb2 = make_double2(0.0, 0.0), nb1 = nb2;
           if (cl[q] > 0) { const double2 v = ub[cb][h - 1]; nb2.x += v.x; nb2.y += v.y; }
-          if (cl[q] + 1 < d.n2) { const double2 v = ub[cb][h + 1]; nb2.x += v.x; nb2.y += v.y; }
-          if (rw[q] > 0) { const double2 v = ub[cb][h - d.n2]; nb1.x += v.x; nb1.y += v.y; }
-          if (rw[q] + 1 < d.n1) { const double2 v = ub[cb][h + d.n2]; nb1.x += v.x; nb1.y += v.y; }
+          if (cl[q] + 1 < n2) { const double2 v = ub[cb][h + 1]; nb2.x += v.x; nb2.y += v.y; }
+          if (rw[q] > 0) { const double2 v = ub[cb][h - n2]; nb1.x += v.x; nb1.y += v.y; }
+          if (rw[q] + 1 < n1) { const double2 v = ub[cb][h + n2]; nb1.x += v.x; nb1.y += v.y; }
           const double2 nb0 = make_double2(prv[q].x + nxt[q].x, prv[q].y + nxt[q].y);
           const uint32_t p = base + po[q];
-          const double a = d.diag + vc[q];
+          const double a = diag + vc[q];
           double2 hz;
-          hz.x = a * c.x - (d.c2 * nb2.x + d.c1 * nb1.x + d.c0 * nb0.x);
-          hz.y = a * c.y - (d.c2 * nb2.y + d.c1 * nb1.y + d.c0 * nb0.y);
+          hz.x = a * c.x - (c2 * nb2.x + c1 * nb1.x + c0 * nb0.x);
+          hz.y = a * c.y - (c2 * nb2.y + c1 * nb1.y + c0 * nb0.y);
           un[p] = c;
           zn[p] = hz;
           const double2 u0 = ujc[q];
@@ -1184,6 +1200,10 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
         vc[q] = vn[q];
       }
       cb ^= 1;
+    };
+    for (int i = ia; i < ib; i += 2) {
+      plane_step(i, B, A);
+      if (i + 1 < ib) plane_step(i + 1, A, B);
     }
     uzx = block_sum(uzx, lds);
     uzy = block_sum(uzy, lds);
@@ -1191,10 +1211,10 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
     ouy = block_sum(ouy, lds);
     nn = block_sum(nn, lds);
     if (threadIdx.x == 0) {
-      double2* part = reinterpret_cast<double2*>(W.part) + d.pbase;
+      double2* part = reinterpret_cast<double2*>(W.part) + pbase;
       part[t] = make_double2(uzx, uzy);
-      part[d.ntiles + t] = make_double2(oux, ouy);
-      W.pnorm[d.tile0 + t] = nn;
+      part[ntiles + t] = make_double2(oux, ouy);
+      W.pnorm[tile0 + t] = nn;
     }
   }
 }
