@@ -262,6 +262,7 @@ constexpr int TPB_ = rexi::TPB;
 // system's rows do not fit or its items outnumber its partial-sum slots.
 bool plan_columns(Solver& sv, int kh, int L) {
   struct Plan { int rows, Lc, nr, n; };
+  if (sv.m < 5) return false;  // two parities of three partial-sum slots
   std::vector<Plan> pl;
   for (auto& d : sv.hsys) {
     const int rows = std::min(d.n1, TPB_ * kh / d.n2 - 2);
@@ -663,14 +664,26 @@ rexi_status init_shifted(rexi_handle* h, hipStream_t stream) {
 
 // The fused Lanczos pass of iteration j: the marching pass when a column plan
 // is selected, else the row-staged pass (n2 <= 512) or the plain one.
+// fused (marching pass only): the pass of iteration j also ends iteration j - 1
+template <int KH>
+void launch_col(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork& SW, int j, bool fused,
+                hipStream_t strm) {
+  if (fused) {
+    const dim3 g((j < sv.m ? sv.col_total : 0) + 1);
+    hipLaunchKernelGGL((rexi::k_lz_step_col<KH, true>), g, dim3(TPB), 0, strm, W, SW, j);
+  } else {
+    hipLaunchKernelGGL((rexi::k_lz_step_col<KH, false>), dim3(sv.col_total), dim3(TPB), 0, strm, W, SW, j);
+  }
+}
+
 template <int PPT>
-void launch_lz_step(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork& SW, int j, hipStream_t strm) {
+void launch_lz_step(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork& SW, int j, hipStream_t strm,
+                    bool fused = false) {
   if (sv.col_kh) {
-    const dim3 g(sv.col_total);
     switch (sv.col_kh) {
-      case 3: hipLaunchKernelGGL((rexi::k_lz_step_col<3>), g, dim3(TPB), 0, strm, W, SW, j); return;
-      case 5: hipLaunchKernelGGL((rexi::k_lz_step_col<5>), g, dim3(TPB), 0, strm, W, SW, j); return;
-      default: hipLaunchKernelGGL((rexi::k_lz_step_col<8>), g, dim3(TPB), 0, strm, W, SW, j); return;
+      case 3: launch_col<3>(sv, W, SW, j, fused, strm); return;
+      case 5: launch_col<5>(sv, W, SW, j, fused, strm); return;
+      default: launch_col<8>(sv, W, SW, j, fused, strm); return;
     }
   }
   bool lds_ok = true;  // the row-staged pass keeps a row of halo on each side in LDS
@@ -766,7 +779,21 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
       hipLaunchKernelGGL(rexi::k_end_iter, dim3(S), dim3(TPB), 0, strm, W, SWl, j, 1, 0);
     }
   };
+  // a single instance that pauses for second passes, with the marching
+  // pass: the pass of iteration j + 1 ends iteration j (one kernel per
+  // iteration); iteration(j) then launches that pass, after a plain pass for
+  // the first iteration and after every second Gram-Schmidt pass
+  const bool fuse = pipe && pause_mode && sv.col_kh != 0;
+  auto plain_step = [&](int j, hipStream_t strm) {
+    Timed t(h, PC_LANCZOS, n * (j > 0 ? 88.0 : 72.0), strm);
+    launch_lz_step<PPT>(sv, W, SWl, j, strm);
+  };
   auto iteration = [&](int j, hipStream_t strm) {
+    if (fuse) {
+      Timed t(h, PC_LANCZOS, j + 1 < m ? n * 88.0 : 0.0, strm);
+      launch_lz_step<PPT>(sv, W, SWl, j + 1, strm, true);
+      return;
+    }
     if (pipe) {
       {
         Timed t(h, PC_LANCZOS, n * (j > 0 ? 88.0 : 72.0), strm);
@@ -838,6 +865,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
     int j = 0;
     int len = h->k_hint > 0 ? h->k_hint : chunk;
     int passes = 0;
+    if (fuse) plain_step(0, stream);
     while (j < m) {
       len = std::max(1, std::min(len, m - j));
       rexi_status rs = launch_chunk(j, len);
@@ -852,6 +880,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
         // second Gram-Schmidt pass of iteration paused_at, then go on after it
         hipLaunchKernelGGL(rexi::k_resume, dim3(S), dim3(64), 0, stream, W, h->SW);
         second_pass(paused_at, stream, G);
+        if (fuse && paused_at + 1 < m) plain_step(paused_at + 1, stream);
         HIPCHK(h, hipGetLastError());
         ++passes;
         j = paused_at + 1;

@@ -88,6 +88,42 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
   return s;
 }
 
+// Sums of four per-thread values over the block (one LDS exchange).
+__device__ __forceinline__ void block_sum4(double& a, double& b, double& c, double& e, double* l4) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  e = wave_sum(e);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    l4[wid] = a;
+    l4[NWAVE + wid] = b;
+    l4[2 * NWAVE + wid] = c;
+    l4[3 * NWAVE + wid] = e;
+  }
+  __syncthreads();
+  a = b = c = e = 0.0;
+#pragma unroll
+  for (int w = 0; w < NWAVE; ++w) {
+    a += l4[w];
+    b += l4[NWAVE + w];
+    c += l4[2 * NWAVE + w];
+    e += l4[3 * NWAVE + w];
+  }
+}
+
+__device__ __forceinline__ double block_max(double v, double* l) {
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) l[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int w = 0; w < NWAVE; ++w) r = fmax(r, l[w]);
+  return r;
+}
+
 // Thread-strided sum of p[0..n) with eight independent loads per thread in
 // flight (the partial sums of a pass are written by other compute dies, so
 // every load is a round trip to memory; a load-add chain would serialise them).
@@ -1038,12 +1074,41 @@ __global__ __launch_bounds__(TPB) void k_lz_step_lds(Work W, ShiftWork SW, int j
 // Items are ordered band-major over the plane ranges, so with col_nr a
 // multiple of 8 the bands of one plane range share a compute die (blocks go
 // round-robin over the 8 dies) and the halo rows they share hit its L2.
-template <int KH>
+// Partial sums of the marching pass for iteration j, per item t, at parity
+// j & 1: <u_{j+1}, z_{j+1}>, <u_j, u_{j+1}>, (||u_{j+1}||^2, 0) in three
+// slots of ntiles entries from pbase + 3 (j & 1) ntiles (the fused pass of
+// iteration j + 1 reads parity j while it writes parity j + 1).
+__device__ __forceinline__ void lz_col_partials(const Work& W, int pbase, int ntiles, int np, int j, double& nn,
+                                                double& uz, double& oux, double& ouy, double* l4) {
+  const double2* pp = reinterpret_cast<const double2*>(W.part) + pbase + 3 * (j & 1) * ntiles;
+  nn = strided_sum2(pp + 2 * ntiles, np).x;
+  uz = strided_sum2(pp, np).x;
+  const double2 o = strided_sum2(pp + ntiles, np);
+  oux = o.x;
+  ouy = o.y;
+  block_sum4(nn, uz, oux, ouy, l4);
+}
+
+__device__ void lz_end_body(Work& W, ShiftWork& SW, int s, int j, int colparts);
+
+// FUSED (a single instance that pauses for second passes; j >= 1): the block
+// after the items ends iteration j - 1 (lz_end_body), while every item block
+// takes beta_j = ||u_j|| and alpha_j = c_j^2 <u_j, z_j> from the partial sums
+// of iteration j - 1 itself (the same reduction in the same order, so the
+// same values); j = m only ends iteration m - 1.
+template <int KH, bool FUSED>
 __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j) {
   __shared__ double lds[NWAVE];
+  __shared__ double l4[4 * NWAVE];
   __shared__ double2 ub[2][TPB * KH];
   const int m = W.m;
-  for (int item = blockIdx.x; item < SW.col_total; item += gridDim.x) {
+  const int nitems = FUSED ? (int)gridDim.x - 1 : (int)gridDim.x;
+  if (FUSED && (int)blockIdx.x == nitems) {
+    lz_end_body(W, SW, 0, j - 1, 1);
+    return;
+  }
+  if (FUSED && j >= m) return;
+  for (int item = blockIdx.x; item < SW.col_total; item += nitems) {
     // the system index is uniform: its descriptor is read once into scalar
     // registers (a reference would be re-read after every store, and each
     // re-read waits for the loads in flight)
@@ -1066,10 +1131,20 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
     const int ib = min(n0, ia + col_L);
     const int nslot = (r1 - r0 + 2) * n2;
     const uint32_t plane = (uint32_t)n1 * (uint32_t)n2;
-    const double cj = W.cscale[(int64_t)s * (m + 1) + j];
-    const double cjm = j > 0 ? W.cscale[(int64_t)s * (m + 1) + j - 1] : 0.0;
-    const double ka = SW.alpha[(int64_t)s * m + j] * cj;
-    const double kb = j > 0 ? SW.beta[(int64_t)s * (m + 1) + j] * cjm : 0.0;
+    double cj, ka, kb;
+    if (FUSED) {
+      double nn, uz, ox, oy;
+      lz_col_partials(W, pbase, ntiles, dref.col_n, j - 1, nn, uz, ox, oy, l4);
+      const double bj = sqrt(nn);
+      cj = bj > 0.0 ? 1.0 / bj : 0.0;
+      ka = cj * cj * uz * cj;
+      kb = bj * W.cscale[(int64_t)s * (m + 1) + j - 1];
+    } else {
+      cj = W.cscale[(int64_t)s * (m + 1) + j];
+      const double cjm = j > 0 ? W.cscale[(int64_t)s * (m + 1) + j - 1] : 0.0;
+      ka = SW.alpha[(int64_t)s * m + j] * cj;
+      kb = j > 0 ? SW.beta[(int64_t)s * (m + 1) + j] * cjm : 0.0;
+    }
     const double2* __restrict__ z = reinterpret_cast<const double2*>(SW.zb) + (j & 1) * SW.zstride + xoff;
     double2* __restrict__ zn = reinterpret_cast<double2*>(SW.zb) + ((j + 1) & 1) * SW.zstride + xoff;
     double2* const bvec = reinterpret_cast<double2*>(W.basis) + bas;
@@ -1211,48 +1286,12 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
     ouy = block_sum(ouy, lds);
     nn = block_sum(nn, lds);
     if (threadIdx.x == 0) {
-      double2* part = reinterpret_cast<double2*>(W.part) + pbase;
+      double2* part = reinterpret_cast<double2*>(W.part) + pbase + 3 * (j & 1) * ntiles;
       part[t] = make_double2(uzx, uzy);
       part[ntiles + t] = make_double2(oux, ouy);
-      W.pnorm[tile0 + t] = nn;
+      part[2 * ntiles + t] = make_double2(nn, 0.0);
     }
   }
-}
-
-// Sums of four per-thread values over the block (one LDS exchange).
-__device__ __forceinline__ void block_sum4(double& a, double& b, double& c, double& e, double* l4) {
-  a = wave_sum(a);
-  b = wave_sum(b);
-  c = wave_sum(c);
-  e = wave_sum(e);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) {
-    l4[wid] = a;
-    l4[NWAVE + wid] = b;
-    l4[2 * NWAVE + wid] = c;
-    l4[3 * NWAVE + wid] = e;
-  }
-  __syncthreads();
-  a = b = c = e = 0.0;
-#pragma unroll
-  for (int w = 0; w < NWAVE; ++w) {
-    a += l4[w];
-    b += l4[NWAVE + w];
-    c += l4[2 * NWAVE + w];
-    e += l4[3 * NWAVE + w];
-  }
-}
-
-__device__ __forceinline__ double block_max(double v, double* l) {
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) l[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double r = 0.0;
-#pragma unroll
-  for (int w = 0; w < NWAVE; ++w) r = fmax(r, l[w]);
-  return r;
 }
 
 // Grid S: end of pipelined iteration j (first pass). beta_{j+1} = ||u_{j+1}||,
@@ -1265,12 +1304,10 @@ __device__ __forceinline__ double block_max(double v, double* l) {
 // partials, the alpha/beta/omega history, the poles' rotations) is loaded
 // up front, so the chain costs about two memory round trips. Requires
 // poles per instance <= TPB for the register path (others take a loop).
-__global__ __launch_bounds__(TPB) void k_lz_end(Work W, ShiftWork SW, int j, int colparts) {
+__device__ void lz_end_body(Work& W, ShiftWork& SW, int s, int j, int colparts) {
   __shared__ double l4[4 * NWAVE];
   __shared__ double hist[4][MAXM + 2];  // alpha, beta, omega row j, omega row j-1
   __shared__ int reo_sh;
-  const int s = blockIdx.x;
-  if (s >= W.S) return;
   const int tid = threadIdx.x;
   const int m = W.m;
   SysState_t& st = W.st[s];
@@ -1287,12 +1324,16 @@ __global__ __launch_bounds__(TPB) void k_lz_end(Work W, ShiftWork SW, int j, int
   double* wprev = omega + (int64_t)((j + 1) & 1) * (m + 1);  // row j-1, becomes row j+1
   double* wcur = omega + (int64_t)(j & 1) * (m + 1);         // row j
   if (j == 0 && tid == 0) wcur[0] = 1.0;                     // omega_{0,0}
-  // round trip 2: everything else
-  const double2* part = reinterpret_cast<const double2*>(W.part) + pbase;
-  double nn = strided_sum(W.pnorm + tile0, np);
-  double uz = strided_sum2(part, np).x;
-  const double2 ou = strided_sum2(part + ntiles, np);
-  double oux = ou.x, ouy = ou.y;
+  // round trip 2: everything else (the partial sums are reduced below)
+  double nn, uz, oux, ouy;
+  if (!colparts) {
+    const double2* part = reinterpret_cast<const double2*>(W.part) + pbase;
+    nn = strided_sum(W.pnorm + tile0, np);
+    uz = strided_sum2(part, np).x;
+    const double2 ou = strided_sum2(part + ntiles, np);
+    oux = ou.x;
+    ouy = ou.y;
+  }
   if (tid <= j) {
     hist[0][tid] = alpha[tid];
     hist[1][tid] = betav[tid];
@@ -1327,9 +1368,12 @@ __global__ __launch_bounds__(TPB) void k_lz_end(Work W, ShiftWork SW, int j, int
     tolp = SW.tol[p];
     itsp = SW.its[p];
   }
-  // partial sums, and max_{k<j} |alpha_k| + beta_k + beta_{k+1} (the k = j
-  // term needs beta_{j+1}) in the same exchange
-  block_sum4(nn, uz, oux, ouy, l4);
+  // partial sums; then max_{k<j} |alpha_k| + beta_k + beta_{k+1} (the k = j
+  // term needs beta_{j+1})
+  if (colparts)
+    lz_col_partials(W, pbase, ntiles, np, j, nn, uz, oux, ouy, l4);
+  else
+    block_sum4(nn, uz, oux, ouy, l4);
   const double beta1 = sqrt(nn);
   const double c1 = beta1 > 0.0 ? 1.0 / beta1 : 0.0;
   const double aj = hist[0][j], bj = hist[1][j];
@@ -1451,6 +1495,11 @@ __global__ __launch_bounds__(TPB) void k_lz_end(Work W, ShiftWork SW, int j, int
     if (unconv == 0.0 || k == m) st.state = ST_FINISH;
     else atomicAdd(&W.counters[j], 1);
   }
+}
+
+__global__ __launch_bounds__(TPB) void k_lz_end(Work W, ShiftWork SW, int j, int colparts) {
+  if ((int)blockIdx.x >= W.S) return;
+  lz_end_body(W, SW, blockIdx.x, j, colparts);
 }
 
 // Grid S: end of pipelined iteration j after a second Gram-Schmidt pass

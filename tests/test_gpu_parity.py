@@ -494,6 +494,25 @@ def test_marching_lanczos_pass(rexi, shape, planes, slots, fits):
     assert all(i["not_converged"] == 0 for i in infos)
 
 
+def test_marching_pass_with_second_passes(rexi):
+    # a long Lanczos run (interior shifts of the double well) loses
+    # orthogonality: the solve pauses for second Gram-Schmidt passes and
+    # resumes with a plain marching pass; the fused passes around them still
+    # reach the certified bound
+    wl = inputs.workload("2d_double_well", scale=40)
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+    ref = ost.DirectStepper(g.n, g.h, wl.V, s, b, wl.dt).step(wl.psi0)
+    out, infos = gpu_steps(g, wl.V, wl.psi0, s, b, wl.dt, 1, solver="shifted", m=256, tol=1e-9, tile=512,
+                           march_planes=4, march_slots=5)
+    e = rel(out[0], ref)
+    i0 = infos[0]
+    print("marching + second passes", e, i0["certified_bound"], i0["total_iterations"], i0["reorth_passes"])
+    assert i0["not_converged"] == 0
+    assert i0["reorth_passes"] >= 1
+    assert e <= i0["certified_bound"] + 3 * iterative_floor(g, wl.V, s, b, wl.dt)
+
+
 @pytest.mark.parametrize("n", [64, 128])
 def test_marching_matches_row_staged_pass(rexi, n):
     # at the benchmarked size and below, every marching configuration the
