@@ -1527,6 +1527,7 @@ __global__ __launch_bounds__(TPB) void k_lz_end_second(Work W, ShiftWork SW, int
 // Shared basis, after the last iteration: back substitution R_p y_p = g_p per
 // pole (one wave per pole, rows in sequence, the row sums across lanes).
 __global__ __launch_bounds__(TPB) void k_shifted_backsub(Work W, ShiftWork SW) {
+  __shared__ double2 band[NWAVE][4][MAXM];
   const int m = W.m;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int p = blockIdx.x * NWAVE + wid;
@@ -1537,6 +1538,38 @@ __global__ __launch_bounds__(TPB) void k_shifted_backsub(Work W, ShiftWork SW) {
   const double2* Rp = reinterpret_cast<const double2*>(SW.R) + (int64_t)p * (m + 1) * m;
   const double2* g = reinterpret_cast<const double2*>(SW.g) + (int64_t)p * (m + 1);
   double2* y = reinterpret_cast<double2*>(SW.y) + (int64_t)p * m;
+  int anyfull = 0;
+  for (int q = lane; q < k; q += 64) anyfull |= full[q];
+  if (!__any(anyfull)) {
+    // no second pass: R has three diagonals, y_r = (g_r - R_{r,r+1} y_{r+1}
+    // - R_{r,r+2} y_{r+2}) / R_rr. The wave stages the band and g in LDS,
+    // then one lane runs the recurrence.
+    double2(*bd)[MAXM] = band[wid];
+    for (int r = lane; r < k; r += 64) {
+      bd[0][r] = Rp[(int64_t)r * (m + 1) + r];
+      bd[1][r] = r + 1 < k ? Rp[(int64_t)(r + 1) * (m + 1) + r] : make_double2(0.0, 0.0);
+      bd[2][r] = r + 2 < k ? Rp[(int64_t)(r + 2) * (m + 1) + r] : make_double2(0.0, 0.0);
+      bd[3][r] = g[r];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane == 0) {
+      double2 y1 = make_double2(0.0, 0.0), y2 = y1;  // y_{r+1}, y_{r+2}
+      for (int r = k - 1; r >= 0; --r) {
+        const double2 t1 = cmul(bd[1][r], y1), t2 = cmul(bd[2][r], y2);
+        const double2 acc = make_double2(bd[3][r].x - (t1.x + t2.x), bd[3][r].y - (t1.y + t2.y));
+        const double2 dd = bd[0][r];
+        const double dn = dd.x * dd.x + dd.y * dd.y;
+        const double2 yr = dn > 0.0 ? make_double2((acc.x * dd.x + acc.y * dd.y) / dn, (acc.y * dd.x - acc.x * dd.y) / dn)
+                                    : make_double2(0.0, 0.0);
+        y[r] = yr;
+        y2 = y1;
+        y1 = yr;
+      }
+    }
+    return;
+  }
   for (int r = k - 1; r >= 0; --r) {
     double ax = 0.0, ay = 0.0;
     for (int q = r + 1 + lane; q < k; q += 64) {
@@ -1739,27 +1772,55 @@ __global__ __launch_bounds__(TPB) void k_combine_out(Work W, ShiftWork SW, doubl
       sprev = s;
     }
     const int t = item - d.tile0;
+    const int n = d.n;
+    const int64_t off = d.off;
+    const T* __restrict__ u0 = basis_vec<T>(W, d, 0);
     double2 acc[PPT];
+    bool in[PPT];
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) acc[q] = make_double2(0.0, 0.0);
-    for (int i = 0; i < k; ++i) {
-      const T* __restrict__ ui = basis_vec<T>(W, d, i);
+    for (int q = 0; q < PPT; ++q) {
+      acc[q] = make_double2(0.0, 0.0);
+      in[q] = t * W.tile + q * TPB + (int)threadIdx.x < n;
+    }
+    const int p0 = t * W.tile + (int)threadIdx.x;
+    // four basis vectors per step: their loads are in flight together; the
+    // accumulation order per point stays i = 0, 1, ..., k - 1
+    constexpr int U = 4;
+    int i = 0;
+    for (; i + U <= k; i += U) {
+      T a[U][PPT];
+#pragma unroll
+      for (int r = 0; r < U; ++r) {
+        const T* __restrict__ ui = u0 + (int64_t)(i + r) * n;
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) a[r][q] = in[q] ? ui[p0 + q * TPB] : T{};
+      }
+#pragma unroll
+      for (int r = 0; r < U; ++r) {
+        const double2 c = coef[i + r];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+          const double2 v = to_d2(a[r][q]);
+          acc[q].x += c.x * v.x - c.y * v.y;
+          acc[q].y += c.x * v.y + c.y * v.x;
+        }
+      }
+    }
+    for (; i < k; ++i) {
+      const T* __restrict__ ui = u0 + (int64_t)i * n;
       const double2 c = coef[i];
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
-        const int p = t * W.tile + q * TPB + threadIdx.x;
-        if (p < d.n) {
-          const double2 a = to_d2(ui[p]);
-          acc[q].x += c.x * a.x - c.y * a.y;
-          acc[q].y += c.x * a.y + c.y * a.x;
+        if (in[q]) {
+          const double2 v = to_d2(ui[p0 + q * TPB]);
+          acc[q].x += c.x * v.x - c.y * v.y;
+          acc[q].y += c.x * v.y + c.y * v.x;
         }
       }
     }
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-      const int p = t * W.tile + q * TPB + threadIdx.x;
-      if (p < d.n) out[d.off + p] = acc[q];
-    }
+    for (int q = 0; q < PPT; ++q)
+      if (in[q]) out[off + p0 + q * TPB] = acc[q];
   }
 }
 
