@@ -248,6 +248,23 @@ def main():
             ya.copy_(xa)
         torch.cuda.synchronize()
 
+    # plain device copy of 1 GiB (torch), best of 5: the practical streaming
+    # rate of this GPU, beside the published peak
+    xa = torch.empty(1 << 26, dtype=torch.complex128, device=dev)
+    ya = torch.empty_like(xa)
+    ya.copy_(xa)
+    torch.cuda.synchronize()
+    copy_ms = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ya.copy_(xa)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_ms.append(e0.elapsed_time(e1))
+    copy_GBs = 2 * (1 << 30) / (min(copy_ms) * 1e-3) / 1e9
+    del xa, ya
+
     roof = None
     if prof is not None:
         # dominant kernel class by summed time over the timed region
@@ -260,6 +277,8 @@ def main():
         traffic = load_traffic(dom, args.precision)
         roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
+                    traffic_GBs=None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1),
+                    copy_GBs=round(copy_GBs, 1), frac_of_copy=round(achieved / copy_GBs, 4),
                     instrumented_ms_per_step=round(prof_ms, 4),
                     avg_launch_ms=round(avg_ms, 5), algorithmic_bytes_per_launch=round(bytes_per_launch),
                     launches=d["launches"],
