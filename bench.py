@@ -140,7 +140,9 @@ def bench_batch(args):
                    "instances": cnt, "points": npts, "poles": int(sum(Ks)), "solver": args.solver,
                    "graph_replay": bool(args.capture)},
         "solve": {"iterations_per_step": int(info["total_iterations"]), "not_converged": int(info["not_converged"]),
-                  "max_rel_residual": info["max_rel_residual"], "workspace_GB": round(ws / 1e9, 2), "m": m_used},
+                  "max_cycles": int(info["max_cycles_used"]), "max_rel_residual": info["max_rel_residual"],
+                  "certified_rel_error_bound": info["certified_bound"], "workspace_GB": round(ws / 1e9, 2),
+                  "m": m_used},
     }
     print(json.dumps(res), flush=True)
 

@@ -142,6 +142,17 @@ typedef struct {
   int32_t march_slots;  /* marching pass: points per thread and plane, 3, 5
                            or 8 (0 = 5); a band holds 256 slots / n2 - 2
                            rows of the plane                                 */
+  int32_t fallback;     /* shared-basis solver: 1 (default) poles that miss
+                           their target within m vectors continue as per-pole
+                           restarted solves (complex64 + FP64 refinement,
+                           restart length fallback_m, max_cycles cycles)
+                           warm-started from the shared-basis iterate; 0: they
+                           are reported in not_converged. Needs host checks
+                           (not with capture_safe)                           */
+  int32_t fallback_m;   /* restart length of those solves, 30                */
+  int64_t fallback_bytes; /* device workspace reserved for them at setup
+                           (0 = min(16 GiB, a quarter of the free memory));
+                           unconverged poles are solved in waves that fit    */
 } rexi_options;
 
 typedef struct {

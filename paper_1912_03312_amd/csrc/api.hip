@@ -56,6 +56,10 @@ struct Solver {
   int col_kh = 0, col_L = 0, col_total = 0;
   std::vector<int32_t> hcol;
   int32_t* dcol = nullptr;
+  // a solver whose systems change between runs (fallback solves) is built
+  // for at most cap_S systems of cap_pts points in total
+  int cap_S = 0;
+  int64_t cap_pts = 0;
   bool ready = false;
 };
 
@@ -87,6 +91,10 @@ struct rexi_handle {
   std::vector<double> tol_sys, dist_sys, lam_lo, lam_hi;
   std::vector<int> Kinst;
   Solver fwd, adj;
+  Solver fb;                          // per-pole solves of poles the shared basis missed
+  int fb_cycles = 0;                  // most cycles of those solves (last step)
+  int fb_poles = 0;                   // poles they took over (last step)
+  int64_t fb_its = 0;                 // their iterations (last step)
   // shared-basis solver: fwd holds one system (H, shift 0) per instance
   bool shifted = false;
   rexi::ShiftWork SW{};
@@ -149,6 +157,7 @@ void destroy_handle(rexi_handle* h) {
   if (!h) return;
   free_solver(h->fwd);
   free_solver(h->adj);
+  free_solver(h->fb);
   for (auto& b : h->sbufs)
     if (b.p) (void)hipFree(b.p);
   if (h->dinst) (void)hipFree(h->dinst);
@@ -293,27 +302,37 @@ bool plan_columns(Solver& sv, int kh, int L) {
 
 rexi_status build_solver(rexi_handle* h, Solver& sv, hipStream_t stream) {
   const int m = sv.m, S = sv.S;
+  const int SA = sv.cap_S > 0 ? sv.cap_S : S;  // systems allocated for
   Work& W = sv.W;
   W = Work{};
   rexi_status st;
 #define ALLOC(ptr, type, count) \
   if ((st = dalloc(h, sv, (type**)&(ptr), (size_t)(count))) != REXI_OK) return st
-  ALLOC(sv.dsys, SysDesc, S);
-  ALLOC(sv.dtile, int32_t, S + 1);
-  ALLOC(sv.dcol, int32_t, S + 1);
+  ALLOC(sv.dsys, SysDesc, SA);
+  ALLOC(sv.dtile, int32_t, SA + 1);
+  ALLOC(sv.dcol, int32_t, SA + 1);
   SysState_t* dst;
-  ALLOC(dst, SysState_t, S);
+  ALLOC(dst, SysState_t, SA);
   W.st = dst;
-  ALLOC(W.H, double, (size_t)S * (m + 1) * m * 2);
-  ALLOC(W.hcur, double, (size_t)S * (m + 1) * 2);
-  ALLOC(W.gvec, double, (size_t)S * (m + 1) * 2);
-  ALLOC(W.gc, double, (size_t)S * m * 2);
-  ALLOC(W.gs, double, (size_t)S * m * 2);
-  ALLOC(W.cscale, double, (size_t)S * (m + 1));
-  ALLOC(W.y, double, (size_t)S * m * 2);
+  ALLOC(W.H, double, (size_t)SA * (m + 1) * m * 2);
+  ALLOC(W.hcur, double, (size_t)SA * (m + 1) * 2);
+  ALLOC(W.gvec, double, (size_t)SA * (m + 1) * 2);
+  ALLOC(W.gc, double, (size_t)SA * m * 2);
+  ALLOC(W.gs, double, (size_t)SA * m * 2);
+  ALLOC(W.cscale, double, (size_t)SA * (m + 1));
+  ALLOC(W.y, double, (size_t)SA * m * 2);
   // partial sums sized for the smallest tile, so the tuner may switch tilings
   size_t npart = 0, nx = 0, nb = 0, ntmax = 0;
+  if (sv.cap_S > 0) {
+    // any set of cap_S systems of cap_pts points: each system adds at most one
+    // partial tile of the smallest tile (512 points)
+    ntmax = (size_t)(sv.cap_pts / (2 * TPB_)) + (size_t)sv.cap_S;
+    npart = (size_t)(m + 1) * ntmax;
+    nx = (size_t)sv.cap_pts;
+    nb = (size_t)(m + 1) * sv.cap_pts;
+  }
   for (auto& d : sv.hsys) {
+    if (sv.cap_S > 0) break;
     const size_t nt = (size_t)(d.n + 2 * TPB_ - 1) / (2 * TPB_);
     npart += (size_t)(m + 1) * nt;
     ntmax += nt;
@@ -323,7 +342,6 @@ rexi_status build_solver(rexi_handle* h, Solver& sv, hipStream_t stream) {
   ALLOC(W.part, double, npart * 2);
   ALLOC(W.pnorm, double, ntmax);
   ALLOC(W.counters, int32_t, sv.max_cycles * (m + 1) + sv.max_cycles + 4);
-  ALLOC(W.tick, int32_t, (size_t)S * 4);
   ALLOC(W.x, double, nx * 2);
   if (sv.prec) {
     float* b;
@@ -335,10 +353,10 @@ rexi_status build_solver(rexi_handle* h, Solver& sv, hipStream_t stream) {
     W.basis = b;
   }
 #undef ALLOC
-  // tickets start at zero and every completed pass returns them to zero
-  HIPCHK(h, hipMemsetAsync(W.tick, 0, (size_t)S * 4 * sizeof(int32_t), stream));
-  HIPCHK(h, hipMemcpyAsync(sv.dsys, sv.hsys.data(), S * sizeof(SysDesc), hipMemcpyHostToDevice, stream));
-  HIPCHK(h, hipMemcpyAsync(sv.dtile, sv.htile.data(), (S + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  if (S > 0) {
+    HIPCHK(h, hipMemcpyAsync(sv.dsys, sv.hsys.data(), S * sizeof(SysDesc), hipMemcpyHostToDevice, stream));
+    HIPCHK(h, hipMemcpyAsync(sv.dtile, sv.htile.data(), (S + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  }
   HIPCHK(h, hipStreamSynchronize(stream));
   W.sys = sv.dsys;
   W.tile_start = sv.dtile;
@@ -365,9 +383,11 @@ int default_grid(int total_tiles, int opt_grid) {
 constexpr int PPT = 8;  // points per thread of the instance-level kernels
 constexpr int TPB = rexi::TPB;
 
+// Restarted cycles of the per-pole solver from the current state: `active`
+// systems are iterating, `total_restarts` restarts were counted so far.
 template <typename T, int PPT>
-rexi_status run_solve(rexi_handle* h, Solver& sv, const double2* r0, const double2* r1, hipStream_t stream,
-                      int* restarts_out) {
+rexi_status run_cycles(rexi_handle* h, Solver& sv, const double2* r0, const double2* r1, hipStream_t stream,
+                       int active, int total_restarts, int* restarts_out) {
   Work& W = sv.W;
   const int G = sv.grid, S = sv.S, m = sv.m;
   const double e = sizeof(T);
@@ -375,16 +395,6 @@ rexi_status run_solve(rexi_handle* h, Solver& sv, const double2* r0, const doubl
   double npts = 0;  // points per system (uniform tiling assumed for byte counts)
   for (auto& d : sv.hsys) npts += d.n;
   const double n_avg = npts / std::max(1, S);
-  {
-    Timed t(h, PC_START, npts * (16.0 + e), stream);
-    hipLaunchKernelGGL((rexi::k_start<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, r0, r1);
-  }
-  {
-    Timed t(h, PC_REDUCE, 0, stream);
-    hipLaunchKernelGGL(rexi::k_start_reduce, dim3(S), dim3(TPB), 0, stream, W);
-  }
-  int active = S;
-  int total_restarts = 0;
   for (int c = 0; c < sv.max_cycles; ++c) {
     for (int j = 0; j < m; ++j) {
       {
@@ -459,6 +469,24 @@ rexi_status run_solve(rexi_handle* h, Solver& sv, const double2* r0, const doubl
   }
   if (restarts_out) *restarts_out = total_restarts;
   return REXI_OK;
+}
+
+template <typename T, int PPT>
+rexi_status run_solve(rexi_handle* h, Solver& sv, const double2* r0, const double2* r1, hipStream_t stream,
+                      int* restarts_out) {
+  Work& W = sv.W;
+  const int G = sv.grid, S = sv.S;
+  double npts = 0;
+  for (auto& d : sv.hsys) npts += d.n;
+  {
+    Timed t(h, PC_START, npts * (16.0 + sizeof(T)), stream);
+    hipLaunchKernelGGL((rexi::k_start<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, r0, r1);
+  }
+  {
+    Timed t(h, PC_REDUCE, 0, stream);
+    hipLaunchKernelGGL(rexi::k_start_reduce, dim3(S), dim3(TPB), 0, stream, W);
+  }
+  return run_cycles<T, PPT>(h, sv, r0, r1, stream, S, 0, restarts_out);
 }
 
 rexi_status solve(rexi_handle* h, Solver& sv, const double2* r0, const double2* r1, hipStream_t stream,
@@ -664,6 +692,138 @@ rexi_status init_shifted(rexi_handle* h, hipStream_t stream) {
 
 // The fused Lanczos pass of iteration j: the marching pass when a column plan
 // is selected, else the row-staged pass (n2 <= 512) or the plain one.
+// Workspace of the per-pole solves that finish poles the shared basis missed:
+// complex64 basis + FP64 refinement, restart length fallback_m, for at most
+// cap_pts points over at most cap_S systems (one wave of those poles).
+rexi_status init_fallback(rexi_handle* h, hipStream_t stream) {
+  Solver& fb = h->fb;
+  fb.hsys.clear();
+  fb.m = h->opt.fallback_m;
+  fb.prec = 1;
+  fb.ppt = 4;
+  fb.tile = TPB_ * fb.ppt;
+  fb.eta = h->opt.reorth_eta;
+  fb.reorth = h->opt.reorth;
+  fb.inner_rtol = h->opt.inner_rtol;
+  fb.max_cycles = h->opt.max_cycles;
+  int64_t nmax = 0, all = 0;
+  for (int i = 0; i < h->ninst; ++i) {
+    nmax = std::max<int64_t>(nmax, h->hinst[i].n);
+    all += (int64_t)h->hinst[i].n * h->Kinst[i];
+  }
+  const double per_pt = (fb.m + 1) * 8.0 + 16.0 + 8.0 * (fb.m + 1) / (2 * TPB_) * 2.0;
+  size_t budget = (size_t)h->opt.fallback_bytes;
+  if (budget == 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(h, REXI_E_HIP, "hipMemGetInfo failed");
+    budget = std::min<size_t>((size_t)16 << 30, fr / 4);
+  }
+  fb.cap_pts = std::min<int64_t>(all, (int64_t)((double)budget / per_pt));
+  if (fb.cap_pts < nmax) return REXI_OK;  // no room for one solve of the largest instance: no fallback
+  fb.cap_S = (int)std::min<int64_t>((int64_t)h->s.size(), 4096);
+  fb.S = 0;
+  fb.total_tiles = 0;
+  fb.htile.assign(1, 0);
+  rexi_status st = build_solver(h, fb, stream);
+  if (st != REXI_OK) return st;
+  fb.grid = 1;
+  return REXI_OK;
+}
+
+// Finish the poles p of `poles` (all missed their target in the shared basis,
+// whose iterates y_p are current) by per-pole solves in waves, and add
+// sum_p w_p x_p to out.
+template <int PPT>
+rexi_status run_fallback(rexi_handle* h, const std::vector<int>& poles, const double2* b, double2* out,
+                         hipStream_t stream) {
+  Solver& fb = h->fb;
+  Solver& sv = h->fwd;
+  std::vector<int> pinst(h->s.size());
+  {
+    int q = 0;
+    for (int i = 0; i < h->ninst; ++i)
+      for (int k = 0; k < h->Kinst[i]; ++k) pinst[q++] = i;
+  }
+  int kshared = 0;
+  {
+    std::vector<SysState_t> sst((size_t)sv.S);
+    HIPCHK(h, hipMemcpyAsync(sst.data(), sv.W.st, sv.S * sizeof(SysState_t), hipMemcpyDeviceToHost, stream));
+    HIPCHK(h, hipStreamSynchronize(stream));
+    for (auto& x : sst) kshared = std::max(kshared, x.kcyc);
+  }
+  h->fb_cycles = 0;
+  h->fb_its = 0;
+  size_t next = 0;
+  while (next < poles.size()) {
+    // one wave: as many poles as fit the workspace
+    fb.hsys.clear();
+    int64_t pts = 0;
+    while (next < poles.size() && (int)fb.hsys.size() < fb.cap_S) {
+      const int p = poles[next];
+      const InstDesc& in = h->hinst[pinst[p]];
+      if (pts + in.n > fb.cap_pts) break;
+      SysDesc d{};
+      d.off = in.off;
+      d.n = in.n;
+      d.n0 = in.n0;
+      d.n1 = in.n1;
+      d.n2 = in.n2;
+      d.d2 = in.d2;
+      d.d1 = in.d1;
+      d.c0 = in.c0;
+      d.c1 = in.c1;
+      d.c2 = in.c2;
+      d.diag = in.diag;
+      d.sre = h->s[p].real();
+      d.sim = h->s[p].imag();
+      d.wre = h->w[p].real();
+      d.wim = h->w[p].imag();
+      d.tol = h->tol_sys[p];
+      d.dist = h->dist_sys[p];
+      d.inst = pinst[p];
+      d.pole = p;
+      fb.hsys.push_back(d);
+      pts += in.n;
+      ++next;
+    }
+    layout_systems(fb, fb.m);
+    fb.W.S = fb.S;
+    fb.W.total_tiles = fb.total_tiles;
+    fb.W.tile = fb.tile;
+    fb.grid = default_grid(fb.total_tiles, 0);
+    HIPCHK(h, hipMemcpyAsync(fb.dsys, fb.hsys.data(), fb.S * sizeof(SysDesc), hipMemcpyHostToDevice, stream));
+    HIPCHK(h, hipMemcpyAsync(fb.dtile, fb.htile.data(), (fb.S + 1) * sizeof(int32_t), hipMemcpyHostToDevice,
+                             stream));
+    Work& F = fb.W;
+    // warm start: x = V y_p, then the explicit residual and restart decision
+    hipLaunchKernelGGL((rexi::k_fb_init_x<PPT>), dim3(fb.grid), dim3(TPB), 0, stream, F, sv.W, h->SW);
+    hipLaunchKernelGGL(rexi::k_fb_state, dim3(fb.S), dim3(TPB), 0, stream, F, sv.W);
+    hipLaunchKernelGGL((rexi::k_residual<float2, 4>), dim3(fb.grid), dim3(TPB), 0, stream, F, b, b);
+    hipLaunchKernelGGL(rexi::k_restart, dim3(fb.S), dim3(TPB), 0, stream, F, 0);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(h->hpin, F.counters + fb.max_cycles * (fb.m + 1), sizeof(int32_t),
+                             hipMemcpyDeviceToHost, stream));
+    HIPCHK(h, hipStreamSynchronize(stream));
+    const int active = h->hpin[0];
+    if (active > 0) {
+      rexi_status rs = run_cycles<float2, 4>(h, fb, b, b, stream, active, active, nullptr);
+      if (rs != REXI_OK) return rs;
+    }
+    hipLaunchKernelGGL(rexi::k_fb_report, dim3(fb.S), dim3(64), 0, stream, F, h->SW, kshared);
+    for (int q = 0; q < fb.S; ++q)
+      hipLaunchKernelGGL(rexi::k_fb_accumulate, dim3(256), dim3(TPB), 0, stream, F, q, out);
+    HIPCHK(h, hipGetLastError());
+    std::vector<SysState_t> fst((size_t)fb.S);
+    HIPCHK(h, hipMemcpyAsync(fst.data(), F.st, fb.S * sizeof(SysState_t), hipMemcpyDeviceToHost, stream));
+    HIPCHK(h, hipStreamSynchronize(stream));
+    for (auto& x : fst) {
+      h->fb_cycles = std::max(h->fb_cycles, x.cycles);
+      h->fb_its += x.its;
+    }
+  }
+  return REXI_OK;
+}
+
 // fused (marching pass only): the pass of iteration j also ends iteration j - 1
 template <int KH>
 void launch_col(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork& SW, int j, bool fused,
@@ -908,13 +1068,37 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
     Timed t(h, PC_REDUCE, 0, stream);
     hipLaunchKernelGGL(rexi::k_shifted_backsub, dim3((h->SW.K + rexi::NWAVE - 1) / rexi::NWAVE), dim3(TPB), 0,
                        stream, W, h->SW);
-    hipLaunchKernelGGL(rexi::k_shifted_z, dim3(S), dim3(TPB), 0, stream, W, h->SW);
+  }
+  // poles that missed their target within the basis: per-pole solves finish
+  // them (host checks only), and they are left out of z
+  std::vector<int> missed;
+  h->fb_poles = 0;
+  h->fb_cycles = 0;
+  h->fb_its = 0;
+  // a system that stopped before m iterations met every pole's target
+  if (h->fb.ready && !h->syncfree && h->k_hint >= m) {
+    std::vector<int32_t> its((size_t)h->SW.K);
+    HIPCHK(h, hipMemcpyAsync(its.data(), h->SW.its, its.size() * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    HIPCHK(h, hipStreamSynchronize(stream));
+    for (int p = 0; p < h->SW.K; ++p)
+      if (its[p] == 0) missed.push_back(p);
+  }
+  rexi::ShiftWork SWz = h->SW;
+  SWz.fb_skip = missed.empty() ? 0 : 1;
+  {
+    Timed t(h, PC_REDUCE, 0, stream);
+    hipLaunchKernelGGL(rexi::k_shifted_z, dim3(S), dim3(TPB), 0, stream, W, SWz);
   }
   {
     Timed t(h, PC_POLESUM, 0, stream);
     hipLaunchKernelGGL((rexi::k_combine_out<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, h->SW, out);
   }
   HIPCHK(h, hipGetLastError());
+  if (!missed.empty()) {
+    h->fb_poles = (int)missed.size();
+    rexi_status rs = run_fallback<PPT>(h, missed, b, out, stream);
+    if (rs != REXI_OK) return rs;
+  }
   return REXI_OK;
 }
 
@@ -1209,6 +1393,10 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
     return fail(nullptr, REXI_E_INVALID_ARG, "march_planes must be in [-1, 1024]");
   if (o.march_slots != 0 && o.march_slots != 3 && o.march_slots != 5 && o.march_slots != 8)
     return fail(nullptr, REXI_E_INVALID_ARG, "march_slots must be 0, 3, 5 or 8");
+  if (o.fallback != 0 && o.fallback != 1) return fail(nullptr, REXI_E_INVALID_ARG, "fallback must be 0 or 1");
+  if (o.fallback_m < 1 || o.fallback_m > 256)
+    return fail(nullptr, REXI_E_INVALID_ARG, "fallback_m must be in [1, 256]");
+  if (o.fallback_bytes < 0) return fail(nullptr, REXI_E_INVALID_ARG, "fallback_bytes < 0");
 
   // ---- validate the instances (host side, before any device work)
   int64_t N = 0, Ktot = 0;
@@ -1318,7 +1506,8 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   } while (0)
   SETUP_CHK(hipMalloc(&h->V64, (size_t)N * sizeof(double)));
   SETUP_CHK(hipMemcpyAsync(h->V64, V_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream));
-  if (o.precision == REXI_PREC_C64_REFINE) {
+  // FP32 V: complex64 inner solves (also those finishing missed shared-basis poles)
+  if (o.precision == REXI_PREC_C64_REFINE || (o.solver == REXI_SOLVER_SHIFTED && o.fallback)) {
     SETUP_CHK(hipMalloc(&h->V32, (size_t)N * sizeof(float)));
     hipLaunchKernelGGL(rexi::k_v_to_f32, dim3(1024), dim3(TPB), 0, stream, h->V64, h->V32, (int64_t)N);
     SETUP_CHK(hipGetLastError());
@@ -1330,7 +1519,7 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   SETUP_CHK(hipMemcpyAsync(h->ditile, h->hitile.data(), (count + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
   SETUP_CHK(hipHostMalloc((void**)&h->hpin, 64 * sizeof(int32_t), hipHostMallocDefault));
   SETUP_CHK(hipStreamSynchronize(stream));
-  h->ws_bytes = (int64_t)N * (o.precision ? 12 : 8);
+  h->ws_bytes = (int64_t)N * (h->V32 ? 12 : 8);
   h->shifted = o.solver == REXI_SOLVER_SHIFTED;
   rexi_status st = h->shifted ? init_shifted(h, stream) : init_solver(h, h->fwd, 1, stream);
   if (st != REXI_OK) {
@@ -1341,6 +1530,7 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   if (o.autotune && o.tile == 0 && o.grid_blocks == 0) st = autotune(h, h->fwd, stream);
   if (st == REXI_OK && h->shifted && o.lanczos == 1 && o.march_planes > 0)
     st = apply_columns(h, h->fwd, o.march_slots ? o.march_slots : 5, o.march_planes, stream);
+  if (st == REXI_OK && h->shifted && o.fallback) st = init_fallback(h, stream);
   if (st != REXI_OK) {
     g_setup_error = h->err;
     destroy_handle(h);
@@ -1412,6 +1602,9 @@ void rexi_default_options(rexi_options* o) {
   o->max_workspace_bytes = 0;
   o->march_planes = 0;
   o->march_slots = 0;
+  o->fallback = 1;
+  o->fallback_m = 30;
+  o->fallback_bytes = 0;
 }
 
 rexi_status rexi_setup(rexi_handle** out, const rexi_grid* g, const double* V_dev, double hbar, double mass,
@@ -1515,9 +1708,10 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
           s0.its = std::max(s0.its, x.its);
           s0.bnorm = std::max(s0.bnorm, x.bnorm);
         }
+        its_total += h->fb_its;
         if (n == nsteps - 1) {
           info->K = K;
-          info->max_cycles_used = 1;
+          info->max_cycles_used = 1 + h->fb_cycles;
           info->not_converged = 0;
           info->max_rel_residual = 0.0;
           double bound = 0.0;
@@ -1526,7 +1720,7 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
             info->max_rel_residual = std::max(info->max_rel_residual, res[k]);
             bound += std::abs(h->w[k]) * res[k] / h->dist_sys[k];
             if (info->iterations) info->iterations[k] = its[k] > 0 ? its[k] : s0.its;
-            if (info->cycles) info->cycles[k] = 1;
+            if (info->cycles) info->cycles[k] = its[k] > s0.its ? 1 + h->fb_cycles : 1;
             if (info->rel_residual) info->rel_residual[k] = res[k];
           }
           info->certified_bound = bound;

@@ -350,6 +350,7 @@ struct ShiftWork {
   int64_t zstride;    // complex elements per z buffer
   const int32_t* col_start;  // [S+1] prefix of column-marching items (null: unused)
   int32_t col_total;
+  int32_t fb_skip;    // 1: poles that missed their target (its = 0) are left out of z
 };
 
 // Grid (S, j + 2): block (s, i) with lo <= i <= j reduces the tile partials
@@ -1601,6 +1602,7 @@ __global__ __launch_bounds__(TPB) void k_shifted_z(Work W, ShiftWork SW) {
   for (int i = threadIdx.x; i < k; i += TPB) {
     double2 zi = make_double2(0.0, 0.0);
     for (int q = SW.pole0[s]; q < SW.pole0[s + 1]; ++q) {
+      if (SW.fb_skip && SW.its[q] == 0) continue;  // finished by a per-pole solve
       const double2 wq = reinterpret_cast<const double2*>(SW.w)[q];
       const double2 yq = reinterpret_cast<const double2*>(SW.y)[(int64_t)q * m + i];
       const double2 tz = cmul(wq, yq);
@@ -1821,6 +1823,98 @@ __global__ __launch_bounds__(TPB) void k_combine_out(Work W, ShiftWork SW, doubl
 #pragma unroll
     for (int q = 0; q < PPT; ++q)
       if (in[q]) out[off + p0 + q * TPB] = acc[q];
+  }
+}
+
+// ------------------------------------------------------------ fallback
+// Poles the shared basis could not finish (its Krylov dimension is capped)
+// continue as per-pole restarted solves warm-started from the shared-basis
+// iterate x_p = V y_p. F is the per-pole solver of those poles, W the shared one.
+
+// x_s = sum_{i<k} y_{p,i} c_i u_i(inst) in FP64 for every system s of F.
+template <int PPT>
+__global__ __launch_bounds__(TPB) void k_fb_init_x(Work F, Work W, ShiftWork SW) {
+  __shared__ double2 coef[MAXM];
+  int sprev = -1;
+  for (int item = blockIdx.x; item < F.total_tiles; item += gridDim.x) {
+    const int s = find_sys(F.tile_start, F.S, item);
+    const SysDesc& d = F.sys[s];
+    const int inst = d.inst;
+    const SysDesc& dw = W.sys[inst];
+    const int k = W.st[inst].kcyc;
+    if (s != sprev) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < k; i += TPB) {
+        const double2 yi = reinterpret_cast<const double2*>(SW.y)[(int64_t)d.pole * W.m + i];
+        const double c = W.cscale[(int64_t)inst * (W.m + 1) + i];
+        coef[i] = make_double2(yi.x * c, yi.y * c);
+      }
+      __syncthreads();
+      sprev = s;
+    }
+    const int t = item - d.tile0;
+    const double2* __restrict__ u0 = basis_vec<double2>(W, dw, 0);
+    double2* __restrict__ x = reinterpret_cast<double2*>(F.x) + d.xoff;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int p = t * F.tile + q * TPB + threadIdx.x;
+      if (p < d.n) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int i = 0; i < k; ++i) {
+          const double2 c = coef[i];
+          const double2 a = u0[(int64_t)i * dw.n + p];
+          acc.x += c.x * a.x - c.y * a.y;
+          acc.y += c.x * a.y + c.y * a.x;
+        }
+        x[p] = acc;
+      }
+    }
+  }
+}
+
+// Per system of F: state of a solve whose first cycle has just ended with the
+// warm-start iterate (the explicit residual and restart decision follow).
+__global__ __launch_bounds__(TPB) void k_fb_state(Work F, Work W) {
+  const int s = blockIdx.x;
+  if (s >= F.S) return;
+  if (s == 0) {
+    const int nc = F.max_cycles * (F.m + 1) + 2;
+    for (int i = threadIdx.x; i < nc; i += TPB) F.counters[i] = 0;
+  }
+  if (threadIdx.x != 0) return;
+  const SysDesc& d = F.sys[s];
+  SysState_t& st = F.st[s];
+  st.bnorm = W.st[d.inst].bnorm;
+  st.rnorm = st.bnorm;
+  st.rho = 1.0;
+  st.its = 0;
+  st.cycles = 0;
+  st.kcyc = 0;
+  st.reorth = 0;
+  st.first = 0;
+  st.state = ST_FINISH;
+}
+
+// Per system of F: its final residual and iteration count replace the pole's.
+__global__ __launch_bounds__(64) void k_fb_report(Work F, ShiftWork SW, int kshared_its) {
+  const int s = blockIdx.x;
+  if (s >= F.S || threadIdx.x != 0) return;
+  const int p = F.sys[s].pole;
+  SW.res[p] = F.st[s].rho;
+  SW.its[p] = kshared_its + F.st[s].its;
+}
+
+// out[inst] += w x of one system of F (systems of one instance are added one
+// launch after another, in pole order).
+__global__ __launch_bounds__(TPB) void k_fb_accumulate(Work F, int s, double2* __restrict__ out) {
+  const SysDesc& d = F.sys[s];
+  const double2* __restrict__ x = reinterpret_cast<const double2*>(F.x) + d.xoff;
+  for (int p = blockIdx.x * TPB + threadIdx.x; p < d.n; p += gridDim.x * TPB) {
+    const double2 xv = x[p];
+    double2 o = out[d.off + p];
+    o.x += d.wre * xv.x - d.wim * xv.y;
+    o.y += d.wre * xv.y + d.wim * xv.x;
+    out[d.off + p] = o;
   }
 }
 

@@ -61,6 +61,8 @@ struct SysDesc {
   int32_t col_L;
   int32_t col_nr;
   int32_t col_n;     // items of the system (col_n = ceil(n1/col_rows) col_nr)
+  int32_t pole;      // fallback solves: the pole (index into s, w) of the system
+  int32_t pad2;
 };
 
 // Instance descriptor (pole sum, apply_H).
@@ -107,7 +109,6 @@ struct Work {
   double* part;     // complex partial sums [pbase + slot * ntiles + t]
   double* pnorm;    // real partial sums [tile]
   int32_t* counters;// [max_cycles * (m + 1) + 2]
-  int32_t* tick;    // [S][4] completion tickets of the passes A, B, A', B'
   double* x;        // FP64 solutions [xoff + i]
   void* basis;      // Krylov bases (complex double or float)
   const double* V64;

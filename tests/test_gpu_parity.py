@@ -408,8 +408,11 @@ def test_step_inside_caller_graph_capture(rexi):
 
 
 # ---------------------------------------------------------------- uneven batch
-@pytest.mark.parametrize("solver,prec", [("shifted", "c128"), ("per_pole", "c128"), ("per_pole", "c64")])
+@pytest.mark.parametrize("solver,prec", [("shifted", "c128"), ("shifted_m24", "c128"), ("per_pole", "c128"),
+                                         ("per_pole", "c64")])
 def test_uneven_batch_matches_oracle_per_instance(rexi, solver, prec):
+    # shifted_m24: a shared basis of 24 vectors is too short for the larger
+    # instances; per-pole solves warm-started from it finish those poles
     import torch
     from paper_1912_03312_amd import rexi as r
     insts = inputs.batch_instances(count=6, sides=(12, 17, 24, 31, 40, 47))
@@ -426,9 +429,10 @@ def test_uneven_batch_matches_oracle_per_instance(rexi, solver, prec):
         bet.append(b)
     cnt = len(insts)
     tol = dict(tol=1e-11, tol_policy="certified") if prec == "c128" else dict(tol=1e-8, tol_policy="certified")
+    m = {"shifted": 256, "shifted_m24": 24}.get(solver, 30)
     h = r.setup_batch(grids, to_dev(np.concatenate(Vs)), [1.0] * cnt, [1.0] * cnt, dts, Ks,
-                      np.concatenate(sig), np.concatenate(bet), solver=solver, precision=prec,
-                      m=256 if solver == "shifted" else 30, max_cycles=200, **tol)
+                      np.concatenate(sig), np.concatenate(bet), solver=solver.split("_m")[0], precision=prec,
+                      m=m, max_cycles=200, **tol)
     p0 = to_dev(np.concatenate(psis))
     out = torch.empty_like(p0)
     info = h.step(p0, out, 1)
@@ -446,6 +450,51 @@ def test_uneven_batch_matches_oracle_per_instance(rexi, solver, prec):
         off += g.size
     print("batch", solver, prec, errs, info["total_iterations"])
     h.close()
+
+
+# ---------------------------------------------------------------- fallback
+@pytest.mark.parametrize("name,scale,m,fallback", [("3d_bumps", 12, 6, 1), ("3d_bumps", 12, 6, 0),
+                                                   ("2d_double_well", 40, 60, 1)])
+def test_shifted_fallback_finishes_missed_poles(rexi, name, scale, m, fallback):
+    # a shared basis of m vectors is too short for these poles: with the
+    # fallback, per-pole solves warm-started from the shared iterate finish
+    # them (to the oracle's bar, or the certificate for the double well);
+    # without it they are reported in not_converged
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    wl = inputs.workload(name, scale=scale)
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+    D = ost.DirectStepper(g.n, g.h, wl.V, s, b, wl.dt)
+    ref = [D.step(wl.psi0)]
+    ref.append(D.step(ref[0]))
+    tol = 1e-11 if name == "3d_bumps" else 1e-9
+    h = r.setup(g.n, g.lo, g.hi, to_dev(wl.V.ravel()), 1.0, 1.0, wl.dt, s, b, solver="shifted", m=m, tol=tol,
+                tol_policy="certified" if name == "3d_bumps" else "relres", fallback=fallback, max_cycles=200)
+    cur = to_dev(wl.psi0.ravel())
+    nxt = torch.empty_like(cur)
+    out, infos = [], []
+    for _ in range(2):
+        infos.append(h.step(cur, nxt, 1, raise_on_nc=False))
+        torch.cuda.synchronize()
+        out.append(nxt.cpu().numpy().reshape(g.n).copy())
+        cur, nxt = nxt, cur
+    h.close()
+    errs = [rel(o, rr) for o, rr in zip(out, ref)]
+    print("fallback", name, m, fallback, errs, [(i["not_converged"], i["max_cycles_used"], i["total_iterations"],
+                                                i["certified_bound"]) for i in infos])
+    if not fallback:
+        assert all(i["not_converged"] > 0 for i in infos)
+        return
+    assert all(i["not_converged"] == 0 for i in infos)
+    assert all(i["max_cycles_used"] > 1 for i in infos)
+    floor = iterative_floor(g, wl.V, s, b, wl.dt)
+    if name == "3d_bumps":
+        assert max(errs) <= max(1e-10, 3 * floor)
+    else:
+        # the second step starts from the GPU's first step: errors add up
+        assert errs[0] <= infos[0]["certified_bound"] + 3 * floor
+        assert errs[1] <= errs[0] * (1 + 1e-3) + infos[1]["certified_bound"] + 3 * floor
 
 
 # ---------------------------------------------------------------- marching pass
