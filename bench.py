@@ -165,6 +165,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the instrumented kernel region")
     ap.add_argument("--calib-copy", action="store_true", help="end with 3 copies of 256 MiB (counter scaling)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the per-pole FP64 and mixed-precision forms timed beside the headline")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -325,6 +327,33 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
+    if not args.no_variants and args.solver == "shifted":
+        # the plain FP64 per-pole form and the batched mixed-precision form
+        # (complex64 inner solves, FP64 refinement) at the same per-pole
+        # target, a few steps each
+        var = {}
+        for name, prec in (("per_pole_c128", "c128"), ("per_pole_c64_refine", "c64")):
+            hv = rexi.setup(g.n, g.lo, g.hi, V, wl.hbar, wl.mass, wl.dt, sigma, beta, precision=prec,
+                            solver="per_pole", tol=args.tol, m=wl.m)
+            a = psi.clone()
+            hv.step(a, out, 1, info=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(2):
+                hv.step(a, out, 1, info=False)
+                a, out = out, a
+            torch.cuda.synchronize()
+            vms = (time.perf_counter() - t0) * 1e3 / 2
+            vi = hv.step(a, out, 1, info=True)
+            hv.close()
+            var[name] = {"value": round(1e3 / vms, 4), "ms_per_step": round(vms, 3),
+                         "iterations_per_step": int(vi["total_iterations"]),
+                         "max_rel_residual": vi["max_rel_residual"], "not_converged": int(vi["not_converged"])}
+            print(f"# variant {name}: {vms:.1f} ms/step", file=sys.stderr, flush=True)
+        var["mixed_speedup_vs_fp64_per_pole"] = round(var["per_pole_c128"]["ms_per_step"]
+                                                      / var["per_pole_c64_refine"]["ms_per_step"], 3)
+        var["shared_basis_speedup_vs_fp64_per_pole"] = round(var["per_pole_c128"]["ms_per_step"] / ms, 2)
+        res["variants"] = var
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(wl, sigma, beta)
