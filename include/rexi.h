@@ -153,6 +153,17 @@ typedef struct {
   int64_t fallback_bytes; /* device workspace reserved for them at setup
                            (0 = min(16 GiB, a quarter of the free memory));
                            unconverged poles are solved in waves that fit    */
+  double stab_eps;      /* weights scaled by (1 - stab_eps), 0 <= stab_eps
+                           < 1 (Section 3.4: |r(iy)| exceeds one by up to
+                           the approximation error ||e||; a factor
+                           1 - eps with eps slightly above ||e|| makes the
+                           step stable). Default 0 (not applied)            */
+  int32_t center;       /* 1: solve with H - c I, c the midpoint of the
+                           spectrum bound [min V, (hbar^2/2m) sum 4/h^2 +
+                           max V] of each instance, and multiply the step by
+                           exp(-i dt c / hbar) (folded into the weights):
+                           the interval the poles must cover halves. The
+                           same step for the exact exponential; 0 default   */
 } rexi_options;
 
 typedef struct {

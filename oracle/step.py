@@ -30,6 +30,19 @@ def shifts_and_weights(sigma, beta, dt, hbar=1.0):
     return 1j * hbar * sigma / dt, 1j * hbar * beta / dt
 
 
+def step_factor(dt, hbar=1.0, center=0.0, stab_eps=0.0):
+    """Scalar that multiplies every weight.
+
+    Stabilisation (Section 3.4): the coefficients beta_j are multiplied by
+    1 - eps, eps slightly above the approximation error, so that |r(iy)| <= 1.
+    Centering (not in the paper): exp(-i dt H / hbar) = exp(-i dt c / hbar)
+    exp(-i dt (H - c) / hbar), so the step may solve with H - c I and multiply
+    by the scalar phase; with c the midpoint of the spectrum the interval the
+    approximation must cover halves.
+    """
+    return (1.0 - stab_eps) * np.exp(-1j * dt * center / hbar)
+
+
 def rational(z, sigma, beta):
     """r(z) = sum_j beta_j / (z - sigma_j) (eq. ``partial-fraction-decomposition``)."""
     z = np.asarray(z, dtype=np.complex128)
@@ -45,10 +58,13 @@ class DirectStepper:
     1D grids use the banded (tridiagonal) LU of LAPACK, the rest SuperLU.
     """
 
-    def __init__(self, n, h, V, sigma, beta, dt, hbar=1.0, mass=1.0):
+    def __init__(self, n, h, V, sigma, beta, dt, hbar=1.0, mass=1.0, center=0.0, stab_eps=0.0):
         self.n = tuple(n)
         self.s, self.w = shifts_and_weights(sigma, beta, dt, hbar)
+        self.w = self.w * step_factor(dt, hbar, center, stab_eps)
         self.H = hamiltonian(n, h, V, hbar, mass)
+        if center != 0.0:
+            self.H = (self.H - center * sp.identity(self.H.shape[0], format="csr")).tocsr()
         N = self.H.shape[0]
         self.N = N
         self.banded = len(self.n) == 1
@@ -143,8 +159,9 @@ class EigStepper:
         c = self.Q.T @ np.asarray(psi, dtype=np.complex128).ravel()
         return (self.Q @ (fvals * c)).reshape(self.n)
 
-    def step(self, psi, sigma, beta, dt):
-        return self.apply(psi, rational(-1j * dt * self.lam / self.hbar, sigma, beta))
+    def step(self, psi, sigma, beta, dt, center=0.0, stab_eps=0.0):
+        f = step_factor(dt, self.hbar, center, stab_eps)
+        return self.apply(psi, f * rational(-1j * dt * (self.lam - center) / self.hbar, sigma, beta))
 
     def exact(self, psi, t):
         return self.apply(psi, np.exp(-1j * t * self.lam / self.hbar))

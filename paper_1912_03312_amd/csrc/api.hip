@@ -88,7 +88,8 @@ struct rexi_handle {
   double* V64 = nullptr;
   float* V32 = nullptr;
   std::vector<cplx> s, w;             // per system (pole), instance order
-  std::vector<double> tol_sys, dist_sys, lam_lo, lam_hi;
+  std::vector<double> tol_sys, dist_sys, lam_lo, lam_hi;  // spectrum bound of the solved operator
+  std::vector<double> center;         // per instance: the solves use H - center I
   std::vector<int> Kinst;
   Solver fwd, adj;
   Solver fb;                          // per-pole solves of poles the shared basis missed
@@ -526,7 +527,7 @@ void make_systems(rexi_handle* h, Solver& sv, bool conj_shift, int rhs_sel) {
       d.c0 = in.c0;
       d.c1 = in.c1;
       d.c2 = in.c2;
-      d.diag = in.diag;
+      d.diag = in.diag - h->center[i];
       const cplx s = conj_shift ? std::conj(h->s[sidx]) : h->s[sidx];
       d.sre = s.real();
       d.sim = s.imag();
@@ -558,7 +559,7 @@ rexi_status init_solver(rexi_handle* h, Solver& sv, int copies, hipStream_t stre
       d.c0 = in.c0;
       d.c1 = in.c1;
       d.c2 = in.c2;
-      d.diag = in.diag;
+      d.diag = in.diag - h->center[i];
       d.tol = 0.0;
       d.dist = 1.0;
       d.inst = i;
@@ -773,7 +774,7 @@ rexi_status run_fallback(rexi_handle* h, const std::vector<int>& poles, const do
       d.c0 = in.c0;
       d.c1 = in.c1;
       d.c2 = in.c2;
-      d.diag = in.diag;
+      d.diag = in.diag - h->center[pinst[p]];
       d.sre = h->s[p].real();
       d.sim = h->s[p].imag();
       d.wre = h->w[p].real();
@@ -1397,6 +1398,8 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   if (o.fallback_m < 1 || o.fallback_m > 256)
     return fail(nullptr, REXI_E_INVALID_ARG, "fallback_m must be in [1, 256]");
   if (o.fallback_bytes < 0) return fail(nullptr, REXI_E_INVALID_ARG, "fallback_bytes < 0");
+  if (!(o.stab_eps >= 0.0 && o.stab_eps < 1.0)) return fail(nullptr, REXI_E_INVALID_ARG, "stab_eps must be in [0, 1)");
+  if (o.center != 0 && o.center != 1) return fail(nullptr, REXI_E_INVALID_ARG, "center must be 0 or 1");
 
   // ---- validate the instances (host side, before any device work)
   int64_t N = 0, Ktot = 0;
@@ -1454,15 +1457,22 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
       vmin = std::min(vmin, Vh[(size_t)p]);
       vmax = std::max(vmax, Vh[(size_t)p]);
     }
-    const double lo = vmin, hi = 2.0 * in.diag + vmax;  // (hbar^2/2m) sum 4/h^2 + max V
+    // spectrum bound of H: [min V, (hbar^2/2m) sum 4/h^2 + max V]; with
+    // centering the solves use H - c I, c its midpoint, and the step is
+    // multiplied by exp(-i dt c / hbar): exp(-i dt H / hbar) is unchanged
+    const double c = o.center ? 0.5 * (vmin + 2.0 * in.diag + vmax) : 0.0;
+    const double lo = vmin - c, hi = 2.0 * in.diag + vmax - c;
     h->lam_lo.push_back(lo);
     h->lam_hi.push_back(hi);
+    h->center.push_back(c);
+    const cplx phase = std::exp(cplx(0.0, -dt[i] * c / hbar[i])) * (1.0 - o.stab_eps);
     for (int k = 0; k < K[i]; ++k, ++kk) {
-      // s_j = i hbar sigma_j / dt, w_j = i hbar beta_j / dt (eq. rational-evaluation, B = hbar I)
+      // s_j = i hbar sigma_j / dt, w_j = i hbar beta_j / dt (eq. rational-evaluation, B = hbar I);
+      // the centering phase and the stabilisation factor (Section 3.4) scale w_j
       const cplx I(0.0, 1.0);
       const cplx sg(sigma[kk].re, sigma[kk].im), bt(beta[kk].re, beta[kk].im);
       const cplx s = I * hbar[i] * sg / dt[i];
-      const cplx w = I * hbar[i] * bt / dt[i];
+      const cplx w = phase * (I * hbar[i] * bt / dt[i]);
       const double re = std::min(std::max(s.real(), lo), hi);
       const double dist = std::abs(cplx(re, 0.0) - s);
       const double scale = std::max({std::fabs(lo), std::fabs(hi), std::abs(s), 1e-300});
@@ -1605,6 +1615,8 @@ void rexi_default_options(rexi_options* o) {
   o->fallback = 1;
   o->fallback_m = 30;
   o->fallback_bytes = 0;
+  o->stab_eps = 0.0;
+  o->center = 0;
 }
 
 rexi_status rexi_setup(rexi_handle** out, const rexi_grid* g, const double* V_dev, double hbar, double mass,

@@ -49,7 +49,8 @@ class Options(C.Structure):
                 ("capture_cycles", C.c_int32), ("graph_chunks", C.c_int32),
                 ("profile", C.c_int32), ("tile", C.c_int32), ("grid_blocks", C.c_int32), ("autotune", C.c_int32),
                 ("max_workspace_bytes", C.c_int64), ("march_planes", C.c_int32), ("march_slots", C.c_int32),
-                ("fallback", C.c_int32), ("fallback_m", C.c_int32), ("fallback_bytes", C.c_int64)]
+                ("fallback", C.c_int32), ("fallback_m", C.c_int32), ("fallback_bytes", C.c_int64),
+                ("stab_eps", C.c_double), ("center", C.c_int32)]
 
 
 class StepInfo(C.Structure):

@@ -452,6 +452,48 @@ def test_uneven_batch_matches_oracle_per_instance(rexi, solver, prec):
     h.close()
 
 
+# ---------------------------------------------------------------- setup variants
+@pytest.mark.parametrize("solver", ["shifted", "per_pole"])
+@pytest.mark.parametrize("name,scale,K,R1", [("1d_harmonic", None, 16, 28.0), ("3d_bumps", 12, 64, 180.0)])
+def test_centered_stabilised_step_matches_oracle(rexi, solver, name, scale, K, R1):
+    # solves with H - c I and the weights scaled by (1 - eps) exp(-i dt c):
+    # two steps against the oracle's direct solves of the same definition
+    wl = inputs.workload(name, scale=scale)
+    g = wl.grid
+    s, b, d = poles(K, R1)
+    lo, hi = ham.gershgorin(g.n, g.h, wl.V)
+    c = 0.5 * (lo + hi)
+    eps = 1.01 * d["err_inf"]
+    psi = inputs.random_state(g.size, 6).reshape(g.n)
+    D = ost.DirectStepper(g.n, g.h, wl.V, s, b, wl.dt, center=c, stab_eps=eps)
+    ref = [D.step(psi)]
+    ref.append(D.step(ref[0]))
+    out, infos = gpu_steps(g, wl.V, psi, s, b, wl.dt, 2, solver=solver, m=200 if solver == "shifted" else 30,
+                           tol=1e-11, tol_policy="certified", center=1, stab_eps=eps, max_cycles=100)
+    errs = [rel(o, r) for o, r in zip(out, ref)]
+    bar = max(1e-10, 3 * iterative_floor(g, wl.V - c, s, b, wl.dt))
+    print("centered", name, solver, errs, bar)
+    assert max(errs) <= bar
+
+
+def test_centering_reaches_the_exact_exponential(rexi):
+    # 1D harmonic at dt = 0.1: the poles cover dt * 28 < dt * lam_max; with
+    # centering the GPU step of a random state matches exp(-i dt H) to the
+    # approximation error, without it the uncovered modes are wrong
+    wl = inputs.workload("1d_harmonic")
+    g = wl.grid
+    s, b, d = poles(16, 28.0)
+    psi = inputs.random_state(g.size, 3).reshape(g.n)
+    ex = ost.EigStepper(g.n, g.h, wl.V).exact(psi, wl.dt)
+    errs = {}
+    for cen in (0, 1):
+        out, infos = gpu_steps(g, wl.V, psi, s, b, wl.dt, 1, solver="shifted", m=200, tol=1e-12, center=cen)
+        errs[cen] = rel(out[0], ex)
+    print("exact exponential, centered / not", errs)
+    assert errs[1] < 1e-6
+    assert errs[0] > 1e-2
+
+
 # ---------------------------------------------------------------- fallback
 @pytest.mark.parametrize("name,scale,m,fallback", [("3d_bumps", 12, 6, 1), ("3d_bumps", 12, 6, 0),
                                                    ("2d_double_well", 40, 60, 1)])

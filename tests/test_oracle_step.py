@@ -226,3 +226,63 @@ def test_cpu_gmres_step_within_certificate(p16):
     bound = sum(abs(Kst.w[j]) * 1e-13 / Kst.s[j].imag for j in range(len(s)))
     assert ost.rel_err(out, ref) <= bound + 50 * d["amplification"] * 2.2e-16
     assert max(its) < 60
+
+
+# ---------------------------------------------------------------- setup variants
+def test_centering_meets_the_accuracy_condition():
+    # 1D harmonic grid at dt = 0.1: dt * lam_max = 37.2 exceeds R1 = 28, so the
+    # uncovered modes of a random state are propagated wrongly; solving with
+    # H - c I (c the midpoint of the spectrum bound) and multiplying by
+    # exp(-i dt c) only has to cover dt * 19 and matches the exact exponential
+    wl = inputs.workload("1d_harmonic")
+    g = wl.grid
+    s, b, d = fcf.faber_cf(16, 28.0)
+    E = ost.EigStepper(g.n, g.h, wl.V)
+    lo, hi = ham.gershgorin(g.n, g.h, wl.V)
+    c = 0.5 * (lo + hi)
+    assert wl.dt * E.lam.max() > 28.0 > wl.dt * 0.5 * (hi - lo)
+    psi = inputs.random_state(g.size, 3)
+    ex = E.exact(psi, wl.dt).ravel()
+    err_plain = ost.rel_err(E.step(psi, s, b, wl.dt).ravel(), ex)
+    err_cent = ost.rel_err(E.step(psi, s, b, wl.dt, center=c).ravel(), ex)
+    assert err_plain > 1e-2
+    assert err_cent < 1e-6
+
+
+@pytest.mark.parametrize("n", [(9, 11), (4, 5, 6)])
+def test_centered_direct_step_matches_eigen_route(n):
+    g = inputs.Grid(n, tuple(-3.0 - a for a in range(len(n))), tuple(4.0 + a for a in range(len(n))))
+    V = inputs.gaussian_bumps(g, 7)
+    lo, hi = ham.gershgorin(g.n, g.h, V)
+    c = 0.5 * (lo + hi)
+    s, b, _ = fcf.faber_cf(16, 32.0)
+    psi = inputs.random_state(g.size, 4)
+    a = ost.DirectStepper(g.n, g.h, V, s, b, 0.1, center=c, stab_eps=1e-6).step(psi).ravel()
+    e = ost.EigStepper(g.n, g.h, V).step(psi, s, b, 0.1, center=c, stab_eps=1e-6).ravel()
+    assert ost.rel_err(a, e) < 1e-11
+
+
+@pytest.mark.parametrize("K,R1", [(16, 28.0), (32, 80.0)])
+def test_stabilised_weights_bound_the_stability_function(K, R1):
+    # Section 3.4: |r(iy)| exceeds one by about the approximation error on the
+    # interval; scaling every beta_j by 1 - eps, eps slightly above ||e||,
+    # brings it to at most one on the whole imaginary axis (checked to 50 R1)
+    s, b, _ = fcf.faber_cf(K, R1)
+    e = fcf.diagnostics(s, b, R1)["err_inf"]
+    y = np.linspace(-50 * R1, 50 * R1, 200001)
+    r = np.abs(ost.rational(1j * y, s, b))
+    assert 0.5 * e < r.max() - 1.0 < 1.5 * e
+    eps = 1.01 * e
+    f = abs(ost.step_factor(1.0, 1.0, 0.0, eps))
+    assert (f * r).max() <= 1.0
+    # and the stabilised step does not grow a random state over many steps
+    g = inputs.Grid((40,), (-6.0,), (6.0,))
+    V = 0.5 * g.axes()[0] ** 2
+    lo, hi = ham.gershgorin(g.n, g.h, V)
+    dt = 0.9 * R1 / hi
+    D = ost.DirectStepper(g.n, g.h, V, s, b, dt, stab_eps=eps)
+    psi = inputs.random_state(g.size, 5)
+    x = psi.copy()
+    for _ in range(20):
+        x = D.step(x).ravel()
+    assert np.linalg.norm(x) <= np.linalg.norm(psi) * (1 + 1e-13)
