@@ -185,6 +185,7 @@ class Workload:
     hbar: float = 1.0
     mass: float = 1.0
     precision: str = "c128"
+    center: bool = False
     note: str = ""
 
 
@@ -204,6 +205,14 @@ def workload(name: str, scale: Optional[int] = None) -> Workload:
       complex64 inner solves refined in FP64 to 1e-10.
     * ``2d_adjoint`` -- 256^2 on [-10, 10]^2, 20 bumps (seed 5), packet
       (seed 50), target packet (seed 51); dt 0.5, 20 steps, K = 32.
+    * ``1d_tunnel`` -- the tunnelling problem of Section 4.1 (Table 2) in
+      finite differences: 8001 points (the paper's degrees of freedom) on
+      [-20.005, 20.005], so h = 0.005 = C_barr and the barrier of height 15 is
+      one grid point of the same integrated strength; packet at -3 with
+      Sigma = 4 I (width 2) and momentum 5; dt 2e-4 for T = 0.2 (1000 steps);
+      K = 10 poles on i[-10, 10] (the largest K that is not degenerate in FP64
+      at R1 = 10). dt lam_max = 16 exceeds R1, so the step is centered
+      (half-width 8).
     """
     if name == "1d_harmonic":
         g = cube(scale or 256, 10.0, 1)
@@ -221,6 +230,10 @@ def workload(name: str, scale: Optional[int] = None) -> Workload:
         g = cube(scale or 256, 10.0, 2)
         return Workload(name, g, gaussian_bumps(g, 5), seeded_packet(g, 50, (-2.0, 0.0), 1.0),
                         dt=0.5, steps=20, K=32, R1=80.0, tol=1e-12)
+    if name == "1d_tunnel":
+        g = Grid((scale or 8001,), (-20.005,), (20.005,))
+        return Workload(name, g, step_barrier_1d(g, 15.0, 0.005), gaussian_packet(g, (-3.0,), 2.0, (5.0,)),
+                        dt=2e-4, steps=1000, K=10, R1=10.0, tol=1e-12, m=100, center=True)
     raise KeyError(name)
 
 

@@ -494,6 +494,61 @@ def test_centering_reaches_the_exact_exponential(rexi):
     assert errs[0] > 1e-2
 
 
+# ---------------------------------------------------------------- tunnelling
+@pytest.mark.parametrize("solver", ["shifted", "per_pole"])
+def test_tunnel_matches_oracle(rexi, solver):
+    # the finite-difference tunnelling problem (8001 points, one-point barrier,
+    # centered step, K = 10 on i[-10, 10]): 20 steps against the oracle's
+    # banded direct solves
+    wl = inputs.workload("1d_tunnel")
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+    lo, hi = ham.gershgorin(g.n, g.h, wl.V)
+    c = 0.5 * (lo + hi)
+    D = ost.DirectStepper(g.n, g.h, wl.V, s, b, wl.dt, center=c)
+    ref, x = [], wl.psi0
+    for _ in range(20):
+        x = D.step(x)
+        ref.append(x)
+    out, infos = gpu_steps(g, wl.V, wl.psi0, s, b, wl.dt, 20, solver=solver, m=100 if solver == "shifted" else 30,
+                           tol=1e-11, tol_policy="certified", center=1, max_cycles=100)
+    errs = [rel(o, r) for o, r in zip(out, ref)]
+    floor = iterative_floor(g, wl.V - c, s, b, wl.dt)
+    # errors of consecutive steps add up: the bar grows with the step index
+    bars = [max(1e-10, 3 * floor) * (k + 1) for k in range(20)]
+    print("tunnel", solver, max(errs), errs[-1], floor)
+    assert all(e <= bb for e, bb in zip(errs, bars))
+
+
+def test_tunnel_full_run_against_exact_propagator(rexi):
+    # T = 0.2 (1000 steps): per covered mode the rational approximation errs
+    # by at most ||e||_inf per step, so the error against exp(-i T H) stays
+    # below steps * ||e||_inf (plus the solves' own error)
+    import scipy.linalg as sla
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    wl = inputs.workload("1d_tunnel")
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+    H = ham.hamiltonian(g.n, g.h, wl.V)
+    lam, Q = sla.eigh_tridiagonal(H.diagonal(), H.diagonal(1))
+    T = wl.dt * wl.steps
+    ex = Q @ (np.exp(-1j * T * lam) * (Q.T @ wl.psi0.ravel()))
+    h = r.setup(g.n, g.lo, g.hi, to_dev(wl.V.ravel()), 1.0, 1.0, wl.dt, s, b, solver="shifted", m=100,
+                tol=1e-11, tol_policy="certified", center=1)
+    a = to_dev(wl.psi0.ravel())
+    out = torch.empty_like(a)
+    info = h.step(a, out, wl.steps)
+    torch.cuda.synchronize()
+    h.close()
+    e = rel(out.cpu().numpy(), ex)
+    nrm = float(np.sqrt(np.sum(np.abs(out.cpu().numpy()) ** 2) * g.h[0]))
+    print("tunnel T=0.2 vs exact", e, "norm", nrm, "bound", wl.steps * d["err_inf"])
+    assert info["not_converged"] == 0
+    assert e <= 2.0 * wl.steps * d["err_inf"]
+    assert abs(nrm - 1.0) <= 2.0 * wl.steps * d["err_inf"]
+
+
 # ---------------------------------------------------------------- fallback
 @pytest.mark.parametrize("name,scale,m,fallback", [("3d_bumps", 12, 6, 1), ("3d_bumps", 12, 6, 0),
                                                    ("2d_double_well", 40, 60, 1)])

@@ -286,3 +286,19 @@ def test_stabilised_weights_bound_the_stability_function(K, R1):
     for _ in range(20):
         x = D.step(x).ravel()
     assert np.linalg.norm(x) <= np.linalg.norm(psi) * (1 + 1e-13)
+
+
+def test_tunnel_workload_geometry():
+    # one barrier point of height 15 at x = 0 (h = C_barr, same integrated
+    # strength 15 * 0.005), a normalised packet, and a spectrum that only the
+    # centered step covers with the poles of i[-10, 10]
+    wl = inputs.workload("1d_tunnel")
+    g = wl.grid
+    (x,) = g.axes()
+    assert g.size == 8001 and abs(g.h[0] - 0.005) < 1e-15
+    idx = np.nonzero(wl.V)[0]
+    assert idx.tolist() == [4000] and abs(x[4000]) < 1e-12 and wl.V[4000] == 15.0
+    assert abs(wl.V.sum() * g.h[0] - 15.0 * 0.005) < 1e-15
+    assert abs(np.sum(np.abs(wl.psi0) ** 2) * g.h[0] - 1.0) < 1e-12
+    lo, hi = ham.gershgorin(g.n, g.h, wl.V)
+    assert wl.dt * hi > wl.R1 > wl.dt * 0.5 * (hi - lo)
