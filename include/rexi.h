@@ -149,7 +149,9 @@ typedef struct {
                            warm-started from the shared-basis iterate; 0: they
                            are reported in not_converged. Needs host checks
                            (not with capture_safe)                           */
-  int32_t fallback_m;   /* restart length of those solves, 30                */
+  int32_t fallback_m;   /* restart length of those solves (and of the
+                           per-pole adjoint solves of a shared-basis
+                           handle), 30                                       */
   int64_t fallback_bytes; /* device workspace reserved for them at setup
                            (0 = min(16 GiB, a quarter of the free memory));
                            unconverged poles are solved in waves that fit    */

@@ -584,7 +584,9 @@ rexi_status init_solver(rexi_handle* h, Solver& sv, int copies, hipStream_t stre
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(h, REXI_E_HIP, "hipMemGetInfo failed");
     budget = (size_t)(0.9 * (double)fr);
   }
-  int m = h->opt.m;
+  // restart length: the option, except for the per-pole (adjoint) solves of a
+  // shared-basis handle, whose m is the basis dimension: they restart at fallback_m
+  int m = (h->shifted && copies > 0) ? h->opt.fallback_m : h->opt.m;
   for (;;) {
     layout_systems(sv, m);
     if (solver_bytes(sv.hsys, m, sv.prec, sv.max_cycles, sv.total_tiles) <= budget) break;
