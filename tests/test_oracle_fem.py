@@ -1,0 +1,90 @@
+"""Pins of the oracle's mass-matrix (Q1 finite element) step.
+
+Checked against: the closed-form spectrum of the 1D linear-element pencil
+(and its Kronecker sums in 2D), the finite-difference Hamiltonian it
+reduces to when the mass matrix is lumped, second-order convergence of the
+harmonic-oscillator ground state, a second route to the same step
+(generalised eigendecomposition), the exact propagator, and conservation
+of the M-norm.
+"""
+import numpy as np
+import pytest
+
+from oracle import faber_cf as fcf
+from oracle import fem
+from oracle import hamiltonian as ham
+from paper_1912_03312_amd import inputs
+
+
+def test_p1_pencil_closed_form_1d_and_kronecker_sum_2d():
+    n, h, hbar, mass = 17, 0.3, 0.8, 1.3
+    A, M = fem.matrices((n,), (h,), np.zeros(n), hbar, mass)
+    lam = np.sort(np.linalg.eigvals(np.linalg.solve(M.toarray(), A.toarray())).real)
+    ref = np.sort(fem.p1_eigenvalues_1d(n, h, hbar, mass))
+    assert np.abs(lam - ref).max() <= 1e-13 * ref.max()
+    # 2D: K = K_0 x M_1 + M_0 x K_1, M = M_0 x M_1 -> eigenvalues add
+    n2, h2 = (7, 9), (0.4, 0.25)
+    A, M = fem.matrices(n2, h2, np.zeros(n2), hbar, mass)
+    lam = np.sort(np.linalg.eigvals(np.linalg.solve(M.toarray(), A.toarray())).real)
+    ref = np.sort(np.add.outer(fem.p1_eigenvalues_1d(n2[0], h2[0], hbar, mass),
+                               fem.p1_eigenvalues_1d(n2[1], h2[1], hbar, mass)).ravel())
+    assert np.abs(lam - ref).max() <= 1e-12 * ref.max()
+
+
+def test_lumped_mass_gives_the_finite_difference_hamiltonian():
+    # replacing M_a by h_a I (row sums) turns K into the second-difference
+    # matrix: (hbar^2/2m) K / h^d + V equals H of the finite differences
+    g = inputs.Grid((5, 6, 4), (-1.0, -2.0, 0.0), (2.0, 1.5, 1.0))
+    V = inputs.gaussian_bumps(g, 3)
+    hbar, mass = 0.9, 1.7
+    K = None
+    for a in range(3):
+        mats = [fem.stiffness_1d(g.n[b], g.h[b]).toarray() if b == a else g.h[b] * np.eye(g.n[b])
+                for b in range(3)]
+        term = np.kron(np.kron(mats[0], mats[1]), mats[2])
+        K = term if K is None else K + term
+    vol = float(np.prod(g.h))
+    H_lumped = hbar * hbar / (2 * mass) * K / vol + np.diag(V.ravel())
+    H_fd = ham.hamiltonian(g.n, g.h, V, hbar, mass).toarray()
+    assert np.abs(H_lumped - H_fd).max() <= 1e-12 * np.abs(H_fd).max()
+    # the potential enters A as h^d diag(V)
+    A, M = fem.matrices(g.n, g.h, np.zeros(g.n), hbar, mass)
+    A2, _ = fem.matrices(g.n, g.h, V, hbar, mass)
+    assert np.abs((A2 - A).toarray() - vol * np.diag(V.ravel())).max() <= 1e-15 * vol * np.abs(V).max()
+
+
+def test_harmonic_ground_state_converges_at_second_order():
+    errs = []
+    for N in (64, 128, 256):
+        g = inputs.cube(N, 8.0, 1)
+        V = 0.5 * g.axes()[0] ** 2
+        errs.append(fem.FemEigStepper(g.n, g.h, V).lam[0] - 0.5)
+    assert all(e > 0 for e in errs)  # Ritz values bound the eigenvalue from above
+    for a, b in zip(errs, errs[1:]):
+        assert 3.6 < a / b < 4.4
+    assert errs[-1] < 1e-4
+
+
+@pytest.mark.parametrize("n", [(9, 11), (6, 7, 5)])
+def test_fem_direct_step_matches_generalised_eigen_route(n):
+    g = inputs.Grid(n, tuple(-3.0 - a for a in range(len(n))), tuple(3.0 + a for a in range(len(n))))
+    V = inputs.gaussian_bumps(g, 7)
+    s, b, _ = fcf.faber_cf(16, 32.0)
+    d = fcf.diagnostics(s, b, 32.0)
+    lo, hi = fem.spectrum_bound(g.n, g.h, V)
+    E = fem.FemEigStepper(g.n, g.h, V)
+    assert lo <= E.lam.min() and E.lam.max() <= hi
+    dt = 0.9 * 32.0 / max(abs(lo), abs(hi))
+    psi = inputs.random_state(g.size, 3)
+    for c, eps in ((0.0, 0.0), (0.5 * (lo + hi), 1e-6)):
+        a = fem.FemDirectStepper(g.n, g.h, V, s, b, dt, center=c, stab_eps=eps).step(psi).ravel()
+        e = E.step(psi, s, b, dt, center=c, stab_eps=eps).ravel()
+        assert np.linalg.norm(a - e) <= 1e-11 * np.linalg.norm(e)
+    # the step is the exact propagator up to the approximation error, and
+    # keeps the M-norm psi^H M psi (conserved by exp(-i dt M^-1 A))
+    a = fem.FemDirectStepper(g.n, g.h, V, s, b, dt).step(psi).ravel()
+    ex = E.exact(psi, dt).ravel()
+    assert np.linalg.norm(a - ex) <= 2.0 * d["err_inf"] * np.linalg.norm(ex) * np.sqrt(np.linalg.cond(E.Mdense))
+    nin = np.real(np.vdot(psi, E.Mdense @ psi))
+    nout = np.real(np.vdot(a, E.Mdense @ a))
+    assert abs(nout / nin - 1.0) <= 4.0 * d["err_inf"]
