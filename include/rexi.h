@@ -91,6 +91,17 @@ typedef enum {
                                (Givens) ones                                  */
 } rexi_solver;
 
+typedef enum {
+  REXI_DISC_FD = 0,         /* finite differences: A = H (3/5/7-point
+                               Laplacian + diag V), B = hbar I                */
+  REXI_DISC_FEM_Q1 = 1      /* tensor-product linear finite elements on the
+                               same nodes (Section 2 with Q1 elements):
+                               A = (hbar^2/2m) K + h^d diag(V) (potential by
+                               nodal quadrature), B = hbar M (consistent mass);
+                               the step is sum_j w_j (A - s_j M)^{-1} M psi.
+                               Per-pole solver only; no adjoint              */
+} rexi_discretization;
+
 typedef struct {
   int32_t precision;   /* rexi_precision, default REXI_PREC_C128            */
   int32_t solver;      /* rexi_solver, default REXI_SOLVER_PER_POLE          */
@@ -165,7 +176,10 @@ typedef struct {
                            max V] of each instance, and multiply the step by
                            exp(-i dt c / hbar) (folded into the weights):
                            the interval the poles must cover halves. The
-                           same step for the exact exponential; 0 default   */
+                           same step for the exact exponential; 0 default.
+                           With Q1 elements: A - c M, c from the bound of
+                           the pencil (A, M)                                */
+  int32_t discretization; /* rexi_discretization, default REXI_DISC_FD      */
 } rexi_options;
 
 typedef struct {
@@ -239,8 +253,9 @@ rexi_status rexi_setup_batch(rexi_handle** out, int32_t count, const rexi_grid* 
 
 /*
  * rexi_apply_H -- y = (H - shift I) x in FP64 (the stencil matvec of the
- * solves). x_dev, y_dev: device rexi_c128[prod n] (no aliasing). For a batch
- * handle, the packed vectors of all instances.
+ * solves); with Q1 elements y = (A - shift M) x. x_dev, y_dev: device
+ * rexi_c128[prod n] (no aliasing). For a batch handle, the packed vectors of
+ * all instances.
  */
 rexi_status rexi_apply_H(rexi_handle* h, const rexi_c128* x_dev, rexi_c128* y_dev,
                          rexi_c128 shift, void* stream);
@@ -264,7 +279,8 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in_dev, rexi_c128* ps
  * with x_j = (H - s_j)^{-1} psi_n and y_j = (H - conj s_j)^{-1} gbar_{n+1}
  * (H is real symmetric, so (H - s)^H = H - conj s). psi_n_dev, gbar_next_dev,
  * gbar_n_dev: device rexi_c128[prod n]; gbar_n may alias gbar_next.
- * dV_accum_dev: device float64[prod n] or NULL. Single-instance handles only.
+ * dV_accum_dev: device float64[prod n] or NULL. Single-instance handles with
+ * finite differences only.
  */
 rexi_status rexi_step_adjoint(rexi_handle* h, const rexi_c128* psi_n_dev,
                               const rexi_c128* gbar_next_dev, rexi_c128* gbar_n_dev,

@@ -121,6 +121,7 @@ struct rexi_handle {
   int k_hint = 0;                     // iterations the last shared-basis solve took
   int reorth_passes = 0;              // second passes of the last shared-basis solve
   double* dnorm = nullptr;            // scratch partials for norms
+  double2* mrhs = nullptr;            // Q1 elements: M psi, the right-hand side of the solves
   std::string err;
   Prof prof;
   int64_t ws_bytes = 0;
@@ -166,6 +167,7 @@ void destroy_handle(rexi_handle* h) {
   if (h->V64) (void)hipFree(h->V64);
   if (h->V32) (void)hipFree(h->V32);
   if (h->dnorm) (void)hipFree(h->dnorm);
+  if (h->mrhs) (void)hipFree(h->mrhs);
   if (h->hpin) (void)hipHostFree(h->hpin);
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
   for (auto& g : h->chunks) (void)hipGraphExecDestroy(g.exec);
@@ -510,6 +512,8 @@ int choose_ppt(int64_t points) {
   return 2;
 }
 
+void copy_fem(SysDesc& d, const InstDesc& in);
+
 // Fill the system table for a set of poles of the handle's instances.
 void make_systems(rexi_handle* h, Solver& sv, bool conj_shift, int rhs_sel) {
   int sidx = 0;
@@ -528,6 +532,7 @@ void make_systems(rexi_handle* h, Solver& sv, bool conj_shift, int rhs_sel) {
       d.c1 = in.c1;
       d.c2 = in.c2;
       d.diag = in.diag - h->center[i];
+      copy_fem(d, in);
       const cplx s = conj_shift ? std::conj(h->s[sidx]) : h->s[sidx];
       d.sre = s.real();
       d.sim = s.imag();
@@ -1336,7 +1341,7 @@ rexi_status autotune(rexi_handle* h, Solver& sv, hipStream_t stream) {
   return st;
 }
 
-InstDesc make_inst(const rexi_grid& g, double hbar, double mass, int64_t off) {
+InstDesc make_inst(const rexi_grid& g, double hbar, double mass, int64_t off, bool fem) {
   InstDesc in{};
   int64_t n[3] = {1, 1, 1};
   double hh[3] = {1, 1, 1};
@@ -1359,7 +1364,30 @@ InstDesc make_inst(const rexi_grid& g, double hbar, double mass, int64_t off) {
   in.c1 = c[1];
   in.c2 = c[2];
   in.diag = 2.0 * (c[0] + c[1] + c[2]);
+  // Q1 elements: 1D mass (h/6) tridiag(1, 4, 1), stiffness (hbar^2/2m)(1/h)
+  // tridiag(-1, 2, -1); an absent (padded) axis contributes the identity
+  in.fem = fem ? 1 : 0;
+  in.fvol = 1.0;
+  for (int a = 0; a < 3; ++a) {
+    const bool present = 3 - nd <= a;
+    in.fmd[a] = present ? 4.0 * hh[a] / 6.0 : 1.0;
+    in.fmo[a] = present ? hh[a] / 6.0 : 0.0;
+    in.fkd[a] = present ? 2.0 * k / hh[a] : 0.0;
+    in.fko[a] = present ? -k / hh[a] : 0.0;
+    if (present) in.fvol *= hh[a];
+  }
   return in;
+}
+
+void copy_fem(SysDesc& d, const InstDesc& in) {
+  d.fem = in.fem;
+  for (int a = 0; a < 3; ++a) {
+    d.fmd[a] = in.fmd[a];
+    d.fmo[a] = in.fmo[a];
+    d.fkd[a] = in.fkd[a];
+    d.fko[a] = in.fko[a];
+  }
+  d.fvol = in.fvol;
 }
 
 rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, const double* V_dev,
@@ -1402,6 +1430,11 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   if (o.fallback_bytes < 0) return fail(nullptr, REXI_E_INVALID_ARG, "fallback_bytes < 0");
   if (!(o.stab_eps >= 0.0 && o.stab_eps < 1.0)) return fail(nullptr, REXI_E_INVALID_ARG, "stab_eps must be in [0, 1)");
   if (o.center != 0 && o.center != 1) return fail(nullptr, REXI_E_INVALID_ARG, "center must be 0 or 1");
+  if (o.discretization != REXI_DISC_FD && o.discretization != REXI_DISC_FEM_Q1)
+    return fail(nullptr, REXI_E_INVALID_ARG, "unknown discretization %d", o.discretization);
+  if (o.discretization == REXI_DISC_FEM_Q1 && o.solver == REXI_SOLVER_SHIFTED)
+    return fail(nullptr, REXI_E_INVALID_ARG,
+                "the shared-basis solver needs B = hbar I (finite differences); use the per-pole solver");
 
   // ---- validate the instances (host side, before any device work)
   int64_t N = 0, Ktot = 0;
@@ -1447,7 +1480,8 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   int itile = 0;
   const int itile_pts = TPB * PPT;
   for (int i = 0; i < count; ++i) {
-    InstDesc in = make_inst(grids[i], hbar[i], mass[i], off);
+    const bool fem = o.discretization == REXI_DISC_FEM_Q1;
+    InstDesc in = make_inst(grids[i], hbar[i], mass[i], off, fem);
     in.sys0 = (int)kk;
     in.nsys = K[i];
     in.tile0 = itile;
@@ -1462,11 +1496,23 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
     // spectrum bound of H: [min V, (hbar^2/2m) sum 4/h^2 + max V]; with
     // centering the solves use H - c I, c its midpoint, and the step is
     // multiplied by exp(-i dt c / hbar): exp(-i dt H / hbar) is unchanged
-    const double c = o.center ? 0.5 * (vmin + 2.0 * in.diag + vmax) : 0.0;
-    const double lo = vmin - c, hi = 2.0 * in.diag + vmax - c;
+    // Q1 elements: a bound of the pencil (A, M) from Rayleigh quotients: the
+    // kinetic part lies in [0, sum_a (hbar^2/2m) 12/h_a^2], the potential part
+    // between V_min and V_max scaled by h^d / eig(M) in [1, 3^d]
+    double blo = vmin, bhi = 2.0 * in.diag + vmax;
+    double mmin = 1.0;  // smallest eigenvalue of M (Euclidean errors from M-norm ones)
+    if (fem) {
+      const double f = std::pow(3.0, (double)grids[i].ndim);
+      blo = std::min(vmin, f * vmin);
+      bhi = 6.0 * in.diag + std::max(vmax, f * vmax);  // 6 diag = sum (hbar^2/2m) 12/h^2
+      for (int a = 0; a < 3; ++a) mmin *= (3 - grids[i].ndim <= a) ? in.fmd[a] / 2.0 : 1.0;  // h/3 per axis
+    }
+    const double c = o.center ? 0.5 * (blo + bhi) : 0.0;
+    const double lo = blo - c, hi = bhi - c;
     h->lam_lo.push_back(lo);
     h->lam_hi.push_back(hi);
-    h->center.push_back(c);
+    // finite differences shift the diagonal (H - c I); elements shift the poles (A - (s + c) M)
+    h->center.push_back(fem ? 0.0 : c);
     const cplx phase = std::exp(cplx(0.0, -dt[i] * c / hbar[i])) * (1.0 - o.stab_eps);
     for (int k = 0; k < K[i]; ++k, ++kk) {
       // s_j = i hbar sigma_j / dt, w_j = i hbar beta_j / dt (eq. rational-evaluation, B = hbar I);
@@ -1490,13 +1536,14 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
       double tol = o.tol;
       if (o.tol_policy == REXI_TOL_CERTIFIED) {
         // sum_j |w_j| rho_j / dist_j <= tol when rho_j = tol dist_j / (K |w_j|)
-        tol = o.tol * dist / ((double)K[i] * std::max(std::abs(w), 1e-300));
+        tol = o.tol * dist * mmin / ((double)K[i] * std::max(std::abs(w), 1e-300));
       }
       tol = std::max(tol, floor_r);
-      h->s.push_back(s);
+      h->s.push_back(fem ? s + c : s);
       h->w.push_back(w);
       h->tol_sys.push_back(tol);
-      h->dist_sys.push_back(dist);
+      // Q1: ||x - x*|| <= ||r|| / (eig_min(M) dist) (norms of M and M^-1)
+      h->dist_sys.push_back(dist * mmin);
     }
     h->Kinst.push_back(K[i]);
     h->hinst.push_back(in);
@@ -1527,6 +1574,7 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   SETUP_CHK(hipMalloc(&h->dinst, count * sizeof(InstDesc)));
   SETUP_CHK(hipMalloc(&h->ditile, (count + 1) * sizeof(int32_t)));
   SETUP_CHK(hipMalloc(&h->dnorm, std::max(1, itile) * sizeof(double)));
+  if (o.discretization == REXI_DISC_FEM_Q1) SETUP_CHK(hipMalloc(&h->mrhs, (size_t)N * sizeof(double2)));
   SETUP_CHK(hipMemcpyAsync(h->dinst, h->hinst.data(), count * sizeof(InstDesc), hipMemcpyHostToDevice, stream));
   SETUP_CHK(hipMemcpyAsync(h->ditile, h->hitile.data(), (count + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
   SETUP_CHK(hipHostMalloc((void**)&h->hpin, 64 * sizeof(int32_t), hipHostMallocDefault));
@@ -1749,7 +1797,14 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
       if (!h->syncfree) prof_collect(h, st);
       continue;
     }
-    rexi_status s1 = solve(h, sv, src, src, st, &restarts);
+    const double2* rhs = src;
+    if (h->mrhs) {
+      // Q1 elements: the systems are (A - s_j M) x_j = M psi
+      hipLaunchKernelGGL(rexi::k_apply_mass, dim3(std::min(h->itotal, 2048)), dim3(TPB), 0, st, h->dinst,
+                         h->ninst, h->ditile, h->itotal, src, h->mrhs, TPB * PPT);
+      rhs = h->mrhs;
+    }
+    rexi_status s1 = solve(h, sv, rhs, rhs, st, &restarts);
     if (s1 != REXI_OK) return s1;
     {
       Timed t(h, PC_POLESUM, (double)h->N * 16.0 * (1.0 + (double)sv.S / h->ninst), st);
@@ -1803,6 +1858,7 @@ rexi_status rexi_step_adjoint(rexi_handle* h, const rexi_c128* psi_n, const rexi
   if (!h) return REXI_E_INVALID_ARG;
   if (!psi_n || !gbar_next || !gbar_n) return fail(h, REXI_E_INVALID_ARG, "NULL vector");
   if (h->ninst != 1) return fail(h, REXI_E_INVALID_ARG, "adjoint needs a single-instance handle");
+  if (h->mrhs) return fail(h, REXI_E_INVALID_ARG, "the adjoint step supports finite differences only");
   hipStream_t st = (hipStream_t)stream;
   if (!h->adj.ready) {
     rexi_status s0 = init_solver(h, h->adj, 2, st);

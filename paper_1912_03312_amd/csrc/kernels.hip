@@ -251,6 +251,63 @@ __device__ __forceinline__ double2 stencil_point_f64(const double2* __restrict__
   return o;
 }
 
+// Q1 finite elements: (A - s M) u at p with A = K' + h^d diag(V) (K' the
+// stiffness matrix times hbar^2/2m) and M the consistent mass matrix, both
+// Kronecker structured: the entry for the neighbour offset (e0, e1, e2) in
+// {-1, 0, 1}^3 is  m0(e0) m1(e1) m2(e2)  for M and
+// k0(e0) m1(e1) m2(e2) + m0(e0) k1(e1) m2(e2) + m0(e0) m1(e1) k2(e2)  for K'
+// (m(0) = md, m(+-1) = mo, k(0) = kd, k(+-1) = ko per axis). Arithmetic in
+// the precision of T (as the finite-difference stencil).
+template <typename T> struct scalar_of;
+template <> struct scalar_of<double2> { using type = double; };
+template <> struct scalar_of<float2> { using type = float; };
+
+template <typename T>
+__device__ __forceinline__ double2 fem_point(const T* __restrict__ u, int n0, int n1, int n2, const FastDiv& d2,
+                                             const FastDiv& d1, const double* md, const double* mo,
+                                             const double* kd, const double* ko, double vol, double vp,
+                                             double sre, double sim, uint32_t p) {
+  using R = typename scalar_of<T>::type;
+  const uint32_t r = fdiv(p, d2);
+  const uint32_t k = p - r * (uint32_t)n2;
+  const uint32_t i0 = fdiv(r, d1);
+  const uint32_t j = r - i0 * (uint32_t)n1;
+  const int plane = n1 * n2;
+  const int lo0 = i0 > 0 ? -1 : 0, hi0 = i0 + 1 < (uint32_t)n0 ? 1 : 0;
+  const int lo1 = j > 0 ? -1 : 0, hi1 = j + 1 < (uint32_t)n1 ? 1 : 0;
+  const int lo2 = k > 0 ? -1 : 0, hi2 = k + 1 < (uint32_t)n2 ? 1 : 0;
+  R mx = 0, my = 0, kx = 0, ky = 0;  // M u and K' u
+  for (int e0 = lo0; e0 <= hi0; ++e0) {
+    const R m0 = (R)(e0 ? mo[0] : md[0]), k0 = (R)(e0 ? ko[0] : kd[0]);
+    for (int e1 = lo1; e1 <= hi1; ++e1) {
+      const R m1 = (R)(e1 ? mo[1] : md[1]), k1 = (R)(e1 ? ko[1] : kd[1]);
+      // the three points along axis 2 at once
+      R sx = 0, sy = 0, tx = 0, ty = 0;  // sum m2 u, sum k2 u
+      for (int e2 = lo2; e2 <= hi2; ++e2) {
+        const T v = u[(int)p + e0 * plane + e1 * n2 + e2];
+        const R m2 = (R)(e2 ? mo[2] : md[2]), k2 = (R)(e2 ? ko[2] : kd[2]);
+        sx += m2 * (R)v.x;
+        sy += m2 * (R)v.y;
+        tx += k2 * (R)v.x;
+        ty += k2 * (R)v.y;
+      }
+      const R mm = m0 * m1;
+      mx += mm * sx;
+      my += mm * sy;
+      const R kk = k0 * m1 + m0 * k1;
+      kx += kk * sx + mm * tx;
+      ky += kk * sy + mm * ty;
+    }
+  }
+  const T c = u[p];
+  const R a = (R)(vol * vp);
+  const R sr = (R)sre, si = (R)sim;
+  // (K' + vol V) u - s M u
+  const R ox = kx + a * (R)c.x - (sr * mx - si * my);
+  const R oy = ky + a * (R)c.y - (sr * my + si * mx);
+  return make_double2((double)ox, (double)oy);
+}
+
 template <typename T> __device__ __forceinline__ double vpot(const Work& W, int64_t idx);
 template <> __device__ __forceinline__ double vpot<double2>(const Work& W, int64_t idx) { return W.V64[idx]; }
 template <> __device__ __forceinline__ double vpot<float2>(const Work& W, int64_t idx) { return (double)W.V32[idx]; }
@@ -428,7 +485,9 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0) {
       if (p < d.n) {
         if (MATVEC) {
           const T* __restrict__ uj = basis_vec<T>(W, d, j);
-          double2 v = stencil_point<T>(uj, d, vpot<T>(W, d.off + p), (uint32_t)p);
+          double2 v = d.fem ? fem_point<T>(uj, d.n0, d.n1, d.n2, d.d2, d.d1, d.fmd, d.fmo, d.fkd, d.fko, d.fvol,
+                                           vpot<T>(W, d.off + p), d.sre, d.sim, (uint32_t)p)
+                            : stencil_point<T>(uj, d, vpot<T>(W, d.off + p), (uint32_t)p);
           v.x *= cj;
           v.y *= cj;
           T vs = from_d2<T>(v);
@@ -1708,8 +1767,11 @@ __global__ __launch_bounds__(TPB) void k_residual(Work W, const double2* __restr
     for (int q = 0; q < PPT; ++q) {
       const int p = t * W.tile + q * TPB + threadIdx.x;
       if (p < d.n) {
-        const double2 hx = stencil_point_f64(x, d.n0, d.n1, d.n2, d.d2, d.d1, d.c0, d.c1, d.c2, d.diag,
-                                             W.V64[d.off + p], d.sre, d.sim, (uint32_t)p);
+        const double2 hx =
+            d.fem ? fem_point<double2>(x, d.n0, d.n1, d.n2, d.d2, d.d1, d.fmd, d.fmo, d.fkd, d.fko, d.fvol,
+                                       W.V64[d.off + p], d.sre, d.sim, (uint32_t)p)
+                  : stencil_point_f64(x, d.n0, d.n1, d.n2, d.d2, d.d1, d.c0, d.c1, d.c2, d.diag, W.V64[d.off + p],
+                                      d.sre, d.sim, (uint32_t)p);
         const double2 bp = b[p];
         const double2 r = make_double2(bp.x - hx.x, bp.y - hx.y);
         u0[p] = from_d2<T>(r);
@@ -1977,8 +2039,31 @@ __global__ __launch_bounds__(TPB) void k_apply_h(const InstDesc* __restrict__ in
     const int t = item - in.tile0;
     const double2* xi = x + in.off;
     for (int p = t * tile + threadIdx.x; p < min((t + 1) * tile, in.n); p += TPB) {
-      y[in.off + p] = stencil_point_f64(xi, in.n0, in.n1, in.n2, in.d2, in.d1, in.c0, in.c1, in.c2, in.diag,
-                                        V[in.off + p], sre, sim, (uint32_t)p);
+      y[in.off + p] = in.fem ? fem_point<double2>(xi, in.n0, in.n1, in.n2, in.d2, in.d1, in.fmd, in.fmo, in.fkd,
+                                                  in.fko, in.fvol, V[in.off + p], sre, sim, (uint32_t)p)
+                             : stencil_point_f64(xi, in.n0, in.n1, in.n2, in.d2, in.d1, in.c0, in.c1, in.c2,
+                                                 in.diag, V[in.off + p], sre, sim, (uint32_t)p);
+    }
+  }
+}
+
+// y = M x per instance (Q1 finite elements: the right-hand side M psi of the
+// shifted systems; copies x where an instance uses finite differences).
+__global__ __launch_bounds__(TPB) void k_apply_mass(const InstDesc* __restrict__ inst, int ninst,
+                                                    const int32_t* __restrict__ itile_start, int itotal,
+                                                    const double2* __restrict__ x, double2* __restrict__ y,
+                                                    int tile) {
+  const double zero[3] = {0.0, 0.0, 0.0};
+  for (int item = blockIdx.x; item < itotal; item += gridDim.x) {
+    const int ii = find_sys(itile_start, ninst, item);
+    const InstDesc& in = inst[ii];
+    const int t = item - in.tile0;
+    const double2* xi = x + in.off;
+    for (int p = t * tile + threadIdx.x; p < min((t + 1) * tile, in.n); p += TPB) {
+      // (0 + 0 V) x - (-1) M x
+      y[in.off + p] = in.fem ? fem_point<double2>(xi, in.n0, in.n1, in.n2, in.d2, in.d1, in.fmd, in.fmo, zero,
+                                                  zero, 0.0, 0.0, -1.0, 0.0, (uint32_t)p)
+                             : xi[p];
     }
   }
 }

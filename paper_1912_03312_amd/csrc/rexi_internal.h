@@ -62,7 +62,12 @@ struct SysDesc {
   int32_t col_nr;
   int32_t col_n;     // items of the system (col_n = ceil(n1/col_rows) col_nr)
   int32_t pole;      // fallback solves: the pole (index into s, w) of the system
-  int32_t pad2;
+  int32_t fem;       // 1: Q1 finite elements, the system is (A - s M) x = M psi
+  // Q1 elements, per padded axis: 1D mass diagonal / off-diagonal, stiffness
+  // (times hbar^2/2m) diagonal / off-diagonal (1, 0, 0, 0 on an absent axis),
+  // and h^d, the weight of the potential (nodal quadrature)
+  double fmd[3], fmo[3], fkd[3], fko[3];
+  double fvol;
 };
 
 // Instance descriptor (pole sum, apply_H).
@@ -76,6 +81,10 @@ struct InstDesc {
   int32_t nsys;      // its poles
   int32_t tile0;     // first tile in the instance tiling
   int32_t ntiles;
+  int32_t fem;       // Q1 finite elements (coefficients as in SysDesc)
+  int32_t pad;
+  double fmd[3], fmo[3], fkd[3], fko[3];
+  double fvol;
 };
 
 enum SysState : int32_t { ST_ACTIVE = 0, ST_FINISH = 1, ST_DONE = 2, ST_PAUSED = 3 };

@@ -50,7 +50,7 @@ class Options(C.Structure):
                 ("profile", C.c_int32), ("tile", C.c_int32), ("grid_blocks", C.c_int32), ("autotune", C.c_int32),
                 ("max_workspace_bytes", C.c_int64), ("march_planes", C.c_int32), ("march_slots", C.c_int32),
                 ("fallback", C.c_int32), ("fallback_m", C.c_int32), ("fallback_bytes", C.c_int64),
-                ("stab_eps", C.c_double), ("center", C.c_int32)]
+                ("stab_eps", C.c_double), ("center", C.c_int32), ("discretization", C.c_int32)]
 
 
 class StepInfo(C.Structure):
@@ -125,6 +125,8 @@ def default_options(**kw) -> Options:
             v = {"per_pole": SOLVER_PER_POLE, "shifted": SOLVER_SHIFTED}[v]
         if k == "tol_policy" and isinstance(v, str):
             v = {"relres": TOL_RELRES, "certified": TOL_CERTIFIED}[v]
+        if k == "discretization" and isinstance(v, str):
+            v = {"fd": 0, "fem": 1}[v]
         if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)

@@ -101,3 +101,9 @@ def test_shifted_solver_option_constraints(rx):
     o = rx.default_options(solver="shifted", precision="c64")
     st, msg = _setup_raw(rx, rx.make_grid((8,), (0,), (1,)), opt=o)
     assert st == rx.REXI_E_INVALID_ARG and "complex128" in msg
+    o = rx.default_options(solver="shifted", discretization="fem")
+    st, msg = _setup_raw(rx, rx.make_grid((8,), (0,), (1,)), opt=o)
+    assert st == rx.REXI_E_INVALID_ARG and "per-pole" in msg
+    o = rx.default_options(discretization=2)
+    st, msg = _setup_raw(rx, rx.make_grid((8,), (0,), (1,)), opt=o)
+    assert st == rx.REXI_E_INVALID_ARG

@@ -494,6 +494,74 @@ def test_centering_reaches_the_exact_exponential(rexi):
     assert errs[0] > 1e-2
 
 
+# ---------------------------------------------------------------- Q1 elements
+def fem_floor(g, V, s, b, dt, center=0.0):
+    """iterative_floor for the pencil (A, M): the spectrum bound of the pencil
+    and Euclidean errors from M-norm ones (eig_min(M) = prod h/3)."""
+    from oracle import fem
+    lo, hi = fem.spectrum_bound(g.n, g.h, V)
+    lo, hi = lo - center, hi - center
+    mmin = float(np.prod([hh / 3.0 for hh in g.h]))
+    sj, wj = ost.shifts_and_weights(s, b, dt)
+    tot = 0.0
+    for sv, wv in zip(sj, wj):
+        re = min(max(sv.real, lo), hi)
+        dist = abs(complex(re, 0.0) - sv)
+        tot += abs(wv) / (dist * mmin) * EPS * (1.0 + (max(abs(lo), abs(hi)) + abs(sv)) / dist)
+    return tot
+
+
+@pytest.mark.parametrize("shape", [(300,), (37, 41), (9, 13, 17), (1,), (1, 5)])
+def test_fem_apply_matches_sparse_product(rexi, shape):
+    import torch
+    from oracle import fem
+    from paper_1912_03312_amd import rexi as r
+    g = inputs.Grid(shape, tuple(-3.0 - a for a in range(len(shape))), tuple(4.0 + a for a in range(len(shape))))
+    V = inputs.gaussian_bumps(g, 7) if g.size > 1 else np.array([0.7])
+    x = inputs.random_state(g.size, 5)
+    s, b, d = poles(16, 28.0)
+    h = r.setup(g.n, g.lo, g.hi, to_dev(V.ravel()), 0.9, 1.3, 0.1, s, b, discretization="fem")
+    y = torch.empty(g.size, dtype=torch.complex128, device="cuda")
+    shift = 0.3 - 2.1j
+    h.apply_H(to_dev(x), y, shift)
+    torch.cuda.synchronize()
+    A, M = fem.matrices(g.n, g.h, V, 0.9, 1.3)
+    ref = A @ x - shift * (M @ x)
+    e = rel(y.cpu().numpy(), ref)
+    h.close()
+    assert e <= 1e-14, e
+
+
+@pytest.mark.parametrize("name,scale,K,R1,prec", [("1d_harmonic", None, 16, 28.0, "c128"),
+                                                  ("2d_adjoint", 33, 32, 80.0, "c128"),
+                                                  ("3d_bumps", 12, 64, 180.0, "c128"),
+                                                  ("3d_bumps", 12, 64, 180.0, "c64"),
+                                                  ("1d_harmonic", None, 16, 28.0, "c64")])
+def test_fem_step_matches_oracle(rexi, name, scale, K, R1, prec):
+    # the step of the mass-matrix form, sum_j w_j (A - s_j M)^{-1} M psi, two
+    # steps against the oracle's direct solves; 1D also centered (A - c M)
+    from oracle import fem
+    wl = inputs.workload(name, scale=scale)
+    g = wl.grid
+    s, b, d = poles(K, R1)
+    cen = 1 if name == "1d_harmonic" else 0
+    lo, hi = fem.spectrum_bound(g.n, g.h, wl.V)
+    c = 0.5 * (lo + hi) if cen else 0.0
+    # dt within the accuracy condition of the (looser) pencil bound
+    dt = min(wl.dt, 0.9 * R1 / (0.5 * (hi - lo) if cen else max(abs(lo), abs(hi))))
+    D = fem.FemDirectStepper(g.n, g.h, wl.V, s, b, dt, center=c)
+    ref = [D.step(wl.psi0)]
+    ref.append(D.step(ref[0]))
+    out, infos = gpu_steps(g, wl.V, wl.psi0, s, b, dt, 2, solver="per_pole", precision=prec, m=30,
+                           tol=1e-11 if prec == "c128" else 1e-8, tol_policy="certified", max_cycles=200,
+                           discretization="fem", center=cen)
+    errs = [rel(o, rr) for o, rr in zip(out, ref)]
+    bar = max(1e-10, 3 * fem_floor(g, wl.V, s, b, dt, c)) if prec == "c128" else 1e-6
+    print("fem", name, prec, "center", cen, errs, bar, [i["total_iterations"] for i in infos])
+    assert max(errs) <= bar
+    assert all(i["not_converged"] == 0 for i in infos)
+
+
 # ---------------------------------------------------------------- tunnelling
 @pytest.mark.parametrize("solver", ["shifted", "per_pole"])
 def test_tunnel_matches_oracle(rexi, solver):
