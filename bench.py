@@ -165,6 +165,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the instrumented kernel region")
     ap.add_argument("--calib-copy", action="store_true", help="end with 3 copies of 256 MiB (counter scaling)")
+    ap.add_argument("--center", action="store_true", help="solve with the spectrum centered (H - cI)")
+    ap.add_argument("--discretization", choices=("fd", "fem"), default="fd",
+                    help="fem: Q1 finite elements, (A - s M)^{-1} M psi (per-pole solver)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the per-pole FP64 and mixed-precision forms timed beside the headline")
     args = ap.parse_args()
@@ -192,7 +195,8 @@ def main():
     V = torch.from_numpy(wl.V.ravel().copy()).to(dev)
     psi = torch.from_numpy(wl.psi0.ravel().copy()).to(dev)
     out = torch.empty_like(psi)
-    opts = dict(precision=args.precision, solver=args.solver, tol=args.tol, m=m)
+    opts = dict(precision=args.precision, solver=args.solver, tol=args.tol, m=m, discretization=args.discretization,
+                center=1 if args.center else 0)
     h = rexi.setup(g.n, g.lo, g.hi, V, wl.hbar, wl.mass, wl.dt, sigma, beta, profile=0,
                    capture_safe=1 if args.capture else 0, **opts)
     print(f"# setup done: {g.n} K={wl.K} precision={args.precision} solver={args.solver}",
@@ -312,6 +316,7 @@ def main():
                            else "per-pole complex128 GMRES")
                         + f", per-pole rel. residual {args.tol:g}, Krylov dimension <= {m_used}",
             "grid": list(g.n), "poles": wl.K, "precision": args.precision, "solver": args.solver,
+            "discretization": args.discretization, "centered": bool(args.center),
             "graph_replay": bool(args.capture), "tiling": tiling,
         },
         "solve": {
@@ -327,7 +332,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
-    if not args.no_variants and args.solver == "shifted":
+    if not args.no_variants and args.solver == "shifted" and args.discretization == "fd":
         # the plain FP64 per-pole form and the batched mixed-precision form
         # (complex64 inner solves, FP64 refinement) at the same per-pole
         # target, a few steps each

@@ -1747,7 +1747,7 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
   Solver& sv = h->fwd;
   const double2* in = (const double2*)psi_in;
   double2* outp = (double2*)psi_out;
-  double norm_in = 0.0;
+  double norm_in = 0.0, fem_norm_in = 0.0;
   int64_t its_total = 0;
   int restarts = 0;
   for (int n = 0; n < nsteps; ++n) {
@@ -1798,6 +1798,11 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
       continue;
     }
     const double2* rhs = src;
+    if (h->mrhs && info && n == nsteps - 1) {
+      // ||psi_n|| before the step overwrites it (in place)
+      rexi_status s3 = vec_norm(h, src, st, &fem_norm_in);
+      if (s3 != REXI_OK) return s3;
+    }
     if (h->mrhs) {
       // Q1 elements: the systems are (A - s_j M) x_j = M psi
       hipLaunchKernelGGL(rexi::k_apply_mass, dim3(std::min(h->itotal, 2048)), dim3(TPB), 0, st, h->dinst,
@@ -1834,8 +1839,8 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
           if (info->cycles) info->cycles[s] = x.cycles;
           if (info->rel_residual) info->rel_residual[s] = x.rho;
         }
-        norm_in = bn;
-        info->certified_bound = bn > 0.0 ? bound / bn : 0.0;
+        norm_in = h->mrhs ? fem_norm_in : bn;  // Q1 elements: the right-hand side is M psi
+        info->certified_bound = norm_in > 0.0 ? bound / norm_in : 0.0;
         info->norm_in = norm_in;
         double no = 0.0;
         rexi_status s2 = vec_norm(h, outp, st, &no);

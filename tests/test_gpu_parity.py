@@ -560,6 +560,9 @@ def test_fem_step_matches_oracle(rexi, name, scale, K, R1, prec):
     print("fem", name, prec, "center", cen, errs, bar, [i["total_iterations"] for i in infos])
     assert max(errs) <= bar
     assert all(i["not_converged"] == 0 for i in infos)
+    # the reported norms are those of psi itself (not of the right-hand side M psi)
+    assert abs(infos[0]["norm_in"] / np.linalg.norm(wl.psi0) - 1.0) < 1e-12
+    assert abs(infos[1]["norm_out"] / np.linalg.norm(ref[1]) - 1.0) < 1e-6
 
 
 # ---------------------------------------------------------------- tunnelling
