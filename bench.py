@@ -39,14 +39,17 @@ def kernel_sources_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, precision: str):
-    """Per-launch HBM bytes of `kernel` from the committed counter summary, or None."""
+def load_traffic(kernel: str, precision: str, tiling=None):
+    """Per-launch HBM bytes of `kernel` from the committed counter summary, or None
+    (also when the kernels or the tuner's tiling differ from those profiled)."""
     path = os.path.join(ROOT, "profiles", "traffic_3d_bumps_128.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
     if d.get("sources") != kernel_sources_hash():
+        return None
+    if tiling is not None and d.get("tiling") != tiling:
         return None
     ent = d.get("kernels", {}).get(f"{kernel}:{precision}")
     return None if ent is None else ent.get("hbm_bytes_per_launch")
@@ -172,6 +175,15 @@ def main():
                     help="skip the per-pole FP64 and mixed-precision forms timed beside the headline")
     args = ap.parse_args()
 
+    if "REXI_TUNE_CACHE" not in os.environ:
+        # the tiling the setup tuner chose for the benchmark shapes on MI355X
+        # (a private copy: the library appends the choices for new shapes)
+        import shutil
+        import tempfile
+        src = os.path.join(ROOT, "paper_1912_03312_amd", "tuning", "mi355x_bench.txt")
+        dst = os.path.join(tempfile.mkdtemp(prefix="rexi_tune_"), "tune.txt")
+        shutil.copyfile(src, dst)
+        os.environ["REXI_TUNE_CACHE"] = dst
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the pole-sharded design is described, not built)", file=sys.stderr)
@@ -282,7 +294,7 @@ def main():
         avg_ms = d["ms"] / d["launches"]
         bytes_per_launch = d["bytes"] / d["launches"]
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        traffic = load_traffic(dom, args.precision)
+        traffic = load_traffic(dom, args.precision, tiling)
         roof = dict(bound="hbm", kernel=dom, achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
                     traffic_GBs=None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1),
@@ -344,11 +356,11 @@ def main():
             hv.step(a, out, 1, info=False)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for _ in range(2):
+            for _ in range(4):
                 hv.step(a, out, 1, info=False)
                 a, out = out, a
             torch.cuda.synchronize()
-            vms = (time.perf_counter() - t0) * 1e3 / 2
+            vms = (time.perf_counter() - t0) * 1e3 / 4
             vi = hv.step(a, out, 1, info=True)
             hv.close()
             var[name] = {"value": round(1e3 / vms, 4), "ms_per_step": round(vms, 3),
