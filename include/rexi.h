@@ -180,6 +180,13 @@ typedef struct {
                            With Q1 elements: A - c M, c from the bound of
                            the pencil (A, M)                                */
   int32_t discretization; /* rexi_discretization, default REXI_DISC_FD      */
+  int32_t adjoint_shared; /* shared-basis handles: 1 (default) the adjoint
+                           step uses two shared bases (psi_n with the poles,
+                           gbar with their conjugates) and forms dL/dV as a
+                           bilinear form of the two bases; per-pole solves
+                           when a pole misses its target within m vectors.
+                           0: always per-pole solves                         */
+  int32_t reserved_opt_;
 } rexi_options;
 
 typedef struct {

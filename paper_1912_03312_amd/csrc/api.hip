@@ -120,6 +120,12 @@ struct rexi_handle {
   std::vector<ChunkGraph> chunks;
   int k_hint = 0;                     // iterations the last shared-basis solve took
   int reorth_passes = 0;              // second passes of the last shared-basis solve
+  // shared-basis adjoint: a second basis for the solves with conjugate shifts
+  Solver fwdA;
+  rexi::ShiftWork SWA{};
+  std::vector<ChunkGraph> chunksA;
+  int k_hintA = 0, reorth_passesA = 0;
+  double2* adj_coef = nullptr;        // [m][m] coefficients of the gradient's bilinear form
   double* dnorm = nullptr;            // scratch partials for norms
   double2* mrhs = nullptr;            // Q1 elements: M psi, the right-hand side of the solves
   std::string err;
@@ -160,6 +166,9 @@ void destroy_handle(rexi_handle* h) {
   free_solver(h->fwd);
   free_solver(h->adj);
   free_solver(h->fb);
+  free_solver(h->fwdA);
+  for (auto& g : h->chunksA) (void)hipGraphExecDestroy(g.exec);
+  if (h->adj_coef) (void)hipFree(h->adj_coef);
   for (auto& b : h->sbufs)
     if (b.p) (void)hipFree(b.p);
   if (h->dinst) (void)hipFree(h->dinst);
@@ -606,13 +615,13 @@ rexi_status init_solver(rexi_handle* h, Solver& sv, int copies, hipStream_t stre
 
 
 // Shared-basis solver: one Krylov system per instance plus per-pole Givens data.
-rexi_status init_shifted(rexi_handle* h, hipStream_t stream) {
-  rexi_status st = init_solver(h, h->fwd, 0, stream);
+// conj: the poles' conjugates (s_j -> conj s_j, w_j -> conj w_j), for R^H.
+rexi_status init_shifted(rexi_handle* h, Solver& sv, rexi::ShiftWork& SW, bool conj, hipStream_t stream) {
+  rexi_status st = init_solver(h, sv, 0, stream);
   if (st != REXI_OK) return st;
-  const int S = h->ninst, m = h->fwd.m;
+  const int S = h->ninst, m = sv.m;
   int K = 0;
   for (int i = 0; i < S; ++i) K += h->Kinst[i];
-  rexi::ShiftWork& SW = h->SW;
   SW.K = K;
   auto al = [&](void** p, size_t bytes) -> rexi_status {
     DevBuf b;
@@ -662,7 +671,7 @@ rexi_status init_shifted(rexi_handle* h, hipStream_t stream) {
   if (h->opt.lanczos == 1) {
     // pipelined recurrence: two z buffers of all instances' points
     int64_t tot = 0;
-    for (auto& d : h->fwd.hsys) tot += d.n;
+    for (auto& d : sv.hsys) tot += d.n;
     void* zb = nullptr;
     if ((st = al(&zb, (size_t)2 * tot * c16))) return st;
     SW.zb = (double*)zb;
@@ -670,7 +679,7 @@ rexi_status init_shifted(rexi_handle* h, hipStream_t stream) {
   }
   if (SW.lanczos) {
     // the orthogonality estimate decides the second passes; the DGKS test is off
-    h->fwd.W.reorth_mode = 3;
+    sv.W.reorth_mode = 3;
   }
   std::vector<double> hs(2 * K), hw(2 * K), ht(K);
   std::vector<int32_t> hp0(S + 1), hpi(K);
@@ -681,10 +690,11 @@ rexi_status init_shifted(rexi_handle* h, hipStream_t stream) {
   }
   hp0[S] = q;
   for (int k = 0; k < K; ++k) {
+    const double sg = conj ? -1.0 : 1.0;
     hs[2 * k] = h->s[k].real();
-    hs[2 * k + 1] = h->s[k].imag();
+    hs[2 * k + 1] = sg * h->s[k].imag();
     hw[2 * k] = h->w[k].real();
-    hw[2 * k + 1] = h->w[k].imag();
+    hw[2 * k + 1] = sg * h->w[k].imag();
     ht[k] = h->tol_sys[k];
   }
   HIPCHK(h, hipMemcpyAsync(s, hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice, stream));
@@ -862,10 +872,33 @@ void launch_lz_step(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork
     hipLaunchKernelGGL((rexi::k_lz_step<PPT>), dim3(sv.grid), dim3(TPB), 0, strm, W, SW, j);
 }
 
-// One shared-basis solve of all poles of every instance; writes the pole sums to out.
+// The tiling and fused Lanczos pass of a solver (defined with the tuner);
+// SWp: the shared-basis data whose column plan they set (null: the handle's).
+rexi_status apply_tiling(rexi_handle* h, Solver& sv, int ppt, int grid, hipStream_t stream,
+                         rexi::ShiftWork* SWp = nullptr);
+rexi_status apply_columns(rexi_handle* h, Solver& sv, int kh, int L, hipStream_t stream,
+                          rexi::ShiftWork* SWp = nullptr);
+
+// One shared-basis solver: its basis and system table, per-pole data, cached
+// chunk graphs and the length of its last solve.
+struct ShiftCtx {
+  Solver* sv;
+  rexi::ShiftWork* SW;
+  std::vector<rexi_handle::ChunkGraph>* chunks;
+  int* k_hint;
+  int* reorth_passes;
+  bool fallback;  // finish missed poles by per-pole solves (the forward solver only)
+};
+
+ShiftCtx fwd_ctx(rexi_handle* h) { return {&h->fwd, &h->SW, &h->chunks, &h->k_hint, &h->reorth_passes, true}; }
+ShiftCtx adj_ctx(rexi_handle* h) { return {&h->fwdA, &h->SWA, &h->chunksA, &h->k_hintA, &h->reorth_passesA, false}; }
+
+// One shared-basis solve of all poles of every instance; writes the pole sums
+// to out (out = nullptr: the solve only, its per-pole coefficients y_p).
 template <typename T, int PPT>
-rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStream_t stream) {
-  Solver& sv = h->fwd;
+rexi_status run_shifted(rexi_handle* h, ShiftCtx cx, const double2* b, double2* out, hipStream_t stream) {
+  Solver& sv = *cx.sv;
+  rexi::ShiftWork& SWc = *cx.SW;
   Work& W = sv.W;
   const int G = sv.grid, m = sv.m;
   const double e = sizeof(T);
@@ -879,29 +912,29 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
   {
     Timed t(h, PC_REDUCE, 0, stream);
     hipLaunchKernelGGL(rexi::k_start_reduce, dim3(S), dim3(TPB), 0, stream, W);
-    hipLaunchKernelGGL(rexi::k_shifted_init, dim3(S), dim3(TPB), 0, stream, W, h->SW);
+    hipLaunchKernelGGL(rexi::k_shifted_init, dim3(S), dim3(TPB), 0, stream, W, SWc);
   }
   const bool pipe = h->opt.lanczos == 1;
   const int colparts = sv.col_kh ? 1 : 0;
   if (pipe) {
     {
       Timed t(h, PC_START, n * 48.0, stream);
-      hipLaunchKernelGGL((rexi::k_lz_matvec<PPT>), dim3(G), dim3(TPB), 0, stream, W, h->SW, 0, 0, 0);
+      hipLaunchKernelGGL((rexi::k_lz_matvec<PPT>), dim3(G), dim3(TPB), 0, stream, W, SWc, 0, 0, 0);
     }
     {
       Timed t(h, PC_REDUCE, 0, stream);
-      hipLaunchKernelGGL(rexi::k_lz_start, dim3(S), dim3(TPB), 0, stream, W, h->SW);
+      hipLaunchKernelGGL(rexi::k_lz_start, dim3(S), dim3(TPB), 0, stream, W, SWc);
     }
   }
   // iterations run in chunks between host reads of the convergence counter;
   // iterations after convergence return at once (device-side state)
   const int chunk = std::max(1, h->opt.check_every);
-  const bool lz = h->SW.lanczos != 0;
+  const bool lz = SWc.lanczos != 0;
   // second Gram-Schmidt passes are rare with the Lanczos estimate: a single
   // instance solved with host checks pauses for them (the host runs the pass
   // and resumes); otherwise they are predicated launches on a quarter grid
   const bool pause_mode = lz && S == 1 && !h->syncfree;
-  rexi::ShiftWork SWl = h->SW;
+  rexi::ShiftWork SWl = SWc;
   SWl.pause_mode = pause_mode ? 1 : 0;
   const int G2 = lz ? std::max(1, G / 4) : G;
   auto second_pass = [&](int j, hipStream_t strm, int grid2) {
@@ -921,7 +954,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
       }
       {
         Timed t(h, PC_REORTH_B, 0, strm);
-        hipLaunchKernelGGL((rexi::k_lz_matvec<PPT>), dim3(grid2), dim3(TPB), 0, strm, W, h->SW, j + 1,
+        hipLaunchKernelGGL((rexi::k_lz_matvec<PPT>), dim3(grid2), dim3(TPB), 0, strm, W, SWc, j + 1,
                            (j + 1) & 1, 1);
       }
       {
@@ -1009,7 +1042,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
         return REXI_OK;
       }
       hipGraphExec_t exec = nullptr;
-      for (auto& c : h->chunks)
+      for (auto& c : (*cx.chunks))
         if (c.j0 == j0 && c.len == len) exec = c.exec;
       if (!exec) {
         if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
@@ -1021,17 +1054,17 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
         hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (ei != hipSuccess) return fail(h, REXI_E_HIP, "chunk instantiation failed: %s", hipGetErrorString(ei));
-        if (h->chunks.size() >= 64) {
-          (void)hipGraphExecDestroy(h->chunks.front().exec);
-          h->chunks.erase(h->chunks.begin());
+        if ((*cx.chunks).size() >= 64) {
+          (void)hipGraphExecDestroy((*cx.chunks).front().exec);
+          (*cx.chunks).erase((*cx.chunks).begin());
         }
-        h->chunks.push_back({j0, len, exec});
+        (*cx.chunks).push_back({j0, len, exec});
       }
       HIPCHK(h, hipGraphLaunch(exec, stream));
       return REXI_OK;
     };
     int j = 0;
-    int len = h->k_hint > 0 ? h->k_hint : chunk;
+    int len = (*cx.k_hint) > 0 ? (*cx.k_hint) : chunk;
     int passes = 0;
     if (fuse) plain_step(0, stream);
     while (j < m) {
@@ -1041,12 +1074,12 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
       // [0]: systems still iterating after the chunk's last iteration; [1]: pause
       HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + (j + len - 1), sizeof(int32_t), hipMemcpyDeviceToHost,
                                stream));
-      HIPCHK(h, hipMemcpyAsync(h->hpin + 1, h->SW.flags + 2, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+      HIPCHK(h, hipMemcpyAsync(h->hpin + 1, SWc.flags + 2, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
       HIPCHK(h, hipStreamSynchronize(stream));
       const int paused_at = pause_mode ? h->hpin[1] : -1;
       if (paused_at >= 0) {
         // second Gram-Schmidt pass of iteration paused_at, then go on after it
-        hipLaunchKernelGGL(rexi::k_resume, dim3(S), dim3(64), 0, stream, W, h->SW);
+        hipLaunchKernelGGL(rexi::k_resume, dim3(S), dim3(64), 0, stream, W, SWc);
         second_pass(paused_at, stream, G);
         if (fuse && paused_at + 1 < m) plain_step(paused_at + 1, stream);
         HIPCHK(h, hipGetLastError());
@@ -1056,7 +1089,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
         HIPCHK(h, hipMemcpyAsync(&s0, W.st, sizeof(SysState_t), hipMemcpyDeviceToHost, stream));
         HIPCHK(h, hipStreamSynchronize(stream));
         if (s0.state != rexi::ST_ACTIVE) break;
-        len = std::max(chunk, h->k_hint - j);
+        len = std::max(chunk, (*cx.k_hint) - j);
         continue;
       }
       j += len;
@@ -1069,13 +1102,13 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
     HIPCHK(h, hipStreamSynchronize(stream));
     int kmax = 1;
     for (auto& x : sst) kmax = std::max(kmax, x.kcyc);
-    h->k_hint = kmax;
-    h->reorth_passes = passes;
+    (*cx.k_hint) = kmax;
+    (*cx.reorth_passes) = passes;
   }
   {
     Timed t(h, PC_REDUCE, 0, stream);
-    hipLaunchKernelGGL(rexi::k_shifted_backsub, dim3((h->SW.K + rexi::NWAVE - 1) / rexi::NWAVE), dim3(TPB), 0,
-                       stream, W, h->SW);
+    hipLaunchKernelGGL(rexi::k_shifted_backsub, dim3((SWc.K + rexi::NWAVE - 1) / rexi::NWAVE), dim3(TPB), 0,
+                       stream, W, SWc);
   }
   // poles that missed their target within the basis: per-pole solves finish
   // them (host checks only), and they are left out of z
@@ -1084,14 +1117,15 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
   h->fb_cycles = 0;
   h->fb_its = 0;
   // a system that stopped before m iterations met every pole's target
-  if (h->fb.ready && !h->syncfree && h->k_hint >= m) {
-    std::vector<int32_t> its((size_t)h->SW.K);
-    HIPCHK(h, hipMemcpyAsync(its.data(), h->SW.its, its.size() * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  if (cx.fallback && h->fb.ready && !h->syncfree && (*cx.k_hint) >= m) {
+    std::vector<int32_t> its((size_t)SWc.K);
+    HIPCHK(h, hipMemcpyAsync(its.data(), SWc.its, its.size() * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     HIPCHK(h, hipStreamSynchronize(stream));
-    for (int p = 0; p < h->SW.K; ++p)
+    for (int p = 0; p < SWc.K; ++p)
       if (its[p] == 0) missed.push_back(p);
   }
-  rexi::ShiftWork SWz = h->SW;
+  if (!out) return REXI_OK;
+  rexi::ShiftWork SWz = SWc;
   SWz.fb_skip = missed.empty() ? 0 : 1;
   {
     Timed t(h, PC_REDUCE, 0, stream);
@@ -1099,7 +1133,7 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
   }
   {
     Timed t(h, PC_POLESUM, 0, stream);
-    hipLaunchKernelGGL((rexi::k_combine_out<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, h->SW, out);
+    hipLaunchKernelGGL((rexi::k_combine_out<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, SWc, out);
   }
   HIPCHK(h, hipGetLastError());
   if (!missed.empty()) {
@@ -1110,13 +1144,79 @@ rexi_status run_shifted(rexi_handle* h, const double2* b, double2* out, hipStrea
   return REXI_OK;
 }
 
-rexi_status shifted_step(rexi_handle* h, const double2* b, double2* out, hipStream_t stream) {
-  switch (h->fwd.ppt) {
-    case 8: return run_shifted<double2, 8>(h, b, out, stream);
-    case 4: return run_shifted<double2, 4>(h, b, out, stream);
-    case 2: return run_shifted<double2, 2>(h, b, out, stream);
+rexi_status shifted_solve(rexi_handle* h, ShiftCtx cx, const double2* b, double2* out, hipStream_t stream) {
+  switch (cx.sv->ppt) {
+    case 8: return run_shifted<double2, 8>(h, cx, b, out, stream);
+    case 4: return run_shifted<double2, 4>(h, cx, b, out, stream);
+    case 2: return run_shifted<double2, 2>(h, cx, b, out, stream);
   }
   return fail(h, REXI_E_INVALID_ARG, "unsupported tiling");
+}
+
+rexi_status shifted_step(rexi_handle* h, const double2* b, double2* out, hipStream_t stream) {
+  return shifted_solve(h, fwd_ctx(h), b, out, stream);
+}
+
+// out = sum_p w_p y_p of a finished shared-basis solve (every pole converged).
+rexi_status shifted_combine(rexi_handle* h, ShiftCtx cx, double2* out, hipStream_t stream) {
+  Solver& sv = *cx.sv;
+  Timed t(h, PC_POLESUM, 0, stream);
+  hipLaunchKernelGGL(rexi::k_shifted_z, dim3(sv.S), dim3(TPB), 0, stream, sv.W, *cx.SW);
+  switch (sv.ppt) {
+    case 8: hipLaunchKernelGGL((rexi::k_combine_out<double2, 8>), dim3(sv.grid), dim3(TPB), 0, stream, sv.W, *cx.SW, out); break;
+    case 4: hipLaunchKernelGGL((rexi::k_combine_out<double2, 4>), dim3(sv.grid), dim3(TPB), 0, stream, sv.W, *cx.SW, out); break;
+    default: hipLaunchKernelGGL((rexi::k_combine_out<double2, 2>), dim3(sv.grid), dim3(TPB), 0, stream, sv.W, *cx.SW, out); break;
+  }
+  HIPCHK(h, hipGetLastError());
+  return REXI_OK;
+}
+
+// Shared-basis adjoint step (single instance). REXI_E_NOT_BUILT when it does
+// not apply (a pole missed its target within the basis, or no room for the
+// second basis): the caller then takes the per-pole solves; nothing has been
+// written then.
+rexi_status shifted_adjoint(rexi_handle* h, const double2* psi_n, const double2* gbar_next, double2* gbar_n,
+                            double* dV, hipStream_t st) {
+  if (!h->fwdA.ready) {
+    std::string keep = h->err;
+    rexi_status s0 = init_shifted(h, h->fwdA, h->SWA, true, st);
+    if (s0 == REXI_E_NO_MEMORY) {
+      h->err = keep;
+      return REXI_E_NOT_BUILT;
+    }
+    if (s0 != REXI_OK) return s0;
+    // the forward solver's tiling and Lanczos pass
+    if ((s0 = apply_tiling(h, h->fwdA, h->fwd.ppt, h->fwd.grid, st, &h->SWA)) != REXI_OK) return s0;
+    if ((s0 = apply_columns(h, h->fwdA, h->fwd.col_kh, h->fwd.col_L, st, &h->SWA)) != REXI_OK) return s0;
+    if (hipMalloc(&h->adj_coef, (size_t)h->fwd.m * h->fwd.m * sizeof(double2)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(h, REXI_E_NO_MEMORY, "adjoint coefficients");
+    }
+  }
+  ShiftCtx cf = fwd_ctx(h);
+  cf.fallback = false;
+  rexi_status s1 = shifted_solve(h, cf, psi_n, nullptr, st);
+  if (s1 != REXI_OK) return s1;
+  s1 = shifted_solve(h, adj_ctx(h), gbar_next, nullptr, st);
+  if (s1 != REXI_OK) return s1;
+  const int K = h->SW.K;
+  std::vector<int32_t> itf((size_t)K), ita((size_t)K);
+  HIPCHK(h, hipMemcpyAsync(itf.data(), h->SW.its, K * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipMemcpyAsync(ita.data(), h->SWA.its, K * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(h, hipStreamSynchronize(st));
+  for (int p = 0; p < K; ++p)
+    if (itf[p] == 0 || ita[p] == 0) return REXI_E_NOT_BUILT;
+  if (dV) {
+    const int ldc = h->fwd.m;
+    Timed t(h, PC_GRAD, 0, st);
+    hipLaunchKernelGGL(rexi::k_adj_coef, dim3(h->fwdA.m), dim3(TPB), 0, st, h->fwd.W, h->SW, h->fwdA.W, h->SWA,
+                       h->adj_coef, ldc);
+    hipLaunchKernelGGL((rexi::k_adj_grad<16>), dim3(std::min(2048, (int)((h->N + TPB - 1) / TPB))), dim3(TPB), 0,
+                       st, h->fwd.W, h->fwdA.W, h->adj_coef, ldc, dV);
+    HIPCHK(h, hipGetLastError());
+  }
+  // gbar_n = sum_p conj(w_p) y_p: the combination of the conjugate-shift solve
+  return shifted_combine(h, adj_ctx(h), gbar_n, st);
 }
 
 
@@ -1178,7 +1278,8 @@ void tune_cache_store(const std::string& key, int ppt, int grid, int kh, int L) 
   fclose(fp);
 }
 
-rexi_status apply_tiling(rexi_handle* h, Solver& sv, int ppt, int grid, hipStream_t stream) {
+rexi_status apply_tiling(rexi_handle* h, Solver& sv, int ppt, int grid, hipStream_t stream,
+                         rexi::ShiftWork* SWp) {
   sv.ppt = ppt;
   sv.tile = TPB * ppt;
   layout_systems(sv, sv.m);
@@ -1190,8 +1291,9 @@ rexi_status apply_tiling(rexi_handle* h, Solver& sv, int ppt, int grid, hipStrea
   HIPCHK(h, hipStreamSynchronize(stream));
   sv.col_kh = 0;  // a new tiling invalidates the column plan
   if (h->shifted) {
-    h->SW.col_start = nullptr;
-    h->SW.col_total = 0;
+    rexi::ShiftWork& SW = SWp ? *SWp : h->SW;
+    SW.col_start = nullptr;
+    SW.col_total = 0;
   }
   return REXI_OK;
 }
@@ -1199,16 +1301,18 @@ rexi_status apply_tiling(rexi_handle* h, Solver& sv, int ppt, int grid, hipStrea
 // Select the fused Lanczos pass: kh = 0 the row-staged pass, else the
 // marching pass with kh slots and L planes per item. REXI_OK with the
 // row-staged pass when the plan does not fit.
-rexi_status apply_columns(rexi_handle* h, Solver& sv, int kh, int L, hipStream_t stream) {
+rexi_status apply_columns(rexi_handle* h, Solver& sv, int kh, int L, hipStream_t stream,
+                          rexi::ShiftWork* SWp) {
+  rexi::ShiftWork& SW = SWp ? *SWp : h->SW;
   sv.col_kh = 0;
-  h->SW.col_start = nullptr;
-  h->SW.col_total = 0;
+  SW.col_start = nullptr;
+  SW.col_total = 0;
   if (kh == 0 || !plan_columns(sv, kh, L)) return REXI_OK;
   HIPCHK(h, hipMemcpyAsync(sv.dsys, sv.hsys.data(), sv.S * sizeof(SysDesc), hipMemcpyHostToDevice, stream));
   HIPCHK(h, hipMemcpyAsync(sv.dcol, sv.hcol.data(), (sv.S + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
   HIPCHK(h, hipStreamSynchronize(stream));
-  h->SW.col_start = sv.dcol;
-  h->SW.col_total = sv.col_total;
+  SW.col_start = sv.dcol;
+  SW.col_total = sv.col_total;
   return REXI_OK;
 }
 
@@ -1431,6 +1535,8 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   if (o.fallback_bytes < 0) return fail(nullptr, REXI_E_INVALID_ARG, "fallback_bytes < 0");
   if (!(o.stab_eps >= 0.0 && o.stab_eps < 1.0)) return fail(nullptr, REXI_E_INVALID_ARG, "stab_eps must be in [0, 1)");
   if (o.center != 0 && o.center != 1) return fail(nullptr, REXI_E_INVALID_ARG, "center must be 0 or 1");
+  if (o.adjoint_shared != 0 && o.adjoint_shared != 1)
+    return fail(nullptr, REXI_E_INVALID_ARG, "adjoint_shared must be 0 or 1");
   if (o.discretization != REXI_DISC_FD && o.discretization != REXI_DISC_FEM_Q1)
     return fail(nullptr, REXI_E_INVALID_ARG, "unknown discretization %d", o.discretization);
   if (o.discretization == REXI_DISC_FEM_Q1 && o.solver == REXI_SOLVER_SHIFTED)
@@ -1582,7 +1688,7 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   SETUP_CHK(hipStreamSynchronize(stream));
   h->ws_bytes = (int64_t)N * (h->V32 ? 12 : 8);
   h->shifted = o.solver == REXI_SOLVER_SHIFTED;
-  rexi_status st = h->shifted ? init_shifted(h, stream) : init_solver(h, h->fwd, 1, stream);
+  rexi_status st = h->shifted ? init_shifted(h, h->fwd, h->SW, false, stream) : init_solver(h, h->fwd, 1, stream);
   if (st != REXI_OK) {
     g_setup_error = h->err;
     destroy_handle(h);
@@ -1668,6 +1774,8 @@ void rexi_default_options(rexi_options* o) {
   o->fallback_bytes = 0;
   o->stab_eps = 0.0;
   o->center = 0;
+  o->discretization = REXI_DISC_FD;
+  o->adjoint_shared = 1;
 }
 
 rexi_status rexi_setup(rexi_handle** out, const rexi_grid* g, const double* V_dev, double hbar, double mass,
@@ -1866,6 +1974,15 @@ rexi_status rexi_step_adjoint(rexi_handle* h, const rexi_c128* psi_n, const rexi
   if (h->ninst != 1) return fail(h, REXI_E_INVALID_ARG, "adjoint needs a single-instance handle");
   if (h->mrhs) return fail(h, REXI_E_INVALID_ARG, "the adjoint step supports finite differences only");
   hipStream_t st = (hipStream_t)stream;
+  if (h->shifted && h->opt.adjoint_shared) {
+    // one shared basis per side; per-pole solves when a pole misses its target
+    rexi_status sa = shifted_adjoint(h, (const double2*)psi_n, (const double2*)gbar_next, (double2*)gbar_n,
+                                     dV_accum, st);
+    if (sa != REXI_E_NOT_BUILT) {
+      if (sa == REXI_OK) prof_collect(h, st);
+      return sa;
+    }
+  }
   if (!h->adj.ready) {
     rexi_status s0 = init_solver(h, h->adj, 2, st);
     if (s0 != REXI_OK) return s0;

@@ -1888,6 +1888,77 @@ __global__ __launch_bounds__(TPB) void k_combine_out(Work W, ShiftWork SW, doubl
   }
 }
 
+// ------------------------------------------------------------ shared-basis adjoint
+// One backward step from two shared bases (single instance): the forward
+// solve on psi_n gives x_p = sum_b a_{p,b} c_b u_b (basis of F), the solve with
+// conjugate shifts on gbar gives y_p = sum_a b_{p,a} c'_a u'_a (basis of A), and
+//   dL/dV = -2 Re sum_p w_p conj(y_p) x_p
+//         = -2 Re sum_{a,b} C_{ab} conj(u'_a) u_b,
+//   C_{ab} = c'_a c_b sum_p w_p conj(b_{p,a}) a_{p,b}
+// (a bilinear form of the two bases per grid point).
+
+// Grid (m) blocks: row a of C (a < k_A), threads over b < k_F.
+__global__ __launch_bounds__(TPB) void k_adj_coef(Work F, ShiftWork SF, Work A, ShiftWork SA, double2* __restrict__ C,
+                                                  int ldc) {
+  const int a = blockIdx.x;
+  const int ka = A.st[0].kcyc, kf = F.st[0].kcyc;
+  if (a >= ka) return;
+  const double ca = A.cscale[a];
+  const double2* wv = reinterpret_cast<const double2*>(SF.w);
+  const double2* ya = reinterpret_cast<const double2*>(SA.y);
+  const double2* yf = reinterpret_cast<const double2*>(SF.y);
+  for (int b = threadIdx.x; b < kf; b += TPB) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int p = 0; p < SF.K; ++p) {
+      const double2 t = cjmul(ya[(int64_t)p * A.m + a], yf[(int64_t)p * F.m + b]);  // conj(b) a
+      const double2 u = cmul(wv[p], t);
+      acc.x += u.x;
+      acc.y += u.y;
+    }
+    const double sc = ca * F.cscale[b];
+    C[(int64_t)a * ldc + b] = make_double2(acc.x * sc, acc.y * sc);
+  }
+}
+
+// dV[p] += -2 Re sum_a conj(u'_a[p]) sum_b C_{ab} u_b[p], AC rows of C at a time.
+template <int AC>
+__global__ __launch_bounds__(TPB) void k_adj_grad(Work F, Work A, const double2* __restrict__ C, int ldc,
+                                                  double* __restrict__ dV) {
+  const int ka = A.st[0].kcyc, kf = F.st[0].kcyc;
+  const SysDesc& df = F.sys[0];
+  const SysDesc& da = A.sys[0];
+  const int n = df.n;
+  const double2* __restrict__ uf = basis_vec<double2>(F, df, 0);
+  const double2* __restrict__ ua = basis_vec<double2>(A, da, 0);
+  for (int p = blockIdx.x * TPB + threadIdx.x; p < n; p += gridDim.x * TPB) {
+    double dv = 0.0;
+    for (int a0 = 0; a0 < ka; a0 += AC) {
+      double2 T[AC];
+#pragma unroll
+      for (int q = 0; q < AC; ++q) T[q] = make_double2(0.0, 0.0);
+      for (int b = 0; b < kf; ++b) {
+        const double2 u = uf[(int64_t)b * n + p];
+#pragma unroll
+        for (int q = 0; q < AC; ++q) {
+          if (a0 + q < ka) {
+            const double2 c = C[(int64_t)(a0 + q) * ldc + b];
+            T[q].x += c.x * u.x - c.y * u.y;
+            T[q].y += c.x * u.y + c.y * u.x;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < AC; ++q) {
+        if (a0 + q < ka) {
+          const double2 g = ua[(int64_t)(a0 + q) * n + p];
+          dv += g.x * T[q].x + g.y * T[q].y;  // Re(conj(g) T)
+        }
+      }
+    }
+    dV[df.off + p] += -2.0 * dv;
+  }
+}
+
 // ------------------------------------------------------------ fallback
 // Poles the shared basis could not finish (its Krylov dimension is capped)
 // continue as per-pole restarted solves warm-started from the shared-basis

@@ -50,7 +50,8 @@ class Options(C.Structure):
                 ("profile", C.c_int32), ("tile", C.c_int32), ("grid_blocks", C.c_int32), ("autotune", C.c_int32),
                 ("max_workspace_bytes", C.c_int64), ("march_planes", C.c_int32), ("march_slots", C.c_int32),
                 ("fallback", C.c_int32), ("fallback_m", C.c_int32), ("fallback_bytes", C.c_int64),
-                ("stab_eps", C.c_double), ("center", C.c_int32), ("discretization", C.c_int32)]
+                ("stab_eps", C.c_double), ("center", C.c_int32), ("discretization", C.c_int32),
+                ("adjoint_shared", C.c_int32), ("reserved_opt_", C.c_int32)]
 
 
 class StepInfo(C.Structure):

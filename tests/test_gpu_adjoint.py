@@ -34,8 +34,9 @@ def _oracle_grad(g, V, psi0, phi, s, b, dt, nsteps):
     return L, gbar, dV
 
 
-@pytest.mark.parametrize("scale,nsteps", [(48, 6), (None, 20)])
-def test_autograd_matches_oracle_adjoint(scale, nsteps):
+@pytest.mark.parametrize("scale,nsteps,solver", [(48, 6, "per_pole"), (None, 20, "per_pole"), (48, 6, "shifted"),
+                                                  (None, 20, "shifted")])
+def test_autograd_matches_oracle_adjoint(scale, nsteps, solver):
     import torch
     from paper_1912_03312_amd.autograd import propagate
     wl = inputs.workload("2d_adjoint", scale=scale)
@@ -47,7 +48,7 @@ def test_autograd_matches_oracle_adjoint(scale, nsteps):
     V = to_dev(wl.V.ravel()).requires_grad_(True)
     phid = to_dev(phi.ravel())
     out = propagate(psi0, V, g.n, g.lo, g.hi, wl.dt, s, b, nsteps, checkpoint_every=5,
-                    tol=1e-12, tol_policy="certified")
+                    tol=1e-12, tol_policy="certified", solver=solver, m=200 if solver == "shifted" else 30)
     ov = g.cell_volume * torch.vdot(phid, out)
     L = (ov.abs() ** 2)
     L.backward()

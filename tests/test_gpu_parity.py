@@ -262,6 +262,50 @@ def test_adjoint_matches_oracle(rexi):
     h.close()
 
 
+@pytest.mark.parametrize("case", ["2d", "3d", "2d_centered", "2d_per_pole_path", "2d_aliased"])
+def test_shared_basis_adjoint_matches_oracle(rexi, case):
+    # the adjoint step of a shared-basis handle: gbar_n from the solve with
+    # conjugate shifts, dL/dV from the bilinear form of the two bases (or,
+    # with adjoint_shared = 0, the per-pole solves)
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    if case.startswith("3d"):
+        g = inputs.cube(12, 6.0, 3)
+        s, b, d = poles(64, 180.0)
+        dt = 1.0
+    else:
+        g = inputs.cube(24, 6.0, 2)
+        s, b, d = poles(16, 32.0)
+        dt = 0.5
+    V = inputs.gaussian_bumps(g, 5)
+    psi = inputs.seeded_packet(g, 50, (-1.0,) + (0.0,) * (g.ndim - 1), 1.0)
+    gb = inputs.random_state(g.size, 9).reshape(g.n)
+    c = 0.0
+    if case == "2d_centered":
+        lo, hi = ham.gershgorin(g.n, g.h, V)
+        c = 0.5 * (lo + hi)
+    D = ost.DirectStepper(g.n, g.h, V, s, b, dt, center=c)
+    g_ref, dV_ref = D.adjoint(psi, gb)
+    h = r.setup(g.n, g.lo, g.hi, to_dev(V.ravel()), 1.0, 1.0, dt, s, b, solver="shifted", m=200, tol=1e-12,
+                tol_policy="certified", center=1 if c else 0,
+                adjoint_shared=0 if case == "2d_per_pole_path" else 1)
+    gin = to_dev(gb.ravel())
+    gout = gin if case == "2d_aliased" else torch.empty(g.size, dtype=torch.complex128, device="cuda")
+    dV = torch.zeros(g.size, dtype=torch.float64, device="cuda")
+    for rep in range(2):  # the second call reuses the adjoint basis and graphs
+        if case == "2d_aliased" and rep:
+            gin.copy_(to_dev(gb.ravel()))
+        dV.zero_()
+        h.step_adjoint(to_dev(psi.ravel()), gin, gout, dV)
+        torch.cuda.synchronize()
+        e_g = rel(gout.cpu().numpy(), g_ref)
+        e_v = rel(dV.cpu().numpy(), dV_ref)
+        print("shared adjoint", case, rep, e_g, e_v)
+        assert e_g <= 1e-9
+        assert e_v <= 1e-8
+    h.close()
+
+
 # ---------------------------------------------------------------- shared basis
 @pytest.mark.parametrize("name,scale,K,R1,m,lz", [("1d_harmonic", None, 16, 28.0, 200, 1),
                                                   ("1d_harmonic", None, 16, 28.0, 200, 0),
