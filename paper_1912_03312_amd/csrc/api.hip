@@ -96,6 +96,7 @@ struct rexi_handle {
   int fb_cycles = 0;                  // most cycles of those solves (last step)
   int fb_poles = 0;                   // poles they took over (last step)
   int64_t fb_its = 0;                 // their iterations (last step)
+  double2* fb_rhs = nullptr;          // a copy of psi when the step is in place (out = psi)
   // shared-basis solver: fwd holds one system (H, shift 0) per instance
   bool shifted = false;
   rexi::ShiftWork SW{};
@@ -177,6 +178,7 @@ void destroy_handle(rexi_handle* h) {
   if (h->V32) (void)hipFree(h->V32);
   if (h->dnorm) (void)hipFree(h->dnorm);
   if (h->mrhs) (void)hipFree(h->mrhs);
+  if (h->fb_rhs) (void)hipFree(h->fb_rhs);
   if (h->hpin) (void)hipHostFree(h->hpin);
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
   for (auto& g : h->chunks) (void)hipGraphExecDestroy(g.exec);
@@ -713,12 +715,15 @@ rexi_status init_shifted(rexi_handle* h, Solver& sv, rexi::ShiftWork& SW, bool c
 // Workspace of the per-pole solves that finish poles the shared basis missed:
 // complex64 basis + FP64 refinement, restart length fallback_m, for at most
 // cap_pts points over at most cap_S systems (one wave of those poles).
+// points per thread of the fallback solves (their tiles are TPB * FB_PPT points)
+constexpr int FB_PPT = 4;
+
 rexi_status init_fallback(rexi_handle* h, hipStream_t stream) {
   Solver& fb = h->fb;
   fb.hsys.clear();
   fb.m = h->opt.fallback_m;
   fb.prec = 1;
-  fb.ppt = 4;
+  fb.ppt = FB_PPT;
   fb.tile = TPB_ * fb.ppt;
   fb.eta = h->opt.reorth_eta;
   fb.reorth = h->opt.reorth;
@@ -745,13 +750,19 @@ rexi_status init_fallback(rexi_handle* h, hipStream_t stream) {
   rexi_status st = build_solver(h, fb, stream);
   if (st != REXI_OK) return st;
   fb.grid = 1;
+  // in-place steps overwrite psi with the shared-basis sum before these
+  // solves read it: they read this copy instead
+  if (hipMalloc(&h->fb_rhs, (size_t)h->N * sizeof(double2)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, REXI_E_NO_MEMORY, "fallback right-hand side");
+  }
+  h->ws_bytes += h->N * (int64_t)sizeof(double2);
   return REXI_OK;
 }
 
 // Finish the poles p of `poles` (all missed their target in the shared basis,
 // whose iterates y_p are current) by per-pole solves in waves, and add
 // sum_p w_p x_p to out.
-template <int PPT>
 rexi_status run_fallback(rexi_handle* h, const std::vector<int>& poles, const double2* b, double2* out,
                          hipStream_t stream) {
   Solver& fb = h->fb;
@@ -814,9 +825,9 @@ rexi_status run_fallback(rexi_handle* h, const std::vector<int>& poles, const do
                              stream));
     Work& F = fb.W;
     // warm start: x = V y_p, then the explicit residual and restart decision
-    hipLaunchKernelGGL((rexi::k_fb_init_x<PPT>), dim3(fb.grid), dim3(TPB), 0, stream, F, sv.W, h->SW);
+    hipLaunchKernelGGL(rexi::k_fb_init_x, dim3(fb.grid), dim3(TPB), 0, stream, F, sv.W, h->SW);
     hipLaunchKernelGGL(rexi::k_fb_state, dim3(fb.S), dim3(TPB), 0, stream, F, sv.W);
-    hipLaunchKernelGGL((rexi::k_residual<float2, 4>), dim3(fb.grid), dim3(TPB), 0, stream, F, b, b);
+    hipLaunchKernelGGL((rexi::k_residual<float2, FB_PPT>), dim3(fb.grid), dim3(TPB), 0, stream, F, b, b);
     hipLaunchKernelGGL(rexi::k_restart, dim3(fb.S), dim3(TPB), 0, stream, F, 0);
     HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipMemcpyAsync(h->hpin, F.counters + fb.max_cycles * (fb.m + 1), sizeof(int32_t),
@@ -824,7 +835,7 @@ rexi_status run_fallback(rexi_handle* h, const std::vector<int>& poles, const do
     HIPCHK(h, hipStreamSynchronize(stream));
     const int active = h->hpin[0];
     if (active > 0) {
-      rexi_status rs = run_cycles<float2, 4>(h, fb, b, b, stream, active, active, nullptr);
+      rexi_status rs = run_cycles<float2, FB_PPT>(h, fb, b, b, stream, active, active, nullptr);
       if (rs != REXI_OK) return rs;
     }
     hipLaunchKernelGGL(rexi::k_fb_report, dim3(fb.S), dim3(64), 0, stream, F, h->SW, kshared);
@@ -1125,6 +1136,11 @@ rexi_status run_shifted(rexi_handle* h, ShiftCtx cx, const double2* b, double2* 
       if (its[p] == 0) missed.push_back(p);
   }
   if (!out) return REXI_OK;
+  const double2* fb_b = b;
+  if (!missed.empty() && (const void*)b == (const void*)out) {
+    HIPCHK(h, hipMemcpyAsync(h->fb_rhs, b, (size_t)h->N * sizeof(double2), hipMemcpyDeviceToDevice, stream));
+    fb_b = h->fb_rhs;
+  }
   rexi::ShiftWork SWz = SWc;
   SWz.fb_skip = missed.empty() ? 0 : 1;
   {
@@ -1138,7 +1154,7 @@ rexi_status run_shifted(rexi_handle* h, ShiftCtx cx, const double2* b, double2* 
   HIPCHK(h, hipGetLastError());
   if (!missed.empty()) {
     h->fb_poles = (int)missed.size();
-    rexi_status rs = run_fallback<PPT>(h, missed, b, out, stream);
+    rexi_status rs = run_fallback(h, missed, fb_b, out, stream);
     if (rs != REXI_OK) return rs;
   }
   return REXI_OK;

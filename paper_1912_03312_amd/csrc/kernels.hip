@@ -1965,7 +1965,6 @@ __global__ __launch_bounds__(TPB) void k_adj_grad(Work F, Work A, const double2*
 // iterate x_p = V y_p. F is the per-pole solver of those poles, W the shared one.
 
 // x_s = sum_{i<k} y_{p,i} c_i u_i(inst) in FP64 for every system s of F.
-template <int PPT>
 __global__ __launch_bounds__(TPB) void k_fb_init_x(Work F, Work W, ShiftWork SW) {
   __shared__ double2 coef[MAXM];
   int sprev = -1;
@@ -1988,19 +1987,17 @@ __global__ __launch_bounds__(TPB) void k_fb_init_x(Work F, Work W, ShiftWork SW)
     const int t = item - d.tile0;
     const double2* __restrict__ u0 = basis_vec<double2>(W, dw, 0);
     double2* __restrict__ x = reinterpret_cast<double2*>(F.x) + d.xoff;
-#pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-      const int p = t * F.tile + q * TPB + threadIdx.x;
-      if (p < d.n) {
-        double2 acc = make_double2(0.0, 0.0);
-        for (int i = 0; i < k; ++i) {
-          const double2 c = coef[i];
-          const double2 a = u0[(int64_t)i * dw.n + p];
-          acc.x += c.x * a.x - c.y * a.y;
-          acc.y += c.x * a.y + c.y * a.x;
-        }
-        x[p] = acc;
+    // the whole tile of F (its own points per thread, not those of W)
+    const int pend = min((t + 1) * F.tile, d.n);
+    for (int p = t * F.tile + (int)threadIdx.x; p < pend; p += TPB) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int i = 0; i < k; ++i) {
+        const double2 c = coef[i];
+        const double2 a = u0[(int64_t)i * dw.n + p];
+        acc.x += c.x * a.x - c.y * a.y;
+        acc.y += c.x * a.y + c.y * a.x;
       }
+      x[p] = acc;
     }
   }
 }

@@ -709,6 +709,72 @@ def test_shifted_fallback_finishes_missed_poles(rexi, name, scale, m, fallback):
         assert errs[1] <= errs[0] * (1 + 1e-3) + infos[1]["certified_bound"] + 3 * floor
 
 
+def test_shifted_fallback_in_place_steps(rexi):
+    # in place (psi_out = psi_in), the shared-basis sum overwrites psi before
+    # the per-pole solves of the missed poles read it: they must read a copy;
+    # two in-place steps on a fresh handle (a handle carries its Krylov-length
+    # hints from step to step) equal two out-of-place ones bit for bit
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    wl = inputs.workload("3d_bumps", scale=12)
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+
+    def handle():
+        return r.setup(g.n, g.lo, g.hi, to_dev(wl.V.ravel()), 1.0, 1.0, wl.dt, s, b, solver="shifted", m=6,
+                       tol=1e-11, tol_policy="certified", max_cycles=200)
+
+    a = to_dev(wl.psi0.ravel())
+    o1 = torch.empty_like(a)
+    o2 = torch.empty_like(a)
+    h = handle()
+    i1 = h.step(a, o1, 1)
+    h.step(o1, o2, 1)
+    h.close()
+    x = a.clone()
+    h = handle()
+    h.step(x, x, 1)
+    i2 = h.step(x, x, 1)
+    h.close()
+    torch.cuda.synchronize()
+    print("fallback in place", rel(x.cpu().numpy(), o2.cpu().numpy()), i1["max_cycles_used"], i2["not_converged"])
+    assert i1["max_cycles_used"] > 1 and i2["not_converged"] == 0
+    assert torch.equal(x, o2)
+
+
+def test_shifted_fallback_independent_of_stale_memory(rexi):
+    # the warm start of the per-pole solves covers every point of their tiles
+    # (which differ from the shared solver's): a fresh handle placed on memory
+    # that held NaNs repeats the first handle's step bit for bit, iteration
+    # counts included
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    wl = inputs.workload("3d_bumps", scale=12)
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+
+    def one_step():
+        h = r.setup(g.n, g.lo, g.hi, to_dev(wl.V.ravel()), 1.0, 1.0, wl.dt, s, b, solver="shifted", m=6,
+                    tol=1e-11, tol_policy="certified", max_cycles=200)
+        o = torch.empty(g.size, dtype=torch.complex128, device="cuda")
+        info = h.step(to_dev(wl.psi0.ravel()), o, 1)
+        torch.cuda.synchronize()
+        h.close()
+        return o, info
+
+    o1, i1 = one_step()
+    torch.cuda.empty_cache()
+    junk = torch.full((1 << 27,), float("nan"), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    del junk
+    torch.cuda.empty_cache()
+    o2, i2 = one_step()
+    print("fallback its", i1["total_iterations"], i2["total_iterations"], i1["max_cycles_used"])
+    assert i1["max_cycles_used"] > 1
+    assert i1["iterations"] == i2["iterations"] and i1["total_iterations"] == i2["total_iterations"]
+    assert torch.equal(o1, o2)
+
+
 # ---------------------------------------------------------------- marching pass
 def _centred_grid(shape, h=0.25):
     return inputs.Grid(tuple(shape), tuple(-0.5 * h * (k + 1) for k in shape), tuple(0.5 * h * (k + 1) for k in shape))
