@@ -153,19 +153,27 @@ typedef struct {
   int32_t march_slots;  /* marching pass: points per thread and plane, 3, 5
                            or 8 (0 = 5); a band holds 256 slots / n2 - 2
                            rows of the plane                                 */
-  int32_t fallback;     /* shared-basis solver: 1 (default) poles that miss
-                           their target within m vectors continue as per-pole
-                           restarted solves (complex64 + FP64 refinement,
-                           restart length fallback_m, max_cycles cycles)
-                           warm-started from the shared-basis iterate; 0: they
-                           are reported in not_converged. Needs host checks
-                           (not with capture_safe)                           */
-  int32_t fallback_m;   /* restart length of those solves (and of the
-                           per-pole adjoint solves of a shared-basis
-                           handle), 30                                       */
-  int64_t fallback_bytes; /* device workspace reserved for them at setup
-                           (0 = min(16 GiB, a quarter of the free memory));
-                           unconverged poles are solved in waves that fit    */
+  int32_t fallback;     /* shared-basis solver, poles that miss their target
+                           within m vectors:
+                           1 (default) restarts on the shared basis: such a
+                           pole takes the Galerkin iterate of the basis,
+                           whose residual is a multiple of the next basis
+                           vector u_m for every such pole of an instance; a
+                           new shared basis on u_m then serves all of them
+                           (cycles of up to m vectors, at most max_cycles);
+                           2: per-pole restarted solves (complex64 + FP64
+                           refinement, restart length fallback_m,
+                           max_cycles cycles) warm-started from the
+                           shared-basis iterate;
+                           0: they are reported in not_converged.
+                           1 and 2 need host checks (not capture_safe)       */
+  int32_t fallback_m;   /* restart length of the per-pole solves of
+                           fallback 2 (and of the per-pole adjoint solves of
+                           a shared-basis handle), 30                        */
+  int64_t fallback_bytes; /* fallback 2: device workspace reserved for the
+                           per-pole solves at setup (0 = min(16 GiB, a
+                           quarter of the free memory)); unconverged poles
+                           are solved in waves that fit                      */
   double stab_eps;      /* weights scaled by (1 - stab_eps), 0 <= stab_eps
                            < 1 (Section 3.4: |r(iy)| exceeds one by up to
                            the approximation error ||e||; a factor

@@ -52,6 +52,7 @@ struct Solver {
   Work W{};
   SysDesc* dsys = nullptr;
   int32_t* dtile = nullptr;
+  int32_t* dtsys = nullptr;   // system of each tile (sized for the smallest tile; null for capacity builds)
   // column-marching Lanczos pass (0: the row-staged pass)
   int col_kh = 0, col_L = 0, col_total = 0;
   std::vector<int32_t> hcol;
@@ -97,6 +98,17 @@ struct rexi_handle {
   int fb_poles = 0;                   // poles they took over (last step)
   int64_t fb_its = 0;                 // their iterations (last step)
   double2* fb_rhs = nullptr;          // a copy of psi when the step is in place (out = psi)
+  // restarts on the shared basis (fallback = 1): the cycles' view of SW,
+  // their right-hand side and per-pole / per-instance bookkeeping
+  bool rs_ready = false;
+  rexi::ShiftWork SWR{};
+  double2* rs_rhs = nullptr;
+  int32_t *rs_miss = nullptr, *rs_kbase = nullptr, *rs_hasmiss = nullptr;
+  double *rs_gam = nullptr, *rs_bn0 = nullptr;
+  int rs_k_hint = 0, rs_reorth = 0;
+  int rs_cycles = 0;                  // restart cycles of the last step
+  int64_t rs_its = 0;                 // their iterations summed over instances
+  std::vector<rexi::SysState_t> st0;  // per-instance states after the first cycle of the last solve
   // shared-basis solver: fwd holds one system (H, shift 0) per instance
   bool shifted = false;
   rexi::ShiftWork SW{};
@@ -119,6 +131,7 @@ struct rexi_handle {
     hipGraphExec_t exec;
   };
   std::vector<ChunkGraph> chunks;
+  std::vector<ChunkGraph> rs_chunks;  // the same for the restart cycles (their own ShiftWork)
   int k_hint = 0;                     // iterations the last shared-basis solve took
   int reorth_passes = 0;              // second passes of the last shared-basis solve
   // shared-basis adjoint: a second basis for the solves with conjugate shifts
@@ -182,6 +195,7 @@ void destroy_handle(rexi_handle* h) {
   if (h->hpin) (void)hipHostFree(h->hpin);
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
   for (auto& g : h->chunks) (void)hipGraphExecDestroy(g.exec);
+  for (auto& g : h->rs_chunks) (void)hipGraphExecDestroy(g.exec);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (auto& e : h->prof.ev) (void)hipEventDestroy(e);
   delete h;
@@ -314,6 +328,19 @@ bool plan_columns(Solver& sv, int kh, int L) {
   return true;
 }
 
+// The per-tile system table of a solver (after its layout changed).
+rexi_status upload_tile_sys(rexi_handle* h, Solver& sv, hipStream_t stream) {
+  sv.W.tile_sys = nullptr;
+  if (!sv.dtsys || sv.S == 0) return REXI_OK;
+  std::vector<int32_t> t((size_t)sv.total_tiles);
+  for (int q = 0; q < sv.S; ++q)
+    for (int it = sv.htile[q]; it < sv.htile[q + 1]; ++it) t[it] = q;
+  HIPCHK(h, hipMemcpyAsync(sv.dtsys, t.data(), t.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  HIPCHK(h, hipStreamSynchronize(stream));
+  sv.W.tile_sys = sv.dtsys;
+  return REXI_OK;
+}
+
 rexi_status build_solver(rexi_handle* h, Solver& sv, hipStream_t stream) {
   const int m = sv.m, S = sv.S;
   const int SA = sv.cap_S > 0 ? sv.cap_S : S;  // systems allocated for
@@ -355,6 +382,7 @@ rexi_status build_solver(rexi_handle* h, Solver& sv, hipStream_t stream) {
   }
   ALLOC(W.part, double, npart * 2);
   ALLOC(W.pnorm, double, ntmax);
+  if (sv.cap_S == 0) ALLOC(sv.dtsys, int32_t, ntmax);
   ALLOC(W.counters, int32_t, sv.max_cycles * (m + 1) + sv.max_cycles + 4);
   ALLOC(W.x, double, nx * 2);
   if (sv.prec) {
@@ -384,6 +412,7 @@ rexi_status build_solver(rexi_handle* h, Solver& sv, hipStream_t stream) {
   W.eta2 = sv.eta * sv.eta;  // DGKS: second pass when ||w - V h|| < eta ||w||
   W.max_cycles = sv.max_cycles;
   W.tile = sv.tile;
+  if ((st = upload_tile_sys(h, sv, stream)) != REXI_OK) return st;
   sv.ready = true;
   return REXI_OK;
 }
@@ -641,7 +670,7 @@ rexi_status init_shifted(rexi_handle* h, Solver& sv, rexi::ShiftWork& SW, bool c
   const size_t c16 = 16, d8 = 8, i4 = 4;
   void *s = nullptr, *w = nullptr, *tol = nullptr, *its = nullptr, *pole0 = nullptr, *pinst = nullptr;
   void *R = nullptr, *g = nullptr, *gc = nullptr, *gs = nullptr, *y = nullptr, *z = nullptr, *res = nullptr;
-  void *alpha = nullptr, *beta = nullptr, *omega = nullptr, *flags = nullptr, *full = nullptr;
+  void *alpha = nullptr, *beta = nullptr, *omega = nullptr, *flags = nullptr, *full = nullptr, *reo = nullptr;
   if ((st = al(&s, K * c16)) || (st = al(&w, K * c16)) || (st = al(&tol, K * d8)) || (st = al(&its, K * i4)) ||
       (st = al(&pole0, (S + 1) * i4)) || (st = al(&pinst, K * i4)) ||
       (st = al(&R, (size_t)K * (m + 1) * m * c16)) || (st = al(&g, (size_t)K * (m + 1) * c16)) ||
@@ -649,8 +678,9 @@ rexi_status init_shifted(rexi_handle* h, Solver& sv, rexi::ShiftWork& SW, bool c
       (st = al(&y, (size_t)K * m * c16)) || (st = al(&z, (size_t)S * m * c16)) || (st = al(&res, K * d8)) ||
       (st = al(&alpha, (size_t)S * m * d8)) || (st = al(&beta, (size_t)S * (m + 1) * d8)) ||
       (st = al(&omega, (size_t)S * 2 * (m + 1) * d8)) || (st = al(&flags, (size_t)S * 4 * i4)) ||
-      (st = al(&full, (size_t)S * m * i4)))
+      (st = al(&full, (size_t)S * m * i4)) || (st = al(&reo, (size_t)(m + 1) * i4)))
     return st;
+  sv.W.reo_any = (int32_t*)reo;
   SW.s = (const double*)s;
   SW.w = (const double*)w;
   SW.tol = (const double*)tol;
@@ -712,6 +742,57 @@ rexi_status init_shifted(rexi_handle* h, Solver& sv, rexi::ShiftWork& SW, bool c
 
 // The fused Lanczos pass of iteration j: the marching pass when a column plan
 // is selected, else the row-staged pass (n2 <= 512) or the plain one.
+// Restart cycles on the shared basis (forward solver): the cycles' view of
+// the shared-basis data (own weights, targets, iteration counts and
+// residuals; the rest shared) and their bookkeeping.
+rexi_status init_restart(rexi_handle* h, hipStream_t stream) {
+  const int K = h->SW.K, S = h->fwd.S;
+  void *gnext = nullptr, *miss = nullptr, *gam = nullptr, *w = nullptr, *tol = nullptr, *its = nullptr,
+       *res = nullptr, *bn0 = nullptr, *kbase = nullptr, *hasmiss = nullptr, *rhs = nullptr;
+  auto al = [&](void** p, size_t bytes) -> rexi_status {
+    DevBuf b;
+    b.bytes = std::max<size_t>(bytes, 256);
+    if (hipMalloc(&b.p, b.bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(h, REXI_E_NO_MEMORY, "restart workspace (%zu bytes)", b.bytes);
+    }
+    h->sbufs.push_back(b);
+    h->ws_bytes += (int64_t)b.bytes;
+    *p = b.p;
+    return REXI_OK;
+  };
+  rexi_status st;
+  if ((st = al(&gnext, (size_t)K * 16)) || (st = al(&miss, (size_t)K * 4)) || (st = al(&gam, (size_t)K * 16)) ||
+      (st = al(&w, (size_t)K * 16)) || (st = al(&tol, (size_t)K * 8)) || (st = al(&its, (size_t)K * 4)) ||
+      (st = al(&res, (size_t)K * 8)) || (st = al(&bn0, (size_t)S * 8)) || (st = al(&kbase, (size_t)S * 4)) ||
+      (st = al(&hasmiss, (size_t)S * 4)) || (st = al(&rhs, (size_t)h->N * 16)))
+    return st;
+  h->SW.gnext = (double*)gnext;
+  rexi::ShiftWork R = h->SW;
+  R.w = (const double*)w;
+  R.tol = (const double*)tol;
+  R.its = (int32_t*)its;
+  R.res = (double*)res;
+  R.fom = 1;
+  R.fb_skip = 0;
+  R.restart = 1;
+  R.miss = (const int32_t*)miss;
+  R.gam = (const double*)gam;
+  R.w0 = h->SW.w;
+  R.tol0 = h->SW.tol;
+  R.bn0 = (const double*)bn0;
+  h->SWR = R;
+  h->rs_miss = (int32_t*)miss;
+  h->rs_gam = (double*)gam;
+  h->rs_bn0 = (double*)bn0;
+  h->rs_kbase = (int32_t*)kbase;
+  h->rs_hasmiss = (int32_t*)hasmiss;
+  h->rs_rhs = (double2*)rhs;
+  h->rs_ready = true;
+  (void)stream;
+  return REXI_OK;
+}
+
 // Workspace of the per-pole solves that finish poles the shared basis missed:
 // complex64 basis + FP64 refinement, restart length fallback_m, for at most
 // cap_pts points over at most cap_S systems (one wave of those poles).
@@ -898,16 +979,23 @@ struct ShiftCtx {
   std::vector<rexi_handle::ChunkGraph>* chunks;
   int* k_hint;
   int* reorth_passes;
-  bool fallback;  // finish missed poles by per-pole solves (the forward solver only)
+  // poles that miss their target within the basis (the forward solver only):
+  // 0 left as they are, 1 restarts on the shared basis, 2 per-pole solves
+  int finish;
 };
 
-ShiftCtx fwd_ctx(rexi_handle* h) { return {&h->fwd, &h->SW, &h->chunks, &h->k_hint, &h->reorth_passes, true}; }
-ShiftCtx adj_ctx(rexi_handle* h) { return {&h->fwdA, &h->SWA, &h->chunksA, &h->k_hintA, &h->reorth_passesA, false}; }
+ShiftCtx fwd_ctx(rexi_handle* h) {
+  return {&h->fwd, &h->SW, &h->chunks, &h->k_hint, &h->reorth_passes, h->opt.fallback};
+}
+ShiftCtx adj_ctx(rexi_handle* h) { return {&h->fwdA, &h->SWA, &h->chunksA, &h->k_hintA, &h->reorth_passesA, 0}; }
+ShiftCtx rs_ctx(rexi_handle* h) { return {&h->fwd, &h->SWR, &h->rs_chunks, &h->rs_k_hint, &h->rs_reorth, 0}; }
 
-// One shared-basis solve of all poles of every instance; writes the pole sums
-// to out (out = nullptr: the solve only, its per-pole coefficients y_p).
+// The Lanczos (or Arnoldi) process of one shared-basis solve on b, up to the
+// per-pole Givens data; with host checks, sst receives the per-instance
+// states at its end and its_sum their iterations.
 template <typename T, int PPT>
-rexi_status run_shifted(rexi_handle* h, ShiftCtx cx, const double2* b, double2* out, hipStream_t stream) {
+rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStream_t stream,
+                         std::vector<SysState_t>* sst_out, int64_t* its_sum) {
   Solver& sv = *cx.sv;
   rexi::ShiftWork& SWc = *cx.SW;
   Work& W = sv.W;
@@ -1112,23 +1200,52 @@ rexi_status run_shifted(rexi_handle* h, ShiftCtx cx, const double2* b, double2* 
     HIPCHK(h, hipMemcpyAsync(sst.data(), W.st, S * sizeof(SysState_t), hipMemcpyDeviceToHost, stream));
     HIPCHK(h, hipStreamSynchronize(stream));
     int kmax = 1;
-    for (auto& x : sst) kmax = std::max(kmax, x.kcyc);
+    int64_t isum = 0;
+    for (auto& x : sst) {
+      kmax = std::max(kmax, x.kcyc);
+      isum += x.its;
+    }
     (*cx.k_hint) = kmax;
     (*cx.reorth_passes) = passes;
+    if (sst_out) *sst_out = sst;
+    if (its_sum) *its_sum = isum;
   }
+  return REXI_OK;
+}
+
+template <typename T, int PPT>
+rexi_status run_restarts(rexi_handle* h, double2* out, hipStream_t stream);
+
+// One shared-basis solve of all poles of every instance; writes the pole sums
+// to out (out = nullptr: the solve only, its per-pole coefficients y_p).
+template <typename T, int PPT>
+rexi_status run_shifted(rexi_handle* h, ShiftCtx cx, const double2* b, double2* out, hipStream_t stream) {
+  Solver& sv = *cx.sv;
+  rexi::ShiftWork& SWc = *cx.SW;
+  Work& W = sv.W;
+  const int G = sv.grid, m = sv.m;
+  h->rs_cycles = 0;
+  h->rs_its = 0;
+  rexi_status ps = shifted_pass<T, PPT>(h, cx, b, stream, &h->st0, nullptr);
+  if (ps != REXI_OK) return ps;
+  // restarts need the Galerkin iterate of the poles that missed their target
+  const bool restart = cx.finish == 1 && h->rs_ready && out && !h->syncfree;
   {
+    rexi::ShiftWork SWb = SWc;
+    SWb.fom = restart ? 1 : 0;
     Timed t(h, PC_REDUCE, 0, stream);
     hipLaunchKernelGGL(rexi::k_shifted_backsub, dim3((SWc.K + rexi::NWAVE - 1) / rexi::NWAVE), dim3(TPB), 0,
-                       stream, W, SWc);
+                       stream, W, SWb);
   }
-  // poles that missed their target within the basis: per-pole solves finish
-  // them (host checks only), and they are left out of z
+  // poles that missed their target within the basis: restarts or per-pole
+  // solves finish them (host checks only)
   std::vector<int> missed;
   h->fb_poles = 0;
   h->fb_cycles = 0;
   h->fb_its = 0;
   // a system that stopped before m iterations met every pole's target
-  if (cx.fallback && h->fb.ready && !h->syncfree && (*cx.k_hint) >= m) {
+  const bool per_pole = cx.finish == 2 && h->fb.ready;
+  if ((restart || per_pole) && !h->syncfree && (*cx.k_hint) >= m) {
     std::vector<int32_t> its((size_t)SWc.K);
     HIPCHK(h, hipMemcpyAsync(its.data(), SWc.its, its.size() * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     HIPCHK(h, hipStreamSynchronize(stream));
@@ -1136,26 +1253,81 @@ rexi_status run_shifted(rexi_handle* h, ShiftCtx cx, const double2* b, double2* 
       if (its[p] == 0) missed.push_back(p);
   }
   if (!out) return REXI_OK;
+  const bool fb = per_pole && !missed.empty();
   const double2* fb_b = b;
-  if (!missed.empty() && (const void*)b == (const void*)out) {
+  if (fb && (const void*)b == (const void*)out) {
     HIPCHK(h, hipMemcpyAsync(h->fb_rhs, b, (size_t)h->N * sizeof(double2), hipMemcpyDeviceToDevice, stream));
     fb_b = h->fb_rhs;
   }
+  // per-pole solves: those poles are left out of z; restarts: they enter
+  // with their Galerkin iterate
   rexi::ShiftWork SWz = SWc;
-  SWz.fb_skip = missed.empty() ? 0 : 1;
+  SWz.fb_skip = fb ? 1 : 0;
   {
     Timed t(h, PC_REDUCE, 0, stream);
-    hipLaunchKernelGGL(rexi::k_shifted_z, dim3(S), dim3(TPB), 0, stream, W, SWz);
+    hipLaunchKernelGGL(rexi::k_shifted_z, dim3(sv.S), dim3(TPB), 0, stream, W, SWz);
   }
   {
     Timed t(h, PC_POLESUM, 0, stream);
-    hipLaunchKernelGGL((rexi::k_combine_out<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, SWc, out);
+    hipLaunchKernelGGL((rexi::k_combine_out<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, SWc, out, 0);
   }
   HIPCHK(h, hipGetLastError());
-  if (!missed.empty()) {
+  if (fb) {
     h->fb_poles = (int)missed.size();
     rexi_status rs = run_fallback(h, missed, fb_b, out, stream);
     if (rs != REXI_OK) return rs;
+  }
+  if (restart && !missed.empty()) {
+    h->fb_poles = (int)missed.size();
+    return run_restarts<T, PPT>(h, out, stream);
+  }
+  return REXI_OK;
+}
+
+// Restart cycles on the shared basis (single forward solver). After a cycle
+// on right-hand side b, a pole that missed its target has the Galerkin
+// iterate of the basis, with residual gnext_p u_k: the residuals of all such
+// poles of an instance are multiples of u_k. The next cycle solves on
+// b' = u_k for those poles only, pole p with weight w_p gam_p (gam_p the
+// product of its gnext over the cycles) and target tol_p ||psi|| / |gam_p|,
+// and adds its sums to out. Instances with no such pole have b' = 0.
+template <typename T, int PPT>
+rexi_status run_restarts(rexi_handle* h, double2* out, hipStream_t stream) {
+  Solver& sv = h->fwd;
+  Work& W = sv.W;
+  const int S = sv.S, G = sv.grid;
+  const rexi::ShiftWork& R = h->SWR;
+  hipLaunchKernelGGL(rexi::k_rs_begin, dim3(S), dim3(TPB), 0, stream, W, h->SW, h->rs_miss, h->rs_gam, h->rs_bn0,
+                     h->rs_kbase, h->rs_hasmiss);
+  hipLaunchKernelGGL(rexi::k_rs_rhs, dim3(G), dim3(TPB), 0, stream, W, h->rs_hasmiss, h->rs_rhs);
+  HIPCHK(h, hipGetLastError());
+  std::vector<int32_t> hm((size_t)S);
+  for (int c = 1; c <= std::max(1, h->opt.max_cycles); ++c) {
+    int64_t isum = 0;
+    rexi_status ps = shifted_pass<T, PPT>(h, rs_ctx(h), h->rs_rhs, stream, nullptr, &isum);
+    if (ps != REXI_OK) return ps;
+    h->rs_cycles = c;
+    h->rs_its += isum;
+    {
+      Timed t(h, PC_REDUCE, 0, stream);
+      hipLaunchKernelGGL(rexi::k_shifted_backsub, dim3((R.K + rexi::NWAVE - 1) / rexi::NWAVE), dim3(TPB), 0,
+                         stream, W, R);
+      hipLaunchKernelGGL(rexi::k_shifted_z, dim3(S), dim3(TPB), 0, stream, W, R);
+    }
+    {
+      Timed t(h, PC_POLESUM, 0, stream);
+      hipLaunchKernelGGL((rexi::k_combine_out<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, R, out, 1);
+    }
+    hipLaunchKernelGGL(rexi::k_rs_merge, dim3(S), dim3(TPB), 0, stream, W, h->SW, R, h->rs_miss, h->rs_gam,
+                       h->rs_bn0, h->rs_kbase, h->rs_hasmiss);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(hm.data(), h->rs_hasmiss, S * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    HIPCHK(h, hipStreamSynchronize(stream));
+    bool any = false;
+    for (int32_t v : hm) any = any || v != 0;
+    if (!any) break;
+    hipLaunchKernelGGL(rexi::k_rs_rhs, dim3(G), dim3(TPB), 0, stream, W, h->rs_hasmiss, h->rs_rhs);
+    HIPCHK(h, hipGetLastError());
   }
   return REXI_OK;
 }
@@ -1179,9 +1351,9 @@ rexi_status shifted_combine(rexi_handle* h, ShiftCtx cx, double2* out, hipStream
   Timed t(h, PC_POLESUM, 0, stream);
   hipLaunchKernelGGL(rexi::k_shifted_z, dim3(sv.S), dim3(TPB), 0, stream, sv.W, *cx.SW);
   switch (sv.ppt) {
-    case 8: hipLaunchKernelGGL((rexi::k_combine_out<double2, 8>), dim3(sv.grid), dim3(TPB), 0, stream, sv.W, *cx.SW, out); break;
-    case 4: hipLaunchKernelGGL((rexi::k_combine_out<double2, 4>), dim3(sv.grid), dim3(TPB), 0, stream, sv.W, *cx.SW, out); break;
-    default: hipLaunchKernelGGL((rexi::k_combine_out<double2, 2>), dim3(sv.grid), dim3(TPB), 0, stream, sv.W, *cx.SW, out); break;
+    case 8: hipLaunchKernelGGL((rexi::k_combine_out<double2, 8>), dim3(sv.grid), dim3(TPB), 0, stream, sv.W, *cx.SW, out, 0); break;
+    case 4: hipLaunchKernelGGL((rexi::k_combine_out<double2, 4>), dim3(sv.grid), dim3(TPB), 0, stream, sv.W, *cx.SW, out, 0); break;
+    default: hipLaunchKernelGGL((rexi::k_combine_out<double2, 2>), dim3(sv.grid), dim3(TPB), 0, stream, sv.W, *cx.SW, out, 0); break;
   }
   HIPCHK(h, hipGetLastError());
   return REXI_OK;
@@ -1210,7 +1382,7 @@ rexi_status shifted_adjoint(rexi_handle* h, const double2* psi_n, const double2*
     }
   }
   ShiftCtx cf = fwd_ctx(h);
-  cf.fallback = false;
+  cf.finish = 0;
   rexi_status s1 = shifted_solve(h, cf, psi_n, nullptr, st);
   if (s1 != REXI_OK) return s1;
   s1 = shifted_solve(h, adj_ctx(h), gbar_next, nullptr, st);
@@ -1305,6 +1477,8 @@ rexi_status apply_tiling(rexi_handle* h, Solver& sv, int ppt, int grid, hipStrea
   HIPCHK(h, hipMemcpyAsync(sv.dsys, sv.hsys.data(), sv.S * sizeof(SysDesc), hipMemcpyHostToDevice, stream));
   HIPCHK(h, hipMemcpyAsync(sv.dtile, sv.htile.data(), (sv.S + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
   HIPCHK(h, hipStreamSynchronize(stream));
+  rexi_status ts = upload_tile_sys(h, sv, stream);
+  if (ts != REXI_OK) return ts;
   sv.col_kh = 0;  // a new tiling invalidates the column plan
   if (h->shifted) {
     rexi::ShiftWork& SW = SWp ? *SWp : h->SW;
@@ -1545,7 +1719,7 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
     return fail(nullptr, REXI_E_INVALID_ARG, "march_planes must be in [-1, 1024]");
   if (o.march_slots != 0 && o.march_slots != 3 && o.march_slots != 5 && o.march_slots != 8)
     return fail(nullptr, REXI_E_INVALID_ARG, "march_slots must be 0, 3, 5 or 8");
-  if (o.fallback != 0 && o.fallback != 1) return fail(nullptr, REXI_E_INVALID_ARG, "fallback must be 0 or 1");
+  if (o.fallback < 0 || o.fallback > 2) return fail(nullptr, REXI_E_INVALID_ARG, "fallback must be 0, 1 or 2");
   if (o.fallback_m < 1 || o.fallback_m > 256)
     return fail(nullptr, REXI_E_INVALID_ARG, "fallback_m must be in [1, 256]");
   if (o.fallback_bytes < 0) return fail(nullptr, REXI_E_INVALID_ARG, "fallback_bytes < 0");
@@ -1689,7 +1863,7 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   SETUP_CHK(hipMalloc(&h->V64, (size_t)N * sizeof(double)));
   SETUP_CHK(hipMemcpyAsync(h->V64, V_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice, stream));
   // FP32 V: complex64 inner solves (also those finishing missed shared-basis poles)
-  if (o.precision == REXI_PREC_C64_REFINE || (o.solver == REXI_SOLVER_SHIFTED && o.fallback)) {
+  if (o.precision == REXI_PREC_C64_REFINE || (o.solver == REXI_SOLVER_SHIFTED && o.fallback == 2)) {
     SETUP_CHK(hipMalloc(&h->V32, (size_t)N * sizeof(float)));
     hipLaunchKernelGGL(rexi::k_v_to_f32, dim3(1024), dim3(TPB), 0, stream, h->V64, h->V32, (int64_t)N);
     SETUP_CHK(hipGetLastError());
@@ -1713,7 +1887,8 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   if (o.autotune && o.tile == 0 && o.grid_blocks == 0) st = autotune(h, h->fwd, stream);
   if (st == REXI_OK && h->shifted && o.lanczos == 1 && o.march_planes > 0)
     st = apply_columns(h, h->fwd, o.march_slots ? o.march_slots : 5, o.march_planes, stream);
-  if (st == REXI_OK && h->shifted && o.fallback) st = init_fallback(h, stream);
+  if (st == REXI_OK && h->shifted && o.fallback == 2) st = init_fallback(h, stream);
+  if (st == REXI_OK && h->shifted && o.fallback == 1) st = init_restart(h, stream);
   if (st != REXI_OK) {
     g_setup_error = h->err;
     destroy_handle(h);
@@ -1884,21 +2059,27 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
         const int K = h->SW.K;
         std::vector<double> res((size_t)K);
         std::vector<int32_t> its((size_t)K);
-        std::vector<SysState_t> sst((size_t)sv.S);
         HIPCHK(h, hipMemcpyAsync(res.data(), h->SW.res, K * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(h, hipMemcpyAsync(its.data(), h->SW.its, K * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HIPCHK(h, hipMemcpyAsync(sst.data(), sv.W.st, sv.S * sizeof(SysState_t), hipMemcpyDeviceToHost, st));
         HIPCHK(h, hipStreamSynchronize(st));
+        // the states of the first cycle (restart cycles reuse the system table)
+        if ((int)h->st0.size() != sv.S) {
+          h->st0.resize((size_t)sv.S);
+          HIPCHK(h, hipMemcpyAsync(h->st0.data(), sv.W.st, sv.S * sizeof(SysState_t), hipMemcpyDeviceToHost, st));
+          HIPCHK(h, hipStreamSynchronize(st));
+        }
+        const std::vector<SysState_t>& sst = h->st0;
         SysState_t s0 = sst[0];
         for (auto& x : sst) {
           its_total += x.its;
           s0.its = std::max(s0.its, x.its);
           s0.bnorm = std::max(s0.bnorm, x.bnorm);
         }
-        its_total += h->fb_its;
+        its_total += h->fb_its + h->rs_its;
+        const int more = h->fb_cycles + h->rs_cycles;
         if (n == nsteps - 1) {
           info->K = K;
-          info->max_cycles_used = 1 + h->fb_cycles;
+          info->max_cycles_used = 1 + more;
           info->not_converged = 0;
           info->max_rel_residual = 0.0;
           double bound = 0.0;
@@ -1907,7 +2088,7 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
             info->max_rel_residual = std::max(info->max_rel_residual, res[k]);
             bound += std::abs(h->w[k]) * res[k] / h->dist_sys[k];
             if (info->iterations) info->iterations[k] = its[k] > 0 ? its[k] : s0.its;
-            if (info->cycles) info->cycles[k] = its[k] > s0.its ? 1 + h->fb_cycles : 1;
+            if (info->cycles) info->cycles[k] = its[k] > s0.its ? 1 + more : 1;
             if (info->rel_residual) info->rel_residual[k] = res[k];
           }
           info->certified_bound = bound;

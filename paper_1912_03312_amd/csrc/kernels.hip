@@ -170,6 +170,11 @@ __device__ __forceinline__ int find_sys(const int32_t* tile_start, int S, int it
   return lo;
 }
 
+// System of work item `item` of W: a table lookup, else the search.
+__device__ __forceinline__ int item_sys(const Work& W, int item) {
+  return W.tile_sys ? W.tile_sys[item] : find_sys(W.tile_start, W.S, item);
+}
+
 template <typename T> __device__ __forceinline__ T* basis_vec(const Work& W, const SysDesc& d, int i) {
   return reinterpret_cast<T*>(W.basis) + d.basis + (int64_t)i * d.n;
 }
@@ -319,7 +324,7 @@ __global__ __launch_bounds__(TPB) void k_start(Work W, const double2* __restrict
                                                const double2* __restrict__ rhs1) {
   __shared__ double lds[NWAVE];
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
-    const int s = find_sys(W.tile_start, W.S, item);
+    const int s = item_sys(W, item);
     const SysDesc& d = W.sys[s];
     const int t = item - d.tile0;
     const double2* __restrict__ b = (d.rhs_sel ? rhs1 : rhs0) + d.off;
@@ -348,6 +353,8 @@ __global__ __launch_bounds__(TPB) void k_start_reduce(Work W) {
   if (s == 0) {
     const int nc = W.max_cycles * (W.m + 1) + 2;
     for (int i = threadIdx.x; i < nc; i += TPB) W.counters[i] = 0;
+    if (W.reo_any)
+      for (int i = threadIdx.x; i <= W.m; i += TPB) W.reo_any[i] = 0;
   }
   double acc = strided_sum(W.pnorm + d.tile0, d.ntiles);
   acc = block_sum(acc, lds);
@@ -408,6 +415,21 @@ struct ShiftWork {
   const int32_t* col_start;  // [S+1] prefix of column-marching items (null: unused)
   int32_t col_total;
   int32_t fb_skip;    // 1: poles that missed their target (its = 0) are left out of z
+  // Restarts on the shared basis. fom = 1: a pole that missed its target takes
+  // the Galerkin iterate of the basis, whose residual is gnext_p u_k (u_k the
+  // stored basis vector k): the residuals of all such poles of an instance
+  // are multiples of one vector, the next cycle's right-hand side.
+  int32_t fom;
+  double* gnext;      // [K] complex: gnext_p = -y_{p,k-1} of the Galerkin iterate
+  // restart = 1 (a restart cycle): only poles with miss[p] take part, with
+  // right-hand side gam_p b (b the cycle's right-hand side); w, tol, its and
+  // res above point to the cycle's own arrays, filled from these at its start
+  int32_t restart;
+  const int32_t* miss;  // [K]
+  const double* gam;    // [K] complex
+  const double* w0;     // [K] complex weights of the step
+  const double* tol0;   // [K] targets relative to ||psi|| of the step
+  const double* bn0;    // [S] ||psi|| per instance
 };
 
 // Grid (S, j + 2): block (s, i) with lo <= i <= j reduces the tile partials
@@ -420,6 +442,7 @@ __global__ __launch_bounds__(TPB) void k_reduce_dots(Work W, int j, int second, 
   const int s = blockIdx.x;
   const int i = blockIdx.y;
   if (s >= W.S || i > j + 1) return;
+  if (second && W.reo_any && !W.reo_any[j]) return;
   SysState_t& st = W.st[s];
   if (st.state != ST_ACTIVE) return;
   if (second && !st.reorth) return;
@@ -466,9 +489,10 @@ __global__ __launch_bounds__(TPB) void k_reduce_dots(Work W, int j, int second, 
 template <typename T, int PPT, bool MATVEC>
 __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0) {
   __shared__ double2 red[NWAVE][MAXM + 1];
+  if (!MATVEC && W.reo_any && !W.reo_any[j]) return;  // no second pass at iteration j
   const int lo = MATVEC ? i0 : 0;
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
-    const int s = find_sys(W.tile_start, W.S, item);
+    const int s = item_sys(W, item);
     const SysState_t& st = W.st[s];
     if (st.state != ST_ACTIVE) continue;
     if (!MATVEC && !st.reorth) continue;
@@ -788,8 +812,9 @@ template <typename T, int PPT>
 __global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second, int i0) {
   __shared__ double lds[NWAVE];
   __shared__ double2 coef[MAXM];
+  if (second && W.reo_any && !W.reo_any[j]) return;
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
-    const int s = find_sys(W.tile_start, W.S, item);
+    const int s = item_sys(W, item);
     const SysState_t& st = W.st[s];
     if (st.state != ST_ACTIVE) continue;
     if (second && !st.reorth) continue;
@@ -811,7 +836,9 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second, in
       hs = 0.0;
       for (int i = lo; i <= j; ++i) hs += hc[i].x * hc[i].x + hc[i].y * hc[i].y;
       const double w2 = st.w2;
-      W.st[s].reorth = (W.reorth_mode == 2) || (W.reorth_mode == 1 && !(w2 - hs >= W.eta2 * w2));
+      const bool reo = (W.reorth_mode == 2) || (W.reorth_mode == 1 && !(w2 - hs >= W.eta2 * w2));
+      W.st[s].reorth = reo ? 1 : 0;
+      if (reo && W.reo_any) W.reo_any[j] = 1;
     }
     T* __restrict__ unew = basis_vec<T>(W, d, j + 1);
     double2 w[PPT];
@@ -859,6 +886,7 @@ __global__ __launch_bounds__(TPB) void k_end_iter(Work W, ShiftWork SW, int j, i
   __shared__ int reo_sh;
   const int s = blockIdx.x;
   if (s >= W.S) return;
+  if (second && W.reo_any && !W.reo_any[j]) return;
   SysState_t& st = W.st[s];
   if (st.state != ST_ACTIVE) return;
   if (second && !st.reorth) return;
@@ -871,6 +899,7 @@ __global__ __launch_bounds__(TPB) void k_end_iter(Work W, ShiftWork SW, int j, i
     const bool reo = pro_decide(W, SW, s, j, beta);
     if (threadIdx.x == 0) {
       st.reorth = reo ? 1 : 0;
+      if (reo && W.reo_any) W.reo_any[j] = 1;
       reo_sh = reo ? 1 : 0;
       if (reo && SW.pause_mode) {
         // hand the second pass to the host: later launches of this chunk skip
@@ -907,8 +936,9 @@ __global__ __launch_bounds__(TPB) void k_end_iter(Work W, ShiftWork SW, int j, i
 template <int PPT>
 __global__ __launch_bounds__(TPB) void k_lz_matvec(Work W, ShiftWork SW, int i, int zsel, int after_reorth) {
   __shared__ double lds[NWAVE];
+  if (after_reorth && W.reo_any && !W.reo_any[i - 1]) return;  // no second pass at iteration i - 1
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
-    const int s = find_sys(W.tile_start, W.S, item);
+    const int s = item_sys(W, item);
     const SysState_t& st = W.st[s];
     if (st.state != ST_ACTIVE) continue;
     if (after_reorth && !st.reorth) continue;
@@ -959,7 +989,7 @@ __global__ __launch_bounds__(TPB) void k_lz_step(Work W, ShiftWork SW, int j) {
   __shared__ double lds[NWAVE];
   const int m = W.m;
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
-    const int s = find_sys(W.tile_start, W.S, item);
+    const int s = item_sys(W, item);
     const SysState_t& st = W.st[s];
     if (st.state != ST_ACTIVE) continue;
     const SysDesc& d = W.sys[s];
@@ -1043,7 +1073,7 @@ __global__ __launch_bounds__(TPB) void k_lz_step_lds(Work W, ShiftWork SW, int j
   __shared__ double2 ub[TPB * PPT + 2 * HMAX];
   const int m = W.m;
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
-    const int s = find_sys(W.tile_start, W.S, item);
+    const int s = item_sys(W, item);
     const SysState_t& st = W.st[s];
     if (st.state != ST_ACTIVE) continue;
     const SysDesc& d = W.sys[s];
@@ -1469,6 +1499,7 @@ __device__ void lz_end_body(Work& W, ShiftWork& SW, int s, int j, int colparts) 
       SW.flags[4 * s + 1] += 1;
     }
     st.reorth = reo ? 1 : 0;
+    if (reo && W.reo_any) W.reo_any[j] = 1;
     if (reo && SW.pause_mode) {
       st.state = ST_PAUSED;
       SW.flags[4 * s + 2] = j;
@@ -1569,6 +1600,7 @@ __global__ __launch_bounds__(TPB) void k_lz_end_second(Work W, ShiftWork SW, int
   __shared__ double lds[NWAVE];
   const int s = blockIdx.x;
   if (s >= W.S) return;
+  if (W.reo_any && !W.reo_any[j]) return;
   SysState_t& st = W.st[s];
   if (st.state != ST_ACTIVE || !st.reorth) return;
   const SysDesc& d = W.sys[s];
@@ -1600,6 +1632,18 @@ __global__ __launch_bounds__(TPB) void k_shifted_backsub(Work W, ShiftWork SW) {
   double2* y = reinterpret_cast<double2*>(SW.y) + (int64_t)p * m;
   int anyfull = 0;
   for (int q = lane; q < k; q += 64) anyfull |= full[q];
+  // Galerkin (FOM) iterate of a pole that missed its target: the square
+  // system (H_k - s_p I) y = ||b|| e_1 has the same rotations 0..k-2 as the
+  // least-squares one; its last pivot is c_{k-1} R_{k-1,k-1} and the last
+  // right-hand side entry g_{k-1} / conj(c_{k-1}), so y_{k-1} is the
+  // least-squares one divided by |c_{k-1}|^2 and the rest follows by the same
+  // back substitution
+  const bool fom = SW.fom && k > 0 && SW.its[p] == 0;
+  double lastscale = 1.0;
+  if (fom) {
+    const double2 c = reinterpret_cast<const double2*>(SW.gc)[(int64_t)p * m + k - 1];
+    lastscale = c.x * c.x + c.y * c.y;
+  }
   if (!__any(anyfull)) {
     // no second pass: R has three diagonals, y_r = (g_r - R_{r,r+1} y_{r+1}
     // - R_{r,r+2} y_{r+2}) / R_rr. The wave stages the band and g in LDS,
@@ -1607,6 +1651,7 @@ __global__ __launch_bounds__(TPB) void k_shifted_backsub(Work W, ShiftWork SW) {
     double2(*bd)[MAXM] = band[wid];
     for (int r = lane; r < k; r += 64) {
       bd[0][r] = Rp[(int64_t)r * (m + 1) + r];
+      if (r == k - 1) bd[0][r] = make_double2(bd[0][r].x * lastscale, bd[0][r].y * lastscale);
       bd[1][r] = r + 1 < k ? Rp[(int64_t)(r + 1) * (m + 1) + r] : make_double2(0.0, 0.0);
       bd[2][r] = r + 2 < k ? Rp[(int64_t)(r + 2) * (m + 1) + r] : make_double2(0.0, 0.0);
       bd[3][r] = g[r];
@@ -1624,6 +1669,7 @@ __global__ __launch_bounds__(TPB) void k_shifted_backsub(Work W, ShiftWork SW) {
         const double2 yr = dn > 0.0 ? make_double2((acc.x * dd.x + acc.y * dd.y) / dn, (acc.y * dd.x - acc.x * dd.y) / dn)
                                     : make_double2(0.0, 0.0);
         y[r] = yr;
+        if (fom && r == k - 1) reinterpret_cast<double2*>(SW.gnext)[p] = make_double2(-yr.x, -yr.y);
         y2 = y1;
         y1 = yr;
       }
@@ -1643,10 +1689,12 @@ __global__ __launch_bounds__(TPB) void k_shifted_backsub(Work W, ShiftWork SW) {
     ay = wave_sum(ay);
     if (lane == 0) {
       const double2 acc = make_double2(g[r].x - ax, g[r].y - ay);
-      const double2 dd = Rp[(int64_t)r * (m + 1) + r];
+      double2 dd = Rp[(int64_t)r * (m + 1) + r];
+      if (r == k - 1) dd = make_double2(dd.x * lastscale, dd.y * lastscale);
       const double dn = dd.x * dd.x + dd.y * dd.y;
       y[r] = dn > 0.0 ? make_double2((acc.x * dd.x + acc.y * dd.y) / dn, (acc.y * dd.x - acc.x * dd.y) / dn)
                       : make_double2(0.0, 0.0);
+      if (fom && r == k - 1) reinterpret_cast<double2*>(SW.gnext)[p] = make_double2(-y[r].x, -y[r].y);
     }
     __threadfence_block();
   }
@@ -1696,8 +1744,107 @@ __global__ __launch_bounds__(TPB) void k_shifted_init(Work W, ShiftWork SW) {
     double2* g = reinterpret_cast<double2*>(SW.g) + (int64_t)p * (W.m + 1);
     for (int i = 0; i <= W.m; ++i) g[i] = make_double2(0.0, 0.0);
     g[0] = make_double2(bn, 0.0);
-    SW.its[p] = bn > 0.0 ? 0 : 1;
-    SW.res[p] = bn > 0.0 ? 1.0 : 0.0;
+    bool on = bn > 0.0;
+    if (SW.restart) {
+      // pole p solves (H - s_p) x = gam_p b: weight w_p gam_p; its target
+      // tol_p ||psi|| / |gam_p| in the norm of b
+      on = on && SW.miss[p] != 0;
+      const double2 ga = reinterpret_cast<const double2*>(SW.gam)[p];
+      const double2 w0 = reinterpret_cast<const double2*>(SW.w0)[p];
+      const double ag = sqrt(ga.x * ga.x + ga.y * ga.y);
+      reinterpret_cast<double2*>(const_cast<double*>(SW.w))[p] =
+          on ? make_double2(w0.x * ga.x - w0.y * ga.y, w0.x * ga.y + w0.y * ga.x) : make_double2(0.0, 0.0);
+      const_cast<double*>(SW.tol)[p] = on && ag > 0.0 ? SW.tol0[p] * SW.bn0[s] / (ag * bn) : 1.0;
+    }
+    SW.its[p] = on ? 0 : 1;
+    SW.res[p] = on ? 1.0 : 0.0;
+  }
+}
+
+// ------------------------------------------------------------ restart cycles
+// Grid S, after the first cycle of a step (fom = 1): the poles that missed
+// their target (residual gnext_p u_k) start the restarts with gam_p = gnext_p;
+// their residual is reported as that of the Galerkin iterate. ||psi|| and
+// the iterations so far are kept per instance.
+__global__ __launch_bounds__(TPB) void k_rs_begin(Work W, ShiftWork SW, int32_t* __restrict__ miss,
+                                                  double* __restrict__ gam, double* __restrict__ bn0,
+                                                  int32_t* __restrict__ kbase, int32_t* __restrict__ hasmiss) {
+  const int s = blockIdx.x;
+  if (s >= W.S) return;
+  const SysState_t& st = W.st[s];
+  const int k = st.kcyc;
+  const double bn = st.bnorm;
+  const double ck = k > 0 ? W.cscale[(int64_t)s * (W.m + 1) + k] : 0.0;
+  const double bk = ck > 0.0 ? 1.0 / ck : 0.0;  // ||u_k||
+  int any = 0;
+  for (int p = SW.pole0[s] + threadIdx.x; p < SW.pole0[s + 1]; p += TPB) {
+    const bool ms = SW.its[p] == 0 && bn > 0.0 && k > 0;
+    const double2 gn = ms ? reinterpret_cast<const double2*>(SW.gnext)[p] : make_double2(0.0, 0.0);
+    miss[p] = ms ? 1 : 0;
+    reinterpret_cast<double2*>(gam)[p] = gn;
+    if (ms) SW.res[p] = sqrt(gn.x * gn.x + gn.y * gn.y) * bk / bn;
+    any |= ms ? 1 : 0;
+  }
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) {
+    bn0[s] = bn;
+    kbase[s] = k;
+    hasmiss[s] = any;
+  }
+}
+
+// Grid S, after restart cycle R (the cycle's arrays) of a step whose arrays
+// are SW: a pole of the cycle that met its target reports its iterations
+// and residual gam_p |g| in the norm of psi; one that missed again carries
+// gam_p gnext_p into the next cycle.
+__global__ __launch_bounds__(TPB) void k_rs_merge(Work W, ShiftWork SW, ShiftWork R, int32_t* __restrict__ miss,
+                                                  double* __restrict__ gam, const double* __restrict__ bn0,
+                                                  int32_t* __restrict__ kbase, int32_t* __restrict__ hasmiss) {
+  const int s = blockIdx.x;
+  if (s >= W.S) return;
+  const SysState_t& st = W.st[s];
+  const int k = st.kcyc;
+  const double bn = st.bnorm;
+  const double ck = k > 0 ? W.cscale[(int64_t)s * (W.m + 1) + k] : 0.0;
+  const double bk = ck > 0.0 ? 1.0 / ck : 0.0;
+  const double b0 = bn0[s];
+  const int kb = kbase[s];
+  int any = 0;
+  for (int p = SW.pole0[s] + threadIdx.x; p < SW.pole0[s + 1]; p += TPB) {
+    if (!miss[p]) continue;
+    double2 ga = reinterpret_cast<const double2*>(gam)[p];
+    if (R.its[p] > 0) {
+      SW.its[p] = kb + R.its[p];
+      SW.res[p] = sqrt(ga.x * ga.x + ga.y * ga.y) * R.res[p] * bn / b0;
+      miss[p] = 0;
+    } else {
+      const double2 gn = reinterpret_cast<const double2*>(R.gnext)[p];
+      ga = make_double2(ga.x * gn.x - ga.y * gn.y, ga.x * gn.y + ga.y * gn.x);
+      reinterpret_cast<double2*>(gam)[p] = ga;
+      SW.res[p] = sqrt(ga.x * ga.x + ga.y * ga.y) * bk / b0;
+      any = 1;
+    }
+  }
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) {
+    kbase[s] = kb + k;
+    hasmiss[s] = any;
+  }
+}
+
+// The next cycle's right-hand side: u_k of every instance that still has
+// poles to finish, zero elsewhere (such instances finish at once).
+__global__ __launch_bounds__(TPB) void k_rs_rhs(Work W, const int32_t* __restrict__ hasmiss,
+                                                double2* __restrict__ rhs) {
+  for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
+    const int s = item_sys(W, item);
+    const SysDesc& d = W.sys[s];
+    const int t = item - d.tile0;
+    const bool on = hasmiss[s] != 0;
+    const double2* __restrict__ u = basis_vec<double2>(W, d, on ? W.st[s].kcyc : 0);
+    double2* __restrict__ r = rhs + d.off;
+    const int pend = min((t + 1) * W.tile, d.n);
+    for (int p = t * W.tile + (int)threadIdx.x; p < pend; p += TPB) r[p] = on ? u[p] : make_double2(0.0, 0.0);
   }
 }
 
@@ -1707,7 +1854,7 @@ template <typename T, int PPT>
 __global__ __launch_bounds__(TPB) void k_update_x(Work W) {
   __shared__ double2 coef[MAXM];
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
-    const int s = find_sys(W.tile_start, W.S, item);
+    const int s = item_sys(W, item);
     const SysState_t& st = W.st[s];
     if (st.state != ST_FINISH) continue;
     const SysDesc& d = W.sys[s];
@@ -1754,7 +1901,7 @@ __global__ __launch_bounds__(TPB) void k_residual(Work W, const double2* __restr
                                                   const double2* __restrict__ rhs1) {
   __shared__ double lds[NWAVE];
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
-    const int s = find_sys(W.tile_start, W.S, item);
+    const int s = item_sys(W, item);
     const SysState_t& st = W.st[s];
     if (st.state != ST_FINISH) continue;
     const SysDesc& d = W.sys[s];
@@ -1818,11 +1965,11 @@ __global__ __launch_bounds__(TPB) void k_restart(Work W, int cycle) {
 
 // out = sum_{i<k} z_i c_i u_i in FP64, per instance (system) of W.
 template <typename T, int PPT>
-__global__ __launch_bounds__(TPB) void k_combine_out(Work W, ShiftWork SW, double2* __restrict__ out) {
+__global__ __launch_bounds__(TPB) void k_combine_out(Work W, ShiftWork SW, double2* __restrict__ out, int accumulate) {
   __shared__ double2 coef[MAXM];
   int sprev = -1;
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
-    const int s = find_sys(W.tile_start, W.S, item);
+    const int s = item_sys(W, item);
     const SysDesc& d = W.sys[s];
     const int k = W.st[s].kcyc;
     if (s != sprev) {
@@ -1881,6 +2028,16 @@ __global__ __launch_bounds__(TPB) void k_combine_out(Work W, ShiftWork SW, doubl
           acc[q].y += c.x * v.y + c.y * v.x;
         }
       }
+    }
+    if (accumulate) {
+      // a restart cycle adds to the sums of the earlier cycles
+#pragma unroll
+      for (int q = 0; q < PPT; ++q)
+        if (in[q]) {
+          const double2 o = out[off + p0 + q * TPB];
+          acc[q].x += o.x;
+          acc[q].y += o.y;
+        }
     }
 #pragma unroll
     for (int q = 0; q < PPT; ++q)

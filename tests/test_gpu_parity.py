@@ -665,13 +665,15 @@ def test_tunnel_full_run_against_exact_propagator(rexi):
 
 
 # ---------------------------------------------------------------- fallback
-@pytest.mark.parametrize("name,scale,m,fallback", [("3d_bumps", 12, 6, 1), ("3d_bumps", 12, 6, 0),
-                                                   ("2d_double_well", 40, 60, 1)])
+@pytest.mark.parametrize("name,scale,m,fallback", [("3d_bumps", 12, 6, 1), ("3d_bumps", 12, 6, 2),
+                                                   ("3d_bumps", 12, 6, 0), ("2d_double_well", 40, 60, 1),
+                                                   ("2d_double_well", 40, 60, 2)])
 def test_shifted_fallback_finishes_missed_poles(rexi, name, scale, m, fallback):
-    # a shared basis of m vectors is too short for these poles: with the
-    # fallback, per-pole solves warm-started from the shared iterate finish
-    # them (to the oracle's bar, or the certificate for the double well);
-    # without it they are reported in not_converged
+    # a shared basis of m vectors is too short for these poles: restarts on
+    # the shared basis (fallback 1) or per-pole solves warm-started from the
+    # shared iterate (fallback 2) finish them (to the oracle's bar, or the
+    # certificate for the double well); without (0) they are reported in
+    # not_converged
     import torch
     from paper_1912_03312_amd import rexi as r
     wl = inputs.workload(name, scale=scale)
@@ -709,7 +711,8 @@ def test_shifted_fallback_finishes_missed_poles(rexi, name, scale, m, fallback):
         assert errs[1] <= errs[0] * (1 + 1e-3) + infos[1]["certified_bound"] + 3 * floor
 
 
-def test_shifted_fallback_in_place_steps(rexi):
+@pytest.mark.parametrize("fallback", [1, 2])
+def test_shifted_fallback_in_place_steps(rexi, fallback):
     # in place (psi_out = psi_in), the shared-basis sum overwrites psi before
     # the per-pole solves of the missed poles read it: they must read a copy;
     # two in-place steps on a fresh handle (a handle carries its Krylov-length
@@ -722,7 +725,7 @@ def test_shifted_fallback_in_place_steps(rexi):
 
     def handle():
         return r.setup(g.n, g.lo, g.hi, to_dev(wl.V.ravel()), 1.0, 1.0, wl.dt, s, b, solver="shifted", m=6,
-                       tol=1e-11, tol_policy="certified", max_cycles=200)
+                       tol=1e-11, tol_policy="certified", max_cycles=200, fallback=fallback)
 
     a = to_dev(wl.psi0.ravel())
     o1 = torch.empty_like(a)
@@ -742,7 +745,8 @@ def test_shifted_fallback_in_place_steps(rexi):
     assert torch.equal(x, o2)
 
 
-def test_shifted_fallback_independent_of_stale_memory(rexi):
+@pytest.mark.parametrize("fallback", [1, 2])
+def test_shifted_fallback_independent_of_stale_memory(rexi, fallback):
     # the warm start of the per-pole solves covers every point of their tiles
     # (which differ from the shared solver's): a fresh handle placed on memory
     # that held NaNs repeats the first handle's step bit for bit, iteration
@@ -755,7 +759,7 @@ def test_shifted_fallback_independent_of_stale_memory(rexi):
 
     def one_step():
         h = r.setup(g.n, g.lo, g.hi, to_dev(wl.V.ravel()), 1.0, 1.0, wl.dt, s, b, solver="shifted", m=6,
-                    tol=1e-11, tol_policy="certified", max_cycles=200)
+                    tol=1e-11, tol_policy="certified", max_cycles=200, fallback=fallback)
         o = torch.empty(g.size, dtype=torch.complex128, device="cuda")
         info = h.step(to_dev(wl.psi0.ravel()), o, 1)
         torch.cuda.synchronize()
