@@ -296,10 +296,11 @@ constexpr int TPB_ = rexi::TPB;
 // Column-marching Lanczos pass: kh slots per thread cover a band of rows of
 // the (i1, i2) plane and one halo row on each side; an item spans L planes.
 // Fills the descriptors and the item prefix; false (nothing changed) if a
-// system's rows do not fit or its items outnumber its partial-sum slots.
+// system's rows do not fit or its six partial-sum slots (two parities of
+// three, max(ntiles, items) entries each) exceed its partial-sum block of
+// (m + 1) ntiles entries.
 bool plan_columns(Solver& sv, int kh, int L) {
   struct Plan { int rows, Lc, nr, n; };
-  if (sv.m < 5) return false;  // two parities of three partial-sum slots
   std::vector<Plan> pl;
   for (auto& d : sv.hsys) {
     const int rows = std::min(d.n1, TPB_ * kh / d.n2 - 2);
@@ -307,8 +308,9 @@ bool plan_columns(Solver& sv, int kh, int L) {
     const int nb = (d.n1 + rows - 1) / rows;
     const int Lc = std::min(L, d.n0);
     const int nr = (d.n0 + Lc - 1) / Lc;
-    if ((int64_t)nb * nr > d.ntiles) return false;
-    pl.push_back({rows, Lc, nr, nb * nr});
+    const int64_t items = (int64_t)nb * nr;
+    if (6 * std::max<int64_t>(d.ntiles, items) > (int64_t)(sv.m + 1) * d.ntiles) return false;
+    pl.push_back({rows, Lc, nr, (int)items});
   }
   sv.hcol.clear();
   int total = 0;
@@ -318,6 +320,7 @@ bool plan_columns(Solver& sv, int kh, int L) {
     d.col_L = pl[i].Lc;
     d.col_nr = pl[i].nr;
     d.col_n = pl[i].n;
+    d.col_cs = std::max(d.ntiles, pl[i].n);
     sv.hcol.push_back(total);
     total += pl[i].n;
   }
@@ -968,6 +971,7 @@ void launch_lz_step(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork
 // SWp: the shared-basis data whose column plan they set (null: the handle's).
 rexi_status apply_tiling(rexi_handle* h, Solver& sv, int ppt, int grid, hipStream_t stream,
                          rexi::ShiftWork* SWp = nullptr);
+void set_row_planes(rexi_handle* h, Solver& sv, bool on);
 rexi_status apply_columns(rexi_handle* h, Solver& sv, int kh, int L, hipStream_t stream,
                           rexi::ShiftWork* SWp = nullptr);
 
@@ -1470,6 +1474,7 @@ rexi_status apply_tiling(rexi_handle* h, Solver& sv, int ppt, int grid, hipStrea
                          rexi::ShiftWork* SWp) {
   sv.ppt = ppt;
   sv.tile = TPB * ppt;
+  if (h->shifted) set_row_planes(h, sv, false);  // the column plan is dropped below
   layout_systems(sv, sv.m);
   sv.grid = grid;
   sv.W.total_tiles = sv.total_tiles;
@@ -1491,13 +1496,39 @@ rexi_status apply_tiling(rexi_handle* h, Solver& sv, int ppt, int grid, hipStrea
 // Select the fused Lanczos pass: kh = 0 the row-staged pass, else the
 // marching pass with kh slots and L planes per item. REXI_OK with the
 // row-staged pass when the plan does not fit.
+// Geometry of the shared-basis systems: as the instance describes it, or,
+// for the marching pass, a 2D instance (1, ny, nx) relabelled (ny, nx, 1) —
+// the same C-order layout, so only the roles change: the pass marches over
+// rows (its "planes"), a row being formed once and the in-row neighbours
+// coming from LDS. The stencil sums are the same, term for term.
+void set_row_planes(rexi_handle* h, Solver& sv, bool on) {
+  for (auto& d : sv.hsys) {
+    const InstDesc& in = h->hinst[d.inst];
+    const bool rp = on && in.n0 == 1 && in.n1 > 1 && in.n2 > 1 && !in.fem;
+    d.n0 = rp ? in.n1 : in.n0;
+    d.n1 = rp ? in.n2 : in.n1;
+    d.n2 = rp ? 1 : in.n2;
+    d.d1 = rp ? rexi::make_fastdiv((uint32_t)in.n2) : in.d1;
+    d.d2 = rp ? rexi::make_fastdiv(1u) : in.d2;
+    d.c0 = rp ? in.c1 : in.c0;
+    d.c1 = rp ? in.c2 : in.c1;
+    d.c2 = rp ? 0.0 : in.c2;
+  }
+}
+
 rexi_status apply_columns(rexi_handle* h, Solver& sv, int kh, int L, hipStream_t stream,
                           rexi::ShiftWork* SWp) {
   rexi::ShiftWork& SW = SWp ? *SWp : h->SW;
   sv.col_kh = 0;
   SW.col_start = nullptr;
   SW.col_total = 0;
-  if (kh == 0 || !plan_columns(sv, kh, L)) return REXI_OK;
+  set_row_planes(h, sv, kh != 0);
+  if (kh == 0 || !plan_columns(sv, kh, L)) {
+    set_row_planes(h, sv, false);
+    HIPCHK(h, hipMemcpyAsync(sv.dsys, sv.hsys.data(), sv.S * sizeof(SysDesc), hipMemcpyHostToDevice, stream));
+    HIPCHK(h, hipStreamSynchronize(stream));
+    return REXI_OK;
+  }
   HIPCHK(h, hipMemcpyAsync(sv.dsys, sv.hsys.data(), sv.S * sizeof(SysDesc), hipMemcpyHostToDevice, stream));
   HIPCHK(h, hipMemcpyAsync(sv.dcol, sv.hcol.data(), (sv.S + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
   HIPCHK(h, hipStreamSynchronize(stream));

@@ -1166,7 +1166,7 @@ __global__ __launch_bounds__(TPB) void k_lz_step_lds(Work W, ShiftWork SW, int j
 // round-robin over the 8 dies) and the halo rows they share hit its L2.
 // Partial sums of the marching pass for iteration j, per item t, at parity
 // j & 1: <u_{j+1}, z_{j+1}>, <u_j, u_{j+1}>, (||u_{j+1}||^2, 0) in three
-// slots of ntiles entries from pbase + 3 (j & 1) ntiles (the fused pass of
+// slots of col_cs entries from pbase + 3 (j & 1) col_cs (the fused pass of
 // iteration j + 1 reads parity j while it writes parity j + 1).
 __device__ __forceinline__ void lz_col_partials(const Work& W, int pbase, int ntiles, int np, int j, double& nn,
                                                 double& uz, double& oux, double& ouy, double* l4) {
@@ -1208,7 +1208,7 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
     const int n0 = dref.n0, n1 = dref.n1, n2 = dref.n2;
     const FastDiv d2 = dref.d2;
     const double c0 = dref.c0, c1 = dref.c1, c2 = dref.c2, diag = dref.diag;
-    const int ntiles = dref.ntiles, tile0 = dref.tile0, pbase = dref.pbase;
+    const int cs = dref.col_cs, pbase = dref.pbase;  // partial-sum slot stride
     const int col_nr = dref.col_nr, col_rows = dref.col_rows, col_L = dref.col_L;
     const int64_t xoff = dref.xoff, voff = dref.off, bas = dref.basis;
     const int npts = dref.n;
@@ -1224,7 +1224,7 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
     double cj, ka, kb;
     if (FUSED) {
       double nn, uz, ox, oy;
-      lz_col_partials(W, pbase, ntiles, dref.col_n, j - 1, nn, uz, ox, oy, l4);
+      lz_col_partials(W, pbase, cs, dref.col_n, j - 1, nn, uz, ox, oy, l4);
       const double bj = sqrt(nn);
       cj = bj > 0.0 ? 1.0 / bj : 0.0;
       ka = cj * cj * uz * cj;
@@ -1376,10 +1376,10 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
     ouy = block_sum(ouy, lds);
     nn = block_sum(nn, lds);
     if (threadIdx.x == 0) {
-      double2* part = reinterpret_cast<double2*>(W.part) + pbase + 3 * (j & 1) * ntiles;
+      double2* part = reinterpret_cast<double2*>(W.part) + pbase + 3 * (j & 1) * cs;
       part[t] = make_double2(uzx, uzy);
-      part[ntiles + t] = make_double2(oux, ouy);
-      part[2 * ntiles + t] = make_double2(nn, 0.0);
+      part[cs + t] = make_double2(oux, ouy);
+      part[2 * cs + t] = make_double2(nn, 0.0);
     }
   }
 }
@@ -1461,7 +1461,7 @@ __device__ void lz_end_body(Work& W, ShiftWork& SW, int s, int j, int colparts) 
   // partial sums; then max_{k<j} |alpha_k| + beta_k + beta_{k+1} (the k = j
   // term needs beta_{j+1})
   if (colparts)
-    lz_col_partials(W, pbase, ntiles, np, j, nn, uz, oux, ouy, l4);
+    lz_col_partials(W, pbase, d.col_cs, np, j, nn, uz, oux, ouy, l4);
   else
     block_sum4(nn, uz, oux, ouy, l4);
   const double beta1 = sqrt(nn);

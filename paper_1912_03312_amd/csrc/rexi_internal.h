@@ -61,6 +61,7 @@ struct SysDesc {
   int32_t col_L;
   int32_t col_nr;
   int32_t col_n;     // items of the system (col_n = ceil(n1/col_rows) col_nr)
+  int32_t col_cs;    // stride of its partial-sum slots, max(ntiles, col_n)
   int32_t pole;      // fallback solves: the pole (index into s, w) of the system
   int32_t fem;       // 1: Q1 finite elements, the system is (A - s M) x = M psi
   // Q1 elements, per padded axis: 1D mass diagonal / off-diagonal, stiffness

@@ -452,11 +452,13 @@ def test_step_inside_caller_graph_capture(rexi):
 
 
 # ---------------------------------------------------------------- uneven batch
-@pytest.mark.parametrize("solver,prec", [("shifted", "c128"), ("shifted_m24", "c128"), ("per_pole", "c128"),
-                                         ("per_pole", "c64")])
+@pytest.mark.parametrize("solver,prec", [("shifted", "c128"), ("shifted_m24", "c128"), ("shifted_march", "c128"),
+                                         ("shifted_m24_march", "c128"), ("per_pole", "c128"), ("per_pole", "c64")])
 def test_uneven_batch_matches_oracle_per_instance(rexi, solver, prec):
     # shifted_m24: a shared basis of 24 vectors is too short for the larger
-    # instances; per-pole solves warm-started from it finish those poles
+    # instances; restart cycles on the shared basis finish those poles.
+    # _march: the marching pass over rows (2D instances relabelled so a row
+    # is a plane), ranges of 4 rows, more items than tiles on most instances
     import torch
     from paper_1912_03312_amd import rexi as r
     insts = inputs.batch_instances(count=6, sides=(12, 17, 24, 31, 40, 47))
@@ -473,10 +475,13 @@ def test_uneven_batch_matches_oracle_per_instance(rexi, solver, prec):
         bet.append(b)
     cnt = len(insts)
     tol = dict(tol=1e-11, tol_policy="certified") if prec == "c128" else dict(tol=1e-8, tol_policy="certified")
-    m = {"shifted": 256, "shifted_m24": 24}.get(solver, 30)
+    m = 24 if "_m24" in solver else (256 if solver.startswith("shifted") else 30)
+    march = dict(march_planes=4, march_slots=3) if solver.endswith("_march") else {}
     h = r.setup_batch(grids, to_dev(np.concatenate(Vs)), [1.0] * cnt, [1.0] * cnt, dts, Ks,
-                      np.concatenate(sig), np.concatenate(bet), solver=solver.split("_m")[0], precision=prec,
-                      m=m, max_cycles=200, **tol)
+                      np.concatenate(sig), np.concatenate(bet), solver=solver.split("_")[0].replace("per", "per_pole"),
+                      precision=prec, m=m, max_cycles=200, **tol, **march)
+    if march:
+        assert h.tiling()["march_slots"] == 3
     p0 = to_dev(np.concatenate(psis))
     out = torch.empty_like(p0)
     info = h.step(p0, out, 1)
@@ -788,7 +793,9 @@ def _centred_grid(shape, h=0.25):
     ((7, 23, 60), 4, 3, True),    # bands of 10 rows (10 + 10 + 3), plane ranges 4 + 3
     ((9, 13, 17), 4, 5, True),    # one band of 13 rows, ranges 4 + 4 + 1
     ((4, 40, 100), 16, 8, True),  # bands 18 + 18 + 4, one range shorter than the item
-    ((37, 41), 8, 5, True),       # 2D: one plane, bands 29 + 8
+    ((37, 41), 8, 5, True),       # 2D, rows as planes: ranges 8 x 4 + 5, more items than tiles
+    ((100, 130), 16, 3, True),    # 2D: ranges 16 x 6 + 4
+    ((20, 800), 4, 3, True),      # 2D: a row longer than the slots, in bands of 766 + 34 points
     ((300,), 4, 5, True),         # 1D: one row
     ((1000,), 4, 3, False),       # a row longer than the slots: row-staged pass
 ])
