@@ -131,6 +131,7 @@ def bench_batch(args):
     ms = (time.perf_counter() - t1) * 1e3 / args.steps
     info = h.step(cur, out, 1, info=True, raise_on_nc=False)
     ws, m_used = h.workspace()
+    tiling = h.tiling()
     h.close()
     npts = int(sum(int(np.prod(g[0])) for g in grids))
     res = {
@@ -141,7 +142,7 @@ def bench_batch(args):
         "config": {"workload": f"{cnt} 2D instances, sides 64..512 on [-10,10]^2, 20 bumps each, "
                                f"dt U(0.2,1), K in {{16,24,32,48}}, {args.solver} solver, tol {args.tol:g}",
                    "instances": cnt, "points": npts, "poles": int(sum(Ks)), "solver": args.solver,
-                   "graph_replay": bool(args.capture)},
+                   "graph_replay": bool(args.capture), "tiling": tiling},
         "solve": {"iterations_per_step": int(info["total_iterations"]), "not_converged": int(info["not_converged"]),
                   "max_cycles": int(info["max_cycles_used"]), "max_rel_residual": info["max_rel_residual"],
                   "certified_rel_error_bound": info["certified_bound"], "workspace_GB": round(ws / 1e9, 2),

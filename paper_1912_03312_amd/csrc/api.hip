@@ -683,6 +683,9 @@ rexi_status init_shifted(rexi_handle* h, Solver& sv, rexi::ShiftWork& SW, bool c
       (st = al(&omega, (size_t)S * 2 * (m + 1) * d8)) || (st = al(&flags, (size_t)S * 4 * i4)) ||
       (st = al(&full, (size_t)S * m * i4)) || (st = al(&reo, (size_t)(m + 1) * i4)))
     return st;
+  void* gp = nullptr;
+  if ((st = al(&gp, i4))) return st;
+  SW.gpause = (int32_t*)gp;
   sv.W.reo_any = (int32_t*)reo;
   SW.s = (const double*)s;
   SW.w = (const double*)w;
@@ -1036,7 +1039,9 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
   // second Gram-Schmidt passes are rare with the Lanczos estimate: a single
   // instance solved with host checks pauses for them (the host runs the pass
   // and resumes); otherwise they are predicated launches on a quarter grid
-  const bool pause_mode = lz && S == 1 && !h->syncfree;
+  // (the pipelined recurrence pauses every system of a batch at once, so
+  // they stay in step: the ends of iteration j have all run when it pauses)
+  const bool pause_mode = lz && !h->syncfree && (S == 1 || h->opt.lanczos == 1);
   rexi::ShiftWork SWl = SWc;
   SWl.pause_mode = pause_mode ? 1 : 0;
   const int G2 = lz ? std::max(1, G / 4) : G;
@@ -1087,7 +1092,7 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
   // pass: the pass of iteration j + 1 ends iteration j (one kernel per
   // iteration); iteration(j) then launches that pass, after a plain pass for
   // the first iteration and after every second Gram-Schmidt pass
-  const bool fuse = pipe && pause_mode && sv.col_kh != 0;
+  const bool fuse = pipe && pause_mode && S == 1 && sv.col_kh != 0;
   auto plain_step = [&](int j, hipStream_t strm) {
     Timed t(h, PC_LANCZOS, n * (j > 0 ? 88.0 : 72.0), strm);
     launch_lz_step<PPT>(sv, W, SWl, j, strm);
@@ -1177,7 +1182,7 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
       // [0]: systems still iterating after the chunk's last iteration; [1]: pause
       HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + (j + len - 1), sizeof(int32_t), hipMemcpyDeviceToHost,
                                stream));
-      HIPCHK(h, hipMemcpyAsync(h->hpin + 1, SWc.flags + 2, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+      HIPCHK(h, hipMemcpyAsync(h->hpin + 1, SWc.gpause, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
       HIPCHK(h, hipStreamSynchronize(stream));
       const int paused_at = pause_mode ? h->hpin[1] : -1;
       if (paused_at >= 0) {
@@ -1188,10 +1193,11 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
         HIPCHK(h, hipGetLastError());
         ++passes;
         j = paused_at + 1;
-        SysState_t s0;
-        HIPCHK(h, hipMemcpyAsync(&s0, W.st, sizeof(SysState_t), hipMemcpyDeviceToHost, stream));
+        // systems still iterating after iteration paused_at (its ends, the
+        // second pass's included, count them)
+        HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + paused_at, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
         HIPCHK(h, hipStreamSynchronize(stream));
-        if (s0.state != rexi::ST_ACTIVE) break;
+        if (h->hpin[0] == 0) break;
         len = std::max(chunk, (*cx.k_hint) - j);
         continue;
       }

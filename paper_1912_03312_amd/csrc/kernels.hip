@@ -409,6 +409,8 @@ struct ShiftWork {
   int32_t* flags;     // [S][4] [0]: reorthogonalise the next vector too; [1]: passes done;
                       // [2]: iteration at which the solve paused (-1: none)
   int32_t pause_mode; // 1: pause for a second pass instead of predicated passes
+  int32_t* gpause;    // [1] iteration at which the solve paused (-1: none): the passes and
+                      // ends of later iterations return at once, for every system
   int32_t* full;      // [S][m] 1 if column j of Hbar has entries above row j - 1
   double* zb;         // [2][sum n] complex: z_j = H u_j of the pipelined recurrence
   int64_t zstride;    // complex elements per z buffer
@@ -905,6 +907,7 @@ __global__ __launch_bounds__(TPB) void k_end_iter(Work W, ShiftWork SW, int j, i
         // hand the second pass to the host: later launches of this chunk skip
         st.state = ST_PAUSED;
         SW.flags[4 * s + 2] = j;
+        *SW.gpause = j;
       }
     }
   } else if (threadIdx.x == 0) {
@@ -984,10 +987,18 @@ __global__ __launch_bounds__(TPB) void k_lz_start(Work W, ShiftWork SW) {
   }
 }
 
+// True when the solve paused (for a second pass) at an iteration before j.
+__device__ __forceinline__ bool paused_before(const ShiftWork& SW, int j) {
+  if (!SW.pause_mode) return false;
+  const int gp = *SW.gpause;
+  return gp >= 0 && gp < j;
+}
+
 template <int PPT>
 __global__ __launch_bounds__(TPB) void k_lz_step(Work W, ShiftWork SW, int j) {
   __shared__ double lds[NWAVE];
   const int m = W.m;
+  if (paused_before(SW, j)) return;
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
     const int s = item_sys(W, item);
     const SysState_t& st = W.st[s];
@@ -1072,6 +1083,7 @@ __global__ __launch_bounds__(TPB) void k_lz_step_lds(Work W, ShiftWork SW, int j
   __shared__ double lds[NWAVE];
   __shared__ double2 ub[TPB * PPT + 2 * HMAX];
   const int m = W.m;
+  if (paused_before(SW, j)) return;
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
     const int s = item_sys(W, item);
     const SysState_t& st = W.st[s];
@@ -1198,6 +1210,7 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
     return;
   }
   if (FUSED && j >= m) return;
+  if (paused_before(SW, j)) return;
   for (int item = blockIdx.x; item < SW.col_total; item += nitems) {
     // the system index is uniform: its descriptor is read once into scalar
     // registers (a reference would be re-read after every store, and each
@@ -1408,6 +1421,10 @@ __device__ void lz_end_body(Work& W, ShiftWork& SW, int s, int j, int colparts) 
   const int npts = d.n;
   const int p0 = SW.pole0[s], p1 = SW.pole0[s + 1];
   if (state != ST_ACTIVE) return;
+  if (SW.pause_mode) {
+    const int gp = *SW.gpause;
+    if (gp >= 0 && gp < j) return;  // the solve paused at an earlier iteration
+  }
   double* alpha = SW.alpha + (int64_t)s * m;
   double* betav = SW.beta + (int64_t)s * (m + 1);
   double* omega = SW.omega + (int64_t)s * 2 * (m + 1);
@@ -1503,6 +1520,7 @@ __device__ void lz_end_body(Work& W, ShiftWork& SW, int s, int j, int colparts) 
     if (reo && SW.pause_mode) {
       st.state = ST_PAUSED;
       SW.flags[4 * s + 2] = j;
+      *SW.gpause = j;
     }
     reo_sh = reo ? 1 : 0;
   }
@@ -1726,6 +1744,7 @@ __global__ __launch_bounds__(64) void k_resume(Work W, ShiftWork SW) {
   if (s >= W.S || threadIdx.x != 0) return;
   if (W.st[s].state == ST_PAUSED) W.st[s].state = ST_ACTIVE;
   SW.flags[4 * s + 2] = -1;
+  if (s == 0) *SW.gpause = -1;
 }
 
 // Grid S: per-instance reset of the pole least-squares data and the
@@ -1738,6 +1757,7 @@ __global__ __launch_bounds__(TPB) void k_shifted_init(Work W, ShiftWork SW) {
     SW.flags[4 * s] = 0;
     SW.flags[4 * s + 1] = 0;
     SW.flags[4 * s + 2] = -1;
+    if (s == 0) *SW.gpause = -1;
     SW.beta[(int64_t)s * (W.m + 1)] = 0.0;
   }
   for (int p = SW.pole0[s] + threadIdx.x; p < SW.pole0[s + 1]; p += TPB) {

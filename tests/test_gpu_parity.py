@@ -851,6 +851,41 @@ def test_marching_pass_with_second_passes(rexi):
     assert e <= i0["certified_bound"] + 3 * iterative_floor(g, wl.V, s, b, wl.dt)
 
 
+@pytest.mark.parametrize("march", [0, 4])
+def test_batch_pauses_for_second_passes(rexi, march):
+    # a batch in which one instance (the double well's interior shifts) needs
+    # second Gram-Schmidt passes: every system pauses at that iteration, the
+    # host runs the pass, and all resume in step; each instance still meets
+    # its certified bound against the oracle
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    wl = inputs.workload("2d_double_well", scale=40)
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+    V2 = inputs.gaussian_bumps(g, 7)
+    psi2 = inputs.seeded_packet(g, 31, (0.5, -0.5), 1.0)
+    Vs, psis = [wl.V, V2], [wl.psi0, psi2]
+    kw = dict(march_planes=march, march_slots=3) if march else dict(march_planes=-1)
+    h = r.setup_batch([(g.n, g.lo, g.hi)] * 2, to_dev(np.concatenate([v.ravel() for v in Vs])), [1.0] * 2,
+                      [1.0] * 2, [wl.dt] * 2, [wl.K] * 2, np.concatenate([s, s]), np.concatenate([b, b]),
+                      solver="shifted", m=256, tol=1e-9, tile=512, **kw)
+    p0 = to_dev(np.concatenate([p.ravel() for p in psis]))
+    out = torch.empty_like(p0)
+    info = h.step(p0, out, 1)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    h.close()
+    errs = []
+    for i in range(2):
+        ref = ost.DirectStepper(g.n, g.h, Vs[i], s, b, wl.dt).step(psis[i]).ravel()
+        errs.append(rel(res[i * g.size:(i + 1) * g.size], ref))
+    floor = max(iterative_floor(g, v, s, b, wl.dt) for v in Vs)
+    print("batch + second passes", march, errs, info["certified_bound"], info["reorth_passes"], info["total_iterations"])
+    assert info["not_converged"] == 0
+    assert info["reorth_passes"] >= 1
+    assert max(errs) <= info["certified_bound"] + 3 * floor
+
+
 @pytest.mark.parametrize("n", [64, 128])
 def test_marching_matches_row_staged_pass(rexi, n):
     # at the benchmarked size and below, every marching configuration the
