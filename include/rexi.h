@@ -276,6 +276,29 @@ rexi_status rexi_apply_H(rexi_handle* h, const rexi_c128* x_dev, rexi_c128* y_de
                          rexi_c128 shift, void* stream);
 
 /*
+ * rexi_estimate_spectrum -- estimates of the extreme eigenvalues of H per
+ * instance, for the step-size condition (Section "Step-Size Requirements",
+ * eq. convergence-condition: the REXI step needs tau sr(M) <= R1, where
+ * sr(M) = max |lambda(H)| / hbar; the paper notes that a few iterations of a
+ * sparse eigensolver give the rough estimate it needs, once per problem).
+ *   iters    Lanczos iterations, 1..256 (fewer on an instance whose Krylov
+ *            space becomes invariant first, e.g. one with <= iters points)
+ *   lo_host, hi_host  host double[instances]: the smallest and largest Ritz
+ *            values of H (finite differences, without centering). They lie
+ *            inside [lambda_min, lambda_max] and approach its ends as iters
+ *            grows; exact once the Krylov space is the whole space.
+ * Lanczos with full re-orthogonalisation (two Gram-Schmidt passes) in FP64
+ * from a fixed pseudo-random real start vector, on the device; the
+ * tridiagonal eigenvalues by Sturm bisection on the host. Allocates and
+ * frees (iters + 1) vectors of the handle's size on the device; the call
+ * synchronises the stream. REXI_E_INVALID_ARG for a Q1-element handle (its
+ * operator is the pencil (A, M)) or iters out of range, REXI_E_NO_MEMORY when
+ * the vectors do not fit.
+ */
+rexi_status rexi_estimate_spectrum(rexi_handle* h, int32_t iters, double* lo_host, double* hi_host,
+                                   void* stream);
+
+/*
  * rexi_step -- nsteps >= 1 REXI steps psi_out = r(tau M)^nsteps psi_in
  * (eq. rational-evaluation). psi_in_dev, psi_out_dev: device rexi_c128[prod n]
  * (packed over instances for a batch); psi_out may equal psi_in. info may be

@@ -1954,6 +1954,115 @@ __global__ void k_norm2_inst(const InstDesc* __restrict__ inst, int ninst, const
   }
 }
 
+// ---------------------------------------------------------------- spectrum estimate
+// Lanczos on H of every instance at once (real start vector, so the basis
+// stays real): the vectors are the handle's global vectors, v_i at i * N.
+
+// Start vector: a fixed pseudo-random real pattern (the instances are
+// normalised separately afterwards).
+__global__ void k_ev_start(double2* __restrict__ v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    const uint64_t z = (uint64_t)i * 0x9E3779B97F4A7C15ull;
+    const double u = (double)((z ^ (z >> 29)) >> 11) * (1.0 / 9007199254740992.0);  // [0, 1)
+    v[i] = make_double2(u - 0.5, 0.0);
+  }
+}
+
+// Per item of the instance tiling: partial <v_i, w> (real parts) for i < nvec,
+// at part[i * itotal + item].
+__global__ void k_ev_dots(const InstDesc* __restrict__ inst, int ninst, const int32_t* __restrict__ itile,
+                          int itotal, const double2* __restrict__ basis, int64_t N, const double2* __restrict__ w,
+                          int nvec, double* __restrict__ part, int tile) {
+  __shared__ double lds[rexi::NWAVE];
+  for (int item = blockIdx.x; item < itotal; item += gridDim.x) {
+    const int ii = rexi::find_sys(itile, ninst, item);
+    const InstDesc& in = inst[ii];
+    const int t = item - in.tile0;
+    const int pend = std::min((t + 1) * tile, in.n);
+    for (int i = 0; i < nvec; ++i) {
+      const double2* __restrict__ v = basis + (int64_t)i * N + in.off;
+      double acc = 0.0;
+      for (int p = t * tile + threadIdx.x; p < pend; p += TPB) {
+        const double2 a = v[p], b = w[in.off + p];
+        acc += a.x * b.x + a.y * b.y;
+      }
+      acc = rexi::block_sum(acc, lds);
+      if (threadIdx.x == 0) part[(int64_t)i * itotal + item] = acc;
+    }
+  }
+}
+
+// w -= sum_{i < nvec} coef[ii * ldc + i] v_i on every instance ii.
+__global__ void k_ev_update(const InstDesc* __restrict__ inst, int ninst, const int32_t* __restrict__ itile,
+                            int itotal, const double2* __restrict__ basis, int64_t N, double2* __restrict__ w,
+                            int nvec, const double* __restrict__ coef, int ldc, int tile) {
+  for (int item = blockIdx.x; item < itotal; item += gridDim.x) {
+    const int ii = rexi::find_sys(itile, ninst, item);
+    const InstDesc& in = inst[ii];
+    const int t = item - in.tile0;
+    const int pend = std::min((t + 1) * tile, in.n);
+    for (int p = t * tile + threadIdx.x; p < pend; p += TPB) {
+      double2 a = w[in.off + p];
+      for (int i = 0; i < nvec; ++i) {
+        const double c = coef[(int64_t)ii * ldc + i];
+        const double2 v = basis[(int64_t)i * N + in.off + p];
+        a.x -= c * v.x;
+        a.y -= c * v.y;
+      }
+      w[in.off + p] = a;
+    }
+  }
+}
+
+// v = scale[ii] w on every instance ii.
+__global__ void k_ev_scale(const InstDesc* __restrict__ inst, int ninst, const int32_t* __restrict__ itile,
+                           int itotal, const double2* __restrict__ w, double2* __restrict__ v,
+                           const double* __restrict__ scale, int tile) {
+  for (int item = blockIdx.x; item < itotal; item += gridDim.x) {
+    const int ii = rexi::find_sys(itile, ninst, item);
+    const InstDesc& in = inst[ii];
+    const int t = item - in.tile0;
+    const double c = scale[ii];
+    const int pend = std::min((t + 1) * tile, in.n);
+    for (int p = t * tile + threadIdx.x; p < pend; p += TPB) {
+      const double2 a = w[in.off + p];
+      v[in.off + p] = make_double2(c * a.x, c * a.y);
+    }
+  }
+}
+
+// Eigenvalues of the symmetric tridiagonal (a, b) below x (Sturm count of
+// the LDL^T pivots; b[i] couples rows i and i + 1).
+int sturm_below(const std::vector<double>& a, const std::vector<double>& b, double x) {
+  int cnt = 0;
+  double d = 1.0;
+  const double tiny = 1e-300;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double off = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+    d = a[i] - x - (i > 0 ? off / d : 0.0);
+    if (d == 0.0) d = -tiny;
+    if (d < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// The r-th smallest eigenvalue (r = 0 .. k-1) of the tridiagonal by bisection
+// inside its Gershgorin interval.
+double tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, int r) {
+  const size_t k = a.size();
+  double lo = 0.0, hi = 0.0;
+  for (size_t i = 0; i < k; ++i) {
+    const double rad = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(b[i]) : 0.0);
+    lo = i == 0 ? a[i] - rad : std::min(lo, a[i] - rad);
+    hi = i == 0 ? a[i] + rad : std::max(hi, a[i] + rad);
+  }
+  for (int it = 0; it < 200 && hi - lo > 4e-16 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_below(a, b, mid) > r) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
 rexi_status vec_norm(rexi_handle* h, const double2* v, hipStream_t stream, double* out) {
   const int tile = TPB * PPT;
   hipLaunchKernelGGL(k_norm2_inst, dim3(std::min(h->itotal, 2048)), dim3(TPB), 0, stream, h->dinst, h->ninst,
@@ -2276,6 +2385,130 @@ rexi_status rexi_workspace_info(const rexi_handle* h, int64_t* bytes, int32_t* m
   if (!h) return REXI_E_INVALID_ARG;
   if (bytes) *bytes = h->ws_bytes;
   if (m_used) *m_used = h->fwd.m;
+  return REXI_OK;
+}
+
+rexi_status rexi_estimate_spectrum(rexi_handle* h, int32_t iters, double* lo_host, double* hi_host, void* stream) {
+  if (!h) return REXI_E_INVALID_ARG;
+  if (!lo_host || !hi_host) return fail(h, REXI_E_INVALID_ARG, "NULL output");
+  if (iters < 1 || iters > 256) return fail(h, REXI_E_INVALID_ARG, "iters must be in [1, 256]");
+  for (const auto& in : h->hinst)
+    if (in.fem) return fail(h, REXI_E_INVALID_ARG, "the spectrum estimate is for the finite-difference H");
+  hipStream_t st = (hipStream_t)stream;
+  const int S = h->ninst, T = h->itotal, tile = TPB * PPT;
+  const int64_t N = h->N;
+  double2* basis = nullptr;
+  double2* w = nullptr;
+  double *part = nullptr, *dcoef = nullptr;
+  const size_t nb = (size_t)(iters + 1) * (size_t)N * sizeof(double2);
+  auto release = [&]() {
+    if (basis) (void)hipFree(basis);
+    if (w) (void)hipFree(w);
+    if (part) (void)hipFree(part);
+    if (dcoef) (void)hipFree(dcoef);
+  };
+  if (hipMalloc(&basis, nb) != hipSuccess || hipMalloc(&w, (size_t)N * sizeof(double2)) != hipSuccess ||
+      hipMalloc(&part, (size_t)(iters + 1) * std::max(1, T) * sizeof(double)) != hipSuccess ||
+      hipMalloc(&dcoef, (size_t)S * (iters + 1) * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    return fail(h, REXI_E_NO_MEMORY, "spectrum estimate workspace (%zu bytes)", nb);
+  }
+  const int G = std::max(1, std::min(T, 2048));
+  // per-instance sums of the item partials of vectors [0, nvec)
+  auto inst_sums = [&](int nvec, std::vector<double>& out) -> rexi_status {
+    std::vector<double> pv((size_t)nvec * T);
+    HIPCHK(h, hipMemcpyAsync(pv.data(), part, pv.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(h, hipStreamSynchronize(st));
+    out.assign((size_t)S * nvec, 0.0);
+    for (int ii = 0; ii < S; ++ii)
+      for (int i = 0; i < nvec; ++i) {
+        double acc = 0.0;
+        for (int t = h->hinst[ii].tile0; t < h->hinst[ii].tile0 + h->hinst[ii].ntiles; ++t)
+          acc += pv[(size_t)i * T + t];
+        out[(size_t)ii * nvec + i] = acc;
+      }
+    return REXI_OK;
+  };
+  std::vector<std::vector<double>> al((size_t)S), be((size_t)S);
+  std::vector<char> live((size_t)S, 1);
+  std::vector<double> sums, scale((size_t)S), coef((size_t)S * (iters + 1));
+  auto lanczos = [&]() -> rexi_status {
+    rexi_status rs = REXI_OK;
+    // v_0 = a pseudo-random vector, normalised per instance
+    hipLaunchKernelGGL(k_ev_start, dim3(1024), dim3(TPB), 0, st, w, N);
+    hipLaunchKernelGGL(k_norm2_inst, dim3(G), dim3(TPB), 0, st, h->dinst, h->ninst, h->ditile, T, w, part, tile);
+    HIPCHK(h, hipGetLastError());
+    if ((rs = inst_sums(1, sums)) != REXI_OK) return rs;
+    for (int ii = 0; ii < S; ++ii) scale[ii] = sums[ii] > 0.0 ? 1.0 / std::sqrt(sums[ii]) : 0.0;
+    HIPCHK(h, hipMemcpyAsync(dcoef, scale.data(), S * sizeof(double), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_ev_scale, dim3(G), dim3(TPB), 0, st, h->dinst, h->ninst, h->ditile, T, w, basis, dcoef,
+                       tile);
+    for (int j = 0; j < iters && rs == REXI_OK; ++j) {
+      double2* vj = basis + (int64_t)j * N;
+      hipLaunchKernelGGL(rexi::k_apply_h, dim3(std::min(T, 2048)), dim3(TPB), 0, st, h->dinst, h->ninst,
+                         h->ditile, T, h->V64, (const double2*)vj, w, 0.0, 0.0, tile);
+      // full re-orthogonalisation: two classical Gram-Schmidt rounds
+      std::fill(coef.begin(), coef.end(), 0.0);
+      for (int round = 0; round < 2; ++round) {
+        hipLaunchKernelGGL(k_ev_dots, dim3(G), dim3(TPB), 0, st, h->dinst, h->ninst, h->ditile, T, basis, N, w,
+                           j + 1, part, tile);
+        HIPCHK(h, hipGetLastError());
+        if ((rs = inst_sums(j + 1, sums)) != REXI_OK) break;
+        std::vector<double> c((size_t)S * (j + 1));
+        for (int ii = 0; ii < S; ++ii)
+          for (int i = 0; i <= j; ++i) {
+            c[(size_t)ii * (j + 1) + i] = live[ii] ? sums[(size_t)ii * (j + 1) + i] : 0.0;
+            coef[(size_t)ii * (iters + 1) + i] += c[(size_t)ii * (j + 1) + i];
+          }
+        HIPCHK(h, hipMemcpyAsync(dcoef, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_ev_update, dim3(G), dim3(TPB), 0, st, h->dinst, h->ninst, h->ditile, T, basis, N, w,
+                           j + 1, dcoef, j + 1, tile);
+      }
+      if (rs != REXI_OK) break;
+      hipLaunchKernelGGL(k_norm2_inst, dim3(G), dim3(TPB), 0, st, h->dinst, h->ninst, h->ditile, T, w, part,
+                         tile);
+      HIPCHK(h, hipGetLastError());
+      if ((rs = inst_sums(1, sums)) != REXI_OK) break;
+      for (int ii = 0; ii < S; ++ii) {
+        if (!live[ii]) {
+          scale[ii] = 0.0;
+          continue;
+        }
+        al[ii].push_back(coef[(size_t)ii * (iters + 1) + j]);
+        const double bn = std::sqrt(sums[ii]);
+        // an invariant subspace (the whole space of a small instance): stop there
+        const double anorm = std::fabs(al[ii].back()) + (be[ii].empty() ? 0.0 : be[ii].back());
+        if (!(bn > 1e-13 * std::max(anorm, 1e-300)) || (int)al[ii].size() >= h->hinst[ii].n) {
+          live[ii] = 0;
+          scale[ii] = 0.0;
+          continue;
+        }
+        be[ii].push_back(bn);
+        scale[ii] = 1.0 / bn;
+      }
+      HIPCHK(h, hipMemcpyAsync(dcoef, scale.data(), S * sizeof(double), hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_ev_scale, dim3(G), dim3(TPB), 0, st, h->dinst, h->ninst, h->ditile, T, w,
+                         basis + (int64_t)(j + 1) * N, dcoef, tile);
+      HIPCHK(h, hipGetLastError());
+    }
+    if (rs != REXI_OK) return rs;
+    HIPCHK(h, hipStreamSynchronize(st));
+    return REXI_OK;
+  };
+  const rexi_status rs = lanczos();
+  release();
+  if (rs != REXI_OK) return rs;
+  for (int ii = 0; ii < S; ++ii) {
+    std::vector<double>& a = al[ii];
+    std::vector<double> b(be[ii].begin(), be[ii].begin() + std::min(be[ii].size(), a.empty() ? 0 : a.size() - 1));
+    if (a.empty()) {
+      lo_host[ii] = hi_host[ii] = 0.0;
+      continue;
+    }
+    lo_host[ii] = tridiag_eig(a, b, 0);
+    hi_host[ii] = tridiag_eig(a, b, (int)a.size() - 1);
+  }
   return REXI_OK;
 }
 

@@ -29,7 +29,8 @@ SOLVER_PER_POLE, SOLVER_SHIFTED = 0, 1
 #: every entry point the header declares
 EXPORTS = ("rexi_default_options", "rexi_setup", "rexi_setup_batch", "rexi_apply_H", "rexi_step",
            "rexi_step_adjoint", "rexi_get_profile", "rexi_profile_reset", "rexi_workspace_info",
-           "rexi_tiling_info", "rexi_destroy", "rexi_status_string", "rexi_last_error")
+           "rexi_tiling_info", "rexi_estimate_spectrum", "rexi_destroy", "rexi_status_string",
+           "rexi_last_error")
 
 
 class c128(C.Structure):
@@ -95,7 +96,7 @@ _lib.rexi_status_string.argtypes = [C.c_int]
 _lib.rexi_status_string.restype = C.c_char_p
 _lib.rexi_last_error.argtypes = [_H, C.c_char_p, C.c_size_t]
 for _f in ("rexi_setup", "rexi_setup_batch", "rexi_apply_H", "rexi_step", "rexi_step_adjoint", "rexi_get_profile",
-           "rexi_profile_reset", "rexi_workspace_info", "rexi_destroy", "rexi_last_error"):
+           "rexi_profile_reset", "rexi_workspace_info", "rexi_destroy", "rexi_last_error", "rexi_estimate_spectrum"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -173,10 +174,11 @@ def _ptr(t, dtype_name: str, numel: int):
 class Handle:
     """A configured REXI propagator (one instance or an uneven batch)."""
 
-    def __init__(self, raw, npts: int, K: int):
+    def __init__(self, raw, npts: int, K: int, count: int = 1):
         self._h = raw
         self.npts = npts
         self.K = K
+        self.count = count
 
     def __del__(self):
         self.close()
@@ -192,6 +194,14 @@ class Handle:
         py = _ptr(y, "complex128", self.npts)
         s = c128(float(np.real(shift)), float(np.imag(shift)))
         _check(_lib.rexi_apply_H(self._h, px, py, s, _stream(stream)), self._h)
+
+    def estimate_spectrum(self, iters: int = 30, stream=None):
+        """``rexi_estimate_spectrum``: (lo, hi) float64 arrays per instance,
+        the extreme Ritz values of H after ``iters`` Lanczos iterations."""
+        lo = (C.c_double * self.count)()
+        hi = (C.c_double * self.count)()
+        _check(_lib.rexi_estimate_spectrum(self._h, int(iters), lo, hi, _stream(stream)), self._h)
+        return np.array(lo[:]), np.array(hi[:])
 
     def step(self, psi_in, psi_out, nsteps: int = 1, info: bool = True, stream=None, raise_on_nc: bool = True):
         """``nsteps`` REXI steps; returns a dict of solve diagnostics (or None)."""
@@ -287,7 +297,7 @@ def setup_batch(grids, V, hbar, mass, dt, K, sigma, beta, options: Optional[Opti
     st = _lib.rexi_setup_batch(C.byref(raw), cnt, G, pv, dbl(hbar), dbl(mass), dbl(dt), Ks,
                                _c128_array(sig), _c128_array(bet), C.byref(o), _stream(stream))
     _check(st, None)
-    return Handle(raw, npts, int(sig.size))
+    return Handle(raw, npts, int(sig.size), cnt)
 
 
 def status_string(s: int) -> str:

@@ -938,3 +938,71 @@ def test_tilings_agree(rexi, solver):
     # certified error bounds
     for o, bd in zip(outs[1:], bounds[1:]):
         assert rel(o, outs[0]) <= bd + bounds[0] + 1e-13
+
+
+# ---------------------------------------------------------------- spectrum estimate
+def _extremes(g, V):
+    import scipy.sparse.linalg as sla
+    H = ham.hamiltonian(g.n, g.h, V)
+    lo = sla.eigsh(H, k=1, which="SA", return_eigenvectors=False)[0]
+    hi = sla.eigsh(H, k=1, which="LA", return_eigenvectors=False)[0]
+    return lo, hi
+
+
+def test_spectrum_estimate_single_instances(rexi):
+    # Lanczos estimates of the extreme eigenvalues of H (the step-size
+    # condition needs the largest |lambda|): inside the spectrum, below the
+    # Gershgorin bound, and close to the ends (eigsh on the oracle's H; the
+    # 1D Laplacian's closed form; exact once the Krylov space is everything)
+    from paper_1912_03312_amd import rexi as r
+    s, b, d = poles(16, 28.0)
+    cases = [((20,), None, 20, 1e-10, 1e-10), ((300,), None, 30, 2e-3, 1e-2), ((24, 24, 24), "bumps", 60, 1e-5, 1e-5)]
+    for shape, pot, iters, tol_hi, tol_lo in cases:
+        g = inputs.Grid(shape, tuple(-3.0 for _ in shape), tuple(4.0 for _ in shape))
+        V = np.zeros(shape) if pot is None else inputs.gaussian_bumps(g, 7)
+        h = r.setup(g.n, g.lo, g.hi, to_dev(V.ravel()), 1.0, 1.0, 0.01, s, b)
+        lo, hi = h.estimate_spectrum(iters)
+        h.close()
+        if pot is None and len(shape) == 1:
+            ev = ham.laplacian_eigenvalues_1d(shape[0], g.h[0])
+            elo, ehi = float(ev.min()), float(ev.max())
+        elif g.size <= 64:
+            ev = np.linalg.eigvalsh(ham.hamiltonian(g.n, g.h, V).toarray())
+            elo, ehi = float(ev[0]), float(ev[-1])
+        else:
+            elo, ehi = _extremes(g, V)
+        glo, ghi = ham.gershgorin(g.n, g.h, V)
+        scale = max(abs(elo), abs(ehi))
+        print("spectrum", shape, iters, lo[0], elo, hi[0], ehi)
+        assert elo - 1e-12 * scale <= lo[0] and hi[0] <= ehi + 1e-12 * scale
+        assert hi[0] <= ghi + 1e-12 * scale and lo[0] >= glo - 1e-12 * scale
+        assert ehi - hi[0] <= tol_hi * scale
+        assert lo[0] - elo <= tol_lo * scale
+
+
+def test_spectrum_estimate_batch_and_errors(rexi):
+    # per-instance estimates of an uneven batch; Q1-element handles and bad
+    # iteration counts are refused
+    from paper_1912_03312_amd import rexi as r
+    s, b, d = poles(16, 28.0)
+    g1 = inputs.Grid((24, 24, 24), (-3.0,) * 3, (4.0,) * 3)
+    g2 = inputs.Grid((40, 33), (-5.0, -4.0), (5.0, 4.0))
+    V1, V2 = inputs.gaussian_bumps(g1, 7), inputs.gaussian_bumps(g2, 8)
+    h = r.setup_batch([(g1.n, g1.lo, g1.hi), (g2.n, g2.lo, g2.hi)],
+                      to_dev(np.concatenate([V1.ravel(), V2.ravel()])), [1.0, 1.0], [1.0, 1.0], [0.01, 0.01],
+                      [16, 16], np.concatenate([s, s]), np.concatenate([b, b]))
+    lo, hi = h.estimate_spectrum(60)
+    with pytest.raises(r.RexiError):
+        h.estimate_spectrum(0)
+    h.close()
+    for k, (g, V) in enumerate([(g1, V1), (g2, V2)]):
+        elo, ehi = _extremes(g, V)
+        scale = max(abs(elo), abs(ehi))
+        print("spectrum batch", k, lo[k], elo, hi[k], ehi)
+        assert elo - 1e-12 * scale <= lo[k] <= elo + 1e-4 * scale
+        assert ehi - 1e-4 * scale <= hi[k] <= ehi + 1e-12 * scale
+    g = inputs.Grid((12, 12), (-3.0, -3.0), (3.0, 3.0))
+    hf = r.setup(g.n, g.lo, g.hi, to_dev(np.zeros(g.size)), 1.0, 1.0, 0.01, s, b, discretization="fem")
+    with pytest.raises(r.RexiError):
+        hf.estimate_spectrum(10)
+    hf.close()
