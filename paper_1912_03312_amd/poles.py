@@ -67,3 +67,36 @@ def faber_cf_poles(K: int, R1: float, L: int | None = None, npts: int = 8000):
     info = dict(L=L, sigma_next=float(sv[K]), err_inf=float(np.max(np.abs(r - np.exp(1j * yy)))),
                 amplification=float(np.sum(np.abs(beta) / sigma.real)))
     return sigma.astype(np.complex128), beta.astype(np.complex128), info
+
+
+def select_poles(dt: float, lam_lo: float, lam_hi: float, err_target: float, hbar: float = 1.0,
+                 centered: bool = False, Ks=(10, 16, 24, 32, 48, 64, 96, 128), margin: float = 1.02):
+    """Per-configuration choice of (K, R1) for a step ``dt`` on a spectrum of
+    H inside [lam_lo, lam_hi] (e.g. ``rexi_estimate_spectrum`` or Gershgorin
+    bounds).
+
+    The step is exact up to the approximation error when the eigenvalues of
+    tau M lie in i[-R1, R1] (Section "Step-Size Requirements", eq.
+    ``convergence-condition``: tau sr(M) <= R1, sr(M) = max |lambda| / hbar), so
+    R1 = margin * dt * w / hbar, where w is max(|lam_lo|, |lam_hi|), or the
+    half-width (lam_hi - lam_lo) / 2 for a step on H - cI with c the midpoint
+    (``center`` option). Returns the smallest K of ``Ks`` whose Faber-CF
+    approximation has err_inf <= err_target, as a dict with K, R1, sigma,
+    beta and the construction's info; (K, R1) pairs for which the CF step is
+    degenerate are skipped. Raises ValueError when no K of ``Ks`` qualifies.
+    """
+    if not (dt > 0 and hbar > 0 and lam_hi >= lam_lo and err_target > 0):
+        raise ValueError("need dt > 0, hbar > 0, lam_hi >= lam_lo and err_target > 0")
+    w = 0.5 * (lam_hi - lam_lo) if centered else max(abs(lam_lo), abs(lam_hi))
+    R1 = max(margin * dt * w / hbar, 1e-3)
+    tried = []
+    for K in sorted(Ks):
+        try:
+            sigma, beta, info = faber_cf_poles(K, R1)
+        except ValueError:
+            tried.append((K, None))
+            continue
+        tried.append((K, info["err_inf"]))
+        if info["err_inf"] <= err_target:
+            return dict(K=K, R1=R1, sigma=sigma, beta=beta, info=info)
+    raise ValueError(f"no K in {tuple(Ks)} reaches err_inf <= {err_target:g} at R1 = {R1:g}: {tried}")
