@@ -141,7 +141,13 @@ struct rexi_handle {
   int k_hintA = 0, reorth_passesA = 0;
   double2* adj_coef = nullptr;        // [m][m] coefficients of the gradient's bilinear form
   double* dnorm = nullptr;            // scratch partials for norms
-  double2* mrhs = nullptr;            // Q1 elements: M psi, the right-hand side of the solves
+  double2* mrhs = nullptr;            // Q1 elements: M psi (per pole), L^T psi (shared basis)
+  // Q1 elements with the shared basis: M = L L^T, the solves run on
+  // Ahat = L^-1 A L^-T (one instance); chol holds the factors of L per axis,
+  // fem_y the operator's intermediate vector
+  bool fem_shared = false;
+  double* chol = nullptr;
+  double2* fem_y = nullptr;
   std::string err;
   Prof prof;
   int64_t ws_bytes = 0;
@@ -191,6 +197,8 @@ void destroy_handle(rexi_handle* h) {
   if (h->V32) (void)hipFree(h->V32);
   if (h->dnorm) (void)hipFree(h->dnorm);
   if (h->mrhs) (void)hipFree(h->mrhs);
+  if (h->chol) (void)hipFree(h->chol);
+  if (h->fem_y) (void)hipFree(h->fem_y);
   if (h->fb_rhs) (void)hipFree(h->fb_rhs);
   if (h->hpin) (void)hipHostFree(h->hpin);
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -426,8 +434,9 @@ int default_grid(int total_tiles, int opt_grid) {
 }
 
 // ---------------------------------------------------------------- solve
-constexpr int PPT = 8;  // points per thread of the instance-level kernels
 constexpr int TPB = rexi::TPB;
+constexpr int INST_PPT = 8;  // points per thread of the instance-level kernels
+constexpr int INST_TILE = TPB * INST_PPT;  // points per tile of the instance tiling (itotal, ditile)
 
 // Restarted cycles of the per-pole solver from the current state: `active`
 // systems are iterating, `total_restarts` restarts were counted so far.
@@ -445,7 +454,7 @@ rexi_status run_cycles(rexi_handle* h, Solver& sv, const double2* r0, const doub
     for (int j = 0; j < m; ++j) {
       {
         Timed t(h, PC_ARNOLDI_A, active * n_avg * ((j + 2) * e + eV), stream);
-        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, true>), dim3(G), dim3(TPB), 0, stream, W, j, 0);
+        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, true>), dim3(G), dim3(TPB), 0, stream, W, j, 0, 0);
       }
       {
         Timed t(h, PC_REDUCE, 0, stream);
@@ -462,7 +471,7 @@ rexi_status run_cycles(rexi_handle* h, Solver& sv, const double2* r0, const doub
       if (sv.reorth) {
         {
           Timed t(h, PC_REORTH_A, 0, stream);
-          hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(G), dim3(TPB), 0, stream, W, j, 0);
+          hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(G), dim3(TPB), 0, stream, W, j, 0, 0);
         }
         {
           Timed t(h, PC_REDUCE, 0, stream);
@@ -1050,7 +1059,7 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
       // re-orthogonalise u_{j+1}, recompute z_{j+1} = H u_{j+1}, then the Givens step
       {
         Timed t(h, PC_REORTH_A, 0, strm);
-        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(grid2), dim3(TPB), 0, strm, W, j, 0);
+        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(grid2), dim3(TPB), 0, strm, W, j, 0, 0);
       }
       {
         Timed t(h, PC_REDUCE, 0, strm);
@@ -1073,7 +1082,7 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
     }
     {
       Timed t(h, PC_REORTH_A, 0, strm);
-      hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(grid2), dim3(TPB), 0, strm, W, j, 0);
+      hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(grid2), dim3(TPB), 0, strm, W, j, 0, 0);
     }
     {
       Timed t(h, PC_REDUCE, 0, strm);
@@ -1118,9 +1127,26 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
     // Lanczos: project on v_{j-1}, v_j only (H is Hermitian); Arnoldi: on all
     const int i0 = lz ? std::max(0, j - 1) : 0;
     const int nproj = j + 1 - i0;
-    {
+    if (h->fem_shared) {
+      // Q1 elements: u_{j+1} <- Ahat u_j = L^-1 A L^-T u_j (three sweeps, the
+      // element operator, three sweeps), then the first pass on it
+      const InstDesc& in = h->hinst[0];
+      double2* b0 = reinterpret_cast<double2*>(W.basis) + sv.hsys[0].basis;
+      const double2* uj = b0 + (int64_t)j * in.n;
+      double2* un = b0 + (int64_t)(j + 1) * in.n;
+      const dim3 gs(std::max(1, std::min((in.n + TPB - 1) / TPB, 2048)));
+      Timed t(h, PC_ARNOLDI_A, n * (12 * 32.0 + (nproj + 1) * e + 8.0), strm);
+      for (int a = 0; a < 3; ++a)
+        hipLaunchKernelGGL(rexi::k_fem_sweep, gs, dim3(TPB), 0, strm, in, h->chol, a == 0 ? uj : h->fem_y,
+                           h->fem_y, a, 1);
+      hipLaunchKernelGGL(rexi::k_apply_h, dim3(std::min(h->itotal, 2048)), dim3(TPB), 0, strm, h->dinst, h->ninst,
+                         h->ditile, h->itotal, h->V64, (const double2*)h->fem_y, un, 0.0, 0.0, INST_TILE);
+      for (int a = 0; a < 3; ++a)
+        hipLaunchKernelGGL(rexi::k_fem_sweep, gs, dim3(TPB), 0, strm, in, h->chol, (const double2*)un, un, a, 0);
+      hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(G), dim3(TPB), 0, strm, W, j, i0, 1);
+    } else {
       Timed t(h, PC_ARNOLDI_A, n * ((nproj + 1) * e + 8.0), strm);
-      hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, true>), dim3(G), dim3(TPB), 0, strm, W, j, i0);
+      hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, true>), dim3(G), dim3(TPB), 0, strm, W, j, i0, 0);
     }
     {
       Timed t(h, PC_REDUCE, 0, strm);
@@ -1352,7 +1378,19 @@ rexi_status shifted_solve(rexi_handle* h, ShiftCtx cx, const double2* b, double2
 }
 
 rexi_status shifted_step(rexi_handle* h, const double2* b, double2* out, hipStream_t stream) {
-  return shifted_solve(h, fwd_ctx(h), b, out, stream);
+  if (!h->fem_shared) return shifted_solve(h, fwd_ctx(h), b, out, stream);
+  // Q1 elements: (A - s M)^-1 M psi = L^-T (Ahat - s)^-1 L^T psi, summed over
+  // the poles on the transformed vector, then one L^-T for the whole sum
+  const InstDesc& in = h->hinst[0];
+  const dim3 gs(std::max(1, std::min((in.n + TPB - 1) / TPB, 2048)));
+  hipLaunchKernelGGL(rexi::k_fem_lt, gs, dim3(TPB), 0, stream, in, h->chol, b, h->mrhs);
+  HIPCHK(h, hipGetLastError());
+  rexi_status st = shifted_solve(h, fwd_ctx(h), h->mrhs, out, stream);
+  if (st != REXI_OK) return st;
+  for (int a = 0; a < 3; ++a)
+    hipLaunchKernelGGL(rexi::k_fem_sweep, gs, dim3(TPB), 0, stream, in, h->chol, (const double2*)out, out, a, 1);
+  HIPCHK(h, hipGetLastError());
+  return REXI_OK;
 }
 
 // out = sum_p w_p y_p of a finished shared-basis solve (every pole converged).
@@ -1569,7 +1607,7 @@ void tune_launch(rexi_handle* h, Solver& sv, const double2* b, int iters, hipStr
   }
   for (int j = 0; j < iters && j < sv.m; ++j) {
     const int i0 = lz ? std::max(0, j - 1) : 0;
-    hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, true>), dim3(G), dim3(TPB), 0, st, W, j, i0);
+    hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, true>), dim3(G), dim3(TPB), 0, st, W, j, i0, 0);
     hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, j + 2), dim3(TPB), 0, st, W, j, 0, i0);
     hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G), dim3(TPB), 0, st, W, j, 0, i0);
     hipLaunchKernelGGL(rexi::k_end_iter, dim3(S), dim3(TPB), 0, st, W, h->shifted ? h->SW : h->noshift, j, 0, 0);
@@ -1766,9 +1804,11 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
     return fail(nullptr, REXI_E_INVALID_ARG, "adjoint_shared must be 0 or 1");
   if (o.discretization != REXI_DISC_FD && o.discretization != REXI_DISC_FEM_Q1)
     return fail(nullptr, REXI_E_INVALID_ARG, "unknown discretization %d", o.discretization);
-  if (o.discretization == REXI_DISC_FEM_Q1 && o.solver == REXI_SOLVER_SHIFTED)
+  if (o.discretization == REXI_DISC_FEM_Q1 && o.solver == REXI_SOLVER_SHIFTED && count != 1)
     return fail(nullptr, REXI_E_INVALID_ARG,
-                "the shared-basis solver needs B = hbar I (finite differences); use the per-pole solver");
+                "Q1 elements with the shared-basis solver take one instance; use the per-pole solver for batches");
+  if (o.discretization == REXI_DISC_FEM_Q1 && o.solver == REXI_SOLVER_SHIFTED && o.fallback == 2)
+    return fail(nullptr, REXI_E_INVALID_ARG, "Q1 elements with the shared-basis solver: fallback 0 or 1");
 
   // ---- validate the instances (host side, before any device work)
   int64_t N = 0, Ktot = 0;
@@ -1810,9 +1850,13 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   h->opt = o;
   h->ninst = count;
   h->N = N;
+  // Q1 elements on the shared basis: the two-pass Lanczos process, whose
+  // matvec is the operator Ahat applied outside the pass kernels
+  h->fem_shared = o.discretization == REXI_DISC_FEM_Q1 && o.solver == REXI_SOLVER_SHIFTED;
+  if (h->fem_shared) h->opt.lanczos = 2;
   int64_t off = 0, kk = 0;
   int itile = 0;
-  const int itile_pts = TPB * PPT;
+  const int itile_pts = INST_TILE;
   for (int i = 0; i < count; ++i) {
     const bool fem = o.discretization == REXI_DISC_FEM_Q1;
     InstDesc in = make_inst(grids[i], hbar[i], mass[i], off, fem);
@@ -1840,6 +1884,9 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
       blo = std::min(vmin, f * vmin);
       bhi = 6.0 * in.diag + std::max(vmax, f * vmax);  // 6 diag = sum (hbar^2/2m) 12/h^2
       for (int a = 0; a < 3; ++a) mmin *= (3 - grids[i].ndim <= a) ? in.fmd[a] / 2.0 : 1.0;  // h/3 per axis
+      // the shared basis solves for xhat = L^T x: its residuals and errors are
+      // those of x in the M-norm, relative to ||psi||_M = ||L^T psi||
+      if (h->fem_shared) mmin = 1.0;
     }
     const double c = o.center ? 0.5 * (blo + bhi) : 0.0;
     const double lo = blo - c, hi = bhi - c;
@@ -1885,6 +1932,24 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   }
   h->hitile.push_back(itile);
   h->itotal = itile;
+  // Q1 shared basis: bidiagonal Cholesky factors of the 1D mass matrices
+  // tridiag(fmo, fmd, fmo) of each axis (d_0 = sqrt(fmd), e_i = fmo / d_{i-1},
+  // d_i = sqrt(fmd - e_i^2)); an absent axis has the factor 1
+  std::vector<double> chol;
+  if (h->fem_shared) {
+    InstDesc& in = h->hinst[0];
+    const int na[3] = {in.n0, in.n1, in.n2};
+    for (int a = 0; a < 3; ++a) {
+      in.loff[a] = (int64_t)chol.size();
+      std::vector<double> d((size_t)na[a]), e((size_t)na[a], 0.0);
+      for (int i = 0; i < na[a]; ++i) {
+        if (i > 0) e[i] = in.fmo[a] / d[i - 1];
+        d[i] = std::sqrt(in.fmd[a] - e[i] * e[i]);
+      }
+      chol.insert(chol.end(), d.begin(), d.end());
+      chol.insert(chol.end(), e.begin(), e.end());
+    }
+  }
 
 #define SETUP_CHK(call)                                                                             \
   do {                                                                                              \
@@ -1909,6 +1974,11 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   SETUP_CHK(hipMalloc(&h->ditile, (count + 1) * sizeof(int32_t)));
   SETUP_CHK(hipMalloc(&h->dnorm, std::max(1, itile) * sizeof(double)));
   if (o.discretization == REXI_DISC_FEM_Q1) SETUP_CHK(hipMalloc(&h->mrhs, (size_t)N * sizeof(double2)));
+  if (h->fem_shared) {
+    SETUP_CHK(hipMalloc(&h->chol, chol.size() * sizeof(double)));
+    SETUP_CHK(hipMemcpyAsync(h->chol, chol.data(), chol.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+    SETUP_CHK(hipMalloc(&h->fem_y, (size_t)N * sizeof(double2)));
+  }
   SETUP_CHK(hipMemcpyAsync(h->dinst, h->hinst.data(), count * sizeof(InstDesc), hipMemcpyHostToDevice, stream));
   SETUP_CHK(hipMemcpyAsync(h->ditile, h->hitile.data(), (count + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
   SETUP_CHK(hipHostMalloc((void**)&h->hpin, 64 * sizeof(int32_t), hipHostMallocDefault));
@@ -1921,8 +1991,9 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
     destroy_handle(h);
     return st;
   }
-  if (o.autotune && o.tile == 0 && o.grid_blocks == 0) st = autotune(h, h->fwd, stream);
-  if (st == REXI_OK && h->shifted && o.lanczos == 1 && o.march_planes > 0)
+  // (the tuner times the stencil passes, which the Q1 shared basis does not use)
+  if (o.autotune && o.tile == 0 && o.grid_blocks == 0 && !h->fem_shared) st = autotune(h, h->fwd, stream);
+  if (st == REXI_OK && h->shifted && h->opt.lanczos == 1 && o.march_planes > 0)
     st = apply_columns(h, h->fwd, o.march_slots ? o.march_slots : 5, o.march_planes, stream);
   if (st == REXI_OK && h->shifted && o.fallback == 2) st = init_fallback(h, stream);
   if (st == REXI_OK && h->shifted && o.fallback == 1) st = init_restart(h, stream);
@@ -2064,7 +2135,7 @@ double tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, i
 }
 
 rexi_status vec_norm(rexi_handle* h, const double2* v, hipStream_t stream, double* out) {
-  const int tile = TPB * PPT;
+  const int tile = INST_TILE;
   hipLaunchKernelGGL(k_norm2_inst, dim3(std::min(h->itotal, 2048)), dim3(TPB), 0, stream, h->dinst, h->ninst,
                      h->ditile, h->itotal, v, h->dnorm, tile);
   HIPCHK(h, hipGetLastError());
@@ -2139,7 +2210,7 @@ rexi_status rexi_apply_H(rexi_handle* h, const rexi_c128* x_dev, rexi_c128* y_de
   Timed t(h, PC_APPLY_H, (double)h->N * 40.0, st);
   hipLaunchKernelGGL(rexi::k_apply_h, dim3(std::min(h->itotal, 2048)), dim3(TPB), 0, st, h->dinst, h->ninst,
                      h->ditile, h->itotal, h->V64, (const double2*)x_dev, (double2*)y_dev, shift.re, shift.im,
-                     TPB * PPT);
+                     INST_TILE);
   HIPCHK(h, hipGetLastError());
   return REXI_OK;
 }
@@ -2199,6 +2270,13 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
   for (int n = 0; n < nsteps; ++n) {
     const double2* src = n == 0 ? in : outp;
     if (h->shifted) {
+      // Q1 elements: ||psi|| before an in-place step overwrites it (the
+      // solves see ||L^T psi||, the M-norm)
+      double psi_norm = 0.0;
+      if (h->fem_shared && info && n == nsteps - 1) {
+        rexi_status s0n = vec_norm(h, src, st, &psi_norm);
+        if (s0n != REXI_OK) return s0n;
+      }
       rexi_status s1 = shifted_step(h, src, outp, st);
       if (s1 != REXI_OK) return s1;
       if (info) {
@@ -2239,7 +2317,7 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
           }
           info->certified_bound = bound;
           info->reorth_passes = h->reorth_passes;
-          info->norm_in = s0.bnorm;
+          info->norm_in = h->fem_shared ? psi_norm : s0.bnorm;
           double no = 0.0;
           rexi_status s2 = vec_norm(h, outp, st, &no);
           if (s2 != REXI_OK) return s2;
@@ -2258,7 +2336,7 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
     if (h->mrhs) {
       // Q1 elements: the systems are (A - s_j M) x_j = M psi
       hipLaunchKernelGGL(rexi::k_apply_mass, dim3(std::min(h->itotal, 2048)), dim3(TPB), 0, st, h->dinst,
-                         h->ninst, h->ditile, h->itotal, src, h->mrhs, TPB * PPT);
+                         h->ninst, h->ditile, h->itotal, src, h->mrhs, INST_TILE);
       rhs = h->mrhs;
     }
     rexi_status s1 = solve(h, sv, rhs, rhs, st, &restarts);
@@ -2266,7 +2344,7 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
     {
       Timed t(h, PC_POLESUM, (double)h->N * 16.0 * (1.0 + (double)sv.S / h->ninst), st);
       hipLaunchKernelGGL(rexi::k_polesum, dim3(std::min(h->itotal, 2048)), dim3(TPB), 0, st, h->dinst, h->ninst,
-                         h->ditile, h->itotal, sv.dsys, sv.W.x, outp, TPB * PPT, 0, 0);
+                         h->ditile, h->itotal, sv.dsys, sv.W.x, outp, INST_TILE, 0, 0);
     }
     HIPCHK(h, hipGetLastError());
     if (info) {
@@ -2339,14 +2417,14 @@ rexi_status rexi_step_adjoint(rexi_handle* h, const rexi_c128* psi_n, const rexi
   if (dV_accum) {
     Timed t(h, PC_GRAD, (double)h->N * (32.0 * K + 16.0), st);
     hipLaunchKernelGGL(rexi::k_grad_v, dim3(std::min(h->itotal, 2048)), dim3(TPB), 0, st, h->dinst, h->ditile,
-                       h->itotal, sv.dsys, sv.W.x, dV_accum, TPB * PPT, K);
+                       h->itotal, sv.dsys, sv.W.x, dV_accum, INST_TILE, K);
     HIPCHK(h, hipGetLastError());
   }
   {
     // gbar_n = sum_j conj(w_j) y_j (systems K..2K-1 hold y_j; their weights are w_j)
     Timed t(h, PC_POLESUM, (double)h->N * 16.0 * (1.0 + K), st);
     hipLaunchKernelGGL(rexi::k_polesum, dim3(std::min(h->itotal, 2048)), dim3(TPB), 0, st, h->dinst, h->ninst,
-                       h->ditile, h->itotal, sv.dsys, sv.W.x, (double2*)gbar_n, TPB * PPT, 1, K);
+                       h->ditile, h->itotal, sv.dsys, sv.W.x, (double2*)gbar_n, INST_TILE, 1, K);
     HIPCHK(h, hipGetLastError());
   }
   // convergence of the 2K solves
@@ -2395,7 +2473,7 @@ rexi_status rexi_estimate_spectrum(rexi_handle* h, int32_t iters, double* lo_hos
   for (const auto& in : h->hinst)
     if (in.fem) return fail(h, REXI_E_INVALID_ARG, "the spectrum estimate is for the finite-difference H");
   hipStream_t st = (hipStream_t)stream;
-  const int S = h->ninst, T = h->itotal, tile = TPB * PPT;
+  const int S = h->ninst, T = h->itotal, tile = INST_TILE;
   const int64_t N = h->N;
   double2* basis = nullptr;
   double2* w = nullptr;

@@ -313,6 +313,90 @@ __device__ __forceinline__ double2 fem_point(const T* __restrict__ u, int n0, in
   return make_double2((double)ox, (double)oy);
 }
 
+// ---------------------------------------------------------------- Q1 shared basis
+// M = L L^T with L = L_0 (x) L_1 (x) L_2, L_a the bidiagonal Cholesky factor
+// of the 1D mass matrix of axis a (chol + loff[a]: diagonal d[n_a], then
+// subdiagonal e[n_a], e_0 = 0; an absent axis has d = 1). The solves
+// (A - s M) x = M psi become (Ahat - s) xhat = L^T psi with
+// Ahat = L^-1 A L^-T and x = L^-T xhat.
+
+// y = L^T x on one instance: (L_a^T)_{i,i} = d_i, (L_a^T)_{i,i+1} = e_{i+1}.
+__global__ __launch_bounds__(TPB) void k_fem_lt(InstDesc in, const double* __restrict__ chol,
+                                               const double2* __restrict__ x, double2* __restrict__ y) {
+  const double* d0 = chol + in.loff[0];
+  const double* d1 = chol + in.loff[1];
+  const double* d2 = chol + in.loff[2];
+  const int64_t plane = (int64_t)in.n1 * in.n2;
+  for (int64_t p = (int64_t)blockIdx.x * TPB + threadIdx.x; p < in.n; p += (int64_t)gridDim.x * TPB) {
+    const uint32_t r = fdiv((uint32_t)p, in.d2);
+    const int i2 = (int)(p - (int64_t)r * in.n2);
+    const int i0 = (int)fdiv(r, in.d1);
+    const int i1 = (int)(r - (uint32_t)i0 * (uint32_t)in.n1);
+    double t0[2] = {d0[i0], i0 + 1 < in.n0 ? d0[in.n0 + i0 + 1] : 0.0};
+    double t1[2] = {d1[i1], i1 + 1 < in.n1 ? d1[in.n1 + i1 + 1] : 0.0};
+    double t2[2] = {d2[i2], i2 + 1 < in.n2 ? d2[in.n2 + i2 + 1] : 0.0};
+    double2 acc = make_double2(0.0, 0.0);
+    for (int a = 0; a < 2; ++a) {
+      if (t0[a] == 0.0) continue;
+      for (int b = 0; b < 2; ++b) {
+        if (t1[b] == 0.0) continue;
+        for (int c = 0; c < 2; ++c) {
+          if (t2[c] == 0.0) continue;
+          const double f = t0[a] * t1[b] * t2[c];
+          const double2 v = x[in.off + p + a * plane + b * in.n2 + c];
+          acc.x += f * v.x;
+          acc.y += f * v.y;
+        }
+      }
+    }
+    y[in.off + p] = acc;
+  }
+}
+
+// One factor along axis `axis` of one instance, one thread per grid line:
+// backward = 0: dst = L_a^-1 src (v_i = (x_i - e_i v_{i-1}) / d_i);
+// backward = 1: dst = L_a^-T src (v_i = (x_i - e_{i+1} v_{i+1}) / d_i).
+// src may equal dst (each line's entry i is read before it is written).
+__global__ __launch_bounds__(TPB) void k_fem_sweep(InstDesc in, const double* __restrict__ chol,
+                                                  const double2* src, double2* dst, int axis, int backward) {
+  const int na = axis == 0 ? in.n0 : (axis == 1 ? in.n1 : in.n2);
+  const double* dg = chol + in.loff[axis];
+  const double* eg = dg + na;
+  const int64_t nl = in.n / na;
+  const int64_t plane = (int64_t)in.n1 * in.n2;
+  for (int64_t l = (int64_t)blockIdx.x * TPB + threadIdx.x; l < nl; l += (int64_t)gridDim.x * TPB) {
+    int64_t base, stride;
+    if (axis == 0) {
+      base = l;  // (i1, i2) = (l / n2, l % n2)
+      stride = plane;
+    } else if (axis == 1) {
+      base = (l / in.n2) * plane + l % in.n2;  // (i0, i2)
+      stride = in.n2;
+    } else {
+      base = l * in.n2;  // row (i0, i1)
+      stride = 1;
+    }
+    const double2* __restrict__ x = src + in.off + base;
+    double2* __restrict__ v = dst + in.off + base;
+    double2 prev = make_double2(0.0, 0.0);
+    if (!backward) {
+      for (int i = 0; i < na; ++i) {
+        const double2 xi = x[i * stride];
+        const double e = i > 0 ? eg[i] : 0.0, rd = 1.0 / dg[i];
+        prev = make_double2((xi.x - e * prev.x) * rd, (xi.y - e * prev.y) * rd);
+        v[i * stride] = prev;
+      }
+    } else {
+      for (int i = na - 1; i >= 0; --i) {
+        const double2 xi = x[i * stride];
+        const double e = i + 1 < na ? eg[i + 1] : 0.0, rd = 1.0 / dg[i];
+        prev = make_double2((xi.x - e * prev.x) * rd, (xi.y - e * prev.y) * rd);
+        v[i * stride] = prev;
+      }
+    }
+  }
+}
+
 template <typename T> __device__ __forceinline__ double vpot(const Work& W, int64_t idx);
 template <> __device__ __forceinline__ double vpot<double2>(const Work& W, int64_t idx) { return W.V64[idx]; }
 template <> __device__ __forceinline__ double vpot<float2>(const Work& W, int64_t idx) { return (double)W.V32[idx]; }
@@ -488,16 +572,20 @@ __global__ __launch_bounds__(TPB) void k_reduce_dots(Work W, int j, int second, 
 // MATVEC: w = c_j (H - s) u_j, written to u_{j+1}. Otherwise w = u_{j+1}
 // (second Gram-Schmidt pass). Partial sums of conj(u_i) w for lo <= i <= j,
 // and of ||w||^2, per tile.
+// PRE (with !MATVEC): the first pass on w = c_j z already formed as z in
+// u_{j+1} by an operator applied outside (the Q1 shared basis); w is scaled
+// and stored back, then the same dots from i0 as the matvec pass.
 template <typename T, int PPT, bool MATVEC>
-__global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0) {
+__global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pre) {
   __shared__ double2 red[NWAVE][MAXM + 1];
-  if (!MATVEC && W.reo_any && !W.reo_any[j]) return;  // no second pass at iteration j
-  const int lo = MATVEC ? i0 : 0;
+  if (!MATVEC && !pre && W.reo_any && !W.reo_any[j]) return;  // no second pass at iteration j
+  const bool first = MATVEC || pre;
+  const int lo = first ? i0 : 0;
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
     const int s = item_sys(W, item);
     const SysState_t& st = W.st[s];
     if (st.state != ST_ACTIVE) continue;
-    if (!MATVEC && !st.reorth) continue;
+    if (!first && !st.reorth) continue;
     const SysDesc& d = W.sys[s];
     const int t = item - d.tile0;
     const double cj = W.cscale[(int64_t)s * (W.m + 1) + j];
@@ -514,6 +602,13 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0) {
           double2 v = d.fem ? fem_point<T>(uj, d.n0, d.n1, d.n2, d.d2, d.d1, d.fmd, d.fmo, d.fkd, d.fko, d.fvol,
                                            vpot<T>(W, d.off + p), d.sre, d.sim, (uint32_t)p)
                             : stencil_point<T>(uj, d, vpot<T>(W, d.off + p), (uint32_t)p);
+          v.x *= cj;
+          v.y *= cj;
+          T vs = from_d2<T>(v);
+          unew[p] = vs;
+          w[q] = to_d2(vs);
+        } else if (pre) {
+          double2 v = to_d2(unew[p]);
           v.x *= cj;
           v.y *= cj;
           T vs = from_d2<T>(v);

@@ -86,6 +86,7 @@ struct InstDesc {
   int32_t pad;
   double fmd[3], fmo[3], fkd[3], fko[3];
   double fvol;
+  int64_t loff[3];   // Q1 shared basis: the Cholesky factor of axis a at chol + loff[a]
 };
 
 enum SysState : int32_t { ST_ACTIVE = 0, ST_FINISH = 1, ST_DONE = 2, ST_PAUSED = 3 };

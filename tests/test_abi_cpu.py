@@ -101,9 +101,21 @@ def test_shifted_solver_option_constraints(rx):
     o = rx.default_options(solver="shifted", precision="c64")
     st, msg = _setup_raw(rx, rx.make_grid((8,), (0,), (1,)), opt=o)
     assert st == rx.REXI_E_INVALID_ARG and "complex128" in msg
-    o = rx.default_options(solver="shifted", discretization="fem")
+    # Q1 elements on the shared basis: one instance, fallback 0 or 1
+    o = rx.default_options(solver="shifted", discretization="fem", fallback=2)
     st, msg = _setup_raw(rx, rx.make_grid((8,), (0,), (1,)), opt=o)
-    assert st == rx.REXI_E_INVALID_ARG and "per-pole" in msg
+    assert st == rx.REXI_E_INVALID_ARG and "fallback" in msg
+    o = rx.default_options(solver="shifted", discretization="fem")
+    G = (rx.Grid * 2)(rx.make_grid((8,), (0,), (1,)), rx.make_grid((6,), (0,), (1,)))
+    dbl = (C.c_double * 2)(1.0, 1.0)
+    Ks = (C.c_int32 * 2)(1, 1)
+    raw = rx._H()
+    st = rx._lib.rexi_setup_batch(C.byref(raw), 2, G, C.c_void_p(8), dbl, dbl, (C.c_double * 2)(0.1, 0.1), Ks,
+                                  rx._c128_array((5 + 1j, 5 + 1j)), rx._c128_array((1 + 0j, 1 + 0j)), C.byref(o),
+                                  None)
+    buf = C.create_string_buffer(256)
+    rx._lib.rexi_last_error(None, buf, 256)
+    assert st == rx.REXI_E_INVALID_ARG and "one instance" in buf.value.decode()
     o = rx.default_options(discretization=2)
     st, msg = _setup_raw(rx, rx.make_grid((8,), (0,), (1,)), opt=o)
     assert st == rx.REXI_E_INVALID_ARG

@@ -614,6 +614,49 @@ def test_fem_step_matches_oracle(rexi, name, scale, K, R1, prec):
     assert abs(infos[1]["norm_out"] / np.linalg.norm(ref[1]) - 1.0) < 1e-6
 
 
+@pytest.mark.parametrize("name,scale,K,R1,m", [("1d_harmonic", None, 16, 28.0, 256), ("2d_adjoint", 33, 32, 80.0, 256),
+                                               ("3d_bumps", 12, 64, 180.0, 256), ("3d_bumps", 12, 64, 180.0, 12)])
+def test_fem_shared_basis_step_matches_oracle(rexi, name, scale, K, R1, m):
+    # the mass-matrix step on one shared basis: M = L L^T (Kronecker product
+    # of the 1D Cholesky factors), solves on Ahat = L^-1 A L^-T from L^T psi,
+    # then L^-T; two steps (the second in place) against the oracle's direct
+    # solves of (A - s M) x = M psi. m = 12 forces restarts on the shared basis.
+    # The targets hold in the M-norm; Euclidean errors differ from M-norm ones
+    # by at most sqrt(cond M) <= 3^(d/2)
+    import torch
+    from oracle import fem
+    from paper_1912_03312_amd import rexi as r
+    wl = inputs.workload(name, scale=scale)
+    g = wl.grid
+    s, b, d = poles(K, R1)
+    cen = 1 if name == "1d_harmonic" else 0
+    lo, hi = fem.spectrum_bound(g.n, g.h, wl.V)
+    c = 0.5 * (lo + hi) if cen else 0.0
+    dt = min(wl.dt, 0.9 * R1 / (0.5 * (hi - lo) if cen else max(abs(lo), abs(hi))))
+    D = fem.FemDirectStepper(g.n, g.h, wl.V, s, b, dt, center=c)
+    ref = [D.step(wl.psi0)]
+    ref.append(D.step(ref[0]))
+    h = r.setup(g.n, g.lo, g.hi, to_dev(wl.V.ravel()), 1.0, 1.0, dt, s, b, solver="shifted", m=m, tol=1e-11,
+                tol_policy="certified", max_cycles=200, discretization="fem", center=cen)
+    x = to_dev(wl.psi0.ravel())
+    o1 = torch.empty_like(x)
+    i1 = h.step(x, o1, 1)
+    out1 = o1.cpu().numpy().reshape(g.n)
+    i2 = h.step(o1, o1, 1)
+    torch.cuda.synchronize()
+    out2 = o1.cpu().numpy().reshape(g.n)
+    h.close()
+    errs = [rel(out1, ref[0]), rel(out2, ref[1])]
+    kappa = 3.0 ** (g.ndim / 2.0)
+    bar = max(1e-10, 3 * fem_floor(g, wl.V, s, b, dt, c)) * kappa
+    print("fem shared", name, m, errs, bar, [(i["total_iterations"], i["max_cycles_used"]) for i in (i1, i2)])
+    assert i1["not_converged"] == 0 and i2["not_converged"] == 0
+    if m < 100:
+        assert i1["max_cycles_used"] > 1
+    assert max(errs) <= bar
+    assert abs(i1["norm_in"] / np.linalg.norm(wl.psi0) - 1.0) < 1e-12
+
+
 # ---------------------------------------------------------------- tunnelling
 @pytest.mark.parametrize("solver", ["shifted", "per_pole"])
 def test_tunnel_matches_oracle(rexi, solver):
