@@ -99,7 +99,10 @@ typedef enum {
                                A = (hbar^2/2m) K + h^d diag(V) (potential by
                                nodal quadrature), B = hbar M (consistent mass);
                                the step is sum_j w_j (A - s_j M)^{-1} M psi.
-                               Per-pole solver only; no adjoint              */
+                               Per-pole solver, or the shared-basis solver
+                               for one instance (M = L L^T with Kronecker
+                               Cholesky factors; Lanczos on L^-1 A L^-T from
+                               L^T psi, targets in the M-norm); no adjoint   */
 } rexi_discretization;
 
 typedef struct {
