@@ -148,6 +148,8 @@ struct rexi_handle {
   bool fem_shared = false;
   double* chol = nullptr;
   double2* fem_y = nullptr;
+  double2* fem_z = nullptr;           // second intermediate (the sweeps run out of place)
+  int fem_warm[3] = {0, 0, 0};        // warm-up entries of a segment per axis
   std::string err;
   Prof prof;
   int64_t ws_bytes = 0;
@@ -199,6 +201,7 @@ void destroy_handle(rexi_handle* h) {
   if (h->mrhs) (void)hipFree(h->mrhs);
   if (h->chol) (void)hipFree(h->chol);
   if (h->fem_y) (void)hipFree(h->fem_y);
+  if (h->fem_z) (void)hipFree(h->fem_z);
   if (h->fb_rhs) (void)hipFree(h->fb_rhs);
   if (h->hpin) (void)hipHostFree(h->hpin);
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -987,6 +990,17 @@ void set_row_planes(rexi_handle* h, Solver& sv, bool on);
 rexi_status apply_columns(rexi_handle* h, Solver& sv, int kh, int L, hipStream_t stream,
                           rexi::ShiftWork* SWp = nullptr);
 
+// One factor sweep of a Q1 shared-basis handle (src != dst): L_a^-1, or
+// L_a^-T when backward.
+void fem_sweep(const rexi_handle* h, const double2* src, double2* dst, int axis, int backward, hipStream_t st) {
+  const InstDesc& in = h->hinst[0];
+  const int na = axis == 0 ? in.n0 : (axis == 1 ? in.n1 : in.n2);
+  const int64_t threads = (int64_t)(in.n / na) * ((na + rexi::FEM_SEG - 1) / rexi::FEM_SEG);
+  const dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>((threads + rexi::FEM_TPB - 1) / rexi::FEM_TPB, 16384)));
+  hipLaunchKernelGGL(rexi::k_fem_sweep, g, dim3(rexi::FEM_TPB), 0, st, in, (const double*)h->chol, src, dst, axis,
+                     backward, h->fem_warm[axis]);
+}
+
 // One shared-basis solver: its basis and system table, per-pole data, cached
 // chunk graphs and the length of its last solve.
 struct ShiftCtx {
@@ -1136,13 +1150,14 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
       double2* un = b0 + (int64_t)(j + 1) * in.n;
       const dim3 gs(std::max(1, std::min((in.n + TPB - 1) / TPB, 2048)));
       Timed t(h, PC_ARNOLDI_A, n * (12 * 32.0 + (nproj + 1) * e + 8.0), strm);
-      for (int a = 0; a < 3; ++a)
-        hipLaunchKernelGGL(rexi::k_fem_sweep, gs, dim3(TPB), 0, strm, in, h->chol, a == 0 ? uj : h->fem_y,
-                           h->fem_y, a, 1);
-      hipLaunchKernelGGL(rexi::k_apply_h, dim3(std::min(h->itotal, 2048)), dim3(TPB), 0, strm, h->dinst, h->ninst,
-                         h->ditile, h->itotal, h->V64, (const double2*)h->fem_y, un, 0.0, 0.0, INST_TILE);
-      for (int a = 0; a < 3; ++a)
-        hipLaunchKernelGGL(rexi::k_fem_sweep, gs, dim3(TPB), 0, strm, in, h->chol, (const double2*)un, un, a, 0);
+      // L^-T: u_j -> z -> y -> z; A: z -> y; L^-1: y -> z -> y -> u_{j+1}
+      fem_sweep(h, uj, h->fem_z, 0, 1, strm);
+      fem_sweep(h, h->fem_z, h->fem_y, 1, 1, strm);
+      fem_sweep(h, h->fem_y, h->fem_z, 2, 1, strm);
+      hipLaunchKernelGGL(rexi::k_fem_apply, gs, dim3(TPB), 0, strm, in, h->V64, (const double2*)h->fem_z, h->fem_y);
+      fem_sweep(h, h->fem_y, h->fem_z, 0, 0, strm);
+      fem_sweep(h, h->fem_z, h->fem_y, 1, 0, strm);
+      fem_sweep(h, h->fem_y, un, 2, 0, strm);
       hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(G), dim3(TPB), 0, strm, W, j, i0, 1);
     } else {
       Timed t(h, PC_ARNOLDI_A, n * ((nproj + 1) * e + 8.0), strm);
@@ -1387,8 +1402,10 @@ rexi_status shifted_step(rexi_handle* h, const double2* b, double2* out, hipStre
   HIPCHK(h, hipGetLastError());
   rexi_status st = shifted_solve(h, fwd_ctx(h), h->mrhs, out, stream);
   if (st != REXI_OK) return st;
-  for (int a = 0; a < 3; ++a)
-    hipLaunchKernelGGL(rexi::k_fem_sweep, gs, dim3(TPB), 0, stream, in, h->chol, (const double2*)out, out, a, 1);
+  // L^-T of the sum: out -> y -> z -> out
+  fem_sweep(h, out, h->fem_y, 0, 1, stream);
+  fem_sweep(h, h->fem_y, h->fem_z, 1, 1, stream);
+  fem_sweep(h, h->fem_z, out, 2, 1, stream);
   HIPCHK(h, hipGetLastError());
   return REXI_OK;
 }
@@ -1942,10 +1959,18 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
     for (int a = 0; a < 3; ++a) {
       in.loff[a] = (int64_t)chol.size();
       std::vector<double> d((size_t)na[a]), e((size_t)na[a], 0.0);
+      // rho: the largest factor by which a sweep step carries an error in v,
+      // |e_i / d_i| forward (L^-1) and |e_{i+1} / d_i| backward (L^-T)
+      double rho = 0.0;
       for (int i = 0; i < na[a]; ++i) {
         if (i > 0) e[i] = in.fmo[a] / d[i - 1];
         d[i] = std::sqrt(in.fmd[a] - e[i] * e[i]);
+        rho = std::max(rho, std::fabs(e[i] / d[i]));
+        if (i > 0) rho = std::max(rho, std::fabs(e[i] / d[i - 1]));
       }
+      // warm-up of a segment: rho^warm <= 2^-64 (the whole line if rho is near 1)
+      h->fem_warm[a] = rho > 0.0 && rho < 0.9 ? std::min(na[a], (int)std::ceil(-64.0 * std::log(2.0) / std::log(rho)))
+                                              : (rho > 0.0 ? na[a] : 0);
       chol.insert(chol.end(), d.begin(), d.end());
       chol.insert(chol.end(), e.begin(), e.end());
     }
@@ -1978,6 +2003,7 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
     SETUP_CHK(hipMalloc(&h->chol, chol.size() * sizeof(double)));
     SETUP_CHK(hipMemcpyAsync(h->chol, chol.data(), chol.size() * sizeof(double), hipMemcpyHostToDevice, stream));
     SETUP_CHK(hipMalloc(&h->fem_y, (size_t)N * sizeof(double2)));
+    SETUP_CHK(hipMalloc(&h->fem_z, (size_t)N * sizeof(double2)));
   }
   SETUP_CHK(hipMemcpyAsync(h->dinst, h->hinst.data(), count * sizeof(InstDesc), hipMemcpyHostToDevice, stream));
   SETUP_CHK(hipMemcpyAsync(h->ditile, h->hitile.data(), (count + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));

@@ -353,18 +353,89 @@ __global__ __launch_bounds__(TPB) void k_fem_lt(InstDesc in, const double* __res
   }
 }
 
-// One factor along axis `axis` of one instance, one thread per grid line:
+// y = A x on one Q1 instance (the element operator without shift: stiffness
+// (hbar^2/2m) K plus h^d V by nodal quadrature), each thread a run of FEM_R
+// consecutive points along the fastest axis: per row of the 3 x 3
+// neighbourhood it loads FEM_R + 2 values once for all FEM_R outputs.
+constexpr int FEM_R = 4;
+__global__ __launch_bounds__(TPB) void k_fem_apply(InstDesc in, const double* __restrict__ V,
+                                                  const double2* __restrict__ x, double2* __restrict__ y) {
+  const int n0 = in.n0, n1 = in.n1, n2 = in.n2;
+  const int runs = (n2 + FEM_R - 1) / FEM_R;
+  const int64_t total = (int64_t)n0 * n1 * runs;
+  const int64_t plane = (int64_t)n1 * n2;
+  const double2* u = x + in.off;
+  for (int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x; q < total; q += (int64_t)gridDim.x * TPB) {
+    const int64_t row = q / runs;
+    const int i2 = (int)(q - row * runs) * FEM_R;
+    const int i0 = (int)(row / n1), i1 = (int)(row - (int64_t)i0 * n1);
+    double mx[FEM_R], my[FEM_R], kx[FEM_R], ky[FEM_R];
+#pragma unroll
+    for (int r = 0; r < FEM_R; ++r) mx[r] = my[r] = kx[r] = ky[r] = 0.0;
+    for (int e0 = -1; e0 <= 1; ++e0) {
+      if (i0 + e0 < 0 || i0 + e0 >= n0) continue;
+      const double m0 = e0 ? in.fmo[0] : in.fmd[0], k0 = e0 ? in.fko[0] : in.fkd[0];
+      for (int e1 = -1; e1 <= 1; ++e1) {
+        if (i1 + e1 < 0 || i1 + e1 >= n1) continue;
+        const double m1 = e1 ? in.fmo[1] : in.fmd[1], k1 = e1 ? in.fko[1] : in.fkd[1];
+        const double2* ur = u + (int64_t)(i0 + e0) * plane + (int64_t)(i1 + e1) * n2;
+        // the row's values at i2 - 1 .. i2 + FEM_R (zero outside the grid)
+        double2 w[FEM_R + 2];
+#pragma unroll
+        for (int k = 0; k < FEM_R + 2; ++k) {
+          const int c = i2 - 1 + k;
+          w[k] = (c >= 0 && c < n2) ? ur[c] : make_double2(0.0, 0.0);
+        }
+        const double mm = m0 * m1, kk = k0 * m1 + m0 * k1;
+#pragma unroll
+        for (int r = 0; r < FEM_R; ++r) {
+          const double2 a = w[r], b = w[r + 1], c = w[r + 2];
+          const double sx = in.fmd[2] * b.x + in.fmo[2] * (a.x + c.x), sy = in.fmd[2] * b.y + in.fmo[2] * (a.y + c.y);
+          const double tx = in.fkd[2] * b.x + in.fko[2] * (a.x + c.x), ty = in.fkd[2] * b.y + in.fko[2] * (a.y + c.y);
+          mx[r] += mm * sx;
+          my[r] += mm * sy;
+          kx[r] += kk * sx + mm * tx;
+          ky[r] += kk * sy + mm * ty;
+        }
+      }
+    }
+    const int64_t p0 = (int64_t)i0 * plane + (int64_t)i1 * n2 + i2;
+#pragma unroll
+    for (int r = 0; r < FEM_R; ++r) {
+      if (i2 + r >= n2) break;
+      const double2 c = u[p0 + r];
+      const double a = in.fvol * V[in.off + p0 + r];
+      y[in.off + p0 + r] = make_double2(kx[r] + a * c.x, ky[r] + a * c.y);
+    }
+  }
+}
+
+// One factor along axis `axis` of one instance:
 // backward = 0: dst = L_a^-1 src (v_i = (x_i - e_i v_{i-1}) / d_i);
 // backward = 1: dst = L_a^-T src (v_i = (x_i - e_{i+1} v_{i+1}) / d_i).
-// src may equal dst (each line's entry i is read before it is written).
-__global__ __launch_bounds__(TPB) void k_fem_sweep(InstDesc in, const double* __restrict__ chol,
-                                                  const double2* src, double2* dst, int axis, int backward) {
+// Each thread takes one segment of FEM_SEG entries of one grid line and
+// starts the recurrence `warm` entries before it (in sweep order) from
+// v = 0: an error in v shrinks by |e/d| <= rho per step, so the segment
+// differs from the exact sweep by at most rho^warm max|v| (the host picks
+// warm with rho^warm below 2^-64; for the Q1 mass factors rho ~ 0.27). The
+// segments of a line are independent, so a sweep has n / n_a * ceil(n_a /
+// FEM_SEG) threads instead of n / n_a. src and dst must differ.
+constexpr int FEM_SEG = 32;
+constexpr int FEM_TPB = 64;
+__global__ __launch_bounds__(FEM_TPB) void k_fem_sweep(InstDesc in, const double* __restrict__ chol,
+                                                      const double2* __restrict__ src, double2* __restrict__ dst,
+                                                      int axis, int backward, int warm) {
   const int na = axis == 0 ? in.n0 : (axis == 1 ? in.n1 : in.n2);
   const double* dg = chol + in.loff[axis];
   const double* eg = dg + na;
   const int64_t nl = in.n / na;
+  const int nseg = (na + FEM_SEG - 1) / FEM_SEG;
   const int64_t plane = (int64_t)in.n1 * in.n2;
-  for (int64_t l = (int64_t)blockIdx.x * TPB + threadIdx.x; l < nl; l += (int64_t)gridDim.x * TPB) {
+  for (int64_t q = (int64_t)blockIdx.x * FEM_TPB + threadIdx.x; q < nl * nseg; q += (int64_t)gridDim.x * FEM_TPB) {
+    // consecutive threads take consecutive lines of one segment (coalesced
+    // along the fastest axis for axes 0 and 1)
+    const int sg = (int)(q / nl);
+    const int64_t l = q - (int64_t)sg * nl;
     int64_t base, stride;
     if (axis == 0) {
       base = l;  // (i1, i2) = (l / n2, l % n2)
@@ -376,23 +447,19 @@ __global__ __launch_bounds__(TPB) void k_fem_sweep(InstDesc in, const double* __
       base = l * in.n2;  // row (i0, i1)
       stride = 1;
     }
-    const double2* __restrict__ x = src + in.off + base;
-    double2* __restrict__ v = dst + in.off + base;
+    const double2* x = src + in.off + base;
+    double2* v = dst + in.off + base;
+    // positions k = 0 .. na-1 in sweep order; this segment writes [k0, k1)
+    const int k0 = sg * FEM_SEG, k1 = min(na, k0 + FEM_SEG);
+    const int ks = max(0, k0 - warm);
     double2 prev = make_double2(0.0, 0.0);
-    if (!backward) {
-      for (int i = 0; i < na; ++i) {
-        const double2 xi = x[i * stride];
-        const double e = i > 0 ? eg[i] : 0.0, rd = 1.0 / dg[i];
-        prev = make_double2((xi.x - e * prev.x) * rd, (xi.y - e * prev.y) * rd);
-        v[i * stride] = prev;
-      }
-    } else {
-      for (int i = na - 1; i >= 0; --i) {
-        const double2 xi = x[i * stride];
-        const double e = i + 1 < na ? eg[i + 1] : 0.0, rd = 1.0 / dg[i];
-        prev = make_double2((xi.x - e * prev.x) * rd, (xi.y - e * prev.y) * rd);
-        v[i * stride] = prev;
-      }
+    for (int k = ks; k < k1; ++k) {
+      const int i = backward ? na - 1 - k : k;
+      const double2 xi = x[i * stride];
+      const double e = backward ? (i + 1 < na ? eg[i + 1] : 0.0) : (i > 0 ? eg[i] : 0.0);
+      const double rd = 1.0 / dg[i];
+      prev = make_double2((xi.x - e * prev.x) * rd, (xi.y - e * prev.y) * rd);
+      if (k >= k0) v[i * stride] = prev;
     }
   }
 }
