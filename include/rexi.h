@@ -126,7 +126,9 @@ typedef struct {
                           partial reorthogonalisation. 1 (default): one fused
                           pass per iteration (update of u_{j+1} and the next
                           matvec together); 2: separate update and matvec
-                          passes; 0: full Arnoldi with DGKS                  */
+                          passes; 0: full Arnoldi with DGKS. Q1 elements
+                          on the shared basis always take 2 (their matvec
+                          is formed outside the pass kernels)            */
   int32_t capture_safe;/* 1: rexi_step(info = NULL) runs a fixed schedule
                           with no host reads (all m iterations; per-pole:
                           capture_cycles cycles), finished poles skipped on

@@ -88,3 +88,36 @@ def test_fem_direct_step_matches_generalised_eigen_route(n):
     nin = np.real(np.vdot(psi, E.Mdense @ psi))
     nout = np.real(np.vdot(a, E.Mdense @ a))
     assert abs(nout / nin - 1.0) <= 4.0 * d["err_inf"]
+
+
+def test_segmented_factor_sweep_bound():
+    # The Q1 shared basis solves with the bidiagonal Cholesky factor of the 1D
+    # mass matrix (h/6) tridiag(1, 4, 1) in independent segments that start
+    # `warm` entries early from zero. A step of the recurrence carries an error
+    # by |e_i/d_i| (forward) or |e_{i+1}/d_i| (backward), at most
+    # 1/(2 + sqrt 3); with warm = ceil(64 ln 2 / -ln rho) the segments agree
+    # with the exact sweep to rho^warm * max|v| (checked here against dense
+    # triangular solves of the factor, on the host).
+    import numpy as np
+    for n, h in [(128, 0.1), (77, 0.37)]:
+        M = fem.mass_1d(n, h).toarray()
+        L = np.linalg.cholesky(M)
+        d, e = np.diag(L), np.concatenate([[0.0], np.diag(L, -1)])
+        rho = max(np.max(e[1:] / d[1:]), np.max(e[1:] / d[:-1]))
+        assert rho <= 1.0 / (2.0 + np.sqrt(3.0)) + 1e-15
+        warm = int(np.ceil(-64.0 * np.log(2.0) / np.log(rho)))
+        assert warm == 34
+        rng = np.random.default_rng(3)
+        x = rng.standard_normal(n)
+        for backward in (False, True):
+            exact = np.linalg.solve(L.T if backward else L, x)
+            seg = np.empty(n)
+            for k0 in range(0, n, 32):
+                prev = 0.0
+                for k in range(max(0, k0 - warm), min(n, k0 + 32)):
+                    i = n - 1 - k if backward else k
+                    ee = (e[i + 1] if i + 1 < n else 0.0) if backward else e[i]
+                    prev = (x[i] - ee * prev) / d[i]
+                    if k >= k0:
+                        seg[i] = prev
+            assert np.max(np.abs(seg - exact)) <= 1e-14 * np.max(np.abs(exact))
