@@ -501,6 +501,55 @@ def test_uneven_batch_matches_oracle_per_instance(rexi, solver, prec):
     h.close()
 
 
+def test_full_uneven_batch_sampled_instances_match_oracle(rexi):
+    # the uneven batch at its full size (256 instances, ~27M points, the
+    # launch configuration the benchmark times: shared basis m = 256 with
+    # restarts): every pole converges, and the four smallest instances match
+    # the oracle's direct solves within the bound
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    insts = inputs.batch_instances(count=256)
+    grids, Vs, psis, dts, Ks, sig, bet = [], [], [], [], [], [], []
+    for it in insts:
+        g = it["grid"]
+        s, b, d = poles(it["K"], inputs.R1_PARITY[it["K"]])
+        grids.append((g.n, g.lo, g.hi))
+        Vs.append(it["V"].ravel())
+        psis.append(it["psi0"].ravel())
+        dts.append(it["dt"])
+        Ks.append(it["K"])
+        sig.append(s)
+        bet.append(b)
+    cnt = len(insts)
+    h = r.setup_batch(grids, to_dev(np.concatenate(Vs)), [1.0] * cnt, [1.0] * cnt, dts, Ks, np.concatenate(sig),
+                      np.concatenate(bet), solver="shifted", m=256, max_cycles=200, tol=1e-10)
+    p0 = to_dev(np.concatenate(psis))
+    out = torch.empty_like(p0)
+    info = h.step(p0, out, 1)
+    torch.cuda.synchronize()
+    h.close()
+    assert info["not_converged"] == 0
+    offs = np.cumsum([0] + [v.size for v in Vs])
+    poff = np.cumsum([0] + Ks)
+    rr = np.array(info["rel_residual"])
+    order = sorted(range(cnt), key=lambda i: Vs[i].size)[:4]
+    errs = []
+    for i in order:
+        g = insts[i]["grid"]
+        ref = ost.DirectStepper(g.n, g.h, insts[i]["V"], sig[i], bet[i], dts[i]).step(insts[i]["psi0"]).ravel()
+        res = out[int(offs[i]):int(offs[i + 1])].cpu().numpy()
+        e = rel(res, ref)
+        # this instance's certificate: sum_p |w_p| rho_p / dist(s_p, spectrum bound)
+        lo, hi = ham.gershgorin(g.n, g.h, insts[i]["V"])
+        sj, wj = ost.shifts_and_weights(sig[i], bet[i], dts[i])
+        dist = np.abs(np.clip(sj.real, lo, hi) - sj)
+        bound = float(np.sum(np.abs(wj) * rr[poff[i]:poff[i + 1]] / dist))
+        bar = bound + 3 * iterative_floor(g, insts[i]["V"], sig[i], bet[i], dts[i])
+        errs.append((i, g.n, Ks[i], e, bar))
+        assert e <= bar, errs[-1]
+    print("full batch", info["total_iterations"], info["max_cycles_used"], errs)
+
+
 # ---------------------------------------------------------------- setup variants
 @pytest.mark.parametrize("solver", ["shifted", "per_pole"])
 @pytest.mark.parametrize("name,scale,K,R1", [("1d_harmonic", None, 16, 28.0), ("3d_bumps", 12, 64, 180.0)])
