@@ -57,6 +57,8 @@ struct Solver {
   int col_kh = 0, col_L = 0, col_total = 0;
   std::vector<int32_t> hcol;
   int32_t* dcol = nullptr;
+  int32_t* dcolsys = nullptr;  // system of each marching item (sized for any plan that fits)
+  int64_t colsys_cap = 0;
   // a solver whose systems change between runs (fallback solves) is built
   // for at most cap_S systems of cap_pts points in total
   int cap_S = 0;
@@ -397,6 +399,13 @@ rexi_status build_solver(rexi_handle* h, Solver& sv, hipStream_t stream) {
   ALLOC(W.part, double, npart * 2);
   ALLOC(W.pnorm, double, ntmax);
   if (sv.cap_S == 0) ALLOC(sv.dtsys, int32_t, ntmax);
+  if (sv.cap_S == 0) {
+    // a marching plan fits when 6 max(ntiles, items) <= (m + 1) ntiles per system
+    int64_t cap = 0;
+    for (auto& d : sv.hsys) cap += (int64_t)(m + 1) * ((d.n + 2 * TPB_ - 1) / (2 * TPB_)) / 6 + 1;
+    sv.colsys_cap = cap;
+    ALLOC(sv.dcolsys, int32_t, cap);
+  }
   ALLOC(W.counters, int32_t, sv.max_cycles * (m + 1) + sv.max_cycles + 4);
   ALLOC(W.x, double, nx * 2);
   if (sv.prec) {
@@ -1549,6 +1558,7 @@ rexi_status apply_tiling(rexi_handle* h, Solver& sv, int ppt, int grid, hipStrea
   if (h->shifted) {
     rexi::ShiftWork& SW = SWp ? *SWp : h->SW;
     SW.col_start = nullptr;
+    SW.col_sys = nullptr;
     SW.col_total = 0;
   }
   return REXI_OK;
@@ -1582,6 +1592,7 @@ rexi_status apply_columns(rexi_handle* h, Solver& sv, int kh, int L, hipStream_t
   rexi::ShiftWork& SW = SWp ? *SWp : h->SW;
   sv.col_kh = 0;
   SW.col_start = nullptr;
+  SW.col_sys = nullptr;
   SW.col_total = 0;
   set_row_planes(h, sv, kh != 0);
   if (kh == 0 || !plan_columns(sv, kh, L)) {
@@ -1592,8 +1603,16 @@ rexi_status apply_columns(rexi_handle* h, Solver& sv, int kh, int L, hipStream_t
   }
   HIPCHK(h, hipMemcpyAsync(sv.dsys, sv.hsys.data(), sv.S * sizeof(SysDesc), hipMemcpyHostToDevice, stream));
   HIPCHK(h, hipMemcpyAsync(sv.dcol, sv.hcol.data(), (sv.S + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  std::vector<int32_t> csys;
+  if (sv.dcolsys && sv.col_total <= sv.colsys_cap) {
+    csys.resize((size_t)sv.col_total);
+    for (int q = 0; q < sv.S; ++q)
+      for (int it = sv.hcol[q]; it < sv.hcol[q + 1]; ++it) csys[it] = q;
+    HIPCHK(h, hipMemcpyAsync(sv.dcolsys, csys.data(), csys.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+  }
   HIPCHK(h, hipStreamSynchronize(stream));
   SW.col_start = sv.dcol;
+  SW.col_sys = csys.empty() ? nullptr : sv.dcolsys;
   SW.col_total = sv.col_total;
   return REXI_OK;
 }

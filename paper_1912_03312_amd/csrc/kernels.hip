@@ -566,6 +566,7 @@ struct ShiftWork {
   double* zb;         // [2][sum n] complex: z_j = H u_j of the pipelined recurrence
   int64_t zstride;    // complex elements per z buffer
   const int32_t* col_start;  // [S+1] prefix of column-marching items (null: unused)
+  const int32_t* col_sys;    // [col_total] system of each item (null: search col_start)
   int32_t col_total;
   int32_t fb_skip;    // 1: poles that missed their target (its = 0) are left out of z
   // Restarts on the shared basis. fom = 1: a pole that missed its target takes
@@ -1377,7 +1378,7 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
     // the system index is uniform: its descriptor is read once into scalar
     // registers (a reference would be re-read after every store, and each
     // re-read waits for the loads in flight)
-    const int s = __builtin_amdgcn_readfirstlane(find_sys(SW.col_start, W.S, item));
+    const int s = __builtin_amdgcn_readfirstlane(SW.col_sys ? SW.col_sys[item] : find_sys(SW.col_start, W.S, item));
     if (W.st[s].state != ST_ACTIVE) continue;
     const SysDesc& dref = W.sys[s];
     const int n0 = dref.n0, n1 = dref.n1, n2 = dref.n2;
