@@ -419,6 +419,38 @@ def test_graph_replays_match_eager(rexi, solver, prec):
     hg.close()
 
 
+def test_graph_replays_match_eager_fem_shared(rexi):
+    # the Q1 shared basis in a captured step: the transform, the factor sweeps
+    # and element operator of every iteration and the final L^-T all replay;
+    # every replay equals the eager step with host checks
+    import torch
+    from oracle import fem
+    from paper_1912_03312_amd import rexi as r
+    wl = inputs.workload("3d_bumps", scale=14)
+    g = wl.grid
+    s, b, d = poles(32, 80.0)
+    lo, hi = fem.spectrum_bound(g.n, g.h, wl.V)
+    dt = 0.9 * 80.0 / max(abs(lo), abs(hi))
+    Vd = to_dev(wl.V.ravel())
+    kw = dict(solver="shifted", discretization="fem", tol=1e-10, m=200)
+    he = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, dt, s, b, **kw)
+    hg = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, dt, s, b, capture_safe=1, **kw)
+    p0 = to_dev(wl.psi0.ravel())
+    ref = torch.empty_like(p0)
+    ie = he.step(p0, ref, 1)
+    assert ie["max_cycles_used"] == 1  # no restart: the captured schedule has none
+    out = torch.empty_like(p0)
+    for rep in range(3):
+        out.zero_()
+        hg.step(p0, out, 1, info=False)
+        junk = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        e = rel(out.cpu().numpy(), ref.cpu().numpy())
+        assert e <= 1e-13, (rep, e)
+    he.close()
+    hg.close()
+
+
 def test_step_inside_caller_graph_capture(rexi):
     # the caller captures rexi_step into its own torch CUDA graph
     import torch
