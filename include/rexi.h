@@ -37,7 +37,9 @@
  *     within that fixed schedule leaves its best iterate in the sum;
  *     rexi_step with info reports convergence.
  *   - Every call returns a rexi_status and never aborts or throws. After an
- *     error, rexi_last_error() holds a message. Handles are not thread-safe.
+ *     error, rexi_last_error() holds a message. Handles are not thread-safe;
+ *     distinct handles may be set up and used from different threads (the
+ *     setup tuner's cache is shared under a lock).
  */
 #ifndef REXI_H
 #define REXI_H

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1493,9 +1494,15 @@ struct TuneKey {
   int ppt, grid;
   int kh, L;  // fused Lanczos pass: 0 row-staged, else marching slots and planes
 };
+// The cache is shared by every handle of the process: tune_mutex guards it
+// (and the file named by REXI_TUNE_CACHE).
 std::vector<TuneKey>& tune_cache() {
   static std::vector<TuneKey> c;
   return c;
+}
+std::mutex& tune_mutex() {
+  static std::mutex mu;
+  return mu;
 }
 
 std::string tune_key(const rexi_handle* h, const Solver& sv) {
@@ -1512,6 +1519,7 @@ std::string tune_key(const rexi_handle* h, const Solver& sv) {
   return k;
 }
 
+// (callers hold tune_mutex)
 void tune_cache_load() {
   static bool loaded = false;
   if (loaded) return;
@@ -1531,6 +1539,7 @@ void tune_cache_load() {
 }
 
 void tune_cache_store(const std::string& key, int ppt, int grid, int kh, int L) {
+  std::lock_guard<std::mutex> lock(tune_mutex());
   tune_cache().push_back({key, ppt, grid, kh, L});
   const char* f = getenv("REXI_TUNE_CACHE");
   if (!f) return;
@@ -1651,15 +1660,25 @@ void tune_launch(rexi_handle* h, Solver& sv, const double2* b, int iters, hipStr
 }
 
 rexi_status autotune(rexi_handle* h, Solver& sv, hipStream_t stream) {
-  tune_cache_load();
   const std::string key = tune_key(h, sv);
   const bool march = h->shifted && h->opt.lanczos == 1 && h->opt.march_planes == 0;
-  for (auto& c : tune_cache())
-    if (c.key == key) {
-      rexi_status st = apply_tiling(h, sv, c.ppt, c.grid, stream);
-      if (st == REXI_OK && march) st = apply_columns(h, sv, c.kh, c.L, stream);
-      return st;
-    }
+  bool found = false;
+  TuneKey hit{};
+  {
+    std::lock_guard<std::mutex> lock(tune_mutex());
+    tune_cache_load();
+    for (auto& c : tune_cache())
+      if (c.key == key) {
+        hit = c;
+        found = true;
+        break;
+      }
+  }
+  if (found) {
+    rexi_status st = apply_tiling(h, sv, hit.ppt, hit.grid, stream);
+    if (st == REXI_OK && march) st = apply_columns(h, sv, hit.kh, hit.L, stream);
+    return st;
+  }
   double2* rhs = nullptr;
   if (hipMalloc(&rhs, (size_t)h->N * sizeof(double2)) != hipSuccess) {
     (void)hipGetLastError();
