@@ -14,9 +14,19 @@
  * Section 3.2. The caller supplies the dimensionless (sigma_j, beta_j);
  * they are computed once, on the host, and do not depend on psi (Section 3.1).
  *
- * Every shifted system is solved by restarted GMRES (x0 = 0) driven by a
- * matrix-free stencil matvec on the GPU, all poles batched together; the
- * weighted pole sum is accumulated on the GPU in FP64 in a fixed pole order.
+ * Two solvers (option solver):
+ *   - per pole: every shifted system is solved by restarted GMRES (x0 = 0)
+ *     driven by a matrix-free stencil matvec on the GPU, all poles batched
+ *     together; the weighted pole sum is accumulated in FP64 in a fixed
+ *     pole order;
+ *   - shared basis: with x0 = 0 all poles of an instance share one Krylov
+ *     space, so one Lanczos process on H (partial reorthogonalisation)
+ *     serves every pole through its own small least-squares problem, and the
+ *     pole sum is one combination of the basis (Section 5 names such shifted
+ *     Krylov methods); poles that need more than m vectors restart on a
+ *     shared basis too (option fallback).
+ * The mass-matrix form with Q1 elements (option discretization) takes
+ * either solver.
  *
  * Grid and layout
  *   n[a] interior points per axis a on [lo[a], hi[a]], zero Dirichlet values
