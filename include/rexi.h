@@ -169,7 +169,10 @@ typedef struct {
                            band of rows does not fit)                         */
   int32_t march_slots;  /* marching pass: points per thread and plane, 3, 5
                            or 8 (0 = 5); a band holds 256 slots / n2 - 2
-                           rows of the plane                                 */
+                           rows of the plane. 2: the tiled pass, items of
+                           16 x 32 points of the plane, which forms H u_j in
+                           the pass and stores no z (56 B per point instead
+                           of 88; instances below 2^27 points)              */
   int32_t fallback;     /* shared-basis solver, poles that miss their target
                            within m vectors:
                            1 (default) restarts on the shared basis: such a
@@ -351,8 +354,8 @@ rexi_status rexi_workspace_info(const rexi_handle* h, int64_t* bytes, int32_t* m
 typedef struct {
   int32_t tile;          /* points per work tile of the grid-stride passes    */
   int32_t grid_blocks;   /* workgroups of the grid-stride passes              */
-  int32_t march_slots;   /* fused Lanczos pass: 0 row-staged, else points per
-                            thread and plane of the marching pass             */
+  int32_t march_slots;   /* fused Lanczos pass: 0 row-staged, 2 tiled, else
+                            points per thread and plane of the marching pass */
   int32_t march_planes;  /* planes per marching work item (0: row-staged)     */
   int32_t march_items;   /* marching work items over all instances            */
   int32_t reserved_;

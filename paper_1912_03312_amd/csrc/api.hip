@@ -313,13 +313,19 @@ constexpr int TPB_ = rexi::TPB;
 // system's rows do not fit or its six partial-sum slots (two parities of
 // three, max(ntiles, items) entries each) exceed its partial-sum block of
 // (m + 1) ntiles entries.
+// kh = 2: the tiled pass, tiles of ZT_R x ZT_C points of the plane (any
+// grid fits; tiles at the edges are clipped).
 bool plan_columns(Solver& sv, int kh, int L) {
   struct Plan { int rows, Lc, nr, n; };
   std::vector<Plan> pl;
   for (auto& d : sv.hsys) {
-    const int rows = std::min(d.n1, TPB_ * kh / d.n2 - 2);
+    const bool tiled = kh == 2;
+    const int rows = tiled ? rexi::ZT_R : std::min(d.n1, TPB_ * kh / d.n2 - 2);
     if (rows < 1) return false;
-    const int nb = (d.n1 + rows - 1) / rows;
+    // the tiled pass addresses a vector with 32-bit byte offsets below 2^31
+    if (tiled && (int64_t)d.n * 16 >= ((int64_t)1 << 31)) return false;
+    const int nb = tiled ? ((d.n1 + rexi::ZT_R - 1) / rexi::ZT_R) * ((d.n2 + rexi::ZT_C - 1) / rexi::ZT_C)
+                         : (d.n1 + rows - 1) / rows;
     const int Lc = std::min(L, d.n0);
     const int nr = (d.n0 + Lc - 1) / Lc;
     const int64_t items = (int64_t)nb * nr;
@@ -979,6 +985,14 @@ void launch_lz_step(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork
                     bool fused = false) {
   if (sv.col_kh) {
     switch (sv.col_kh) {
+      case 2:
+        if (fused) {
+          const dim3 g((j < sv.m ? sv.col_total : 0) + 1);
+          hipLaunchKernelGGL((rexi::k_lz_step_tile<true>), g, dim3(TPB), 0, strm, W, SW, j);
+        } else {
+          hipLaunchKernelGGL((rexi::k_lz_step_tile<false>), dim3(sv.col_total), dim3(TPB), 0, strm, W, SW, j);
+        }
+        return;
       case 3: launch_col<3>(sv, W, SW, j, fused, strm); return;
       case 5: launch_col<5>(sv, W, SW, j, fused, strm); return;
       default: launch_col<8>(sv, W, SW, j, fused, strm); return;
@@ -1126,19 +1140,24 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
   // iteration); iteration(j) then launches that pass, after a plain pass for
   // the first iteration and after every second Gram-Schmidt pass
   const bool fuse = pipe && pause_mode && S == 1 && sv.col_kh != 0;
+  // algorithmic bytes per point of the pass of iteration j: reads z_j, u_j,
+  // u_{j-1}, V and writes u_{j+1}, z_{j+1} (no u_{j-1} at j = 0); the tiled
+  // pass forms z_j in place and stores no z
+  const bool ztile = sv.col_kh == 2;
+  auto lz_bytes = [&](int j) { return ztile ? (j > 0 ? 56.0 : 40.0) : (j > 0 ? 88.0 : 72.0); };
   auto plain_step = [&](int j, hipStream_t strm) {
-    Timed t(h, PC_LANCZOS, n * (j > 0 ? 88.0 : 72.0), strm);
+    Timed t(h, PC_LANCZOS, n * lz_bytes(j), strm);
     launch_lz_step<PPT>(sv, W, SWl, j, strm);
   };
   auto iteration = [&](int j, hipStream_t strm) {
     if (fuse) {
-      Timed t(h, PC_LANCZOS, j + 1 < m ? n * 88.0 : 0.0, strm);
+      Timed t(h, PC_LANCZOS, j + 1 < m ? n * lz_bytes(j + 1) : 0.0, strm);
       launch_lz_step<PPT>(sv, W, SWl, j + 1, strm, true);
       return;
     }
     if (pipe) {
       {
-        Timed t(h, PC_LANCZOS, n * (j > 0 ? 88.0 : 72.0), strm);
+        Timed t(h, PC_LANCZOS, n * lz_bytes(j), strm);
         launch_lz_step<PPT>(sv, W, SWl, j, strm);
       }
       {
@@ -1603,7 +1622,7 @@ rexi_status apply_columns(rexi_handle* h, Solver& sv, int kh, int L, hipStream_t
   SW.col_start = nullptr;
   SW.col_sys = nullptr;
   SW.col_total = 0;
-  set_row_planes(h, sv, kh != 0);
+  set_row_planes(h, sv, kh != 0 && kh != 2);  // the tiled pass keeps the instance's geometry
   if (kh == 0 || !plan_columns(sv, kh, L)) {
     set_row_planes(h, sv, false);
     HIPCHK(h, hipMemcpyAsync(sv.dsys, sv.hsys.data(), sv.S * sizeof(SysDesc), hipMemcpyHostToDevice, stream));
@@ -1729,7 +1748,7 @@ rexi_status autotune(rexi_handle* h, Solver& sv, hipStream_t stream) {
   int best_kh = 0, best_L = 0;
   if (st == REXI_OK && march) {
     best = 1e30f;
-    for (int kh : {0, 3, 5, 8}) {
+    for (int kh : {0, 3, 5, 8, 2}) {
       for (int L : {4, 8, 16}) {
         if (kh == 0 && L != 4) continue;
         if ((st = apply_columns(h, sv, kh, L, stream)) != REXI_OK) break;
@@ -1847,8 +1866,8 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
     return fail(nullptr, REXI_E_INVALID_ARG, "tile must be 0 (tuned), 512, 1024 or 2048 points");
   if (o.march_planes < -1 || o.march_planes > 1024)
     return fail(nullptr, REXI_E_INVALID_ARG, "march_planes must be in [-1, 1024]");
-  if (o.march_slots != 0 && o.march_slots != 3 && o.march_slots != 5 && o.march_slots != 8)
-    return fail(nullptr, REXI_E_INVALID_ARG, "march_slots must be 0, 3, 5 or 8");
+  if (o.march_slots != 0 && o.march_slots != 2 && o.march_slots != 3 && o.march_slots != 5 && o.march_slots != 8)
+    return fail(nullptr, REXI_E_INVALID_ARG, "march_slots must be 0, 2, 3, 5 or 8");
   if (o.fallback < 0 || o.fallback > 2) return fail(nullptr, REXI_E_INVALID_ARG, "fallback must be 0, 1 or 2");
   if (o.fallback_m < 1 || o.fallback_m > 256)
     return fail(nullptr, REXI_E_INVALID_ARG, "fallback_m must be in [1, 256]");

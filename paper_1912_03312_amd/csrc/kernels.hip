@@ -1560,6 +1560,238 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
   }
 }
 
+// Tiled marching pass (no stored z): the same iteration as k_lz_step_col, but
+// H u_j is formed inside the pass, so z is neither read nor written (a point
+// moves u_j, u_{j-1}, V and u_{j+1}: 56 B instead of 88 B). An item is a tile
+// of ZT_R x ZT_C points of the (i1, i2) plane over col_L consecutive planes.
+// Its region holds one halo row/column before the tile and two after: u_j is
+// read on the whole region, u_{j+1} = c_j H u_j - alpha_j c_j u_j -
+// beta_j c_{j-1} u_{j-1} is formed on the tile and one ring after it, and
+// <u_{j+1}, H u_{j+1}> comes from the energy form of the Hermitian stencil,
+//   <u, H u> = sum_i V_i |u_i|^2 + sum_a c_a sum_i (|u_i - u_{i+e_a}|^2
+//              + [i_a = 0] |u_i|^2)   (u = 0 outside the grid),
+// which needs only forward neighbours. Along the planes u_j of three planes
+// and u_{j+1} of two stay in registers; in-plane neighbours come from LDS.
+// Every global access is a raw buffer access: a slot outside the grid or the
+// item's planes takes an offset past the buffer's end, which the hardware's
+// range check turns into a zero load or a dropped store. The steps are
+// therefore straight-line code, and the loads issued one step ahead are
+// waited for only where they are used.
+constexpr int ZT_R = 16, ZT_C = 32;
+constexpr int ZT_W = ZT_C + 3;              // region width
+constexpr int ZT_N = ZT_W * (ZT_R + 3);     // region slots
+constexpr int ZT_KH = (ZT_N + TPB - 1) / TPB;
+constexpr uint32_t ZT_OOB = 0x80000000u;    // past the end of every buffer (records < 2^31 bytes)
+
+typedef unsigned int zt_u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int zt_u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t zt_rsrc(const void* p, uint32_t bytes) {
+  // raw buffer (stride 0), 32-bit data format: offsets >= bytes are out of range
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ double2 zt_load2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ double zt_load1(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void zt_store2(__amdgpu_buffer_rsrc_t r, uint32_t off, double2 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(zt_u32x4, v), r, off, 0, 0);
+}
+
+template <bool FUSED>
+__global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int j) {
+  __shared__ double lds[NWAVE];
+  __shared__ double l4[4 * NWAVE];
+  __shared__ double2 ub[2][ZT_KH * TPB];
+  __shared__ double2 wb[2][ZT_KH * TPB];
+  constexpr int KH = ZT_KH;
+  const int m = W.m;
+  const int nitems = FUSED ? (int)gridDim.x - 1 : (int)gridDim.x;
+  if (FUSED && (int)blockIdx.x == nitems) {
+    lz_end_body(W, SW, 0, j - 1, 1);
+    return;
+  }
+  if (FUSED && j >= m) return;
+  if (paused_before(SW, j)) return;
+  for (int item = blockIdx.x; item < SW.col_total; item += nitems) {
+    const int s = __builtin_amdgcn_readfirstlane(SW.col_sys ? SW.col_sys[item] : find_sys(SW.col_start, W.S, item));
+    if (W.st[s].state != ST_ACTIVE) continue;
+    const SysDesc& dref = W.sys[s];
+    const int n0 = dref.n0, n1 = dref.n1, n2 = dref.n2;
+    const double c0 = dref.c0, c1 = dref.c1, c2 = dref.c2, diag = dref.diag;
+    const int cs = dref.col_cs, pbase = dref.pbase;
+    const int col_nr = dref.col_nr, col_L = dref.col_L;
+    const int64_t voff = dref.off, bas = dref.basis;
+    const int npts = dref.n;
+    const int t = item - SW.col_start[s];
+    const int tile = t / col_nr;
+    const int rng = t - tile * col_nr;
+    const int ntc = (n2 + ZT_C - 1) / ZT_C;
+    const int tr = tile / ntc;
+    const int r0 = tr * ZT_R;
+    const int c0c = (tile - tr * ntc) * ZT_C;
+    const int ia = rng * col_L;
+    const int ib = min(n0, ia + col_L);
+    const uint32_t plane = (uint32_t)n1 * (uint32_t)n2;
+    double cj, ka, kb;
+    if (FUSED) {
+      double nn, uz, ox, oy;
+      lz_col_partials(W, pbase, cs, dref.col_n, j - 1, nn, uz, ox, oy, l4);
+      const double bj = sqrt(nn);
+      cj = bj > 0.0 ? 1.0 / bj : 0.0;
+      ka = cj * cj * uz * cj;
+      kb = bj * W.cscale[(int64_t)s * (m + 1) + j - 1];
+    } else {
+      cj = W.cscale[(int64_t)s * (m + 1) + j];
+      const double cjm = j > 0 ? W.cscale[(int64_t)s * (m + 1) + j - 1] : 0.0;
+      ka = SW.alpha[(int64_t)s * m + j] * cj;
+      kb = j > 0 ? SW.beta[(int64_t)s * (m + 1) + j] * cjm : 0.0;
+    }
+    // u_{j-1} is read at j = 0 too (as u_0, finite), where kb = 0 removes it
+    const double2* const bvec = reinterpret_cast<const double2*>(W.basis) + bas;
+    const uint32_t vbytes = (uint32_t)npts * 16u;
+    const __amdgpu_buffer_rsrc_t ru = zt_rsrc(bvec + (int64_t)j * npts, vbytes);
+    const __amdgpu_buffer_rsrc_t rm = zt_rsrc(bvec + (int64_t)(j > 0 ? j - 1 : 0) * npts, vbytes);
+    const __amdgpu_buffer_rsrc_t rn = zt_rsrc(bvec + (int64_t)(j + 1) * npts, vbytes);
+    const __amdgpu_buffer_rsrc_t rv = zt_rsrc(W.V64 + voff, (uint32_t)npts * 8u);
+    // slot geometry: in-plane offset; valid = inside the grid, fw = on the
+    // tile or its forward ring (u_{j+1} formed), own = on the tile; eb = the
+    // coefficients of the boundary edges before row 0 / column 0; hf, ho =
+    // the slot, or an interior slot for slots whose neighbours are not read
+    uint32_t po[KH];
+    bool valid[KH], fw[KH], own[KH];
+    double eb[KH];
+    int hf[KH], ho[KH];
+#pragma unroll
+    for (int q = 0; q < KH; ++q) {
+      const int h = (int)threadIdx.x + q * TPB;
+      const int rr = h / ZT_W;
+      const int cc = h - rr * ZT_W;
+      const int row = r0 - 1 + rr, col = c0c - 1 + cc;
+      valid[q] = h < ZT_N && row >= 0 && row < n1 && col >= 0 && col < n2;
+      fw[q] = valid[q] && rr >= 1 && rr <= ZT_R + 1 && cc >= 1 && cc <= ZT_C + 1;
+      own[q] = valid[q] && rr >= 1 && rr <= ZT_R && cc >= 1 && cc <= ZT_C;
+      po[q] = valid[q] ? (uint32_t)row * (uint32_t)n2 + (uint32_t)col : 0u;
+      eb[q] = (row == 0 ? c1 : 0.0) + (col == 0 ? c2 : 0.0);
+      hf[q] = fw[q] ? h : ZT_W + 1;
+      ho[q] = own[q] ? h : ZT_W + 1;
+    }
+    const double2 zero = make_double2(0.0, 0.0);
+    using Vec = double2[KH];
+    using Sca = double[KH];
+    // byte offset of plane i at the slots where sel holds (in: plane i is read)
+    auto offs = [&](uint32_t (&o)[KH], int i, bool in, const bool (&sel)[KH], uint32_t esz) {
+      const uint32_t base = in ? (uint32_t)i * plane : 0u;
+#pragma unroll
+      for (int q = 0; q < KH; ++q) o[q] = (in && sel[q]) ? (base + po[q]) * esz : ZT_OOB;
+    };
+    auto fetch_u = [&](Vec& U, int i, bool in) {
+      uint32_t o[KH];
+      offs(o, i, in && i >= 0 && i < n0, valid, 16u);
+#pragma unroll
+      for (int q = 0; q < KH; ++q) U[q] = zt_load2(ru, o[q]);
+    };
+    auto fetch_mv = [&](Vec& M, Sca& Vp, int i, bool in) {
+      uint32_t o[KH], ov[KH];
+      offs(o, i, in && i >= 0 && i < n0, fw, 16u);
+      offs(ov, i, in && i >= 0 && i < n0, fw, 8u);
+#pragma unroll
+      for (int q = 0; q < KH; ++q) {
+        M[q] = zt_load2(rm, o[q]);
+        Vp[q] = zt_load1(rv, ov[q]);
+      }
+    };
+    Vec Ua, Ub, Uc, Ud, Ma, Mb, Wa, Wb;
+    Sca Va, Vb;
+    double en = 0.0, oux = 0.0, ouy = 0.0, nn = 0.0;
+    // step p: u_{j+1} of plane p + 1 (on the tile and its forward ring) and
+    // the forward-difference terms of plane p. U0..U2 = u_j of planes p..p+2,
+    // U3 receives plane p + 3; Mx, Vx = u_{j-1}, V of plane p + 1, My, Vy
+    // receive plane p + 2; Wc = u_{j+1} of plane p, Wn receives plane p + 1.
+    // Steps past the item's last plane change nothing.
+    auto step = [&](int p, Vec& U0, Vec& U1, Vec& U2, Vec& U3, Vec& Mx, Vec& My, Sca& Vx, Sca& Vy, Vec& Wc,
+                    Vec& Wn) {
+      const int bu = (p + 1) & 1;
+#pragma unroll
+      for (int q = 0; q < KH; ++q) ub[bu][threadIdx.x + q * TPB] = U1[q];
+      fetch_u(U3, p + 3, p + 3 <= ib + 1);
+      fetch_mv(My, Vy, p + 2, p + 2 <= ib);
+      __syncthreads();  // ub[bu] is written; wb[p & 1] (plane p) is complete
+      const bool form = p + 1 < n0 && p + 1 <= ib;
+      const bool keep = p + 1 < ib;  // plane p + 1 belongs to the item
+      const double ep = p + 1 == 0 ? c0 : 0.0;
+      const uint32_t sbase = keep ? (uint32_t)(p + 1) * plane : 0u;
+#pragma unroll
+      for (int q = 0; q < KH; ++q) {
+        const int h = hf[q];
+        const double2 c = U1[q];
+        const double2 l = ub[bu][h - 1], r = ub[bu][h + 1];
+        const double2 a = ub[bu][h - ZT_W], b = ub[bu][h + ZT_W];
+        const double2 nb2 = make_double2(l.x + r.x, l.y + r.y);
+        const double2 nb1 = make_double2(a.x + b.x, a.y + b.y);
+        const double2 nb0 = make_double2(U0[q].x + U2[q].x, U0[q].y + U2[q].y);
+        const double d = diag + Vx[q];
+        double2 hu;
+        hu.x = d * c.x - (c2 * nb2.x + c1 * nb1.x + c0 * nb0.x);
+        hu.y = d * c.y - (c2 * nb2.y + c1 * nb1.y + c0 * nb0.y);
+        const bool f = form && fw[q];
+        const double2 w = f ? make_double2(cj * hu.x - ka * c.x - kb * Mx[q].x, cj * hu.y - ka * c.y - kb * Mx[q].y)
+                            : zero;
+        const bool k = keep && own[q];
+        zt_store2(rn, k ? (sbase + po[q]) * 16u : ZT_OOB, w);
+        const double w2 = k ? w.x * w.x + w.y * w.y : 0.0;
+        nn += w2;
+        en += (Vx[q] + eb[q] + ep) * w2;
+        oux += k ? c.x * w.x + c.y * w.y : 0.0;
+        ouy += k ? c.x * w.y - c.y * w.x : 0.0;
+        Wn[q] = w;
+        wb[bu][threadIdx.x + q * TPB] = w;
+      }
+      if (p >= ia && p < ib) {
+        const int bw = p & 1;
+#pragma unroll
+        for (int q = 0; q < KH; ++q) {
+          const int h = ho[q];
+          const double2 c = Wc[q];
+          const double2 r = wb[bw][h + 1], b = wb[bw][h + ZT_W], f = Wn[q];
+          const double dx = c.x - r.x, dy = c.y - r.y;
+          const double ex = c.x - b.x, ey = c.y - b.y;
+          const double fx = c.x - f.x, fy = c.y - f.y;
+          const double e = c2 * (dx * dx + dy * dy) + c1 * (ex * ex + ey * ey) + c0 * (fx * fx + fy * fy);
+          en += own[q] ? e : 0.0;
+        }
+      }
+    };
+    __syncthreads();  // ub, wb of the previous item are no longer read
+    fetch_u(Ua, ia - 1, true);
+    fetch_u(Ub, ia, true);
+    fetch_u(Uc, ia + 1, true);
+    fetch_mv(Ma, Va, ia, true);
+#pragma unroll
+    for (int q = 0; q < KH; ++q) Wa[q] = zero;
+    step(ia - 1, Ua, Ub, Uc, Ud, Ma, Mb, Va, Vb, Wa, Wb);
+    // col_L further steps in groups of four (a fixed count: straight-line code)
+    for (int g = 0, p = ia; g < (col_L + 3) / 4; ++g, p += 4) {
+      step(p, Ub, Uc, Ud, Ua, Mb, Ma, Vb, Va, Wb, Wa);
+      step(p + 1, Uc, Ud, Ua, Ub, Ma, Mb, Va, Vb, Wa, Wb);
+      step(p + 2, Ud, Ua, Ub, Uc, Mb, Ma, Vb, Va, Wb, Wa);
+      step(p + 3, Ua, Ub, Uc, Ud, Ma, Mb, Va, Vb, Wa, Wb);
+    }
+    en = block_sum(en, lds);
+    oux = block_sum(oux, lds);
+    ouy = block_sum(ouy, lds);
+    nn = block_sum(nn, lds);
+    if (threadIdx.x == 0) {
+      double2* part = reinterpret_cast<double2*>(W.part) + pbase + 3 * (j & 1) * cs;
+      part[t] = make_double2(en, 0.0);
+      part[cs + t] = make_double2(oux, ouy);
+      part[2 * cs + t] = make_double2(nn, 0.0);
+    }
+  }
+}
+
 // Grid S: end of pipelined iteration j (first pass). beta_{j+1} = ||u_{j+1}||,
 // alpha_{j+1} = c_{j+1}^2 Re <u_{j+1}, z_{j+1}>; column j of Hbar is
 // (beta_j, alpha_j, beta_{j+1}) at rows j-1, j, j+1. The orthogonality

@@ -922,6 +922,10 @@ def _centred_grid(shape, h=0.25):
     ((20, 800), 4, 3, True),      # 2D: a row longer than the slots, in bands of 766 + 34 points
     ((300,), 4, 5, True),         # 1D: one row
     ((1000,), 4, 3, False),       # a row longer than the slots: row-staged pass
+    ((7, 23, 60), 4, 2, True),    # tiled pass: 2 x 2 tiles of 16 x 32 (both clipped), ranges 4 + 3
+    ((9, 40, 70), 3, 2, True),    # tiled pass: 3 x 3 tiles, ranges 3 x 3
+    ((37, 41), 8, 2, True),       # tiled pass over one 2D plane of 3 x 2 tiles
+    ((300,), 4, 2, True),         # tiled pass over a 1D grid: a single row of tiles
 ])
 def test_marching_lanczos_pass(rexi, shape, planes, slots, fits):
     # the fused Lanczos pass that marches along the slowest axis, over ragged
@@ -956,7 +960,8 @@ def test_marching_lanczos_pass(rexi, shape, planes, slots, fits):
     assert all(i["not_converged"] == 0 for i in infos)
 
 
-def test_marching_pass_with_second_passes(rexi):
+@pytest.mark.parametrize("slots", [5, 2])
+def test_marching_pass_with_second_passes(rexi, slots):
     # a long Lanczos run (interior shifts of the double well) loses
     # orthogonality: the solve pauses for second Gram-Schmidt passes and
     # resumes with a plain marching pass; the fused passes around them still
@@ -966,17 +971,17 @@ def test_marching_pass_with_second_passes(rexi):
     s, b, d = poles(wl.K, wl.R1)
     ref = ost.DirectStepper(g.n, g.h, wl.V, s, b, wl.dt).step(wl.psi0)
     out, infos = gpu_steps(g, wl.V, wl.psi0, s, b, wl.dt, 1, solver="shifted", m=256, tol=1e-9, tile=512,
-                           march_planes=4, march_slots=5)
+                           march_planes=4, march_slots=slots)
     e = rel(out[0], ref)
     i0 = infos[0]
-    print("marching + second passes", e, i0["certified_bound"], i0["total_iterations"], i0["reorth_passes"])
+    print("marching + second passes", slots, e, i0["certified_bound"], i0["total_iterations"], i0["reorth_passes"])
     assert i0["not_converged"] == 0
     assert i0["reorth_passes"] >= 1
     assert e <= i0["certified_bound"] + 3 * iterative_floor(g, wl.V, s, b, wl.dt)
 
 
-@pytest.mark.parametrize("march", [0, 4])
-def test_batch_pauses_for_second_passes(rexi, march):
+@pytest.mark.parametrize("march,slots", [(0, 0), (4, 3), (4, 2)])
+def test_batch_pauses_for_second_passes(rexi, march, slots):
     # a batch in which one instance (the double well's interior shifts) needs
     # second Gram-Schmidt passes: every system pauses at that iteration, the
     # host runs the pass, and all resume in step; each instance still meets
@@ -989,7 +994,7 @@ def test_batch_pauses_for_second_passes(rexi, march):
     V2 = inputs.gaussian_bumps(g, 7)
     psi2 = inputs.seeded_packet(g, 31, (0.5, -0.5), 1.0)
     Vs, psis = [wl.V, V2], [wl.psi0, psi2]
-    kw = dict(march_planes=march, march_slots=3) if march else dict(march_planes=-1)
+    kw = dict(march_planes=march, march_slots=slots) if march else dict(march_planes=-1)
     h = r.setup_batch([(g.n, g.lo, g.hi)] * 2, to_dev(np.concatenate([v.ravel() for v in Vs])), [1.0] * 2,
                       [1.0] * 2, [wl.dt] * 2, [wl.K] * 2, np.concatenate([s, s]), np.concatenate([b, b]),
                       solver="shifted", m=256, tol=1e-9, tile=512, **kw)
@@ -1004,7 +1009,7 @@ def test_batch_pauses_for_second_passes(rexi, march):
         ref = ost.DirectStepper(g.n, g.h, Vs[i], s, b, wl.dt).step(psis[i]).ravel()
         errs.append(rel(res[i * g.size:(i + 1) * g.size], ref))
     floor = max(iterative_floor(g, v, s, b, wl.dt) for v in Vs)
-    print("batch + second passes", march, errs, info["certified_bound"], info["reorth_passes"], info["total_iterations"])
+    print("batch + second passes", march, slots, errs, info["certified_bound"], info["reorth_passes"], info["total_iterations"])
     assert info["not_converged"] == 0
     assert info["reorth_passes"] >= 1
     assert max(errs) <= info["certified_bound"] + 3 * floor
@@ -1022,7 +1027,7 @@ def test_marching_matches_row_staged_pass(rexi, n):
     Vd = to_dev(wl.V.ravel())
     p0 = to_dev(wl.psi0.ravel())
     outs, bounds, tilings = [], [], []
-    for planes, slots in [(-1, 0), (4, 3), (8, 5), (16, 8), (7, 5)]:
+    for planes, slots in [(-1, 0), (4, 3), (8, 5), (16, 8), (7, 5), (16, 2), (5, 2)]:
         h = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, wl.dt, s, b, solver="shifted", m=100, tol=1e-12,
                     tol_policy="certified", tile=1024, march_planes=planes, march_slots=slots)
         tilings.append(h.tiling())
