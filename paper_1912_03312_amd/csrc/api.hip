@@ -118,6 +118,8 @@ struct rexi_handle {
   rexi::ShiftWork noshift{};          // K = 0: per-pole Givens in pass B
   std::vector<DevBuf> sbufs;
   int32_t* hpin = nullptr;            // pinned counters read-back
+  SysState_t* hst = nullptr;          // pinned system states read with each convergence check
+  int hst_cap = 0;
   // capture-safe steps: no host reads, fixed schedule (set while launching one)
   bool syncfree = false;
   hipStream_t cap_stream = nullptr;   // internal stream for graph capture
@@ -207,6 +209,7 @@ void destroy_handle(rexi_handle* h) {
   if (h->fem_z) (void)hipFree(h->fem_z);
   if (h->fb_rhs) (void)hipFree(h->fb_rhs);
   if (h->hpin) (void)hipHostFree(h->hpin);
+  if (h->hst) (void)hipHostFree(h->hst);
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
   for (auto& g : h->chunks) (void)hipGraphExecDestroy(g.exec);
   for (auto& g : h->rs_chunks) (void)hipGraphExecDestroy(g.exec);
@@ -1241,8 +1244,20 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
       HIPCHK(h, hipGraphLaunch(exec, stream));
       return REXI_OK;
     };
+    // the system states travel with every convergence check, so the check
+    // that ends the solve also brings them
+    if (h->hst_cap < S) {
+      if (h->hst) (void)hipHostFree(h->hst);
+      h->hst = nullptr;
+      h->hst_cap = 0;
+      HIPCHK(h, hipHostMalloc((void**)&h->hst, (size_t)S * sizeof(SysState_t), hipHostMallocDefault));
+      h->hst_cap = S;
+    }
     int j = 0;
-    int len = (*cx.k_hint) > 0 ? (*cx.k_hint) : chunk;
+    // two iterations past the previous solve's length: the count drifts by
+    // one between steps, and iterations after convergence cost a launch each
+    // (finished systems skip them) where one more check costs a round trip
+    int len = (*cx.k_hint) > 0 ? (*cx.k_hint) + 2 : chunk;
     int passes = 0;
     if (fuse) plain_step(0, stream);
     while (j < m) {
@@ -1253,6 +1268,7 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
       HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + (j + len - 1), sizeof(int32_t), hipMemcpyDeviceToHost,
                                stream));
       HIPCHK(h, hipMemcpyAsync(h->hpin + 1, SWc.gpause, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+      HIPCHK(h, hipMemcpyAsync(h->hst, W.st, S * sizeof(SysState_t), hipMemcpyDeviceToHost, stream));
       HIPCHK(h, hipStreamSynchronize(stream));
       const int paused_at = pause_mode ? h->hpin[1] : -1;
       if (paused_at >= 0) {
@@ -1266,6 +1282,7 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
         // systems still iterating after iteration paused_at (its ends, the
         // second pass's included, count them)
         HIPCHK(h, hipMemcpyAsync(h->hpin, W.counters + paused_at, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        HIPCHK(h, hipMemcpyAsync(h->hst, W.st, S * sizeof(SysState_t), hipMemcpyDeviceToHost, stream));
         HIPCHK(h, hipStreamSynchronize(stream));
         if (h->hpin[0] == 0) break;
         len = std::max(chunk, (*cx.k_hint) - j);
@@ -1275,10 +1292,9 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
       if (h->hpin[0] == 0) break;
       len = chunk;
     }
-    // the next solve starts with one chunk of this solve's length
-    std::vector<SysState_t> sst((size_t)S);
-    HIPCHK(h, hipMemcpyAsync(sst.data(), W.st, S * sizeof(SysState_t), hipMemcpyDeviceToHost, stream));
-    HIPCHK(h, hipStreamSynchronize(stream));
+    // the next solve starts with one chunk of this solve's length (states
+    // from the last check, taken after the last iteration launched)
+    std::vector<SysState_t> sst(h->hst, h->hst + S);
     int kmax = 1;
     int64_t isum = 0;
     for (auto& x : sst) {

@@ -926,6 +926,7 @@ def _centred_grid(shape, h=0.25):
     ((9, 40, 70), 3, 2, True),    # tiled pass: 3 x 3 tiles, ranges 3 x 3
     ((37, 41), 8, 2, True),       # tiled pass over one 2D plane of 3 x 2 tiles
     ((300,), 4, 2, True),         # tiled pass over a 1D grid: a single row of tiles
+    ((3, 5, 7), 8, 2, True),      # tiled pass: one clipped tile, an item longer than the grid
 ])
 def test_marching_lanczos_pass(rexi, shape, planes, slots, fits):
     # the fused Lanczos pass that marches along the slowest axis, over ragged
