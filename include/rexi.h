@@ -169,10 +169,12 @@ typedef struct {
                            band of rows does not fit)                         */
   int32_t march_slots;  /* marching pass: points per thread and plane, 3, 5
                            or 8 (0 = 5); a band holds 256 slots / n2 - 2
-                           rows of the plane. 2: the tiled pass, items of
-                           16 x 32 points of the plane, which forms H u_j in
-                           the pass and stores no z (56 B per point instead
-                           of 88; instances below 2^27 points)              */
+                           rows of the plane. 2: the tiled pass, which forms
+                           H u_j in the pass and stores no z (56 B per point
+                           instead of 88; instances below 2^27 points); its
+                           items are 16 x 32 points of the plane, or, when
+                           every instance is 2D, strips of 253 points of a
+                           row marching along the rows                       */
   int32_t fallback;     /* shared-basis solver, poles that miss their target
                            within m vectors:
                            1 (default) restarts on the shared basis: such a

@@ -56,6 +56,7 @@ struct Solver {
   int32_t* dtsys = nullptr;   // system of each tile (sized for the smallest tile; null for capacity builds)
   // column-marching Lanczos pass (0: the row-staged pass)
   int col_kh = 0, col_L = 0, col_total = 0;
+  bool col_strip = false;  // tiled pass over strips of rows (2D instances relabelled (rows, 1, columns))
   std::vector<int32_t> hcol;
   int32_t* dcol = nullptr;
   int32_t* dcolsys = nullptr;  // system of each marching item (sized for any plan that fits)
@@ -316,19 +317,19 @@ constexpr int TPB_ = rexi::TPB;
 // system's rows do not fit or its six partial-sum slots (two parities of
 // three, max(ntiles, items) entries each) exceed its partial-sum block of
 // (m + 1) ntiles entries.
-// kh = 2: the tiled pass, tiles of ZT_R x ZT_C points of the plane (any
-// grid fits; tiles at the edges are clipped).
-bool plan_columns(Solver& sv, int kh, int L) {
+// kh = 2: the tiled pass, tiles of ZT_R x ZT_C points of the plane, or (strip)
+// strips of ZS_C points of a row (any grid fits; tiles at the edges are clipped).
+bool plan_columns(Solver& sv, int kh, int L, bool strip) {
   struct Plan { int rows, Lc, nr, n; };
   std::vector<Plan> pl;
   for (auto& d : sv.hsys) {
     const bool tiled = kh == 2;
-    const int rows = tiled ? rexi::ZT_R : std::min(d.n1, TPB_ * kh / d.n2 - 2);
+    const int tr = strip ? 1 : rexi::ZT_R, tc = strip ? rexi::ZS_C : rexi::ZT_C;
+    const int rows = tiled ? tr : std::min(d.n1, TPB_ * kh / d.n2 - 2);
     if (rows < 1) return false;
     // the tiled pass addresses a vector with 32-bit byte offsets below 2^31
     if (tiled && (int64_t)d.n * 16 >= ((int64_t)1 << 31)) return false;
-    const int nb = tiled ? ((d.n1 + rexi::ZT_R - 1) / rexi::ZT_R) * ((d.n2 + rexi::ZT_C - 1) / rexi::ZT_C)
-                         : (d.n1 + rows - 1) / rows;
+    const int nb = tiled ? ((d.n1 + tr - 1) / tr) * ((d.n2 + tc - 1) / tc) : (d.n1 + rows - 1) / rows;
     const int Lc = std::min(L, d.n0);
     const int nr = (d.n0 + Lc - 1) / Lc;
     const int64_t items = (int64_t)nb * nr;
@@ -351,6 +352,7 @@ bool plan_columns(Solver& sv, int kh, int L) {
   sv.col_total = total;
   sv.col_kh = kh;
   sv.col_L = L;
+  sv.col_strip = strip;
   return true;
 }
 
@@ -983,18 +985,25 @@ void launch_col(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork& SW
   }
 }
 
+template <int TR, int TC>
+void launch_tile(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork& SW, int j, bool fused,
+                 hipStream_t strm) {
+  if (fused) {
+    const dim3 g((j < sv.m ? sv.col_total : 0) + 1);
+    hipLaunchKernelGGL((rexi::k_lz_step_tile<TR, TC, true>), g, dim3(TPB), 0, strm, W, SW, j);
+  } else {
+    hipLaunchKernelGGL((rexi::k_lz_step_tile<TR, TC, false>), dim3(sv.col_total), dim3(TPB), 0, strm, W, SW, j);
+  }
+}
+
 template <int PPT>
 void launch_lz_step(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork& SW, int j, hipStream_t strm,
                     bool fused = false) {
   if (sv.col_kh) {
     switch (sv.col_kh) {
       case 2:
-        if (fused) {
-          const dim3 g((j < sv.m ? sv.col_total : 0) + 1);
-          hipLaunchKernelGGL((rexi::k_lz_step_tile<true>), g, dim3(TPB), 0, strm, W, SW, j);
-        } else {
-          hipLaunchKernelGGL((rexi::k_lz_step_tile<false>), dim3(sv.col_total), dim3(TPB), 0, strm, W, SW, j);
-        }
+        if (sv.col_strip) launch_tile<1, rexi::ZS_C>(sv, W, SW, j, fused, strm);
+        else launch_tile<rexi::ZT_R, rexi::ZT_C>(sv, W, SW, j, fused, strm);
         return;
       case 3: launch_col<3>(sv, W, SW, j, fused, strm); return;
       case 5: launch_col<5>(sv, W, SW, j, fused, strm); return;
@@ -1013,7 +1022,7 @@ void launch_lz_step(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork
 // SWp: the shared-basis data whose column plan they set (null: the handle's).
 rexi_status apply_tiling(rexi_handle* h, Solver& sv, int ppt, int grid, hipStream_t stream,
                          rexi::ShiftWork* SWp = nullptr);
-void set_row_planes(rexi_handle* h, Solver& sv, bool on);
+void set_row_planes(rexi_handle* h, Solver& sv, int mode);
 rexi_status apply_columns(rexi_handle* h, Solver& sv, int kh, int L, hipStream_t stream,
                           rexi::ShiftWork* SWp = nullptr);
 
@@ -1588,7 +1597,7 @@ rexi_status apply_tiling(rexi_handle* h, Solver& sv, int ppt, int grid, hipStrea
                          rexi::ShiftWork* SWp) {
   sv.ppt = ppt;
   sv.tile = TPB * ppt;
-  if (h->shifted) set_row_planes(h, sv, false);  // the column plan is dropped below
+  if (h->shifted) set_row_planes(h, sv, 0);  // the column plan is dropped below
   layout_systems(sv, sv.m);
   sv.grid = grid;
   sv.W.total_tiles = sv.total_tiles;
@@ -1611,24 +1620,35 @@ rexi_status apply_tiling(rexi_handle* h, Solver& sv, int ppt, int grid, hipStrea
 // Select the fused Lanczos pass: kh = 0 the row-staged pass, else the
 // marching pass with kh slots and L planes per item. REXI_OK with the
 // row-staged pass when the plan does not fit.
-// Geometry of the shared-basis systems: as the instance describes it, or,
-// for the marching pass, a 2D instance (1, ny, nx) relabelled (ny, nx, 1) —
-// the same C-order layout, so only the roles change: the pass marches over
-// rows (its "planes"), a row being formed once and the in-row neighbours
-// coming from LDS. The stencil sums are the same, term for term.
-void set_row_planes(rexi_handle* h, Solver& sv, bool on) {
+// Geometry of the shared-basis systems: as the instance describes it (mode
+// 0), or, for the marching passes, a 2D instance (1, ny, nx) relabelled with
+// its rows as the planes: (ny, nx, 1) for the row-band pass (mode 1), whose
+// band is then a run of a row's points, or (ny, 1, nx) for the tiled pass
+// (mode 2), whose tiles are then strips of a row. The C-order layout is the
+// same, so only the roles change; the stencil sums are the same, term for term.
+void set_row_planes(rexi_handle* h, Solver& sv, int mode) {
   for (auto& d : sv.hsys) {
     const InstDesc& in = h->hinst[d.inst];
-    const bool rp = on && in.n0 == 1 && in.n1 > 1 && in.n2 > 1 && !in.fem;
+    const bool rp = mode != 0 && in.n0 == 1 && in.n1 > 1 && in.n2 > 1 && !in.fem;
+    const bool strip = rp && mode == 2;
     d.n0 = rp ? in.n1 : in.n0;
-    d.n1 = rp ? in.n2 : in.n1;
-    d.n2 = rp ? 1 : in.n2;
-    d.d1 = rp ? rexi::make_fastdiv((uint32_t)in.n2) : in.d1;
-    d.d2 = rp ? rexi::make_fastdiv(1u) : in.d2;
+    d.n1 = rp ? (strip ? 1 : in.n2) : in.n1;
+    d.n2 = rp ? (strip ? in.n2 : 1) : in.n2;
+    d.d1 = rp ? rexi::make_fastdiv((uint32_t)d.n1) : in.d1;
+    d.d2 = rp ? rexi::make_fastdiv((uint32_t)d.n2) : in.d2;
     d.c0 = rp ? in.c1 : in.c0;
-    d.c1 = rp ? in.c2 : in.c1;
-    d.c2 = rp ? 0.0 : in.c2;
+    d.c1 = rp ? (strip ? 0.0 : in.c2) : in.c1;
+    d.c2 = rp ? (strip ? in.c2 : 0.0) : in.c2;
   }
+}
+
+// every system is a 2D instance (the tiled pass takes strips of its rows)
+bool all_2d(rexi_handle* h, const Solver& sv) {
+  for (auto& d : sv.hsys) {
+    const InstDesc& in = h->hinst[d.inst];
+    if (!(in.n0 == 1 && in.n1 > 1 && in.n2 > 1 && !in.fem)) return false;
+  }
+  return !sv.hsys.empty();
 }
 
 rexi_status apply_columns(rexi_handle* h, Solver& sv, int kh, int L, hipStream_t stream,
@@ -1638,9 +1658,12 @@ rexi_status apply_columns(rexi_handle* h, Solver& sv, int kh, int L, hipStream_t
   SW.col_start = nullptr;
   SW.col_sys = nullptr;
   SW.col_total = 0;
-  set_row_planes(h, sv, kh != 0 && kh != 2);  // the tiled pass keeps the instance's geometry
-  if (kh == 0 || !plan_columns(sv, kh, L)) {
-    set_row_planes(h, sv, false);
+  // the tiled pass keeps a 3D instance's geometry and takes strips of a 2D
+  // instance's rows; the row-band pass marches over the rows of 2D instances
+  const bool strip = kh == 2 && all_2d(h, sv);
+  set_row_planes(h, sv, kh == 0 ? 0 : kh == 2 ? (strip ? 2 : 0) : 1);
+  if (kh == 0 || !plan_columns(sv, kh, L, strip)) {
+    set_row_planes(h, sv, 0);
     HIPCHK(h, hipMemcpyAsync(sv.dsys, sv.hsys.data(), sv.S * sizeof(SysDesc), hipMemcpyHostToDevice, stream));
     HIPCHK(h, hipStreamSynchronize(stream));
     return REXI_OK;

@@ -1563,7 +1563,7 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
 // Tiled marching pass (no stored z): the same iteration as k_lz_step_col, but
 // H u_j is formed inside the pass, so z is neither read nor written (a point
 // moves u_j, u_{j-1}, V and u_{j+1}: 56 B instead of 88 B). An item is a tile
-// of ZT_R x ZT_C points of the (i1, i2) plane over col_L consecutive planes.
+// of TR x TC points of the (i1, i2) plane over col_L consecutive planes.
 // Its region holds one halo row/column before the tile and two after: u_j is
 // read on the whole region, u_{j+1} = c_j H u_j - alpha_j c_j u_j -
 // beta_j c_{j-1} u_{j-1} is formed on the tile and one ring after it, and
@@ -1577,10 +1577,16 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
 // range check turns into a zero load or a dropped store. The steps are
 // therefore straight-line code, and the loads issued one step ahead are
 // waited for only where they are used.
+// Tile shapes: 16 x 32 points of the (i1, i2) plane for 3D grids; for 2D
+// grids, relabelled (rows, 1, columns), strips of 253 points of a row (the
+// region is the strip with one column before and two after: 256 slots).
 constexpr int ZT_R = 16, ZT_C = 32;
-constexpr int ZT_W = ZT_C + 3;              // region width
-constexpr int ZT_N = ZT_W * (ZT_R + 3);     // region slots
-constexpr int ZT_KH = (ZT_N + TPB - 1) / TPB;
+constexpr int ZS_C = 253;
+template <int TR, int TC> struct ZTile {
+  static constexpr int W = TC + 3;                    // region width
+  static constexpr int N = W * (TR > 1 ? TR + 3 : 1);  // region slots (TR = 1: no row halo, n1 = 1)
+  static constexpr int KH = (N + TPB - 1) / TPB;
+};
 constexpr uint32_t ZT_OOB = 0x80000000u;    // past the end of every buffer (records < 2^31 bytes)
 
 typedef unsigned int zt_u32x2 __attribute__((ext_vector_type(2)));
@@ -1600,13 +1606,16 @@ __device__ __forceinline__ void zt_store2(__amdgpu_buffer_rsrc_t r, uint32_t off
   __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(zt_u32x4, v), r, off, 0, 0);
 }
 
-template <bool FUSED>
+template <int TR, int TC, bool FUSED>
 __global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int j) {
+  constexpr int KH = ZTile<TR, TC>::KH;
+  constexpr int ZT_W = ZTile<TR, TC>::W;
+  constexpr int ZT_N = ZTile<TR, TC>::N;
+  constexpr bool ROWS = TR > 1;  // the region has rows (TR = 1: n1 = 1)
   __shared__ double lds[NWAVE];
   __shared__ double l4[4 * NWAVE];
-  __shared__ double2 ub[2][ZT_KH * TPB];
-  __shared__ double2 wb[2][ZT_KH * TPB];
-  constexpr int KH = ZT_KH;
+  __shared__ double2 ub[2][KH * TPB];
+  __shared__ double2 wb[2][KH * TPB];
   const int m = W.m;
   const int nitems = FUSED ? (int)gridDim.x - 1 : (int)gridDim.x;
   if (FUSED && (int)blockIdx.x == nitems) {
@@ -1628,10 +1637,10 @@ __global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int 
     const int t = item - SW.col_start[s];
     const int tile = t / col_nr;
     const int rng = t - tile * col_nr;
-    const int ntc = (n2 + ZT_C - 1) / ZT_C;
+    const int ntc = (n2 + TC - 1) / TC;
     const int tr = tile / ntc;
-    const int r0 = tr * ZT_R;
-    const int c0c = (tile - tr * ntc) * ZT_C;
+    const int r0 = tr * TR;
+    const int c0c = (tile - tr * ntc) * TC;
     const int ia = rng * col_L;
     const int ib = min(n0, ia + col_L);
     const uint32_t plane = (uint32_t)n1 * (uint32_t)n2;
@@ -1667,16 +1676,16 @@ __global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int 
 #pragma unroll
     for (int q = 0; q < KH; ++q) {
       const int h = (int)threadIdx.x + q * TPB;
-      const int rr = h / ZT_W;
-      const int cc = h - rr * ZT_W;
-      const int row = r0 - 1 + rr, col = c0c - 1 + cc;
+      const int rr = ROWS ? h / ZT_W : 1;
+      const int cc = ROWS ? h - rr * ZT_W : h;
+      const int row = ROWS ? r0 - 1 + rr : 0, col = c0c - 1 + cc;
       valid[q] = h < ZT_N && row >= 0 && row < n1 && col >= 0 && col < n2;
-      fw[q] = valid[q] && rr >= 1 && rr <= ZT_R + 1 && cc >= 1 && cc <= ZT_C + 1;
-      own[q] = valid[q] && rr >= 1 && rr <= ZT_R && cc >= 1 && cc <= ZT_C;
+      fw[q] = valid[q] && rr >= 1 && rr <= TR + 1 && cc >= 1 && cc <= TC + 1;
+      own[q] = valid[q] && rr >= 1 && rr <= TR && cc >= 1 && cc <= TC;
       po[q] = valid[q] ? (uint32_t)row * (uint32_t)n2 + (uint32_t)col : 0u;
       eb[q] = (row == 0 ? c1 : 0.0) + (col == 0 ? c2 : 0.0);
-      hf[q] = fw[q] ? h : ZT_W + 1;
-      ho[q] = own[q] ? h : ZT_W + 1;
+      hf[q] = fw[q] ? h : (ROWS ? ZT_W + 1 : 1);
+      ho[q] = own[q] ? h : (ROWS ? ZT_W + 1 : 1);
     }
     const double2 zero = make_double2(0.0, 0.0);
     using Vec = double2[KH];
@@ -1728,7 +1737,7 @@ __global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int 
         const int h = hf[q];
         const double2 c = U1[q];
         const double2 l = ub[bu][h - 1], r = ub[bu][h + 1];
-        const double2 a = ub[bu][h - ZT_W], b = ub[bu][h + ZT_W];
+        const double2 a = ROWS ? ub[bu][h - ZT_W] : zero, b = ROWS ? ub[bu][h + ZT_W] : zero;
         const double2 nb2 = make_double2(l.x + r.x, l.y + r.y);
         const double2 nb1 = make_double2(a.x + b.x, a.y + b.y);
         const double2 nb0 = make_double2(U0[q].x + U2[q].x, U0[q].y + U2[q].y);
@@ -1755,7 +1764,7 @@ __global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int 
         for (int q = 0; q < KH; ++q) {
           const int h = ho[q];
           const double2 c = Wc[q];
-          const double2 r = wb[bw][h + 1], b = wb[bw][h + ZT_W], f = Wn[q];
+          const double2 r = wb[bw][h + 1], b = ROWS ? wb[bw][h + ZT_W] : zero, f = Wn[q];
           const double dx = c.x - r.x, dy = c.y - r.y;
           const double ex = c.x - b.x, ey = c.y - b.y;
           const double fx = c.x - f.x, fy = c.y - f.y;

@@ -485,12 +485,14 @@ def test_step_inside_caller_graph_capture(rexi):
 
 # ---------------------------------------------------------------- uneven batch
 @pytest.mark.parametrize("solver,prec", [("shifted", "c128"), ("shifted_m24", "c128"), ("shifted_march", "c128"),
-                                         ("shifted_m24_march", "c128"), ("per_pole", "c128"), ("per_pole", "c64")])
+                                         ("shifted_m24_march", "c128"), ("shifted_tiled", "c128"),
+                                         ("shifted_m24_tiled", "c128"), ("per_pole", "c128"), ("per_pole", "c64")])
 def test_uneven_batch_matches_oracle_per_instance(rexi, solver, prec):
     # shifted_m24: a shared basis of 24 vectors is too short for the larger
     # instances; restart cycles on the shared basis finish those poles.
     # _march: the marching pass over rows (2D instances relabelled so a row
-    # is a plane), ranges of 4 rows, more items than tiles on most instances
+    # is a plane), ranges of 4 rows, more items than tiles on most instances;
+    # _tiled: the tiled pass over strips of rows, ranges of 4 rows
     import torch
     from paper_1912_03312_amd import rexi as r
     insts = inputs.batch_instances(count=6, sides=(12, 17, 24, 31, 40, 47))
@@ -508,12 +510,13 @@ def test_uneven_batch_matches_oracle_per_instance(rexi, solver, prec):
     cnt = len(insts)
     tol = dict(tol=1e-11, tol_policy="certified") if prec == "c128" else dict(tol=1e-8, tol_policy="certified")
     m = 24 if "_m24" in solver else (256 if solver.startswith("shifted") else 30)
-    march = dict(march_planes=4, march_slots=3) if solver.endswith("_march") else {}
+    slots = 3 if solver.endswith("_march") else 2 if solver.endswith("_tiled") else 0
+    march = dict(march_planes=4, march_slots=slots) if slots else {}
     h = r.setup_batch(grids, to_dev(np.concatenate(Vs)), [1.0] * cnt, [1.0] * cnt, dts, Ks,
                       np.concatenate(sig), np.concatenate(bet), solver=solver.split("_")[0].replace("per", "per_pole"),
                       precision=prec, m=m, max_cycles=200, **tol, **march)
     if march:
-        assert h.tiling()["march_slots"] == 3
+        assert h.tiling()["march_slots"] == slots
     p0 = to_dev(np.concatenate(psis))
     out = torch.empty_like(p0)
     info = h.step(p0, out, 1)
@@ -927,6 +930,8 @@ def _centred_grid(shape, h=0.25):
     ((37, 41), 8, 2, True),       # tiled pass over one 2D plane of 3 x 2 tiles
     ((300,), 4, 2, True),         # tiled pass over a 1D grid: a single row of tiles
     ((3, 5, 7), 8, 2, True),      # tiled pass: one clipped tile, an item longer than the grid
+    ((100, 130), 16, 2, True),    # tiled pass over strips of a 2D grid's rows: ranges 16 x 6 + 4
+    ((20, 800), 4, 2, True),      # 2D: rows of 800 points in strips of 253 + 253 + 253 + 41
 ])
 def test_marching_lanczos_pass(rexi, shape, planes, slots, fits):
     # the fused Lanczos pass that marches along the slowest axis, over ragged
