@@ -1081,10 +1081,12 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
   }
   const bool pipe = h->opt.lanczos == 1;
   const int colparts = sv.col_kh ? 1 : 0;
+  // the tiled pass forms H u_j itself: the matvecs outside it store no z
+  const bool zfree = sv.col_kh == 2;
   if (pipe) {
     {
-      Timed t(h, PC_START, n * 48.0, stream);
-      hipLaunchKernelGGL((rexi::k_lz_matvec<PPT>), dim3(G), dim3(TPB), 0, stream, W, SWc, 0, 0, 0);
+      Timed t(h, PC_START, n * (zfree ? 32.0 : 48.0), stream);
+      hipLaunchKernelGGL((rexi::k_lz_matvec<PPT>), dim3(G), dim3(TPB), 0, stream, W, SWc, 0, zfree ? -1 : 0, 0);
     }
     {
       Timed t(h, PC_REDUCE, 0, stream);
@@ -1122,7 +1124,7 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
       {
         Timed t(h, PC_REORTH_B, 0, strm);
         hipLaunchKernelGGL((rexi::k_lz_matvec<PPT>), dim3(grid2), dim3(TPB), 0, strm, W, SWc, j + 1,
-                           (j + 1) & 1, 1);
+                           zfree ? -1 : (j + 1) & 1, 1);
       }
       {
         Timed t(h, PC_REDUCE, 0, strm);
@@ -1700,7 +1702,7 @@ void tune_launch(rexi_handle* h, Solver& sv, const double2* b, int iters, hipStr
   if (h->shifted) hipLaunchKernelGGL(rexi::k_shifted_init, dim3(S), dim3(TPB), 0, st, W, h->SW);
   const bool lz = h->shifted && h->SW.lanczos;
   if (h->shifted && h->opt.lanczos == 1) {
-    hipLaunchKernelGGL((rexi::k_lz_matvec<PPT>), dim3(G), dim3(TPB), 0, st, W, h->SW, 0, 0, 0);
+    hipLaunchKernelGGL((rexi::k_lz_matvec<PPT>), dim3(G), dim3(TPB), 0, st, W, h->SW, 0, sv.col_kh == 2 ? -1 : 0, 0);
     hipLaunchKernelGGL(rexi::k_lz_start, dim3(S), dim3(TPB), 0, st, W, h->SW);
     for (int j = 0; j < iters && j < sv.m; ++j) {
       launch_lz_step<PPT>(sv, W, h->SW, j, st);

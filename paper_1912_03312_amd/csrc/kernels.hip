@@ -1111,7 +1111,8 @@ __global__ __launch_bounds__(TPB) void k_lz_matvec(Work W, ShiftWork SW, int i, 
     const SysDesc& d = W.sys[s];
     const int t = item - d.tile0;
     const double2* __restrict__ u = basis_vec<double2>(W, d, i);
-    double2* __restrict__ z = reinterpret_cast<double2*>(SW.zb) + zsel * SW.zstride + d.xoff;
+    // zsel < 0: z is not stored (the tiled pass forms H u_j itself)
+    double2* __restrict__ z = reinterpret_cast<double2*>(SW.zb) + (zsel < 0 ? 0 : zsel) * SW.zstride + d.xoff;
     double uzx = 0.0, uzy = 0.0, nn = 0.0;
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
@@ -1119,7 +1120,7 @@ __global__ __launch_bounds__(TPB) void k_lz_matvec(Work W, ShiftWork SW, int i, 
       if (p < d.n) {
         const double2 c = u[p];
         const double2 hz = stencil_point<double2>(u, d, W.V64[d.off + p], (uint32_t)p);
-        z[p] = hz;
+        if (zsel >= 0) z[p] = hz;
         uzx += c.x * hz.x + c.y * hz.y;
         uzy += c.x * hz.y - c.y * hz.x;
         nn += c.x * c.x + c.y * c.y;
@@ -2072,8 +2073,11 @@ __global__ __launch_bounds__(TPB) void k_shifted_backsub(Work W, ShiftWork SW) {
     // then one lane runs the recurrence.
     double2(*bd)[MAXM] = band[wid];
     for (int r = lane; r < k; r += 64) {
-      bd[0][r] = Rp[(int64_t)r * (m + 1) + r];
-      if (r == k - 1) bd[0][r] = make_double2(bd[0][r].x * lastscale, bd[0][r].y * lastscale);
+      // the reciprocal pivot 1 / R_rr (0 for a zero pivot), formed in parallel
+      double2 dd = Rp[(int64_t)r * (m + 1) + r];
+      if (r == k - 1) dd = make_double2(dd.x * lastscale, dd.y * lastscale);
+      const double dn = dd.x * dd.x + dd.y * dd.y;
+      bd[0][r] = dn > 0.0 ? make_double2(dd.x / dn, -dd.y / dn) : make_double2(0.0, 0.0);
       bd[1][r] = r + 1 < k ? Rp[(int64_t)(r + 1) * (m + 1) + r] : make_double2(0.0, 0.0);
       bd[2][r] = r + 2 < k ? Rp[(int64_t)(r + 2) * (m + 1) + r] : make_double2(0.0, 0.0);
       bd[3][r] = g[r];
@@ -2086,10 +2090,7 @@ __global__ __launch_bounds__(TPB) void k_shifted_backsub(Work W, ShiftWork SW) {
       for (int r = k - 1; r >= 0; --r) {
         const double2 t1 = cmul(bd[1][r], y1), t2 = cmul(bd[2][r], y2);
         const double2 acc = make_double2(bd[3][r].x - (t1.x + t2.x), bd[3][r].y - (t1.y + t2.y));
-        const double2 dd = bd[0][r];
-        const double dn = dd.x * dd.x + dd.y * dd.y;
-        const double2 yr = dn > 0.0 ? make_double2((acc.x * dd.x + acc.y * dd.y) / dn, (acc.y * dd.x - acc.x * dd.y) / dn)
-                                    : make_double2(0.0, 0.0);
+        const double2 yr = cmul(acc, bd[0][r]);
         y[r] = yr;
         if (fom && r == k - 1) reinterpret_cast<double2*>(SW.gnext)[p] = make_double2(-yr.x, -yr.y);
         y2 = y1;
@@ -2123,22 +2124,36 @@ __global__ __launch_bounds__(TPB) void k_shifted_backsub(Work W, ShiftWork SW) {
 }
 
 // Grid S: z_s = sum_{p in s} w_p y_p in pole order.
+// The weights are staged in LDS with a flag that leaves out a pole finished
+// by a per-pole solve, so the loads of y for consecutive poles are independent.
 __global__ __launch_bounds__(TPB) void k_shifted_z(Work W, ShiftWork SW) {
+  __shared__ double2 wl[TPB];
+  __shared__ int kl[TPB];
   const int s = blockIdx.x;
   if (s >= W.S) return;
   const int m = W.m;
   const int k = W.st[s].kcyc;
-  for (int i = threadIdx.x; i < k; i += TPB) {
-    double2 zi = make_double2(0.0, 0.0);
-    for (int q = SW.pole0[s]; q < SW.pole0[s + 1]; ++q) {
-      if (SW.fb_skip && SW.its[q] == 0) continue;  // finished by a per-pole solve
-      const double2 wq = reinterpret_cast<const double2*>(SW.w)[q];
-      const double2 yq = reinterpret_cast<const double2*>(SW.y)[(int64_t)q * m + i];
-      const double2 tz = cmul(wq, yq);
-      zi.x += tz.x;
-      zi.y += tz.y;
+  const int q0 = SW.pole0[s], q1 = SW.pole0[s + 1];
+  for (int c0 = q0; c0 < q1; c0 += TPB) {
+    const int nc = min(TPB, q1 - c0);
+    __syncthreads();
+    if ((int)threadIdx.x < nc) {
+      const int q = c0 + threadIdx.x;
+      kl[threadIdx.x] = !(SW.fb_skip && SW.its[q] == 0);  // 0: finished by a per-pole solve
+      wl[threadIdx.x] = reinterpret_cast<const double2*>(SW.w)[q];
     }
-    reinterpret_cast<double2*>(SW.z)[(int64_t)s * m + i] = zi;
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += TPB) {
+      double2 zi = c0 == q0 ? make_double2(0.0, 0.0) : reinterpret_cast<double2*>(SW.z)[(int64_t)s * m + i];
+      const double2* yi = reinterpret_cast<const double2*>(SW.y) + (int64_t)c0 * m + i;
+#pragma unroll 8
+      for (int c = 0; c < nc; ++c) {
+        const double2 tz = cmul(wl[c], yi[(int64_t)c * m]);
+        zi.x += kl[c] ? tz.x : 0.0;
+        zi.y += kl[c] ? tz.y : 0.0;
+      }
+      reinterpret_cast<double2*>(SW.z)[(int64_t)s * m + i] = zi;
+    }
   }
 }
 
