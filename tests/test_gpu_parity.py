@@ -362,6 +362,42 @@ def test_shifted_full_size_3d_separable(rexi):
     assert e2 <= max(1e-10, 10 * d["amplification"] * EPS)
 
 
+def test_shifted_full_size_in_bench_launch_configuration(rexi):
+    # the launch configuration bench.py times on 128^3, 64 poles (tiled pass
+    # over 16 x 32 tiles, 16 planes per item, tiles of 1024 points, 1024
+    # blocks; the stored tuner choice), on the separable potential whose
+    # exact step the oracle evaluates at full size, two steps in place
+    import torch
+    from paper_1912_03312_amd import rexi as r
+    g = inputs.cube(128, 15.0, 3)
+    x = g.axes()
+    parts = [0.02 * xa * xa for xa in x]
+    V = parts[0][:, None, None] + parts[1][None, :, None] + parts[2][None, None, :]
+    psi0 = inputs.seeded_packet(g, 30, (0.0, 0.0, 0.0), 2.0)
+    s, b, d = poles(64, 180.0)
+    S = ost.SeparableStepper(g.n, g.h, parts)
+    ref1 = S.step(psi0, s, b, 1.0)
+    ref2 = S.step(ref1, s, b, 1.0)
+    h = r.setup(g.n, g.lo, g.hi, to_dev(V.ravel()), 1.0, 1.0, 1.0, s, b, solver="shifted", m=100, tol=1e-10,
+                tile=1024, grid_blocks=1024, march_planes=16, march_slots=2)
+    t = h.tiling()
+    assert (t["tile"], t["grid_blocks"], t["march_slots"], t["march_planes"], t["march_items"]) == \
+        (1024, 1024, 2, 16, 256), t
+    psi = to_dev(psi0.ravel())
+    infos = [h.step(psi, psi, 1)]
+    torch.cuda.synchronize()
+    e1 = rel(psi.cpu().numpy(), ref1)
+    infos.append(h.step(psi, psi, 1))
+    torch.cuda.synchronize()
+    e2 = rel(psi.cpu().numpy(), ref2)
+    h.close()
+    print("bench launch configuration, separable 128^3:", e1, e2, [i["total_iterations"] for i in infos],
+          [i["certified_bound"] for i in infos])
+    assert all(i["not_converged"] == 0 for i in infos)
+    assert e1 <= max(1e-6, infos[0]["certified_bound"])
+    assert e2 <= max(2e-6, infos[0]["certified_bound"] + infos[1]["certified_bound"])
+
+
 def test_shifted_matches_per_pole_on_bench_workload(rexi):
     # the benchmarked 128^3 workload: both solvers agree within their bounds
     import torch
