@@ -978,7 +978,7 @@ template <int KH>
 void launch_col(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork& SW, int j, bool fused,
                 hipStream_t strm) {
   if (fused) {
-    const dim3 g((j < sv.m ? sv.col_total : 0) + 1);
+    const dim3 g((j < sv.m ? sv.col_total : 0) + sv.S);
     hipLaunchKernelGGL((rexi::k_lz_step_col<KH, true>), g, dim3(TPB), 0, strm, W, SW, j);
   } else {
     hipLaunchKernelGGL((rexi::k_lz_step_col<KH, false>), dim3(sv.col_total), dim3(TPB), 0, strm, W, SW, j);
@@ -989,7 +989,7 @@ template <int TR, int TC>
 void launch_tile(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork& SW, int j, bool fused,
                  hipStream_t strm) {
   if (fused) {
-    const dim3 g((j < sv.m ? sv.col_total : 0) + 1);
+    const dim3 g((j < sv.m ? sv.col_total : 0) + sv.S);
     hipLaunchKernelGGL((rexi::k_lz_step_tile<TR, TC, true>), g, dim3(TPB), 0, strm, W, SW, j);
   } else {
     hipLaunchKernelGGL((rexi::k_lz_step_tile<TR, TC, false>), dim3(sv.col_total), dim3(TPB), 0, strm, W, SW, j);
@@ -1149,11 +1149,13 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
       hipLaunchKernelGGL(rexi::k_end_iter, dim3(S), dim3(TPB), 0, strm, W, SWl, j, 1, 0);
     }
   };
-  // a single instance that pauses for second passes, with the marching
-  // pass: the pass of iteration j + 1 ends iteration j (one kernel per
-  // iteration); iteration(j) then launches that pass, after a plain pass for
-  // the first iteration and after every second Gram-Schmidt pass
-  const bool fuse = pipe && pause_mode && S == 1 && sv.col_kh != 0;
+  // systems that pause together for second passes, with a marching pass:
+  // the pass of iteration j + 1 also ends iteration j of every system (one
+  // kernel per iteration, S blocks after the items); iteration(j) then
+  // launches that pass, after a plain pass for the first iteration and after
+  // every second Gram-Schmidt pass (which recomputes the pass that ran past
+  // the pause)
+  const bool fuse = pipe && pause_mode && sv.col_kh != 0;
   // algorithmic bytes per point of the pass of iteration j: reads z_j, u_j,
   // u_{j-1}, V and writes u_{j+1}, z_{j+1} (no u_{j-1} at j = 0); the tiled
   // pass forms z_j in place and stores no z

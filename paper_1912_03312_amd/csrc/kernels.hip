@@ -1357,8 +1357,8 @@ __device__ __forceinline__ void lz_col_partials(const Work& W, int pbase, int nt
 
 __device__ void lz_end_body(Work& W, ShiftWork& SW, int s, int j, int colparts);
 
-// FUSED (a single instance that pauses for second passes; j >= 1): the block
-// after the items ends iteration j - 1 (lz_end_body), while every item block
+// FUSED (systems that pause together for second passes; j >= 1): the S blocks
+// after the items end iteration j - 1 of each system (lz_end_body), while every item block
 // takes beta_j = ||u_j|| and alpha_j = c_j^2 <u_j, z_j> from the partial sums
 // of iteration j - 1 itself (the same reduction in the same order, so the
 // same values); j = m only ends iteration m - 1.
@@ -1368,9 +1368,9 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
   __shared__ double l4[4 * NWAVE];
   __shared__ double2 ub[2][TPB * KH];
   const int m = W.m;
-  const int nitems = FUSED ? (int)gridDim.x - 1 : (int)gridDim.x;
-  if (FUSED && (int)blockIdx.x == nitems) {
-    lz_end_body(W, SW, 0, j - 1, 1);
+  const int nitems = FUSED ? (int)gridDim.x - W.S : (int)gridDim.x;
+  if (FUSED && (int)blockIdx.x >= nitems) {
+    lz_end_body(W, SW, (int)blockIdx.x - nitems, j - 1, 1);
     return;
   }
   if (FUSED && j >= m) return;
@@ -1618,9 +1618,9 @@ __global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int 
   __shared__ double2 ub[2][KH * TPB];
   __shared__ double2 wb[2][KH * TPB];
   const int m = W.m;
-  const int nitems = FUSED ? (int)gridDim.x - 1 : (int)gridDim.x;
-  if (FUSED && (int)blockIdx.x == nitems) {
-    lz_end_body(W, SW, 0, j - 1, 1);
+  const int nitems = FUSED ? (int)gridDim.x - W.S : (int)gridDim.x;
+  if (FUSED && (int)blockIdx.x >= nitems) {
+    lz_end_body(W, SW, (int)blockIdx.x - nitems, j - 1, 1);
     return;
   }
   if (FUSED && j >= m) return;
