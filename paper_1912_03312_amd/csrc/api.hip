@@ -2051,7 +2051,8 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   h->itotal = itile;
   // Q1 shared basis: bidiagonal Cholesky factors of the 1D mass matrices
   // tridiag(fmo, fmd, fmo) of each axis (d_0 = sqrt(fmd), e_i = fmo / d_{i-1},
-  // d_i = sqrt(fmd - e_i^2)); an absent axis has the factor 1
+  // d_i = sqrt(fmd - e_i^2)); an absent axis has the factor 1. Per axis:
+  // d, e and 1 / d, n_a entries each
   std::vector<double> chol;
   if (h->fem_shared) {
     InstDesc& in = h->hinst[0];
@@ -2073,6 +2074,7 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
                                               : (rho > 0.0 ? na[a] : 0);
       chol.insert(chol.end(), d.begin(), d.end());
       chol.insert(chol.end(), e.begin(), e.end());
+      for (int i = 0; i < na[a]; ++i) chol.push_back(1.0 / d[(size_t)i]);  // reciprocal pivots of the sweeps
     }
   }
 

@@ -422,12 +422,14 @@ __global__ __launch_bounds__(TPB) void k_fem_apply(InstDesc in, const double* __
 // FEM_SEG) threads instead of n / n_a. src and dst must differ.
 constexpr int FEM_SEG = 32;
 constexpr int FEM_TPB = 64;
+constexpr int FEM_UNR = 8;
 __global__ __launch_bounds__(FEM_TPB) void k_fem_sweep(InstDesc in, const double* __restrict__ chol,
                                                       const double2* __restrict__ src, double2* __restrict__ dst,
                                                       int axis, int backward, int warm) {
   const int na = axis == 0 ? in.n0 : (axis == 1 ? in.n1 : in.n2);
   const double* dg = chol + in.loff[axis];
   const double* eg = dg + na;
+  const double* rg = dg + 2 * na;  // 1 / d
   const int64_t nl = in.n / na;
   const int nseg = (na + FEM_SEG - 1) / FEM_SEG;
   const int64_t plane = (int64_t)in.n1 * in.n2;
@@ -449,17 +451,33 @@ __global__ __launch_bounds__(FEM_TPB) void k_fem_sweep(InstDesc in, const double
     }
     const double2* x = src + in.off + base;
     double2* v = dst + in.off + base;
-    // positions k = 0 .. na-1 in sweep order; this segment writes [k0, k1)
+    // positions k = 0 .. na-1 in sweep order; this segment writes [k0, k1).
+    // The inputs of FEM_UNR positions are loaded before their steps run (the
+    // last group repeats position k1 - 1 past the end, unused), so the loads
+    // of a group are in flight together; the pivots' reciprocals are stored.
     const int k0 = sg * FEM_SEG, k1 = min(na, k0 + FEM_SEG);
     const int ks = max(0, k0 - warm);
     double2 prev = make_double2(0.0, 0.0);
-    for (int k = ks; k < k1; ++k) {
-      const int i = backward ? na - 1 - k : k;
-      const double2 xi = x[i * stride];
-      const double e = backward ? (i + 1 < na ? eg[i + 1] : 0.0) : (i > 0 ? eg[i] : 0.0);
-      const double rd = 1.0 / dg[i];
-      prev = make_double2((xi.x - e * prev.x) * rd, (xi.y - e * prev.y) * rd);
-      if (k >= k0) v[i * stride] = prev;
+    for (int kb = ks; kb < k1; kb += FEM_UNR) {
+      double2 xv[FEM_UNR];
+      double ev[FEM_UNR], rv[FEM_UNR];
+#pragma unroll
+      for (int u = 0; u < FEM_UNR; ++u) {
+        const int k = min(kb + u, k1 - 1);
+        const int i = backward ? na - 1 - k : k;
+        xv[u] = x[(int64_t)i * stride];
+        ev[u] = backward ? (i + 1 < na ? eg[i + 1] : 0.0) : (i > 0 ? eg[i] : 0.0);
+        rv[u] = rg[i];
+      }
+#pragma unroll
+      for (int u = 0; u < FEM_UNR; ++u) {
+        const int k = kb + u;
+        if (k < k1) {
+          const int i = backward ? na - 1 - k : k;
+          prev = make_double2((xv[u].x - ev[u] * prev.x) * rv[u], (xv[u].y - ev[u] * prev.y) * rv[u]);
+          if (k >= k0) v[(int64_t)i * stride] = prev;
+        }
+      }
     }
   }
 }
