@@ -1258,14 +1258,9 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
       return REXI_OK;
     };
     // the system states travel with every convergence check, so the check
-    // that ends the solve also brings them
-    if (h->hst_cap < S) {
-      if (h->hst) (void)hipHostFree(h->hst);
-      h->hst = nullptr;
-      h->hst_cap = 0;
-      HIPCHK(h, hipHostMalloc((void**)&h->hst, (size_t)S * sizeof(SysState_t), hipHostMallocDefault));
-      h->hst_cap = S;
-    }
+    // that ends the solve also brings them (pinned buffer of one state per
+    // instance, allocated at setup)
+    if (h->hst_cap < S) return fail(h, REXI_E_INVALID_ARG, "internal: %d system states, room for %d", S, h->hst_cap);
     int j = 0;
     // two iterations past the previous solve's length: the count drifts by
     // one between steps, and iterations after convergence cost a launch each
@@ -2110,6 +2105,9 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   SETUP_CHK(hipMemcpyAsync(h->dinst, h->hinst.data(), count * sizeof(InstDesc), hipMemcpyHostToDevice, stream));
   SETUP_CHK(hipMemcpyAsync(h->ditile, h->hitile.data(), (count + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
   SETUP_CHK(hipHostMalloc((void**)&h->hpin, 64 * sizeof(int32_t), hipHostMallocDefault));
+  // a shared-basis solve has one system per instance
+  SETUP_CHK(hipHostMalloc((void**)&h->hst, (size_t)std::max(1, count) * sizeof(SysState_t), hipHostMallocDefault));
+  h->hst_cap = std::max(1, count);
   SETUP_CHK(hipStreamSynchronize(stream));
   h->ws_bytes = (int64_t)N * (h->V32 ? 12 : 8);
   h->shifted = o.solver == REXI_SOLVER_SHIFTED;
