@@ -1608,7 +1608,6 @@ template <int TR, int TC> struct ZTile {
 };
 constexpr uint32_t ZT_OOB = 0x80000000u;    // past the end of every buffer (records < 2^31 bytes)
 
-typedef unsigned int zt_u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int zt_u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t zt_rsrc(const void* p, uint32_t bytes) {
