@@ -80,6 +80,7 @@ def test_invalid_arguments_are_rejected_without_device(rx, case):
 @pytest.mark.parametrize("field,value", [("m", 0), ("m", 257), ("reorth_eta", 0.0), ("reorth_eta", 1.0), ("solver", 5), ("max_cycles", 0), ("tol", -1.0),
                                          ("precision", 7), ("reorth", 3), ("inner_rtol", 1.5),
                                          ("march_planes", -2), ("march_planes", 1025), ("march_slots", 4),
+                                         ("march_slots", 1), ("march_slots", 6), ("march_slots", -1),
                                          ("fallback", 3), ("fallback", -1), ("fallback_m", 0), ("fallback_m", 257),
                                          ("fallback_bytes", -1), ("stab_eps", -0.1), ("stab_eps", 1.0),
                                          ("stab_eps", float("nan")), ("center", 2)])
