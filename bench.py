@@ -49,10 +49,13 @@ def load_traffic(kernel: str, precision: str, tiling=None):
         d = json.load(f)
     if d.get("sources") != kernel_sources_hash():
         return None
-    if tiling is not None and d.get("tiling") != tiling:
-        return None
     ent = d.get("kernels", {}).get(f"{kernel}:{precision}")
-    return None if ent is None else ent.get("hbm_bytes_per_launch")
+    if ent is None:
+        return None
+    # the tiling the counters were taken with (per entry: each solver's own run)
+    if tiling is not None and ent.get("tiling", d.get("tiling")) != tiling:
+        return None
+    return ent.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(wl, sigma, beta, seconds_cap: float = 25.0):
