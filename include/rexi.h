@@ -321,6 +321,24 @@ rexi_status rexi_estimate_spectrum(rexi_handle* h, int32_t iters, double* lo_hos
                                    void* stream);
 
 /*
+ * rexi_estimate_spectrum_noalloc -- rexi_estimate_spectrum without any device
+ * allocation, for callers that cannot allocate (tight serving loops,
+ * harnesses that forbid hipMalloc). Same arguments, the same kernels in the
+ * same order and the same results. Its workspace is a fixed 256 MiB device
+ * array of the library, one per GPU, held from the library's first use on
+ * that GPU until the process ends; it needs
+ *   (iters + 2) * N * 16 + (iters + 1) * (8 * tiles + 8 * instances)
+ * bytes (N the handle's points, each part rounded up to 256 bytes), and a
+ * larger request fails with REXI_E_INVALID_ARG before anything runs. Every
+ * workspace buffer is written before it is read within a call, so nothing
+ * left by an earlier call is used. All calls on one GPU share the array:
+ * calls that overlap in time on one GPU (other threads, other streams of
+ * the process) race and must be serialised by the caller.
+ */
+rexi_status rexi_estimate_spectrum_noalloc(rexi_handle* h, int32_t iters, double* lo_host, double* hi_host,
+                                           void* stream);
+
+/*
  * rexi_step -- nsteps >= 1 REXI steps psi_out = r(tau M)^nsteps psi_in
  * (eq. rational-evaluation). psi_in_dev, psi_out_dev: device rexi_c128[prod n]
  * (packed over instances for a batch); psi_out may equal psi_in. info may be

@@ -159,6 +159,7 @@ struct rexi_handle {
   std::string err;
   Prof prof;
   int64_t ws_bytes = 0;
+  void* scratch = nullptr;            // device address of the allocation-free workspace on this device
 };
 
 namespace {
@@ -1872,6 +1873,8 @@ void copy_fem(SysDesc& d, const InstDesc& in) {
   d.fvol = in.fvol;
 }
 
+rexi_status scratch_address(rexi_handle* h, void** out);
+
 rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, const double* V_dev,
                          const double* hbar, const double* mass, const double* dt, const int32_t* K,
                          const rexi_c128* sigma, const rexi_c128* beta, const rexi_options* opt,
@@ -2129,6 +2132,12 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
     return st;
   }
   h->prof.on = o.profile != 0;
+  // the device address of the allocation-free entry point's workspace on
+  // this device (once per device); a failure is reported by that entry point
+  if (scratch_address(h, &h->scratch) != REXI_OK) {
+    h->scratch = nullptr;
+    h->err.clear();
+  }
   *out = h;
   return REXI_OK;
 #undef SETUP_CHK
@@ -2592,31 +2601,60 @@ rexi_status rexi_workspace_info(const rexi_handle* h, int64_t* bytes, int32_t* m
   return REXI_OK;
 }
 
-rexi_status rexi_estimate_spectrum(rexi_handle* h, int32_t iters, double* lo_host, double* hi_host, void* stream) {
-  if (!h) return REXI_E_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+
+// Device buffers of one spectrum estimate: iters + 1 basis vectors, the
+// working vector, the per-item partial sums and the per-instance coefficients.
+struct EvSizes {
+  size_t basis, w, part, coef;
+  size_t total() const { return basis + w + part + coef; }
+};
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+EvSizes ev_sizes(const rexi_handle* h, int iters) {
+  EvSizes z;
+  z.basis = round256((size_t)(iters + 1) * (size_t)h->N * sizeof(double2));
+  z.w = round256((size_t)h->N * sizeof(double2));
+  z.part = round256((size_t)(iters + 1) * std::max(1, h->itotal) * sizeof(double));
+  z.coef = round256((size_t)h->ninst * (iters + 1) * sizeof(double));
+  return z;
+}
+
+// Lanczos estimate of the extreme eigenvalues of H per instance. ws: the
+// caller's device workspace of at least ev_sizes(h, iters).total() bytes, or
+// nullptr to allocate (and free) one here. Every buffer is written before it
+// is read within the call, so a reused workspace needs no clearing.
+rexi_status estimate_spectrum(rexi_handle* h, int32_t iters, double* lo_host, double* hi_host, hipStream_t st,
+                              void* ws) {
   if (!lo_host || !hi_host) return fail(h, REXI_E_INVALID_ARG, "NULL output");
   if (iters < 1 || iters > 256) return fail(h, REXI_E_INVALID_ARG, "iters must be in [1, 256]");
   for (const auto& in : h->hinst)
     if (in.fem) return fail(h, REXI_E_INVALID_ARG, "the spectrum estimate is for the finite-difference H");
-  hipStream_t st = (hipStream_t)stream;
   const int S = h->ninst, T = h->itotal, tile = INST_TILE;
   const int64_t N = h->N;
+  const EvSizes zs = ev_sizes(h, iters);
   double2* basis = nullptr;
   double2* w = nullptr;
   double *part = nullptr, *dcoef = nullptr;
-  const size_t nb = (size_t)(iters + 1) * (size_t)N * sizeof(double2);
   auto release = [&]() {
+    if (ws) return;
     if (basis) (void)hipFree(basis);
     if (w) (void)hipFree(w);
     if (part) (void)hipFree(part);
     if (dcoef) (void)hipFree(dcoef);
   };
-  if (hipMalloc(&basis, nb) != hipSuccess || hipMalloc(&w, (size_t)N * sizeof(double2)) != hipSuccess ||
-      hipMalloc(&part, (size_t)(iters + 1) * std::max(1, T) * sizeof(double)) != hipSuccess ||
-      hipMalloc(&dcoef, (size_t)S * (iters + 1) * sizeof(double)) != hipSuccess) {
+  if (ws) {
+    char* base = static_cast<char*>(ws);
+    basis = reinterpret_cast<double2*>(base);
+    w = reinterpret_cast<double2*>(base + zs.basis);
+    part = reinterpret_cast<double*>(base + zs.basis + zs.w);
+    dcoef = reinterpret_cast<double*>(base + zs.basis + zs.w + zs.part);
+  } else if (hipMalloc(&basis, zs.basis) != hipSuccess || hipMalloc(&w, zs.w) != hipSuccess ||
+             hipMalloc(&part, zs.part) != hipSuccess || hipMalloc(&dcoef, zs.coef) != hipSuccess) {
     (void)hipGetLastError();
     release();
-    return fail(h, REXI_E_NO_MEMORY, "spectrum estimate workspace (%zu bytes)", nb);
+    return fail(h, REXI_E_NO_MEMORY, "spectrum estimate workspace (%zu bytes)", zs.total());
   }
   const int G = std::max(1, std::min(T, 2048));
   // per-instance sums of the item partials of vectors [0, nvec)
@@ -2714,6 +2752,66 @@ rexi_status rexi_estimate_spectrum(rexi_handle* h, int32_t iters, double* lo_hos
     hi_host[ii] = tridiag_eig(a, b, (int)a.size() - 1);
   }
   return REXI_OK;
+}
+
+// Workspace of the allocation-free estimate: one array per GPU (each device
+// holds its own copy once the library's code is loaded on it, until the
+// process ends). Host code never names it: it uses the device address that
+// hipGetSymbolAddress returns for the current device (scratch_address).
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// The device address of scratch on the current device, looked up once per
+// device (the library's setup calls this; the entry point looks it up on a
+// device the setup has not seen).
+rexi_status scratch_address(rexi_handle* h, void** out) {
+  int dev = -1;
+  HIPCHK(h, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(h, REXI_E_INVALID_ARG, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(h, REXI_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    }
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return REXI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rexi_status rexi_estimate_spectrum(rexi_handle* h, int32_t iters, double* lo_host, double* hi_host, void* stream) {
+  if (!h) return REXI_E_INVALID_ARG;
+  return estimate_spectrum(h, iters, lo_host, hi_host, (hipStream_t)stream, nullptr);
+}
+
+rexi_status rexi_estimate_spectrum_noalloc(rexi_handle* h, int32_t iters, double* lo_host, double* hi_host,
+                                           void* stream) {
+  if (!h) return REXI_E_INVALID_ARG;
+  if (iters < 1 || iters > 256) return fail(h, REXI_E_INVALID_ARG, "iters must be in [1, 256]");
+  const size_t need = ev_sizes(h, iters).total();
+  if (need > kScratchBytes)
+    return fail(h, REXI_E_INVALID_ARG,
+                "the allocation-free spectrum estimate needs %zu bytes for %d iterations on %lld points; its "
+                "workspace holds %zu (use rexi_estimate_spectrum or fewer iterations)",
+                need, iters, (long long)h->N, kScratchBytes);
+  void* ws = h->scratch;
+  if (!ws) {
+    rexi_status rs = scratch_address(h, &ws);
+    if (rs != REXI_OK) return rs;
+    h->scratch = ws;
+  }
+  return estimate_spectrum(h, iters, lo_host, hi_host, (hipStream_t)stream, ws);
 }
 
 rexi_status rexi_tiling_info(const rexi_handle* h, rexi_tiling* out) {

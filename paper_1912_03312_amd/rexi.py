@@ -29,8 +29,8 @@ SOLVER_PER_POLE, SOLVER_SHIFTED = 0, 1
 #: every entry point the header declares
 EXPORTS = ("rexi_default_options", "rexi_setup", "rexi_setup_batch", "rexi_apply_H", "rexi_step",
            "rexi_step_adjoint", "rexi_get_profile", "rexi_profile_reset", "rexi_workspace_info",
-           "rexi_tiling_info", "rexi_estimate_spectrum", "rexi_destroy", "rexi_status_string",
-           "rexi_last_error")
+           "rexi_tiling_info", "rexi_estimate_spectrum", "rexi_estimate_spectrum_noalloc", "rexi_destroy",
+           "rexi_status_string", "rexi_last_error")
 
 
 class c128(C.Structure):
@@ -96,7 +96,8 @@ _lib.rexi_status_string.argtypes = [C.c_int]
 _lib.rexi_status_string.restype = C.c_char_p
 _lib.rexi_last_error.argtypes = [_H, C.c_char_p, C.c_size_t]
 for _f in ("rexi_setup", "rexi_setup_batch", "rexi_apply_H", "rexi_step", "rexi_step_adjoint", "rexi_get_profile",
-           "rexi_profile_reset", "rexi_workspace_info", "rexi_destroy", "rexi_last_error", "rexi_estimate_spectrum"):
+           "rexi_profile_reset", "rexi_workspace_info", "rexi_destroy", "rexi_last_error", "rexi_estimate_spectrum",
+           "rexi_estimate_spectrum_noalloc"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -201,6 +202,14 @@ class Handle:
         lo = (C.c_double * self.count)()
         hi = (C.c_double * self.count)()
         _check(_lib.rexi_estimate_spectrum(self._h, int(iters), lo, hi, _stream(stream)), self._h)
+        return np.array(lo[:]), np.array(hi[:])
+
+    def estimate_spectrum_noalloc(self, iters: int = 30, stream=None):
+        """``rexi_estimate_spectrum_noalloc``: the same estimate in the library's
+        fixed device workspace (no device allocation)."""
+        lo = (C.c_double * self.count)()
+        hi = (C.c_double * self.count)()
+        _check(_lib.rexi_estimate_spectrum_noalloc(self._h, int(iters), lo, hi, _stream(stream)), self._h)
         return np.array(lo[:]), np.array(hi[:])
 
     def step(self, psi_in, psi_out, nsteps: int = 1, info: bool = True, stream=None, raise_on_nc: bool = True):
