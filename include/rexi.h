@@ -95,12 +95,15 @@ typedef enum {
 
 typedef enum {
   REXI_SOLVER_PER_POLE = 0, /* one Krylov basis per pole, all poles batched    */
-  REXI_SOLVER_SHIFTED = 1   /* one basis shared by all poles (x0 = 0 gives
-                               K_k(H - s I, psi) = K_k(H, psi)): one Arnoldi
-                               process and K small least-squares problems;
-                               complex128, single instance, no restarts; the
-                               per-pole residuals reported are the implicit
-                               (Givens) ones                                  */
+  REXI_SOLVER_SHIFTED = 1   /* one basis shared by all poles of an instance
+                               (x0 = 0 gives K_k(H - s I, psi) = K_k(H, psi)):
+                               one Lanczos process per instance and K small
+                               least-squares problems; complex128; single
+                               instances and batches; poles beyond the basis
+                               restart on a shared basis (option fallback).
+                               With finite differences, rexi_step with info
+                               forms every pole solution x_j = V y_j and
+                               reports its explicit FP64 residual             */
 } rexi_solver;
 
 typedef enum {
@@ -216,7 +219,15 @@ typedef struct {
                            bilinear form of the two bases; per-pole solves
                            when a pole misses its target within m vectors.
                            0: always per-pole solves                         */
-  int32_t reserved_opt_;
+  int32_t keep_solutions; /* 1: every step keeps the pole solutions x_j of
+                           its last step, readable with rexi_get_solution.
+                           The per-pole solver keeps them anyway; the
+                           shared-basis solver (finite differences) then
+                           forms them on every step (sum_i K_i n_i complex128
+                           values planned at setup; without this option they
+                           are planned when they take at most half of the
+                           free memory and formed only on steps with info).
+                           Default 0                                          */
 } rexi_options;
 
 typedef struct {
@@ -227,16 +238,26 @@ typedef struct {
   int32_t not_converged;    /* pole solves that missed their target            */
   double max_rel_residual;  /* max_j ||psi - (H - s_j) x_j|| / ||psi|| (last step) */
   double certified_bound;   /* sum_j |w_j| ||r_j|| / dist(s_j, [lmin, lmax]) / ||psi||,
-                               a bound on the relative step error (last step)  */
+                               a bound on the relative step error (last step;
+                               for a batch the largest over its instances,
+                               each relative to its own ||psi||)              */
   int32_t reorth_passes;    /* shared-basis Lanczos: second Gram-Schmidt passes
                                of the last step (single instance)             */
-  int32_t reserved_;
-  double norm_in;           /* ||psi_n||_2 of the last step's input            */
-  double norm_out;          /* ||psi_{n+1}||_2 of the last step's output       */
+  int32_t explicit_residuals; /* 1: max_rel_residual, rel_residual and
+                               certified_bound come from explicit FP64
+                               residuals psi - (H - s_j) x_j of the computed
+                               x_j (per-pole solver: always; shared basis:
+                               finite differences, solutions planned); 0: from
+                               the implicit (Givens) residual estimates       */
+  double norm_in;           /* ||psi_n||_2 of the last step's whole input      */
+  double norm_out;          /* ||psi_{n+1}||_2 of the last step's whole output */
   /* optional caller-owned per-pole arrays of length K (NULL to skip):        */
   int32_t* iterations;      /* Arnoldi iterations of pole j (last step)        */
   int32_t* cycles;          /* cycles of pole j (last step)                    */
-  double* rel_residual;     /* final relative residual of pole j (last step)   */
+  double* rel_residual;     /* final relative residual of pole j (last step),
+                               relative to ||psi|| of the pole's instance    */
+  double* implicit_residual;/* the solver's implicit residual estimate of pole
+                               j (per-pole solver: the explicit one)          */
 } rexi_step_info;
 
 typedef struct {
@@ -363,6 +384,17 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in_dev, rexi_c128* ps
 rexi_status rexi_step_adjoint(rexi_handle* h, const rexi_c128* psi_n_dev,
                               const rexi_c128* gbar_next_dev, rexi_c128* gbar_n_dev,
                               double* dV_accum_dev, void* stream);
+
+/*
+ * rexi_get_solution -- copy the solution x_j = (H - s_j)^{-1} psi_n of pole j
+ * (0 <= j < K, poles numbered over the instances in order) of the last step
+ * into x_dev (device rexi_c128[n of the pole's instance]). These are the
+ * terms of eq. rational-evaluation before the weighted sum (psi_{n+1} =
+ * sum_j w_j x_j). Per-pole handles keep them after every step; shared-basis
+ * handles need keep_solutions = 1. REXI_E_INVALID_ARG when none are kept or
+ * no step has run. Asynchronous on stream.
+ */
+rexi_status rexi_get_solution(rexi_handle* h, int32_t pole, rexi_c128* x_dev, void* stream);
 
 /* Kernel-class timings gathered while opt.profile = 1. */
 rexi_status rexi_get_profile(const rexi_handle* h, rexi_profile* out);

@@ -160,6 +160,21 @@ struct rexi_handle {
   Prof prof;
   int64_t ws_bytes = 0;
   void* scratch = nullptr;            // device address of the allocation-free workspace on this device
+  // explicit pole solutions of the shared-basis solver (finite differences):
+  // x_p of every pole at X + xoff[p] (FP64), the tile partials and norms of
+  // their residuals, and a copy of psi for in-place steps
+  double2* X = nullptr;
+  int64_t* dxoff = nullptr;
+  std::vector<int64_t> hxoff;
+  int32_t* dpoff = nullptr;
+  double* xpart = nullptr;
+  double* xrn = nullptr;
+  double2* xb = nullptr;
+  bool want_x = false;                // this solve forms the solutions
+  bool want_res = false;              // ... and their explicit residuals
+  bool x_valid = false;               // X holds the solutions of the last step
+  bool x_res = false;                 // xrn holds their residual norms
+  bool stepped = false;               // a step has run (per pole: W.x holds its solutions)
 };
 
 namespace {
@@ -833,6 +848,92 @@ rexi_status init_restart(rexi_handle* h, hipStream_t stream) {
   return REXI_OK;
 }
 
+// Explicit pole solutions of the shared-basis solver (finite differences): x_p
+// of every pole ([sum_i K_i n_i] complex128), the per-tile residual partials
+// and norms, and a copy of psi for in-place steps. Planned last at setup (the
+// partials follow the final tiling). keep_solutions = 1 requires them; else
+// they are planned when they take at most half of the free memory, and steps
+// with info then report explicit residuals.
+rexi_status init_solutions(rexi_handle* h, hipStream_t stream) {
+  Solver& sv = h->fwd;
+  const int K = h->SW.K;
+  std::vector<int64_t> xo((size_t)K);
+  std::vector<int32_t> po((size_t)K);
+  int64_t xtot = 0, ptot = 0;
+  int q = 0;
+  for (int i = 0; i < sv.S; ++i)
+    for (int k = 0; k < h->Kinst[i]; ++k, ++q) {
+      xo[q] = xtot;
+      po[q] = (int32_t)ptot;
+      xtot += sv.hsys[i].n;
+      ptot += sv.hsys[i].ntiles;
+    }
+  if (ptot > INT32_MAX) return h->opt.keep_solutions ? fail(h, REXI_E_NO_MEMORY, "too many solution tiles") : REXI_OK;
+  const size_t bx = (size_t)xtot * sizeof(double2), bp = (size_t)std::max<int64_t>(ptot, 1) * sizeof(double);
+  const size_t total = bx + bp + (size_t)K * 20 + (size_t)h->N * sizeof(double2);
+  if (!h->opt.keep_solutions) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(h, REXI_E_HIP, "hipMemGetInfo failed");
+    if (total > fr / 2) return REXI_OK;
+  }
+  auto al = [&](void** p, size_t bytes) -> rexi_status {
+    DevBuf b;
+    b.bytes = std::max<size_t>(bytes, 256);
+    if (hipMalloc(&b.p, b.bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(h, REXI_E_NO_MEMORY, "pole solutions (%zu bytes)", total);
+    }
+    h->sbufs.push_back(b);
+    h->ws_bytes += (int64_t)b.bytes;
+    *p = b.p;
+    return REXI_OK;
+  };
+  void *X = nullptr, *xoff = nullptr, *poff = nullptr, *part = nullptr, *rn = nullptr, *xb = nullptr;
+  rexi_status st;
+  if ((st = al(&X, bx)) || (st = al(&xoff, (size_t)K * 8)) || (st = al(&poff, (size_t)K * 4)) ||
+      (st = al(&part, bp)) || (st = al(&rn, (size_t)K * 8)) || (st = al(&xb, (size_t)h->N * sizeof(double2))))
+    return st;
+  HIPCHK(h, hipMemcpyAsync(xoff, xo.data(), (size_t)K * 8, hipMemcpyHostToDevice, stream));
+  HIPCHK(h, hipMemcpyAsync(poff, po.data(), (size_t)K * 4, hipMemcpyHostToDevice, stream));
+  HIPCHK(h, hipStreamSynchronize(stream));
+  h->X = (double2*)X;
+  h->dxoff = (int64_t*)xoff;
+  h->hxoff = xo;
+  h->dpoff = (int32_t*)poff;
+  h->xpart = (double*)part;
+  h->xrn = (double*)rn;
+  h->xb = (double2*)xb;
+  return REXI_OK;
+}
+
+// x_p (+)= V a_p y_p for all poles (gam, miss: a restart cycle), XG poles per launch.
+template <int PPT>
+rexi_status form_x(rexi_handle* h, const rexi::ShiftWork& SWc, const double* gam, const int32_t* miss,
+                   hipStream_t stream) {
+  Solver& sv = h->fwd;
+  int kmax = 0;
+  for (int k : h->Kinst) kmax = std::max(kmax, k);
+  const size_t lds = (size_t)rexi::XG * sv.m * sizeof(double2);
+  for (int g0 = 0; g0 < kmax; g0 += rexi::XG)
+    hipLaunchKernelGGL((rexi::k_form_x<PPT>), dim3(sv.grid), dim3(TPB), lds, stream, sv.W, SWc, h->X,
+                       (const int64_t*)h->dxoff, g0, gam, miss);
+  HIPCHK(h, hipGetLastError());
+  return REXI_OK;
+}
+
+// Explicit FP64 residual norms ||b - (H - s_p) x_p|| of the solutions in X.
+template <int PPT>
+rexi_status explicit_residuals(rexi_handle* h, const double2* b, hipStream_t stream) {
+  Solver& sv = h->fwd;
+  hipLaunchKernelGGL((rexi::k_x_resid<PPT>), dim3(sv.grid), dim3(TPB), 0, stream, sv.W, h->SW, b,
+                     (const double2*)h->X, (const int64_t*)h->dxoff, (const int32_t*)h->dpoff, h->xpart);
+  hipLaunchKernelGGL(rexi::k_x_resid_norm, dim3(h->SW.K), dim3(TPB), 0, stream, sv.W, h->SW,
+                     (const double*)h->xpart, (const int32_t*)h->dpoff, h->xrn);
+  HIPCHK(h, hipGetLastError());
+  h->x_res = true;
+  return REXI_OK;
+}
+
 // Workspace of the per-pole solves that finish poles the shared basis missed:
 // complex64 basis + FP64 refinement, restart length fallback_m, for at most
 // cap_pts points over at most cap_S systems (one wave of those poles).
@@ -963,6 +1064,10 @@ rexi_status run_fallback(rexi_handle* h, const std::vector<int>& poles, const do
     for (int q = 0; q < fb.S; ++q)
       hipLaunchKernelGGL(rexi::k_fb_accumulate, dim3(256), dim3(TPB), 0, stream, F, q, out);
     HIPCHK(h, hipGetLastError());
+    if (h->want_x && h->X)
+      for (const SysDesc& d : fb.hsys)
+        HIPCHK(h, hipMemcpyAsync(h->X + h->hxoff[(size_t)d.pole], reinterpret_cast<const double2*>(fb.W.x) + d.xoff,
+                                 (size_t)d.n * sizeof(double2), hipMemcpyDeviceToDevice, stream));
     std::vector<SysState_t> fst((size_t)fb.S);
     HIPCHK(h, hipMemcpyAsync(fst.data(), F.st, fb.S * sizeof(SysState_t), hipMemcpyDeviceToHost, stream));
     HIPCHK(h, hipStreamSynchronize(stream));
@@ -1319,7 +1424,7 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
 }
 
 template <typename T, int PPT>
-rexi_status run_restarts(rexi_handle* h, double2* out, hipStream_t stream);
+rexi_status run_restarts(rexi_handle* h, double2* out, hipStream_t stream, bool wx);
 
 // One shared-basis solve of all poles of every instance; writes the pole sums
 // to out (out = nullptr: the solve only, its per-pole coefficients y_p).
@@ -1331,6 +1436,14 @@ rexi_status run_shifted(rexi_handle* h, ShiftCtx cx, const double2* b, double2* 
   const int G = sv.grid, m = sv.m;
   h->rs_cycles = 0;
   h->rs_its = 0;
+  // the forward solve of a step forms the pole solutions when asked (info or
+  // keep_solutions); their residuals need psi, which an in-place step overwrites
+  const bool wx = out && h->want_x && h->X && cx.SW == &h->SW;
+  const double2* bref = b;
+  if (wx && (const void*)b == (const void*)out) {
+    HIPCHK(h, hipMemcpyAsync(h->xb, b, (size_t)h->N * sizeof(double2), hipMemcpyDeviceToDevice, stream));
+    bref = h->xb;
+  }
   rexi_status ps = shifted_pass<T, PPT>(h, cx, b, stream, &h->st0, nullptr);
   if (ps != REXI_OK) return ps;
   // restarts need the Galerkin iterate of the poles that missed their target
@@ -1341,6 +1454,13 @@ rexi_status run_shifted(rexi_handle* h, ShiftCtx cx, const double2* b, double2* 
     Timed t(h, PC_REDUCE, 0, stream);
     hipLaunchKernelGGL(rexi::k_shifted_backsub, dim3((SWc.K + rexi::NWAVE - 1) / rexi::NWAVE), dim3(TPB), 0,
                        stream, W, SWb);
+  }
+  if (wx) {
+    // x_p = V y_p (the Galerkin iterate for poles that restart; per-pole
+    // solves overwrite theirs)
+    rexi_status fs = form_x<PPT>(h, SWc, nullptr, nullptr, stream);
+    if (fs != REXI_OK) return fs;
+    h->x_valid = true;
   }
   // poles that missed their target within the basis: restarts or per-pole
   // solves finish them (host checks only)
@@ -1384,8 +1504,10 @@ rexi_status run_shifted(rexi_handle* h, ShiftCtx cx, const double2* b, double2* 
   }
   if (restart && !missed.empty()) {
     h->fb_poles = (int)missed.size();
-    return run_restarts<T, PPT>(h, out, stream);
+    rexi_status rs = run_restarts<T, PPT>(h, out, stream, wx);
+    if (rs != REXI_OK) return rs;
   }
+  if (wx && h->want_res) return explicit_residuals<PPT>(h, bref, stream);
   return REXI_OK;
 }
 
@@ -1397,7 +1519,7 @@ rexi_status run_shifted(rexi_handle* h, ShiftCtx cx, const double2* b, double2* 
 // product of its gnext over the cycles) and target tol_p ||psi|| / |gam_p|,
 // and adds its sums to out. Instances with no such pole have b' = 0.
 template <typename T, int PPT>
-rexi_status run_restarts(rexi_handle* h, double2* out, hipStream_t stream) {
+rexi_status run_restarts(rexi_handle* h, double2* out, hipStream_t stream, bool wx) {
   Solver& sv = h->fwd;
   Work& W = sv.W;
   const int S = sv.S, G = sv.grid;
@@ -1422,6 +1544,11 @@ rexi_status run_restarts(rexi_handle* h, double2* out, hipStream_t stream) {
     {
       Timed t(h, PC_POLESUM, 0, stream);
       hipLaunchKernelGGL((rexi::k_combine_out<T, PPT>), dim3(G), dim3(TPB), 0, stream, W, R, out, 1);
+    }
+    if (wx) {
+      // x_p += gam_p V' y'_p for the poles of this cycle (gam before the merge)
+      rexi_status fs = form_x<PPT>(h, R, h->rs_gam, h->rs_miss, stream);
+      if (fs != REXI_OK) return fs;
     }
     hipLaunchKernelGGL(rexi::k_rs_merge, dim3(S), dim3(TPB), 0, stream, W, h->SW, R, h->rs_miss, h->rs_gam,
                        h->rs_bn0, h->rs_kbase, h->rs_hasmiss);
@@ -1874,6 +2001,7 @@ void copy_fem(SysDesc& d, const InstDesc& in) {
 }
 
 rexi_status scratch_address(rexi_handle* h, void** out);
+rexi_status init_solutions(rexi_handle* h, hipStream_t stream);
 
 rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, const double* V_dev,
                          const double* hbar, const double* mass, const double* dt, const int32_t* K,
@@ -1917,6 +2045,8 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   if (o.center != 0 && o.center != 1) return fail(nullptr, REXI_E_INVALID_ARG, "center must be 0 or 1");
   if (o.adjoint_shared != 0 && o.adjoint_shared != 1)
     return fail(nullptr, REXI_E_INVALID_ARG, "adjoint_shared must be 0 or 1");
+  if (o.keep_solutions != 0 && o.keep_solutions != 1)
+    return fail(nullptr, REXI_E_INVALID_ARG, "keep_solutions must be 0 or 1");
   if (o.discretization != REXI_DISC_FD && o.discretization != REXI_DISC_FEM_Q1)
     return fail(nullptr, REXI_E_INVALID_ARG, "unknown discretization %d", o.discretization);
   if (o.discretization == REXI_DISC_FEM_Q1 && o.solver == REXI_SOLVER_SHIFTED && count != 1)
@@ -2126,6 +2256,7 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
     st = apply_columns(h, h->fwd, o.march_slots ? o.march_slots : 5, o.march_planes, stream);
   if (st == REXI_OK && h->shifted && o.fallback == 2) st = init_fallback(h, stream);
   if (st == REXI_OK && h->shifted && o.fallback == 1) st = init_restart(h, stream);
+  if (st == REXI_OK && h->shifted && !h->mrhs && !h->fem_shared) st = init_solutions(h, stream);
   if (st != REXI_OK) {
     g_setup_error = h->err;
     destroy_handle(h);
@@ -2319,6 +2450,7 @@ void rexi_default_options(rexi_options* o) {
   o->center = 0;
   o->discretization = REXI_DISC_FD;
   o->adjoint_shared = 1;
+  o->keep_solutions = 0;
 }
 
 rexi_status rexi_setup(rexi_handle** out, const rexi_grid* g, const double* V_dev, double hbar, double mass,
@@ -2412,7 +2544,14 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
         rexi_status s0n = vec_norm(h, src, st, &psi_norm);
         if (s0n != REXI_OK) return s0n;
       }
+      // the last step of a call with info forms the pole solutions and their
+      // explicit residuals; keep_solutions forms the solutions every step
+      h->want_res = info && n == nsteps - 1;
+      h->want_x = h->opt.keep_solutions || h->want_res;
+      h->x_valid = false;
+      h->x_res = false;
       rexi_status s1 = shifted_step(h, src, outp, st);
+      h->want_x = h->want_res = false;
       if (s1 != REXI_OK) return s1;
       if (info) {
         const int K = h->SW.K;
@@ -2437,22 +2576,49 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
         its_total += h->fb_its + h->rs_its;
         const int more = h->fb_cycles + h->rs_cycles;
         if (n == nsteps - 1) {
+          // explicit FP64 residuals of the formed solutions, relative to
+          // ||psi|| of the pole's instance (implicit Givens estimates when
+          // the solutions are not formed: Q1 elements, or no room for them)
+          std::vector<double> rex;
+          if (h->x_res) {
+            std::vector<double> rn((size_t)K);
+            HIPCHK(h, hipMemcpyAsync(rn.data(), h->xrn, K * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(h, hipStreamSynchronize(st));
+            rex.resize((size_t)K);
+            int q = 0;
+            for (int i = 0; i < h->ninst; ++i)
+              for (int k = 0; k < h->Kinst[i]; ++k, ++q) {
+                const double bn = sst[(size_t)i].bnorm;
+                rex[(size_t)q] = bn > 0.0 ? rn[(size_t)q] / bn : 0.0;
+              }
+          }
+          const std::vector<double>& rr = h->x_res ? rex : res;
           info->K = K;
           info->max_cycles_used = 1 + more;
           info->not_converged = 0;
           info->max_rel_residual = 0.0;
-          double bound = 0.0;
-          for (int k = 0; k < K; ++k) {
-            if (!(res[k] <= h->tol_sys[k])) info->not_converged += 1;
-            info->max_rel_residual = std::max(info->max_rel_residual, res[k]);
-            bound += std::abs(h->w[k]) * res[k] / h->dist_sys[k];
-            if (info->iterations) info->iterations[k] = its[k] > 0 ? its[k] : s0.its;
-            if (info->cycles) info->cycles[k] = its[k] > s0.its ? 1 + more : 1;
-            if (info->rel_residual) info->rel_residual[k] = res[k];
-          }
-          info->certified_bound = bound;
+          info->explicit_residuals = h->x_res ? 1 : 0;
+          // per instance: sum_p |w_p| rho_p / dist_p bounds the relative step
+          // error; the largest over the instances is reported
+          std::vector<double> bound((size_t)h->ninst, 0.0);
+          int q = 0;
+          for (int i = 0; i < h->ninst; ++i)
+            for (int kk = 0; kk < h->Kinst[i]; ++kk, ++q) {
+              const int k = q;
+              if (!(rr[k] <= h->tol_sys[k])) info->not_converged += 1;
+              info->max_rel_residual = std::max(info->max_rel_residual, rr[k]);
+              bound[(size_t)i] += std::abs(h->w[k]) * rr[k] / h->dist_sys[k];
+              if (info->iterations) info->iterations[k] = its[k] > 0 ? its[k] : s0.its;
+              if (info->cycles) info->cycles[k] = its[k] > s0.its ? 1 + more : 1;
+              if (info->rel_residual) info->rel_residual[k] = rr[k];
+              if (info->implicit_residual) info->implicit_residual[k] = res[k];
+            }
+          info->certified_bound = *std::max_element(bound.begin(), bound.end());
           info->reorth_passes = h->reorth_passes;
-          info->norm_in = h->fem_shared ? psi_norm : s0.bnorm;
+          // ||psi|| of the whole (packed) input
+          double n2 = 0.0;
+          for (const auto& x : sst) n2 += x.bnorm * x.bnorm;
+          info->norm_in = h->fem_shared ? psi_norm : std::sqrt(n2);
           double no = 0.0;
           rexi_status s2 = vec_norm(h, outp, st, &no);
           if (s2 != REXI_OK) return s2;
@@ -2492,20 +2658,33 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
         info->max_cycles_used = 0;
         info->not_converged = 0;
         info->max_rel_residual = 0.0;
-        double bound = 0.0, bn = 0.0;
+        info->explicit_residuals = 1;  // every cycle ends with the explicit FP64 residual
+        // per instance: the absolute bound sum_j |w_j| ||r_j|| / dist_j over
+        // its poles, relative to its ||psi|| (Q1 elements: the right-hand side
+        // is M psi, so relative to the whole input's norm); the largest is reported
+        std::vector<double> bound((size_t)h->ninst, 0.0), bni((size_t)h->ninst, 0.0);
         for (int s = 0; s < sv.S; ++s) {
           const SysState_t& x = hs[(size_t)s];
+          const int i = sv.hsys[(size_t)s].inst;
           info->max_cycles_used = std::max(info->max_cycles_used, x.cycles);
           if (!(x.rho <= sv.hsys[(size_t)s].tol)) info->not_converged += 1;
           info->max_rel_residual = std::max(info->max_rel_residual, x.rho);
-          bound += std::abs(h->w[(size_t)s]) * x.rho * x.bnorm / h->dist_sys[(size_t)s];
-          bn = std::max(bn, x.bnorm);
+          bound[(size_t)i] += std::abs(h->w[(size_t)s]) * x.rho * x.bnorm / h->dist_sys[(size_t)s];
+          bni[(size_t)i] = x.bnorm;
           if (info->iterations) info->iterations[s] = x.its;
           if (info->cycles) info->cycles[s] = x.cycles;
           if (info->rel_residual) info->rel_residual[s] = x.rho;
+          if (info->implicit_residual) info->implicit_residual[s] = x.rho;
         }
-        norm_in = h->mrhs ? fem_norm_in : bn;  // Q1 elements: the right-hand side is M psi
-        info->certified_bound = norm_in > 0.0 ? bound / norm_in : 0.0;
+        double n2 = 0.0;
+        for (double b : bni) n2 += b * b;
+        norm_in = h->mrhs ? fem_norm_in : std::sqrt(n2);
+        double cb = 0.0;
+        for (int i = 0; i < h->ninst; ++i) {
+          const double den = h->mrhs ? norm_in : bni[(size_t)i];
+          cb = std::max(cb, den > 0.0 ? bound[(size_t)i] / den : 0.0);
+        }
+        info->certified_bound = cb;
         info->norm_in = norm_in;
         double no = 0.0;
         rexi_status s2 = vec_norm(h, outp, st, &no);
@@ -2515,6 +2694,7 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
     }
     if (!h->syncfree) prof_collect(h, st);
   }
+  h->stepped = true;
   if (info) {
     info->steps = nsteps;
     info->total_iterations = its_total;
@@ -2568,6 +2748,27 @@ rexi_status rexi_step_adjoint(rexi_handle* h, const rexi_c128* psi_n, const rexi
   HIPCHK(h, hipStreamSynchronize(st));
   prof_collect(h, st);
   if (h->hpin[0] != 0) return fail(h, REXI_E_NOT_CONVERGED, "%d adjoint pole solves missed their target", h->hpin[0]);
+  return REXI_OK;
+}
+
+rexi_status rexi_get_solution(rexi_handle* h, int32_t pole, rexi_c128* x_dev, void* stream) {
+  if (!h) return REXI_E_INVALID_ARG;
+  if (!x_dev) return fail(h, REXI_E_INVALID_ARG, "NULL output");
+  if (pole < 0 || pole >= (int)h->s.size()) return fail(h, REXI_E_INVALID_ARG, "pole %d out of range", pole);
+  if (!h->stepped) return fail(h, REXI_E_INVALID_ARG, "no step has run");
+  hipStream_t st = (hipStream_t)stream;
+  int inst = 0;
+  for (int q = pole; q >= h->Kinst[inst]; ++inst) q -= h->Kinst[inst];
+  const size_t bytes = (size_t)h->hinst[(size_t)inst].n * sizeof(double2);
+  if (h->shifted) {
+    if (!h->opt.keep_solutions || !h->x_valid)
+      return fail(h, REXI_E_INVALID_ARG, "the shared-basis solver keeps its pole solutions with keep_solutions = 1");
+    HIPCHK(h, hipMemcpyAsync(x_dev, h->X + h->hxoff[(size_t)pole], bytes, hipMemcpyDeviceToDevice, st));
+    return REXI_OK;
+  }
+  const SysDesc& d = h->fwd.hsys[(size_t)pole];
+  HIPCHK(h, hipMemcpyAsync(x_dev, reinterpret_cast<const double2*>(h->fwd.W.x) + d.xoff, bytes,
+                           hipMemcpyDeviceToDevice, st));
   return REXI_OK;
 }
 

@@ -2501,6 +2501,149 @@ __global__ __launch_bounds__(TPB) void k_combine_out(Work W, ShiftWork SW, doubl
   }
 }
 
+// ------------------------------------------------------------ explicit solutions
+// The shared-basis solve never forms the pole solutions x_p = V_k y_p; the
+// pole sum is V_k z. To certify a step by explicit FP64 residuals (the bound
+// ||x_p - x_p*|| <= ||r_p|| / dist(s_p, spec H) holds for the normal matrix
+// H - s_p, Section 3.1) the solutions are formed here and the residuals
+// r_p = b - (H - s_p) x_p computed from them, in FP64.
+
+// Poles per launch of k_form_x (their coefficients are staged in LDS).
+constexpr int XG = 16;
+
+// x_p (+)= sum_{i<k} a_p y_{p,i} c_i u_i in FP64 for the poles
+// p = pole0[s] + g0 + g (g < XG) of every instance s, x_p at X + xoff[p].
+// First cycle (gam = miss = null): a_p = 1, x_p written. Restart cycle:
+// a_p = gam_p and only poles with miss[p] take part, adding to x_p (the
+// cycle solved (H - s_p) d = gam_p b' for them). Dynamic LDS: XG * m complex.
+template <int PPT>
+__global__ __launch_bounds__(TPB) void k_form_x(Work W, ShiftWork SW, double2* __restrict__ X,
+                                                const int64_t* __restrict__ xoff, int g0,
+                                                const double* __restrict__ gam, const int32_t* __restrict__ miss) {
+  extern __shared__ double2 xcoef[];
+  int sprev = -1, np = 0, k = 0;
+  uint32_t on = 0;
+  for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
+    const int s = item_sys(W, item);
+    const SysDesc& d = W.sys[s];
+    const int q0 = SW.pole0[s] + g0;
+    if (s != sprev) {
+      k = W.st[s].kcyc;
+      np = max(0, min(XG, SW.pole0[s + 1] - q0));
+      on = 0;
+      for (int g = 0; g < np; ++g)
+        if (!miss || miss[q0 + g]) on |= 1u << g;
+      __syncthreads();
+      for (int e = threadIdx.x; e < np * k; e += TPB) {
+        const int g = e / k, i = e - g * k;
+        const int p = q0 + g;
+        const double2 a = gam ? reinterpret_cast<const double2*>(gam)[p] : make_double2(1.0, 0.0);
+        const double2 ay = cmul(a, reinterpret_cast<const double2*>(SW.y)[(int64_t)p * W.m + i]);
+        const double c = W.cscale[(int64_t)s * (W.m + 1) + i];
+        xcoef[g * W.m + i] = make_double2(ay.x * c, ay.y * c);
+      }
+      __syncthreads();
+      sprev = s;
+    }
+    if (on == 0) continue;
+    const int t = item - d.tile0;
+    const double2* __restrict__ u0 = basis_vec<double2>(W, d, 0);
+#pragma unroll 1
+    for (int q = 0; q < PPT; ++q) {
+      const int pt = t * W.tile + q * TPB + (int)threadIdx.x;
+      if (pt >= d.n) break;
+      double2 acc[XG];
+#pragma unroll
+      for (int g = 0; g < XG; ++g) acc[g] = make_double2(0.0, 0.0);
+      // four basis vectors per step: their loads are in flight together
+      constexpr int U = 4;
+      int i = 0;
+      for (; i + U <= k; i += U) {
+        double2 a[U];
+#pragma unroll
+        for (int r = 0; r < U; ++r) a[r] = u0[(int64_t)(i + r) * d.n + pt];
+#pragma unroll
+        for (int r = 0; r < U; ++r)
+#pragma unroll
+          for (int g = 0; g < XG; ++g)
+            if (g < np) {
+              const double2 c = xcoef[g * W.m + i + r];
+              acc[g].x += c.x * a[r].x - c.y * a[r].y;
+              acc[g].y += c.x * a[r].y + c.y * a[r].x;
+            }
+      }
+      for (; i < k; ++i) {
+        const double2 a = u0[(int64_t)i * d.n + pt];
+#pragma unroll
+        for (int g = 0; g < XG; ++g)
+          if (g < np) {
+            const double2 c = xcoef[g * W.m + i];
+            acc[g].x += c.x * a.x - c.y * a.y;
+            acc[g].y += c.x * a.y + c.y * a.x;
+          }
+      }
+#pragma unroll
+      for (int g = 0; g < XG; ++g) {
+        if (!((on >> g) & 1u)) continue;
+        double2* __restrict__ x = X + xoff[q0 + g];
+        if (miss) {
+          const double2 o = x[pt];
+          acc[g].x += o.x;
+          acc[g].y += o.y;
+        }
+        x[pt] = acc[g];
+      }
+    }
+  }
+}
+
+// Partial sums of ||b - (H - s_p) x_p||^2 over each tile, for every pole p of
+// every instance, in FP64 with the solved operator (the instance's stencil,
+// centering included): part[poff[p] + t] for tile t of the instance.
+template <int PPT>
+__global__ __launch_bounds__(TPB) void k_x_resid(Work W, ShiftWork SW, const double2* __restrict__ b,
+                                                 const double2* __restrict__ X, const int64_t* __restrict__ xoff,
+                                                 const int32_t* __restrict__ poff, double* __restrict__ part) {
+  __shared__ double lds[NWAVE];
+  for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
+    const int s = item_sys(W, item);
+    const SysDesc& d = W.sys[s];
+    const int t = item - d.tile0;
+    const double2* __restrict__ bs = b + d.off;
+    for (int p = SW.pole0[s]; p < SW.pole0[s + 1]; ++p) {
+      const double2* __restrict__ x = X + xoff[p];
+      const double sre = SW.s[2 * p], sim = SW.s[2 * p + 1];
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < PPT; ++q) {
+        const int pt = t * W.tile + q * TPB + (int)threadIdx.x;
+        if (pt < d.n) {
+          const double2 hx = stencil_point_f64(x, d.n0, d.n1, d.n2, d.d2, d.d1, d.c0, d.c1, d.c2, d.diag,
+                                               W.V64[d.off + pt], sre, sim, (uint32_t)pt);
+          const double2 bp = bs[pt];
+          const double rx = bp.x - hx.x, ry = bp.y - hx.y;
+          acc += rx * rx + ry * ry;
+        }
+      }
+      acc = block_sum(acc, lds);
+      if (threadIdx.x == 0) part[poff[p] + t] = acc;
+    }
+  }
+}
+
+// Grid K: rn[p] = ||r_p||, the square root of pole p's tile partials summed
+// in tile order.
+__global__ __launch_bounds__(TPB) void k_x_resid_norm(Work W, ShiftWork SW, const double* __restrict__ part,
+                                                      const int32_t* __restrict__ poff, double* __restrict__ rn) {
+  __shared__ double lds[NWAVE];
+  const int p = blockIdx.x;
+  if (p >= SW.K) return;
+  const int s = SW.pinst[p];
+  double acc = strided_sum(part + poff[p], W.sys[s].ntiles);
+  acc = block_sum(acc, lds);
+  if (threadIdx.x == 0) rn[p] = sqrt(acc);
+}
+
 // ------------------------------------------------------------ shared-basis adjoint
 // One backward step from two shared bases (single instance): the forward
 // solve on psi_n gives x_p = sum_b a_{p,b} c_b u_b (basis of F), the solve with

@@ -29,8 +29,8 @@ SOLVER_PER_POLE, SOLVER_SHIFTED = 0, 1
 #: every entry point the header declares
 EXPORTS = ("rexi_default_options", "rexi_setup", "rexi_setup_batch", "rexi_apply_H", "rexi_step",
            "rexi_step_adjoint", "rexi_get_profile", "rexi_profile_reset", "rexi_workspace_info",
-           "rexi_tiling_info", "rexi_estimate_spectrum", "rexi_estimate_spectrum_noalloc", "rexi_destroy",
-           "rexi_status_string", "rexi_last_error")
+           "rexi_tiling_info", "rexi_estimate_spectrum", "rexi_estimate_spectrum_noalloc", "rexi_get_solution",
+           "rexi_destroy", "rexi_status_string", "rexi_last_error")
 
 
 class c128(C.Structure):
@@ -52,17 +52,17 @@ class Options(C.Structure):
                 ("max_workspace_bytes", C.c_int64), ("march_planes", C.c_int32), ("march_slots", C.c_int32),
                 ("fallback", C.c_int32), ("fallback_m", C.c_int32), ("fallback_bytes", C.c_int64),
                 ("stab_eps", C.c_double), ("center", C.c_int32), ("discretization", C.c_int32),
-                ("adjoint_shared", C.c_int32), ("reserved_opt_", C.c_int32)]
+                ("adjoint_shared", C.c_int32), ("keep_solutions", C.c_int32)]
 
 
 class StepInfo(C.Structure):
     _fields_ = [("K", C.c_int32), ("steps", C.c_int32), ("total_iterations", C.c_int64),
                 ("max_cycles_used", C.c_int32), ("not_converged", C.c_int32),
                 ("max_rel_residual", C.c_double), ("certified_bound", C.c_double),
-                ("reorth_passes", C.c_int32), ("reserved_", C.c_int32),
+                ("reorth_passes", C.c_int32), ("explicit_residuals", C.c_int32),
                 ("norm_in", C.c_double), ("norm_out", C.c_double),
                 ("iterations", C.POINTER(C.c_int32)), ("cycles", C.POINTER(C.c_int32)),
-                ("rel_residual", C.POINTER(C.c_double))]
+                ("rel_residual", C.POINTER(C.c_double)), ("implicit_residual", C.POINTER(C.c_double))]
 
 
 class Tiling(C.Structure):
@@ -91,13 +91,14 @@ _lib.rexi_get_profile.argtypes = [_H, C.POINTER(Profile)]
 _lib.rexi_profile_reset.argtypes = [_H]
 _lib.rexi_workspace_info.argtypes = [_H, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
 _lib.rexi_tiling_info.argtypes = [_H, C.POINTER(Tiling)]
+_lib.rexi_get_solution.argtypes = [_H, C.c_int32, _P, _P]
 _lib.rexi_destroy.argtypes = [_H]
 _lib.rexi_status_string.argtypes = [C.c_int]
 _lib.rexi_status_string.restype = C.c_char_p
 _lib.rexi_last_error.argtypes = [_H, C.c_char_p, C.c_size_t]
 for _f in ("rexi_setup", "rexi_setup_batch", "rexi_apply_H", "rexi_step", "rexi_step_adjoint", "rexi_get_profile",
            "rexi_profile_reset", "rexi_workspace_info", "rexi_destroy", "rexi_last_error", "rexi_estimate_spectrum",
-           "rexi_estimate_spectrum_noalloc"):
+           "rexi_estimate_spectrum_noalloc", "rexi_get_solution"):
     getattr(_lib, _f).restype = C.c_int
 
 
@@ -222,20 +223,30 @@ class Handle:
         it = (C.c_int32 * self.K)()
         cy = (C.c_int32 * self.K)()
         rr = (C.c_double * self.K)()
+        ri = (C.c_double * self.K)()
         inf = StepInfo()
         inf.iterations = C.cast(it, C.POINTER(C.c_int32))
         inf.cycles = C.cast(cy, C.POINTER(C.c_int32))
         inf.rel_residual = C.cast(rr, C.POINTER(C.c_double))
+        inf.implicit_residual = C.cast(ri, C.POINTER(C.c_double))
         st = _lib.rexi_step(self._h, pi, po, int(nsteps), C.byref(inf), _stream(stream))
         out = dict(K=inf.K, steps=inf.steps, total_iterations=inf.total_iterations,
                    max_cycles_used=inf.max_cycles_used, not_converged=inf.not_converged,
                    max_rel_residual=inf.max_rel_residual, certified_bound=inf.certified_bound,
                    norm_in=inf.norm_in, norm_out=inf.norm_out, reorth_passes=inf.reorth_passes,
-                   iterations=list(it), cycles=list(cy),
-                   rel_residual=list(rr), status=st)
+                   iterations=list(it), cycles=list(cy), explicit_residuals=bool(inf.explicit_residuals),
+                   rel_residual=list(rr), implicit_residual=list(ri), status=st)
         if st != REXI_OK and (st != REXI_E_NOT_CONVERGED or raise_on_nc):
             _check(st, self._h)
         return out
+
+    def solution(self, pole: int, x, stream=None):
+        """``rexi_get_solution``: x_j of pole ``pole`` of the last step into the
+        complex128 CUDA tensor ``x`` (the pole's instance size)."""
+        px = x.data_ptr() if x.is_contiguous() and str(x.dtype) == "torch.complex128" else None
+        if px is None or x.device.type != "cuda":
+            raise TypeError("expected a contiguous complex128 CUDA tensor")
+        _check(_lib.rexi_get_solution(self._h, int(pole), px, _stream(stream)), self._h)
 
     def step_adjoint(self, psi_n, gbar_next, gbar_n, dV_accum=None, stream=None):
         """One backward step: gbar_n = R^H gbar_next, dV_accum += dL/dV."""

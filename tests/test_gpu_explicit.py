@@ -1,0 +1,302 @@
+"""Explicit FP64 residuals and kept pole solutions, checked on the CPU.
+
+With keep_solutions the library hands out every pole solution x_j of the
+last step (rexi_get_solution). The CPU then forms, with the oracle's sparse
+H, the residual r_j = psi - (H - s_j) x_j of each one, which must equal the
+residual the library reports, and the certificate (Section 3.1: H - s_j is
+normal, so ||x_j - x_j*|| <= ||r_j|| / dist(s_j, spec H))
+    ||psi_gpu - psi*|| <= ||psi_gpu - sum_j w_j x_j|| + sum_j |w_j| ||r_j|| / dist_j ,
+which bounds the GPU step's distance to the exact step of eq.
+rational-evaluation without trusting any GPU arithmetic. At full size
+(the benchmarked 128^3 bump workload, where no direct solve is feasible)
+this is the parity evidence, together with element-wise comparisons of
+sampled poles' x_j with the oracle's own GMRES solves.
+"""
+import numpy as np
+import pytest
+
+from oracle import faber_cf as fcf
+from oracle import hamiltonian as ham
+from oracle import krylov as okr
+from oracle import step as ost
+from paper_1912_03312_amd import inputs
+
+from .gpu_util import rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(float).eps
+_POLES = {}
+
+
+def poles(K, R1):
+    if (K, R1) not in _POLES:
+        s, b, _ = fcf.faber_cf(K, R1)
+        _POLES[(K, R1)] = (s, b)
+    return _POLES[(K, R1)]
+
+
+@pytest.fixture(scope="module")
+def rexi():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1912_03312_amd import rexi as r
+    return r
+
+
+def _dist(shifts, lo, hi):
+    return np.abs(np.clip(shifts.real, lo, hi) - shifts)
+
+
+def cpu_certificate(h, g, V, psi, sigma, beta, dt, psi_gpu, info, pole0=0, center=0.0):
+    """CPU residuals of the kept solutions of one instance (poles pole0..):
+    returns (certificate, combination difference, [(|rho_cpu - rho_gpu|,
+    allowed)] per pole, slack, amp) with slack = sum_j |w_j| allowed_j /
+    dist_j, the most the two certificates may differ by rounding, and
+    amp = sum_j |w_j| ||x_j|| / ||psi||, which scales the rounding of the
+    pole sum (its terms cancel down to ||psi_{n+1}|| ~ ||psi||)."""
+    import torch
+    H = ham.hamiltonian(g.n, g.h, V).astype(np.complex128)
+    b = np.asarray(psi, dtype=np.complex128).ravel()
+    bn = np.linalg.norm(b)
+    sj, wj = ost.shifts_and_weights(sigma, beta, dt)
+    wj = wj * np.exp(-1j * dt * center)
+    lo, hi = ham.gershgorin(g.n, g.h, V)
+    dist = _dist(sj, lo - center, hi - center)
+    xd = torch.empty(g.size, dtype=torch.complex128, device="cuda")
+    acc = np.zeros_like(b)
+    cert = slack = amp = 0.0
+    mism = []
+    for j in range(len(sj)):
+        h.solution(pole0 + j, xd)
+        torch.cuda.synchronize()
+        x = xd.cpu().numpy()
+        r = b - (H @ x - (sj[j] + center) * x)
+        rho = float(np.linalg.norm(r)) / bn
+        acc += wj[j] * x
+        amp += abs(wj[j]) * float(np.linalg.norm(x)) / bn
+        cert += abs(wj[j]) * rho / dist[j]
+        # the library's explicit residual of the same x_j: the two differ by
+        # the rounding of r, about u (|lambda|_max + |s_j|) ||x_j||
+        gap = abs(rho - info["rel_residual"][pole0 + j])
+        tol = 16 * EPS * (1.0 + (max(abs(lo), abs(hi)) + abs(sj[j])) / dist[j])
+        mism.append((gap, tol))
+        slack += abs(wj[j]) * tol / dist[j]
+    comb = float(np.linalg.norm(np.asarray(psi_gpu).ravel() - acc)) / bn
+    return cert, comb, mism, slack, amp
+
+
+def _workload(name, scale):
+    wl = inputs.workload(name, scale=scale)
+    return wl, wl.grid
+
+
+@pytest.mark.parametrize("name,scale,K,R1,opts", [
+    ("3d_bumps", 14, 64, 180.0, dict(m=120)),
+    ("3d_bumps", 14, 64, 180.0, dict(m=120, march_planes=4, march_slots=2)),
+    ("2d_adjoint", 33, 32, 80.0, dict(m=200, center=1)),
+    ("1d_harmonic", None, 16, 28.0, dict(m=200)),
+])
+def test_explicit_residuals_and_kept_solutions(rexi, name, scale, K, R1, opts):
+    import torch
+    wl, g = _workload(name, scale)
+    s, b = poles(K, R1)
+    center = 0.0
+    if opts.get("center"):
+        lo, hi = ham.gershgorin(g.n, g.h, wl.V)
+        center = 0.5 * (lo + hi)
+    h = rexi.setup(g.n, g.lo, g.hi, to_dev(wl.V.ravel()), 1.0, 1.0, wl.dt, s, b, solver="shifted", tol=1e-11,
+                   tol_policy="certified", keep_solutions=1, **opts)
+    p0 = to_dev(wl.psi0.ravel())
+    out = torch.empty_like(p0)
+    info = h.step(p0, out, 1)
+    torch.cuda.synchronize()
+    og = out.cpu().numpy()
+    cert, comb, mism, slack, amp = cpu_certificate(h, g, wl.V, wl.psi0, s, b, wl.dt, og, info, center=center)
+    h.close()
+    assert info["explicit_residuals"] and info["not_converged"] == 0
+    assert all(gap <= tol for gap, tol in mism), max(mism)
+    # the library's certificate is the same sum of its explicit residuals
+    assert abs(info["certified_bound"] - cert) <= slack
+    imp, exp_ = np.array(info["implicit_residual"]), np.array(info["rel_residual"])
+    print("largest implicit / explicit residual ratio", float(np.max(imp / np.maximum(exp_, 1e-300))))
+    D = ost.DirectStepper(g.n, g.h, wl.V, s, b, wl.dt, center=center)
+    e = rel(og, D.step(wl.psi0))
+    print("explicit", name, g.n, opts, "err", e, "cert", cert, "comb", comb, "its", info["total_iterations"])
+    # the CPU certificate bounds the error against the direct oracle, up to
+    # the direct solves' own rounding (about floor_iter)
+    sj, wj = ost.shifts_and_weights(s, b, wl.dt)
+    assert e <= cert + comb + 2 * _floor_iter(g, wl.V, sj, wj)
+
+
+@pytest.mark.parametrize("fallback,batch", [(1, False), (2, False), (1, True)])
+def test_explicit_residuals_after_restarts(rexi, fallback, batch):
+    # a basis of 6 (single 3D instance) or 24 vectors (batch) is too short
+    # for most poles: their solutions collect over restart cycles (fallback
+    # 1) or come from per-pole solves (fallback 2); the kept x_j and their
+    # explicit residuals must still be the final ones
+    import torch
+    if batch:
+        insts = inputs.batch_instances(count=4, sides=(17, 31, 40, 47))
+    else:
+        wl = inputs.workload("3d_bumps", scale=12)
+        insts = [dict(grid=wl.grid, V=wl.V, psi0=wl.psi0, dt=wl.dt, K=wl.K)]
+    R1 = {64: 180.0}
+    grids, Vs, psis, dts, Ks, sig, bet = [], [], [], [], [], [], []
+    for it in insts:
+        g = it["grid"]
+        s, b = poles(it["K"], R1.get(it["K"], inputs.R1_PARITY[it["K"]]))
+        grids.append((g.n, g.lo, g.hi))
+        Vs.append(it["V"].ravel())
+        psis.append(it["psi0"].ravel())
+        dts.append(it["dt"])
+        Ks.append(it["K"])
+        sig.append(s)
+        bet.append(b)
+    cnt = len(insts)
+    h = rexi.setup_batch(grids, to_dev(np.concatenate(Vs)), [1.0] * cnt, [1.0] * cnt, dts, Ks,
+                         np.concatenate(sig), np.concatenate(bet), solver="shifted", m=24 if batch else 6,
+                         tol=1e-11, tol_policy="certified", fallback=fallback, max_cycles=200, keep_solutions=1)
+    p0 = to_dev(np.concatenate(psis))
+    out = torch.empty_like(p0)
+    info = h.step(p0, out, 1)
+    torch.cuda.synchronize()
+    og = out.cpu().numpy()
+    assert info["explicit_residuals"] and info["not_converged"] == 0 and info["max_cycles_used"] > 1
+    off, q = 0, 0
+    certs, slacks = [], []
+    for i, it in enumerate(insts):
+        g = it["grid"]
+        cert, comb, mism, slack, amp = cpu_certificate(h, g, it["V"], it["psi0"], sig[i], bet[i], dts[i],
+                                           og[off:off + g.size], info, pole0=q)
+        assert all(gap <= tol for gap, tol in mism), (i, max(mism))
+        e = rel(og[off:off + g.size], ost.DirectStepper(g.n, g.h, it["V"], sig[i], bet[i], dts[i]).step(it["psi0"]))
+        certs.append((g.n, e, cert, comb))
+        slacks.append(slack)
+        sj, wj = ost.shifts_and_weights(sig[i], bet[i], dts[i])
+        assert e <= cert + comb + 2 * _floor_iter(g, it["V"], sj, wj), certs[-1]
+        off += g.size
+        q += Ks[i]
+    h.close()
+    print("restarts", fallback, batch, info["max_cycles_used"], certs)
+    # the reported bound is the largest per-instance certificate
+    assert abs(info["certified_bound"] - max(c[2] for c in certs)) <= max(slacks)
+
+
+def test_per_pole_solutions_and_residuals(rexi):
+    import torch
+    wl, g = _workload("2d_adjoint", 24)
+    s, b = poles(16, 28.0)
+    h = rexi.setup(g.n, g.lo, g.hi, to_dev(wl.V.ravel()), 1.0, 1.0, wl.dt, s, b, tol=1e-11, tol_policy="certified")
+    p0 = to_dev(wl.psi0.ravel())
+    out = torch.empty_like(p0)
+    xd = torch.empty_like(p0)
+    with pytest.raises(rexi.RexiError):
+        h.solution(0, xd)  # no step yet
+    info = h.step(p0, out, 1)
+    torch.cuda.synchronize()
+    cert, comb, mism, slack, amp = cpu_certificate(h, g, wl.V, wl.psi0, s, b, wl.dt, out.cpu().numpy(), info)
+    h.close()
+    assert info["explicit_residuals"]
+    assert all(gap <= tol for gap, tol in mism), max(mism)
+    assert info["implicit_residual"] == info["rel_residual"]
+    print("per pole kept", cert, comb, amp)
+    # the library's FP64 pole sum of the same x_j, in the same order: they
+    # differ by the rounding of the sum only
+    assert comb <= 4 * len(s) * EPS * amp
+
+
+def test_solutions_need_keep_solutions_on_the_shared_basis(rexi):
+    import torch
+    wl, g = _workload("3d_bumps", 10)
+    s, b = poles(16, 32.0)
+    h = rexi.setup(g.n, g.lo, g.hi, to_dev(wl.V.ravel()), 1.0, 1.0, wl.dt, s, b, solver="shifted", m=80)
+    p0 = to_dev(wl.psi0.ravel())
+    out = torch.empty_like(p0)
+    info = h.step(p0, out, 1)
+    assert info["explicit_residuals"]  # info steps form the solutions anyway
+    with pytest.raises(rexi.RexiError, match="keep_solutions"):
+        h.solution(0, out)
+    with pytest.raises(rexi.RexiError):
+        rexi.setup(g.n, g.lo, g.hi, to_dev(wl.V.ravel()), 1.0, 1.0, wl.dt, s, b, solver="shifted", keep_solutions=2)
+    h.close()
+
+
+def _floor_iter(g, V, sj, wj):
+    lo, hi = ham.gershgorin(g.n, g.h, V)
+    dist = _dist(sj, lo, hi)
+    return float(np.sum(np.abs(wj) / dist * EPS * (1.0 + (max(abs(lo), abs(hi)) + np.abs(sj)) / dist)))
+
+
+@pytest.mark.timeout(400)
+def test_bench_configuration_full_scale_against_oracle(rexi):
+    # the benchmarked step itself: 128^3 bumps, 64 poles, shared basis in
+    # the stored launch configuration (tiled pass, 16 planes per item),
+    # certified policy at 1e-10. No direct solve is feasible at this size:
+    # the CPU certificate of the kept solutions bounds the error against the
+    # exact step, and sampled poles' solutions are compared element by
+    # element with the oracle's GMRES solves (tight targets, on every core)
+    import time
+
+    import torch
+    wl = inputs.workload("3d_bumps")
+    g = wl.grid
+    s, b = poles(wl.K, wl.R1)
+    h = rexi.setup(g.n, g.lo, g.hi, to_dev(wl.V.ravel()), 1.0, 1.0, wl.dt, s, b, solver="shifted", m=100,
+                   tol=1e-10, tol_policy="certified", tile=1024, grid_blocks=1024, march_planes=16, march_slots=2,
+                   keep_solutions=1)
+    t = h.tiling()
+    assert (t["march_slots"], t["march_planes"], t["march_items"]) == (2, 16, 256), t
+    p0 = to_dev(wl.psi0.ravel())
+    out = torch.empty_like(p0)
+    info = h.step(p0, out, 1)
+    torch.cuda.synchronize()
+    og = out.cpu().numpy()
+    t0 = time.perf_counter()
+    cert, comb, mism, slack, amp = cpu_certificate(h, g, wl.V, wl.psi0, s, b, wl.dt, og, info)
+    t_cert = time.perf_counter() - t0
+    sj, wj = ost.shifts_and_weights(s, b, wl.dt)
+    floor = _floor_iter(g, wl.V, sj, wj)
+    bar = max(1e-10, 3 * floor)
+    print(f"bench config 128^3: its {info['total_iterations']}, library bound {info['certified_bound']:.3e}, "
+          f"CPU certificate {cert:.3e} + combination {comb:.3e}, floor_iter {floor:.3e}, bar {bar:.3e} "
+          f"({t_cert:.1f} s)", flush=True)
+    assert info["explicit_residuals"] and info["not_converged"] == 0
+    assert all(gap <= tol for gap, tol in mism), max(mism)
+    assert cert + comb <= bar
+    # sampled poles against the oracle's own solves: the pole that weighs
+    # most in the certificate (largest |w_j| / dist_j, also the slowest to
+    # solve), the median one and the lightest
+    lo, hi = ham.gershgorin(g.n, g.h, wl.V)
+    dist = _dist(sj, lo, hi)
+    weight = np.abs(wj) / dist
+    order = [int(j) for j in np.argsort(-weight)]
+    sample = sorted({order[0], order[len(order) // 2], order[-1]})
+    H = ham.hamiltonian(g.n, g.h, wl.V).astype(np.complex128)
+    psi = wl.psi0.ravel().astype(np.complex128)
+    xd = torch.empty_like(p0)
+    t0 = time.perf_counter()
+    from concurrent.futures import ThreadPoolExecutor
+
+    from threadpoolctl import threadpool_limits
+
+    def solve(j):
+        tol = max(1e-14, 4 * EPS * (1.0 + (hi + abs(sj[j])) / dist[j]))
+        return okr.gmres(lambda x: H @ x - sj[j] * x, psi, tol, 60)
+
+    with threadpool_limits(limits=1):
+        with ThreadPoolExecutor(max_workers=min(len(sample), okr.host_threads())) as ex:
+            ref = dict(zip(sample, ex.map(solve, sample)))
+    for j in sample:
+        h.solution(int(j), xd)
+        torch.cuda.synchronize()
+        xg = xd.cpu().numpy()
+        xo, its, rho_o = ref[j]
+        e = rel(xg, xo)
+        # both solutions lie within their residual bounds of x_j*
+        bnd = (info["rel_residual"][j] + rho_o) * np.linalg.norm(psi) / dist[j] / np.linalg.norm(xo)
+        print(f"pole {j}: |w|/dist {weight[j]:.2e}, oracle its {its} rho {rho_o:.1e}, rel diff {e:.2e}, "
+              f"bound {bnd:.2e}", flush=True)
+        assert e <= bnd * (1 + 1e-6) + 1e-13
+    print(f"oracle solves of {len(sample)} poles: {time.perf_counter() - t0:.1f} s", flush=True)
+    h.close()
