@@ -125,7 +125,8 @@ typedef struct {
   int32_t solver;      /* rexi_solver, default REXI_SOLVER_PER_POLE          */
   int32_t m;           /* Krylov dimension per cycle (restart length), 30;
                           at most 256. For the shared-basis solver the
-                          largest Krylov dimension (no restarts)             */
+                          largest basis of one cycle (poles that need more
+                          restart on a new shared basis, option fallback)   */
   int32_t max_cycles;  /* restarts / refinement sweeps per solve, 20         */
   double tol;          /* see tol_policy, default 1e-10                      */
   int32_t tol_policy;  /* rexi_tol_policy, default REXI_TOL_RELRES           */

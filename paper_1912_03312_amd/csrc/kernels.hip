@@ -562,6 +562,11 @@ struct ShiftWork {
   const double* s;    // [K] complex shifts
   const double* w;    // [K] complex weights
   const double* tol;  // [K] target relative residuals
+  // certified policy: cw[p] = |w_p| / dist(s_p, spectrum bound); an instance
+  // also stops once sum_p cw[p] ||r_p|| <= tau ||b|| / 2 (null: per-pole
+  // targets only)
+  const double* cw;
+  double tau;
   double* R;          // [K][(m+1) m] complex, rotated Hessenberg per pole
   double* g;          // [K][m+1] complex
   double* gc;         // [K][m] complex
@@ -908,7 +913,7 @@ __device__ void givens_shifted(Work& W, ShiftWork& SW, int s, int j, double beta
   const double2* hcol = reinterpret_cast<const double2*>(Hs) + (int64_t)j * (m + 1);
   const double bn = st.bnorm;
   const int i_start = banded ? max(0, j - 2) : 0;
-  double unconv = 0.0;
+  double unconv = 0.0, wsum = 0.0;
   for (int p = SW.pole0[s] + threadIdx.x; p < SW.pole0[s + 1]; p += TPB) {
     double2* Rp = reinterpret_cast<double2*>(SW.R) + (int64_t)p * (m + 1) * m;
     double2* col = Rp + (int64_t)j * (m + 1);
@@ -973,8 +978,19 @@ __device__ void givens_shifted(Work& W, ShiftWork& SW, int s, int j, double beta
     } else {
       unconv += 1.0;
     }
+    if (SW.cw) wsum += SW.cw[p] * res;
   }
   unconv = block_sum(unconv, lds);
+  if (SW.cw && unconv > 0.0) {
+    // the certified sum of the whole instance already meets its target: every
+    // pole stops here (each one's share of the budget is not needed)
+    wsum = block_sum(wsum, lds);
+    if (wsum <= 0.5 * SW.tau * bn) {
+      for (int p = SW.pole0[s] + threadIdx.x; p < SW.pole0[s + 1]; p += TPB)
+        if (SW.its[p] == 0) SW.its[p] = j + 1;
+      unconv = 0.0;
+    }
+  }
   if (threadIdx.x == 0) {
     const int k = j + 1;
     SW.full[(int64_t)s * m + j] = banded ? 0 : 1;
@@ -1960,7 +1976,7 @@ __device__ void lz_end_body(Work& W, ShiftWork& SW, int s, int j, int colparts) 
   // alpha_j - s_p (row j); rotations j-2 and j-1 act on it, then the new
   // rotation j annihilates beta_{j+1}
   const double bn = st.bnorm;
-  double unconv = 0.0;
+  double unconv = 0.0, wsum = 0.0;
   for (int q = p; q < p1; q += TPB) {
     if (q != p) {  // poles beyond the first TPB: load here
       const double2* gcv = reinterpret_cast<const double2*>(SW.gc) + (int64_t)q * m;
@@ -2011,9 +2027,16 @@ __device__ void lz_end_body(Work& W, ShiftWork& SW, int s, int j, int colparts) 
     } else {
       unconv += 1.0;
     }
+    if (SW.cw) wsum += SW.cw[q] * res;
   }
-  double z0 = 0.0, z1 = 0.0, z2 = 0.0;
-  block_sum4(unconv, z0, z1, z2, l4);
+  double z1 = 0.0, z2 = 0.0;
+  block_sum4(unconv, wsum, z1, z2, l4);
+  if (SW.cw && unconv > 0.0 && wsum <= 0.5 * SW.tau * bn) {
+    // the certified sum of the whole instance already meets its target
+    for (int q = p; q < p1; q += TPB)
+      if (SW.its[q] == 0) SW.its[q] = j + 1;
+    unconv = 0.0;
+  }
   if (tid == 0) {
     const int k = j + 1;
     SW.full[(int64_t)s * m + j] = 0;

@@ -13,8 +13,8 @@ def pytest_configure(config):
 
 
 def pytest_sessionstart(session):
-    # tests load the in-tree library; build it only when nothing is built
-    lib = os.path.join(ROOT, "paper_1912_03312_amd", "librexi.so")
-    if not os.path.exists(lib):
-        from paper_1912_03312_amd.build import build
-        build()
+    # tests load the in-tree library: build it when none is built or when it
+    # was built from other sources than the current ones
+    from paper_1912_03312_amd import build as b
+    if not b.is_current():
+        b.build()
