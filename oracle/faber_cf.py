@@ -1,32 +1,45 @@
 """Faber-Caratheodory-Fejer poles and weights (oracle, FP64, test infrastructure).
 
-Follows Section 3.2 of the paper:
+Only the test suite, the smoke check and the CPU-baseline leg of the
+benchmark use this module; it shares nothing with the GPU path.
 
-* Faber coefficients of ``f = exp`` for the conformal map
-  ``eta(z) = (R1/2)(z - 1/z)`` (eq. ``map-to-imaginary``), from the contour
-  integral of eq. ``faber-series`` sampled on the unit circle (the FFT route
-  the paper names for Maclaurin coefficients).
-* Algorithm 1 (CF): Hankel matrix of the coefficients, its SVD, the
-  (n+1)-st singular triplet, the best approximation ``r~*`` of Theorem 1, the
-  exterior roots of ``q``, the Laurent sequence of ``q_out r~*`` and the CF
-  approximant with the negative-index terms dropped.
-* Algorithm 2 (FaberCF): poles ``sigma_j = eta(z_j)``, Faber sequences of
-  ``w -> 1/(w - sigma_k)``, Maclaurin coefficients of ``r_cf`` and the K x K
-  linear system for the weights ``beta``.
+What is computed (Section 3.2). A rational function
+r(w) = sum_k beta_k / (w - sigma_k) with K poles is sought that approximates
+exp(w) on the segment i[-R1, R1]. The construction works in the disc:
 
-Readings where the text is garbled (index typos in Theorem 1 and
-Algorithm 1): the Hankel matrix is (L+1) x (L+1) with entries ``a_{i+j}``
-(zero beyond L); ``p(z) = sum_k u_k z^k`` and ``q(z) = sum_k v_{L-k} z^k``
-(0-based), ``u, v`` the (n+1)-st columns of ``U`` and ``V`` in
-``H = U S V^H``; the Laurent sequence is that of ``q_out * r~*``.
+* The map eta(z) = (R1/2)(z - 1/z) (eq. ``map-to-imaginary``) takes the unit
+  circle onto the segment, and exp(eta(e^{it})) = exp(i R1 sin t). The Faber
+  coefficients of exp (eq. ``faber-series``) are therefore the Fourier
+  coefficients of that function: the Bessel values a_j = J_j(R1), real. They
+  are sampled here by an FFT on the circle.
+* Theorem 1 (Caratheodory-Fejer): how well the truncated series
+  h(z) = sum_{j<=L} a_j z^j can be matched on the circle by functions with K
+  poles outside the disc is read off the Hankel matrix [a_{i+j}]. Its
+  entries are real, so it is real symmetric and its singular values are the
+  moduli of its eigenvalues. With lam the (K+1)-st eigenvalue in modulus and
+  v its (real) eigenvector, read as the polynomial v(z) = sum_j v_j z^j, the
+  best approximation r~* satisfies
+      h(z) - r~*(z) = lam v(z) / v(1/z),
+  which has modulus |lam| all round the circle (v(1/z) is the conjugate of
+  v(z) there). Its poles outside the disc are z_k = 1/zeta_k for the roots
+  zeta_k of v inside the disc; there must be exactly K of them.
+* The CF approximant keeps those K poles: r_cf = N(z) / prod_k (z - z_k) with
+  N the part of degree below K of the Laurent series of
+  prod_k (z - z_k) r~*(z) on the circle.
+* Back on the segment the poles are sigma_k = eta(z_k). The Faber transform
+  is linear and takes 1/(w - sigma_k) to 1/(eta'(z_k) (z - z_k)) on the disc
+  (its Maclaurin coefficients are -z_k^{-n-1} / eta'(z_k)), so the weights
+  solve "transform of r = r_cf". Section 3.2 imposes this on the first K
+  Maclaurin coefficients; that K x K system becomes numerically singular as
+  K grows (condition number past 1e15 near K = 24); beyond ``cond_max`` = 1e9
+  (where the system's rounding, about cond * 1e-16, reaches the size of the
+  approximation error itself: K = 16, R1 = 28 has 7.8e9) the weights are the
+  linear least-squares fit of r to exp on the segment instead (same poles).
+  ``info['weights']`` says which route was taken.
 
-Reading for the weights: the K x K system of Algorithm 2 becomes
-numerically singular as K grows (its condition number passes 1e15 near
-K = 24). When its condition number exceeds ``cond_max`` the weights are
-instead the linear least-squares fit of ``sum_k beta_k/(iy - sigma_k)`` to
-``exp(iy)`` on ``y`` in ``[-R1, R1]`` -- same poles, a different but
-well-posed route to the residues. ``info['weights']`` records which route
-was taken.
+Readings where the text is garbled (the index typos of Theorem 1): the
+Hankel matrix is (L+1) x (L+1) with entries a_{i+j}, zero beyond L, and the
+(n+1)-st singular pair is the one of index K (0-based).
 """
 from __future__ import annotations
 
@@ -73,36 +86,54 @@ def default_L(K, R1):
     return L
 
 
-def cf(a, n, M=None):
-    """Algorithm 1: CF approximation of ``h(z) = sum_{j<=L} a_j z^j`` with
-    numerator degree ``n - 1`` and denominator degree ``n``.
+def _poly(c, z):
+    """sum_j c_j z^j for ascending coefficients ``c``."""
+    return np.polyval(np.asarray(c)[::-1], z)
 
-    Returns ``(num, zk, info)``: ``num`` the coefficients ``d_0..d_{K-1}`` of the
-    numerator (ascending), ``zk`` the K roots of ``q`` outside the unit disc (so
-    ``r_cf = num(z) / prod_k (z - zk)``) and diagnostics.
-    """
-    a = np.asarray(a, dtype=np.complex128)
+
+def hankel_spectrum(a):
+    """Eigen-decomposition of the real symmetric Hankel matrix [a_{i+j}]
+    (zero past L), ordered by decreasing eigenvalue modulus: returns the
+    signed eigenvalues (their moduli are the singular values) and the
+    eigenvectors as columns."""
+    a = np.asarray(a)
+    if np.iscomplexobj(a):
+        if np.max(np.abs(a.imag)) > 1e-13 * np.max(np.abs(a)):
+            raise ValueError("the Faber coefficients of exp on i[-R1, R1] are real")
+        a = a.real
     L = a.size - 1
-    # Hankel matrix of Theorem 1 / Algorithm 1: H[i, j] = a_{i+j}, zero past L
-    idx = np.add.outer(np.arange(L + 1), np.arange(L + 1))
-    H = np.where(idx <= L, a[np.minimum(idx, L)], 0.0)
-    U, S, Vh = np.linalg.svd(H)
-    s = S[n]                       # (n+1)-st singular value
-    u = U[:, n]                    # (n+1)-st column of U
-    v = np.conj(Vh[n, :])          # (n+1)-st column of V, H = U S V^H
-    p = u                          # p(z) = sum_k u_k z^k           (ascending)
-    q = v[::-1]                    # q(z) = sum_k v_{L-k} z^k      (ascending)
+    i = np.arange(L + 1)
+    idx = i[:, None] + i[None, :]
+    Hk = np.where(idx <= L, a[np.minimum(idx, L)], 0.0)
+    lam, vec = np.linalg.eigh(Hk)
+    order = np.argsort(-np.abs(lam), kind="stable")
+    return lam[order], vec[:, order]
+
+
+def cf(a, K, M=None):
+    """Caratheodory-Fejer approximation of type (K-1, K) of
+    ``h(z) = sum_{j<=L} a_j z^j`` on the unit circle (Theorem 1).
+
+    Returns ``(num, zk, info)``: ``num`` the ascending coefficients of the
+    numerator N of r_cf, ``zk`` its poles outside the disc (so
+    ``r_cf = N(z) / prod_k (z - zk)``) and diagnostics, among them ``h_fun``
+    and ``rtilde`` (the best approximation r~*) for checking Theorem 1.
+    """
+    a = np.asarray(a)
+    L = a.size - 1
+    lam_all, vec = hankel_spectrum(a)
+    lam, v = lam_all[K], vec[:, K]
+    hc = a.real if np.iscomplexobj(a) else a
 
     def h_of(z):
-        return np.polyval(a[::-1], z)
+        return _poly(hc, z)
 
     def rtilde(z):
-        return h_of(z) - s * z ** L * np.polyval(p[::-1], z) / np.polyval(q[::-1], z)
+        return h_of(z) - lam * _poly(v, z) / _poly(v, 1.0 / z)
 
-    roots = np.roots(q[::-1])
-    zk = roots[np.abs(roots) > 1.0]
-    K = zk.size
-    M = M or max(4096, 8 * (L + n))
+    zeta = np.roots(v[::-1])             # the roots of v(z)
+    zk = 1.0 / zeta[np.abs(zeta) < 1.0]  # poles of r~* outside the disc
+    M = M or max(4096, 8 * (L + K))
 
     def qout(z):
         out = np.ones_like(z)
@@ -110,44 +141,41 @@ def cf(a, n, M=None):
             out = out * (z - r)
         return out
 
-    d = laurent_coefficients(lambda z: qout(z) * rtilde(z), n - 1, M)
-    num = d[:K]
-    info = dict(L=L, sigma_next=float(s), singular_values=S, exterior_roots=K,
-                n=n, p=p, q=q, h_fun=h_of, rtilde=rtilde)
+    num = laurent_coefficients(lambda z: qout(z) * rtilde(z), K - 1, M)[: zk.size]
+    info = dict(L=L, sigma_next=float(abs(lam)), lam=float(lam), singular_values=np.abs(lam_all),
+                exterior_roots=int(zk.size), n=K, v=v, h_fun=h_of, rtilde=rtilde)
     return num, zk, info
 
 
-def faber_cf(K, R1, L=None, M=None, cond_max=1e10, ls_points=20001):
-    """Algorithm 2: poles ``sigma`` and weights ``beta`` of
-    ``r(w) = sum_k beta_k / (w - sigma_k) ~ exp(w)`` on ``i[-R1, R1]``.
+def faber_cf(K, R1, L=None, M=None, cond_max=1e9, ls_points=20001):
+    """Poles ``sigma`` and weights ``beta`` of ``r(w) = sum_k beta_k / (w - sigma_k)
+    ~ exp(w)`` on ``i[-R1, R1]`` (Section 3.2).
 
-    Returns ``(sigma, beta, info)``. ``info`` holds the CF data, the condition
-    number of the K x K system and which route produced the weights.
+    Returns ``(sigma, beta, info)``; ``info`` holds the CF data, the condition
+    number of the Maclaurin matching system and which route gave the weights.
     """
     L = L or default_L(K, R1)
     a = faber_sequence_exp(R1, L, M)
     num, zk, info = cf(a, K, M)
     Kf = zk.size
     sigma = eta(zk, R1)
-    # Faber sequences of w -> 1/(w - sigma_k): Laurent coefficients of
-    # 1/(eta(z) - sigma_k) on a circle between 1/|z_k| and |z_k| (the unit circle)
-    Mb = M or max(4096, 8 * (L + K))
-    B = np.empty((Kf, Kf), dtype=np.complex128)
-    for k in range(Kf):
-        B[:, k] = laurent_coefficients(lambda z: 1.0 / (eta(z, R1) - sigma[k]), Kf - 1, Mb)
 
-    # Maclaurin coefficients of r_cf (analytic in the closed unit disc)
     def rcf(z):
         den = np.ones_like(z)
         for r in zk:
             den = den * (z - r)
-        return np.polyval(num[::-1], z) / den
+        return _poly(num, z) / den
 
-    c = laurent_coefficients(rcf, Kf - 1, Mb)
-    condB = float(np.linalg.cond(B))
+    # transform of r = r_cf on the first Kf Maclaurin coefficients: the
+    # transform of 1/(w - sigma_k) contributes -z_k^{-n-1} / eta'(z_k) to
+    # coefficient n; r_cf is analytic on the closed disc
+    n = np.arange(Kf)[:, None]
+    B = -zk[None, :] ** (-n - 1.0) / eta_prime(zk, R1)[None, :]
+    c = laurent_coefficients(rcf, Kf - 1, M or max(4096, 8 * (L + K)))
+    condB = float(np.linalg.cond(B)) if Kf else np.inf
     if condB <= cond_max:
         beta = np.linalg.solve(B, c)
-        route = "algorithm2"
+        route = "maclaurin"
     else:
         beta = least_squares_weights(sigma, R1, ls_points)
         route = "least_squares"
