@@ -345,8 +345,32 @@ def bench_batch(args, summary=False):
              "m": m_used}
     log(f"# batch: {ms:.1f} ms/step")
     if summary:
-        return dict(instances=cnt, points=npts, poles=int(sum(Ks)), steps=steps, value=round(1e3 / ms, 3),
-                    unit="steps/s", ms_per_step=round(ms, 2), graph_replay=bool(args.capture), solve=solve)
+        res = dict(instances=cnt, points=npts, poles=int(sum(Ks)), steps=steps, value=round(1e3 / ms, 3),
+                   unit="steps/s", ms_per_step=round(ms, 2), graph_replay=bool(args.capture), solve=solve)
+        if not args.capture:
+            # the same batch as one captured step per call (restart cycles on the
+            # shared basis inside the graph: two more than the eager step took)
+            ncyc = int(info["max_cycles_used"]) + 2
+            hg = rexi.setup_batch(grids, V, [1.0] * cnt, [1.0] * cnt, dts, Ks, np.concatenate(sig),
+                                  np.concatenate(bet), solver=args.solver, precision=args.precision, tol=args.tol,
+                                  tol_policy=args.tol_policy, m=m, capture_safe=1, capture_cycles=ncyc,
+                                  max_cycles=200)
+            cur = psi.clone()
+            for _ in range(2):  # record the graphs of both buffer orders
+                hg.step(cur, out, 1, info=False)
+                cur, out = out, cur
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(steps):
+                hg.step(cur, out, 1, info=False)
+                cur, out = out, cur
+            torch.cuda.synchronize()
+            cms = (time.perf_counter() - t1) * 1e3 / steps
+            hg.close()
+            res["captured"] = dict(value=round(1e3 / cms, 3), ms_per_step=round(cms, 2), graph_replay=True,
+                                   capture_cycles=ncyc)
+            log(f"# batch captured: {cms:.1f} ms/step")
+        return res
     res = {
         "metric": "REXI batch steps/sec, uneven 2D batch", "value": round(1e3 / ms, 4), "unit": "steps/s",
         "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),

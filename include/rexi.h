@@ -151,8 +151,18 @@ typedef struct {
                           the device. Captured once per (psi_in, psi_out,
                           nsteps) into a HIP graph that is replayed on the
                           stream; if the stream is itself being captured,
-                          the schedule is enqueued into the caller's graph  */
-  int32_t capture_cycles; /* per-pole solver, capture_safe: cycles, 4       */
+                          the schedule is enqueued into the caller's graph.
+                          The shared basis with the tiled pass (march_slots
+                          2) takes one launch per iteration; a second
+                          Gram-Schmidt pass takes up to 31 launches of that
+                          schedule (the first one is covered: m + 32
+                          launches), so a captured solve with several may
+                          stop below m vectors                              */
+  int32_t capture_cycles; /* capture_safe: cycles of a captured solve, the
+                          first included: per-pole solver 4, shared basis
+                          1 (no restarts) when 0 (the default); shared basis
+                          with fallback 1: capture_cycles - 1 restart cycles
+                          on the shared basis                               */
   int32_t graph_chunks;   /* shared-basis solver: replay cached HIP graphs of
                              iteration chunks between host checks, 1        */
   int32_t profile;     /* 1: time kernel classes with HIP events             */

@@ -175,6 +175,7 @@ struct rexi_handle {
   bool x_valid = false;               // X holds the solutions of the last step
   bool x_res = false;                 // xrn holds their residual norms
   bool stepped = false;               // a step has run (per pole: W.x holds its solutions)
+  int32_t* jdev = nullptr;            // device iteration indices of captured schedules (2 ints)
 };
 
 namespace {
@@ -549,7 +550,7 @@ rexi_status run_cycles(rexi_handle* h, Solver& sv, const double2* r0, const doub
     }
     HIPCHK(h, hipGetLastError());
     if (h->syncfree) {
-      if (c + 1 >= std::max(1, h->opt.capture_cycles)) break;
+      if (c + 1 >= (h->opt.capture_cycles > 0 ? h->opt.capture_cycles : 4)) break;
       continue;
     }
     // restarted count of this cycle: counters[max_cycles*(m+1)] accumulates; read the total
@@ -735,6 +736,11 @@ rexi_status init_shifted(rexi_handle* h, Solver& sv, rexi::ShiftWork& SW, bool c
   void* gp = nullptr;
   if ((st = al(&gp, i4))) return st;
   SW.gpause = (int32_t*)gp;
+  if (!h->jdev) {
+    void* jd = nullptr;
+    if ((st = al(&jd, 2 * i4))) return st;
+    h->jdev = (int32_t*)jd;
+  }
   // certified policy: the weights of the instance-wide stopping test
   SW.cw = nullptr;
   SW.tau = h->opt.tol;
@@ -1341,7 +1347,58 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
     }
     if ((sv.reorth || lz) && !pause_mode) second_pass(j, strm, G2);
   };
-  if (h->syncfree) {
+  // captured schedule with the fused tiled pass: one launch per iteration
+  // whose index lives on the device, so that a pause for a second pass (which
+  // the host cannot see) only shifts the later launches; after every group
+  // of QB launches a recovery runs the second pass of a paused iteration and
+  // the pass after it (each launch predicated: nothing happens without a
+  // pause). A pause costs the rest of its group; the schedule has QB launches
+  // beyond m, so the first pause costs no iteration and later ones shorten
+  // the largest Krylov dimension a captured solve reaches.
+  const bool capfuse = h->syncfree && pipe && lz && sv.col_kh == 2 && h->jdev;
+  if (capfuse) {
+    constexpr int QB = 32;
+    Work Wd = W;
+    Wd.jdev = h->jdev;
+    rexi::ShiftWork SWd = SWc;
+    SWd.pause_mode = 1;
+    hipLaunchKernelGGL(rexi::k_cap_init, dim3(1), dim3(64), 0, stream, Wd);
+    {
+      Timed t(h, PC_LANCZOS, n * lz_bytes(0), stream);
+      launch_lz_step<PPT>(sv, Wd, SWd, 0, stream);
+    }
+    const int total = m + QB;
+    for (int L = 1; L <= total;) {
+      for (int b = 0; b < QB && L <= total; ++b, ++L) {
+        Timed t(h, PC_LANCZOS, 0, stream);
+        launch_lz_step<PPT>(sv, Wd, SWd, rexi::JD_LAUNCH - L, stream, true);
+      }
+      hipLaunchKernelGGL(rexi::k_resume, dim3(S), dim3(64), 0, stream, Wd, SWd);
+      {
+        Timed t(h, PC_REORTH_A, 0, stream);
+        hipLaunchKernelGGL((rexi::k_arnoldi_a<T, PPT, false>), dim3(G2), dim3(TPB), 0, stream, Wd, rexi::JD_REC, 0, 0);
+      }
+      {
+        Timed t(h, PC_REDUCE, 0, stream);
+        hipLaunchKernelGGL(rexi::k_reduce_dots, dim3(S, m + 1), dim3(TPB), 0, stream, Wd, rexi::JD_REC, 1, 0);
+      }
+      {
+        Timed t(h, PC_REORTH_B, 0, stream);
+        hipLaunchKernelGGL((rexi::k_arnoldi_b<T, PPT>), dim3(G2), dim3(TPB), 0, stream, Wd, rexi::JD_REC, 1, 0);
+        hipLaunchKernelGGL((rexi::k_lz_matvec<PPT>), dim3(G2), dim3(TPB), 0, stream, Wd, SWc, rexi::JD_REC1, -1, 1);
+      }
+      {
+        Timed t(h, PC_REDUCE, 0, stream);
+        hipLaunchKernelGGL(rexi::k_lz_end_second, dim3(S), dim3(TPB), 0, stream, Wd, SWd, rexi::JD_REC);
+      }
+      {
+        Timed t(h, PC_LANCZOS, 0, stream);
+        launch_lz_step<PPT>(sv, Wd, SWd, rexi::JD_REC1, stream);
+      }
+      hipLaunchKernelGGL(rexi::k_cap_sync, dim3(1), dim3(64), 0, stream, Wd, L);
+    }
+    HIPCHK(h, hipGetLastError());
+  } else if (h->syncfree) {
     for (int j = 0; j < m; ++j) iteration(j, stream);
   } else {
     // chunks of iterations between host checks: the first spans as many
@@ -1459,8 +1516,11 @@ rexi_status run_shifted(rexi_handle* h, ShiftCtx cx, const double2* b, double2* 
   }
   rexi_status ps = shifted_pass<T, PPT>(h, cx, b, stream, &h->st0, nullptr);
   if (ps != REXI_OK) return ps;
-  // restarts need the Galerkin iterate of the poles that missed their target
-  const bool restart = cx.finish == 1 && h->rs_ready && out && !h->syncfree;
+  // restarts need the Galerkin iterate of the poles that missed their target;
+  // a captured schedule runs capture_cycles - 1 restart cycles (predicated on
+  // the device: an instance without missed poles finishes each at once)
+  const int cap_restarts = h->syncfree ? std::max(0, h->opt.capture_cycles - 1) : 0;
+  const bool restart = cx.finish == 1 && h->rs_ready && out && (!h->syncfree || cap_restarts > 0);
   {
     rexi::ShiftWork SWb = SWc;
     SWb.fom = restart ? 1 : 0;
@@ -1520,7 +1580,7 @@ rexi_status run_shifted(rexi_handle* h, ShiftCtx cx, const double2* b, double2* 
     rexi_status rs = run_fallback(h, missed, fb_b, out, stream);
     if (rs != REXI_OK) return rs;
   }
-  if (restart && !missed.empty()) {
+  if (restart && (h->syncfree || !missed.empty())) {
     h->fb_poles = (int)missed.size();
     rexi_status rs = run_restarts<T, PPT>(h, out, stream, wx);
     if (rs != REXI_OK) return rs;
@@ -1548,7 +1608,9 @@ rexi_status run_restarts(rexi_handle* h, double2* out, hipStream_t stream, bool 
   HIPCHK(h, hipGetLastError());
   std::vector<int32_t> hm((size_t)S);
   std::vector<SysState_t> cst;
-  for (int c = 1; c <= std::max(1, h->opt.max_cycles); ++c) {
+  // a captured step: a fixed number of cycles, no host reads
+  const int ncyc = h->syncfree ? std::max(0, h->opt.capture_cycles - 1) : std::max(1, h->opt.max_cycles);
+  for (int c = 1; c <= ncyc; ++c) {
     int64_t isum = 0;
     rexi_status ps = shifted_pass<T, PPT>(h, rs_ctx(h), h->rs_rhs, stream, &cst, &isum);
     if (ps != REXI_OK) return ps;
@@ -1576,6 +1638,11 @@ rexi_status run_restarts(rexi_handle* h, double2* out, hipStream_t stream, bool 
     hipLaunchKernelGGL(rexi::k_rs_merge, dim3(S), dim3(TPB), 0, stream, W, h->SW, R, h->rs_miss, h->rs_gam,
                        h->rs_bn0, h->rs_kbase, h->rs_hasmiss);
     HIPCHK(h, hipGetLastError());
+    if (h->syncfree) {
+      if (c < ncyc)
+        hipLaunchKernelGGL(rexi::k_rs_rhs, dim3(G), dim3(TPB), 0, stream, W, h->rs_hasmiss, h->rs_rhs);
+      continue;
+    }
     HIPCHK(h, hipMemcpyAsync(hm.data(), h->rs_hasmiss, S * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     HIPCHK(h, hipStreamSynchronize(stream));
     bool any = false;
@@ -2068,6 +2135,8 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
   if (o.center != 0 && o.center != 1) return fail(nullptr, REXI_E_INVALID_ARG, "center must be 0 or 1");
   if (o.adjoint_shared != 0 && o.adjoint_shared != 1)
     return fail(nullptr, REXI_E_INVALID_ARG, "adjoint_shared must be 0 or 1");
+  if (o.capture_cycles < 0 || o.capture_cycles > 64)
+    return fail(nullptr, REXI_E_INVALID_ARG, "capture_cycles must be in [0, 64]");
   if (o.keep_solutions != 0 && o.keep_solutions != 1)
     return fail(nullptr, REXI_E_INVALID_ARG, "keep_solutions must be 0 or 1");
   if (o.discretization != REXI_DISC_FD && o.discretization != REXI_DISC_FEM_Q1)
@@ -2456,7 +2525,7 @@ void rexi_default_options(rexi_options* o) {
   o->inner_rtol = 1e-5;
   o->check_every = 4;
   o->lanczos = 1;
-  o->capture_cycles = 4;
+  o->capture_cycles = 0;
   o->graph_chunks = 1;
   o->autotune = 1;
   o->capture_safe = 0;

@@ -179,6 +179,22 @@ template <typename T> __device__ __forceinline__ T* basis_vec(const Work& W, con
   return reinterpret_cast<T*>(W.basis) + d.basis + (int64_t)i * d.n;
 }
 
+// Iteration indices of captured schedules. A launch's iteration is its
+// argument when that is >= 0. A captured schedule cannot read anything on the
+// host, so its launches take the index from the device instead: JD_REC is
+// the iteration paused for a second Gram-Schmidt pass and JD_REC1 the one
+// after it (-1, nothing to do, when no pass is pending); JD_LAUNCH - L is
+// launch L of the fused sequence, which runs iteration L minus the launches
+// that pauses took (a paused solve skips launches until its pass has run).
+constexpr int JD_REC = -1, JD_REC1 = -2, JD_LAUNCH = -16;
+__device__ __forceinline__ int dev_iter(const Work& W, int j) {
+  if (j >= 0) return j;
+  const int rec = W.jdev[0];
+  if (j == JD_REC) return rec;
+  if (j == JD_REC1) return rec < 0 ? -1 : rec + 1;
+  return (JD_LAUNCH - j) - W.jdev[1];
+}
+
 // (H - s) u at point p, for storage type T, in the arithmetic of T.
 template <typename T>
 __device__ __forceinline__ double2 stencil_point(const T* __restrict__ u, const SysDesc& d,
@@ -616,6 +632,8 @@ struct ShiftWork {
 // the second (re-orthogonalisation) pass adds its correction.
 __global__ __launch_bounds__(TPB) void k_reduce_dots(Work W, int j, int second, int i0) {
   __shared__ double lds[NWAVE];
+  j = dev_iter(W, j);
+  if (j < 0) return;
   const int s = blockIdx.x;
   const int i = blockIdx.y;
   if (s >= W.S || i > j + 1) return;
@@ -669,6 +687,8 @@ __global__ __launch_bounds__(TPB) void k_reduce_dots(Work W, int j, int second, 
 template <typename T, int PPT, bool MATVEC>
 __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pre) {
   __shared__ double2 red[NWAVE][MAXM + 1];
+  j = dev_iter(W, j);
+  if (j < 0) return;
   if (!MATVEC && !pre && W.reo_any && !W.reo_any[j]) return;  // no second pass at iteration j
   const bool first = MATVEC || pre;
   const int lo = first ? i0 : 0;
@@ -1011,6 +1031,8 @@ template <typename T, int PPT>
 __global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second, int i0) {
   __shared__ double lds[NWAVE];
   __shared__ double2 coef[MAXM];
+  j = dev_iter(W, j);
+  if (j < 0) return;
   if (second && W.reo_any && !W.reo_any[j]) return;
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
     const int s = item_sys(W, item);
@@ -1136,6 +1158,8 @@ __global__ __launch_bounds__(TPB) void k_end_iter(Work W, ShiftWork SW, int j, i
 template <int PPT>
 __global__ __launch_bounds__(TPB) void k_lz_matvec(Work W, ShiftWork SW, int i, int zsel, int after_reorth) {
   __shared__ double lds[NWAVE];
+  i = dev_iter(W, i);
+  if (i < 0) return;
   if (after_reorth && W.reo_any && !W.reo_any[i - 1]) return;  // no second pass at iteration i - 1
   for (int item = blockIdx.x; item < W.total_tiles; item += gridDim.x) {
     const int s = item_sys(W, item);
@@ -1651,6 +1675,8 @@ __global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int 
   __shared__ double2 ub[2][KH * TPB];
   __shared__ double2 wb[2][KH * TPB];
   const int m = W.m;
+  j = dev_iter(W, j);
+  if (j < 0 || (!FUSED && j >= m)) return;
   const int nitems = FUSED ? (int)gridDim.x - W.S : (int)gridDim.x;
   if (FUSED && (int)blockIdx.x >= nitems) {
     lz_end_body(W, SW, (int)blockIdx.x - nitems, j - 1, 1);
@@ -2061,6 +2087,8 @@ __global__ __launch_bounds__(TPB) void k_lz_end(Work W, ShiftWork SW, int j, int
 // then the Givens step of every pole on the full column.
 __global__ __launch_bounds__(TPB) void k_lz_end_second(Work W, ShiftWork SW, int j) {
   __shared__ double lds[NWAVE];
+  j = dev_iter(W, j);
+  if (j < 0) return;
   const int s = blockIdx.x;
   if (s >= W.S) return;
   if (W.reo_any && !W.reo_any[j]) return;
@@ -2203,7 +2231,32 @@ __global__ __launch_bounds__(64) void k_resume(Work W, ShiftWork SW) {
   if (s >= W.S || threadIdx.x != 0) return;
   if (W.st[s].state == ST_PAUSED) W.st[s].state = ST_ACTIVE;
   SW.flags[4 * s + 2] = -1;
-  if (s == 0) *SW.gpause = -1;
+  if (s == 0) {
+    // a captured schedule keeps the paused iteration for its second pass
+    if (W.jdev) W.jdev[0] = *SW.gpause;
+    *SW.gpause = -1;
+  }
+}
+
+// Captured schedules: no pass pending, no launch lost (a kernel, so that a
+// graph records no memset).
+__global__ __launch_bounds__(64) void k_cap_init(Work W) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    W.jdev[0] = -1;
+    W.jdev[1] = 0;
+  }
+}
+
+// After the second pass of iteration r and the pass of iteration r + 1 (the
+// recovery that follows a group of fused launches), launch Lnext of the fused
+// sequence runs iteration r + 2.
+__global__ __launch_bounds__(64) void k_cap_sync(Work W, int Lnext) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const int r = W.jdev[0];
+  if (r >= 0) {
+    W.jdev[1] = Lnext - (r + 2);
+    W.jdev[0] = -1;
+  }
 }
 
 // Grid S: per-instance reset of the pole least-squares data and the

@@ -135,6 +135,8 @@ struct Work {
   const int32_t* tile_sys;  // [total_tiles] system of each tile (null: search tile_start)
   int32_t* reo_any; // [m + 1] shared basis: 1 if any system takes a second pass at
                     // iteration j (null: per-system flags only)
+  int32_t* jdev;    // captured schedules: [0] the iteration paused for a second pass
+                    // (-1: none), [1] launches lost to pauses (null: host indices)
 };
 
 }  // namespace rexi
