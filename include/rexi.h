@@ -153,11 +153,8 @@ typedef struct {
                           stream; if the stream is itself being captured,
                           the schedule is enqueued into the caller's graph.
                           The shared basis with the tiled pass (march_slots
-                          2) takes one launch per iteration; a second
-                          Gram-Schmidt pass takes up to 31 launches of that
-                          schedule (the first one is covered: m + 32
-                          launches), so a captured solve with several may
-                          stop below m vectors                              */
+                          2) takes one launch per iteration, with room for
+                          capture_pauses second Gram-Schmidt passes        */
   int32_t capture_cycles; /* capture_safe: cycles of a captured solve, the
                           first included: per-pole solver 4, shared basis
                           1 (no restarts) when 0 (the default); shared basis
@@ -239,6 +236,14 @@ typedef struct {
                            are planned when they take at most half of the
                            free memory and formed only on steps with info).
                            Default 0                                          */
+  int32_t capture_pauses; /* capture_safe, shared basis with the tiled pass:
+                           second Gram-Schmidt passes per cycle the captured
+                           schedule makes room for (each takes up to 15
+                           launches of it); 0 (default): 2 for a single
+                           instance, max(2, m / 32) for a batch (whose
+                           instances all pause when one needs a pass). A
+                           cycle that pauses more stops below m vectors    */
+  int32_t reserved_opt2_;
 } rexi_options;
 
 typedef struct {

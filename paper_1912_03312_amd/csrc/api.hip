@@ -1353,11 +1353,13 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
   // of QB launches a recovery runs the second pass of a paused iteration and
   // the pass after it (each launch predicated: nothing happens without a
   // pause). A pause costs the rest of its group; the schedule has QB launches
-  // beyond m, so the first pause costs no iteration and later ones shorten
-  // the largest Krylov dimension a captured solve reaches.
+  // beyond m for each of the capture_pauses pauses it makes room for (more
+  // pauses shorten the largest Krylov dimension a captured solve reaches).
   const bool capfuse = h->syncfree && pipe && lz && sv.col_kh == 2 && h->jdev;
   if (capfuse) {
-    constexpr int QB = 32;
+    constexpr int QB = 16;
+    // (a batch pauses all its instances whenever one needs a pass)
+    const int QR = h->opt.capture_pauses > 0 ? h->opt.capture_pauses : S == 1 ? 2 : std::max(2, m / 32);
     Work Wd = W;
     Wd.jdev = h->jdev;
     rexi::ShiftWork SWd = SWc;
@@ -1367,7 +1369,7 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
       Timed t(h, PC_LANCZOS, n * lz_bytes(0), stream);
       launch_lz_step<PPT>(sv, Wd, SWd, 0, stream);
     }
-    const int total = m + QB;
+    const int total = m + QR * QB;
     for (int L = 1; L <= total;) {
       for (int b = 0; b < QB && L <= total; ++b, ++L) {
         Timed t(h, PC_LANCZOS, 0, stream);
@@ -1392,10 +1394,12 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
         hipLaunchKernelGGL(rexi::k_lz_end_second, dim3(S), dim3(TPB), 0, stream, Wd, SWd, rexi::JD_REC);
       }
       {
+        // (its first block also moves the later launches: launch L runs r + 2)
+        rexi::ShiftWork SWr = SWd;
+        SWr.cap_next = L;
         Timed t(h, PC_LANCZOS, 0, stream);
-        launch_lz_step<PPT>(sv, Wd, SWd, rexi::JD_REC1, stream);
+        launch_lz_step<PPT>(sv, Wd, SWr, rexi::JD_REC1, stream);
       }
-      hipLaunchKernelGGL(rexi::k_cap_sync, dim3(1), dim3(64), 0, stream, Wd, L);
     }
     HIPCHK(h, hipGetLastError());
   } else if (h->syncfree) {
@@ -2137,6 +2141,8 @@ rexi_status setup_common(rexi_handle** out, int count, const rexi_grid* grids, c
     return fail(nullptr, REXI_E_INVALID_ARG, "adjoint_shared must be 0 or 1");
   if (o.capture_cycles < 0 || o.capture_cycles > 64)
     return fail(nullptr, REXI_E_INVALID_ARG, "capture_cycles must be in [0, 64]");
+  if (o.capture_pauses < 0 || o.capture_pauses > 64)
+    return fail(nullptr, REXI_E_INVALID_ARG, "capture_pauses must be in [0, 64]");
   if (o.keep_solutions != 0 && o.keep_solutions != 1)
     return fail(nullptr, REXI_E_INVALID_ARG, "keep_solutions must be 0 or 1");
   if (o.discretization != REXI_DISC_FD && o.discretization != REXI_DISC_FEM_Q1)
@@ -2543,6 +2549,8 @@ void rexi_default_options(rexi_options* o) {
   o->discretization = REXI_DISC_FD;
   o->adjoint_shared = 1;
   o->keep_solutions = 0;
+  o->capture_pauses = 0;
+  o->reserved_opt2_ = 0;
 }
 
 rexi_status rexi_setup(rexi_handle** out, const rexi_grid* g, const double* V_dev, double hbar, double mass,

@@ -599,6 +599,7 @@ struct ShiftWork {
   int32_t* flags;     // [S][4] [0]: reorthogonalise the next vector too; [1]: passes done;
                       // [2]: iteration at which the solve paused (-1: none)
   int32_t pause_mode; // 1: pause for a second pass instead of predicated passes
+  int32_t cap_next;   // captured schedules: the fused launch that follows a recovery
   int32_t* gpause;    // [1] iteration at which the solve paused (-1: none): the passes and
                       // ends of later iterations return at once, for every system
   int32_t* full;      // [S][m] 1 if column j of Hbar has entries above row j - 1
@@ -1675,8 +1676,15 @@ __global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int 
   __shared__ double2 ub[2][KH * TPB];
   __shared__ double2 wb[2][KH * TPB];
   const int m = W.m;
+  const int jarg = j;
   j = dev_iter(W, j);
-  if (j < 0 || (!FUSED && j >= m)) return;
+  if (j < 0) return;
+  if (!FUSED && jarg == JD_REC1 && blockIdx.x == 0 && threadIdx.x == 0) {
+    // the pass after a captured second pass of iteration j - 1: the next fused
+    // launch runs iteration j + 1 (no block of this launch reads this index)
+    W.jdev[1] = SW.cap_next - (j + 1);
+  }
+  if (!FUSED && j >= m) return;
   const int nitems = FUSED ? (int)gridDim.x - W.S : (int)gridDim.x;
   if (FUSED && (int)blockIdx.x >= nitems) {
     lz_end_body(W, SW, (int)blockIdx.x - nitems, j - 1, 1);
@@ -2244,18 +2252,6 @@ __global__ __launch_bounds__(64) void k_cap_init(Work W) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     W.jdev[0] = -1;
     W.jdev[1] = 0;
-  }
-}
-
-// After the second pass of iteration r and the pass of iteration r + 1 (the
-// recovery that follows a group of fused launches), launch Lnext of the fused
-// sequence runs iteration r + 2.
-__global__ __launch_bounds__(64) void k_cap_sync(Work W, int Lnext) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  const int r = W.jdev[0];
-  if (r >= 0) {
-    W.jdev[1] = Lnext - (r + 2);
-    W.jdev[0] = -1;
   }
 }
 

@@ -52,7 +52,8 @@ class Options(C.Structure):
                 ("max_workspace_bytes", C.c_int64), ("march_planes", C.c_int32), ("march_slots", C.c_int32),
                 ("fallback", C.c_int32), ("fallback_m", C.c_int32), ("fallback_bytes", C.c_int64),
                 ("stab_eps", C.c_double), ("center", C.c_int32), ("discretization", C.c_int32),
-                ("adjoint_shared", C.c_int32), ("keep_solutions", C.c_int32)]
+                ("adjoint_shared", C.c_int32), ("keep_solutions", C.c_int32), ("capture_pauses", C.c_int32),
+                ("reserved_opt2_", C.c_int32)]
 
 
 class StepInfo(C.Structure):
