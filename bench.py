@@ -416,15 +416,6 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven batch among the other workloads")
     args = ap.parse_args()
 
-    if "REXI_TUNE_CACHE" not in os.environ:
-        # the tiling the setup tuner chose for the benchmark shapes on MI355X
-        # (a private copy: the library appends the choices for new shapes)
-        import shutil
-        import tempfile
-        src = os.path.join(ROOT, "paper_1912_03312_amd", "tuning", "mi355x_bench.txt")
-        dst = os.path.join(tempfile.mkdtemp(prefix="rexi_tune_"), "tune.txt")
-        shutil.copyfile(src, dst)
-        os.environ["REXI_TUNE_CACHE"] = dst
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the pole-sharded design is described, not built)", file=sys.stderr)

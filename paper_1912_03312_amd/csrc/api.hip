@@ -1913,7 +1913,7 @@ __global__ void k_tune_rhs(double2* __restrict__ v, int64_t n) {
 }
 
 template <typename T, int PPT>
-void tune_launch(rexi_handle* h, Solver& sv, const double2* b, int iters, hipStream_t st) {
+void tune_launch(rexi_handle* h, Solver& sv, const double2* b, int iters, hipStream_t st, bool fused = false) {
   Work& W = sv.W;
   const int G = sv.grid, S = sv.S;
   hipLaunchKernelGGL((rexi::k_start<T, PPT>), dim3(G), dim3(TPB), 0, st, W, b, b);
@@ -1923,6 +1923,15 @@ void tune_launch(rexi_handle* h, Solver& sv, const double2* b, int iters, hipStr
   if (h->shifted && h->opt.lanczos == 1) {
     hipLaunchKernelGGL((rexi::k_lz_matvec<PPT>), dim3(G), dim3(TPB), 0, st, W, h->SW, 0, sv.col_kh == 2 ? -1 : 0, 0);
     hipLaunchKernelGGL(rexi::k_lz_start, dim3(S), dim3(TPB), 0, st, W, h->SW);
+    if (fused && sv.col_kh) {
+      // the solve's own schedule: a plain pass, then one fused launch per
+      // iteration (each also ends the previous iteration)
+      rexi::ShiftWork SWp = h->SW;
+      SWp.pause_mode = 1;
+      launch_lz_step<PPT>(sv, W, SWp, 0, st);
+      for (int j = 1; j < iters && j < sv.m; ++j) launch_lz_step<PPT>(sv, W, SWp, j, st, true);
+      return;
+    }
     for (int j = 0; j < iters && j < sv.m; ++j) {
       launch_lz_step<PPT>(sv, W, h->SW, j, st);
       hipLaunchKernelGGL(rexi::k_lz_end, dim3(S), dim3(TPB), 0, st, W, h->SW, j, sv.col_kh ? 1 : 0);
@@ -2004,32 +2013,37 @@ rexi_status autotune(rexi_handle* h, Solver& sv, hipStream_t stream) {
   }
   rexi_status st = apply_tiling(h, sv, best_ppt, best_grid, stream);
   // second stage (pipelined Lanczos): the row-staged pass against the
-  // marching pass over slots x planes per item, on the chosen tiling
+  // marching and tiled passes over slots x planes per item, on the chosen
+  // tiling. Each candidate runs the solve's own schedule (fused launches
+  // where the pass has them) for 24 iterations, five times after a warm-up
+  // run; the median decides, and a later candidate must be 2% faster
   int best_kh = 0, best_L = 0;
   if (st == REXI_OK && march) {
     best = 1e30f;
+    const int lz_iters = std::min(24, sv.m);
     for (int kh : {0, 3, 5, 8, 2}) {
       for (int L : {4, 8, 16}) {
         if (kh == 0 && L != 4) continue;
         if ((st = apply_columns(h, sv, kh, L, stream)) != REXI_OK) break;
         if (sv.col_kh != kh) continue;  // the plan does not fit
-        float tmin = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
+        std::vector<float> tr;
+        for (int rep = 0; rep < 6; ++rep) {
           HIPCHK(h, hipEventRecord(e0, stream));
           switch (best_ppt) {
-            case 8: tune_launch<double2, 8>(h, sv, rhs, 3 * iters, stream); break;
-            case 4: tune_launch<double2, 4>(h, sv, rhs, 3 * iters, stream); break;
-            default: tune_launch<double2, 2>(h, sv, rhs, 3 * iters, stream); break;
+            case 8: tune_launch<double2, 8>(h, sv, rhs, lz_iters, stream, true); break;
+            case 4: tune_launch<double2, 4>(h, sv, rhs, lz_iters, stream, true); break;
+            default: tune_launch<double2, 2>(h, sv, rhs, lz_iters, stream, true); break;
           }
           HIPCHK(h, hipEventRecord(e1, stream));
           HIPCHK(h, hipEventSynchronize(e1));
           float ms = 0.f;
           HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
-          tmin = std::min(tmin, ms);
+          if (rep > 0) tr.push_back(ms);  // the first run warms the caches and code
         }
-        // a later candidate must be clearly faster: run-to-run noise does not flip the choice
-        if (tmin < 0.97f * best) {
-          best = tmin;
+        std::sort(tr.begin(), tr.end());
+        const float tmed = tr[tr.size() / 2];
+        if (tmed < 0.98f * best) {
+          best = tmed;
           best_kh = kh;
           best_L = L;
         }

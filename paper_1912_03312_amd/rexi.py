@@ -179,6 +179,7 @@ class Handle:
 
     def __init__(self, raw, npts: int, K: int, count: int = 1):
         self._h = raw
+        self._destroy = _lib.rexi_destroy  # kept: the module may be torn down first at exit
         self.npts = npts
         self.K = K
         self.count = count
@@ -188,7 +189,7 @@ class Handle:
 
     def close(self):
         if getattr(self, "_h", None):
-            _lib.rexi_destroy(self._h)
+            self._destroy(self._h)
             self._h = None
 
     def apply_H(self, x, y, shift: complex = 0.0, stream=None):

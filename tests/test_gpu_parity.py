@@ -1180,3 +1180,19 @@ def test_spectrum_estimate_batch_and_errors(rexi):
     with pytest.raises(r.RexiError):
         hf.estimate_spectrum(10)
     hf.close()
+
+
+def test_tuner_picks_the_measured_best_pass_at_full_size(rexi):
+    # the setup tuner, run on the benchmark's shape, picks the pass measured
+    # fastest in sweeps (the tiled pass, 16 planes per item): the benchmark
+    # times the tuner's own choice
+    from paper_1912_03312_amd import rexi as r
+    wl = inputs.workload("3d_bumps")
+    g = wl.grid
+    s, b, d = poles(wl.K, wl.R1)
+    h = r.setup(g.n, g.lo, g.hi, to_dev(wl.V.ravel()), 1.0, 1.0, wl.dt, s, b, solver="shifted", m=100, tol=1e-10,
+                tol_policy="certified")
+    t = h.tiling()
+    h.close()
+    print("tuned tiling, 128^3", t)
+    assert (t["march_slots"], t["march_planes"]) == (2, 16), t
