@@ -2718,14 +2718,17 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
           // the pole's target; near the FP64 floor the explicit residual of
           // the computed x_p may exceed a floored target by rounding); under
           // the certified policy an instance whose explicit certified sum
-          // meets tol has converged, whatever the share of each pole
-          std::vector<double> bound((size_t)h->ninst, 0.0);
+          // meets its plan has converged, whatever the share of each pole:
+          // the plan is tol, or the sum of |w_p| rho_p* / dist_p over its
+          // floored targets where the FP64 floors exceed tol
+          std::vector<double> bound((size_t)h->ninst, 0.0), plan((size_t)h->ninst, 0.0);
           std::vector<int> miss((size_t)h->ninst, 0);
           int q = 0;
           for (int i = 0; i < h->ninst; ++i)
             for (int kk = 0; kk < h->Kinst[i]; ++kk, ++q) {
               const int k = q;
               if (!(res[k] <= h->tol_sys[k])) miss[(size_t)i] += 1;
+              plan[(size_t)i] += std::abs(h->w[k]) * h->tol_sys[k] / h->dist_sys[k];
               info->max_rel_residual = std::max(info->max_rel_residual, rr[k]);
               bound[(size_t)i] += std::abs(h->w[k]) * rr[k] / h->dist_sys[k];
               if (info->iterations) info->iterations[k] = its[k] > 0 ? its[k] : s0.its;
@@ -2734,7 +2737,8 @@ rexi_status rexi_step(rexi_handle* h, const rexi_c128* psi_in, rexi_c128* psi_ou
               if (info->implicit_residual) info->implicit_residual[k] = res[k];
             }
           for (int i = 0; i < h->ninst; ++i)
-            if (!(h->opt.tol_policy == REXI_TOL_CERTIFIED && bound[(size_t)i] <= h->opt.tol))
+            if (!(h->opt.tol_policy == REXI_TOL_CERTIFIED &&
+                  bound[(size_t)i] <= std::max(h->opt.tol, plan[(size_t)i])))
               info->not_converged += miss[(size_t)i];
           info->certified_bound = *std::max_element(bound.begin(), bound.end());
           info->reorth_passes = h->reorth_passes;

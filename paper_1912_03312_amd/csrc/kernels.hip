@@ -733,7 +733,45 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
       }
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int i = lo; i <= j; ++i) {
+    // the projections conj(u_i) w in blocks of AU basis vectors: their loads
+    // are issued together (a tall-skinny matrix-vector product), then AU
+    // independent wave reductions; each dot is summed in the same order as
+    // one vector at a time
+    constexpr int AU = 8;
+    int i = lo;
+    for (; i + AU <= j + 1; i += AU) {
+      T a[AU][PPT];
+#pragma unroll
+      for (int r = 0; r < AU; ++r) {
+        const T* __restrict__ ui = basis_vec<T>(W, d, i + r);
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+          const int p = t * W.tile + q * TPB + threadIdx.x;
+          a[r][q] = p < d.n ? ui[p] : T{};
+        }
+      }
+      double2 acc[AU];
+#pragma unroll
+      for (int r = 0; r < AU; ++r) {
+        acc[r] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+          const int p = t * W.tile + q * TPB + threadIdx.x;
+          if (p < d.n) {
+            const double2 c = cjmul(to_d2(a[r][q]), w[q]);
+            acc[r].x += c.x;
+            acc[r].y += c.y;
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < AU; ++r) {
+        acc[r].x = wave_sum(acc[r].x);
+        acc[r].y = wave_sum(acc[r].y);
+        if (lane == 0) red[wid][i + r] = acc[r];
+      }
+    }
+    for (; i <= j; ++i) {
       const T* __restrict__ ui = basis_vec<T>(W, d, i);
       double2 acc = make_double2(0.0, 0.0);
 #pragma unroll

@@ -300,3 +300,88 @@ def test_bench_configuration_full_scale_against_oracle(rexi):
         assert e <= bnd * (1 + 1e-6) + 1e-13
     print(f"oracle solves of {len(sample)} poles: {time.perf_counter() - t0:.1f} s", flush=True)
     h.close()
+
+
+@pytest.mark.timeout(300)
+def test_double_well_full_size_against_exact_separable_step(rexi):
+    # the 512^2 double well (its potential is separable, so the oracle's
+    # exact separable eigendecomposition evaluates the step at full size):
+    # 20 steps of the shared basis with restarts, certified policy
+    import torch
+    wl = inputs.workload("2d_double_well")
+    g = wl.grid
+    s, b = poles(wl.K, wl.R1)
+    vx, vy = inputs.double_well_parts(g)
+    S = ost.SeparableStepper(g.n, g.h, [vx, vy])
+    h = rexi.setup(g.n, g.lo, g.hi, to_dev(wl.V.ravel()), 1.0, 1.0, wl.dt, s, b, solver="shifted", m=256,
+                   max_cycles=200, tol=1e-10, tol_policy="certified")
+    cur = to_dev(wl.psi0.ravel())
+    nxt = torch.empty_like(cur)
+    ref = wl.psi0
+    sj, wj = ost.shifts_and_weights(s, b, wl.dt)
+    bar = max(1e-10, 3 * _floor_iter(g, wl.V, sj, wj))
+    errs = []
+    for k in range(wl.steps):
+        info = h.step(cur, nxt, 1)
+        torch.cuda.synchronize()
+        # each step against the exact step of the GPU's own input: the error of
+        # that one step, free of what the earlier steps left behind
+        ref = S.step(cur.cpu().numpy().reshape(g.n), s, b, wl.dt)
+        errs.append(rel(nxt.cpu().numpy(), ref))
+        assert info["not_converged"] == 0 and info["explicit_residuals"]
+        assert errs[-1] <= max(bar, info["certified_bound"] + 3 * _floor_iter(g, wl.V, sj, wj)), (k, errs[-1], bar)
+        cur, nxt = nxt, cur
+    h.close()
+    print("double well 512^2: per-step errors max", max(errs), "bar", bar, "cycles", info["max_cycles_used"])
+
+
+@pytest.mark.timeout(300)
+def test_full_uneven_batch_largest_instances_certified_on_cpu(rexi):
+    # the full uneven batch (256 instances): the largest ones (512^2, where
+    # direct solves take seconds per pole) are checked by the CPU residuals of
+    # their kept pole solutions; the smallest against the oracle's direct step
+    import torch
+    insts = inputs.batch_instances(count=256)
+    grids, Vs, psis, dts, Ks, sig, bet = [], [], [], [], [], [], []
+    for it in insts:
+        g = it["grid"]
+        s, b = poles(it["K"], inputs.R1_PARITY[it["K"]])
+        grids.append((g.n, g.lo, g.hi))
+        Vs.append(it["V"].ravel())
+        psis.append(it["psi0"].ravel())
+        dts.append(it["dt"])
+        Ks.append(it["K"])
+        sig.append(s)
+        bet.append(b)
+    cnt = len(insts)
+    h = rexi.setup_batch(grids, to_dev(np.concatenate(Vs)), [1.0] * cnt, [1.0] * cnt, dts, Ks, np.concatenate(sig),
+                         np.concatenate(bet), solver="shifted", m=256, max_cycles=200, tol=1e-10,
+                         tol_policy="certified", keep_solutions=1)
+    p0 = to_dev(np.concatenate(psis))
+    out = torch.empty_like(p0)
+    info = h.step(p0, out, 1, raise_on_nc=False)
+    torch.cuda.synchronize()
+    og = out.cpu().numpy()
+    offs = np.cumsum([0] + [v.size for v in Vs])
+    poff = np.cumsum([0] + Ks)
+    largest = sorted(range(cnt), key=lambda i: -Vs[i].size)[:3]
+    smallest = sorted(range(cnt), key=lambda i: Vs[i].size)[:2]
+    res = []
+    for i in largest + smallest:
+        g = insts[i]["grid"]
+        cert, comb, mism, slack, amp = cpu_certificate(h, g, insts[i]["V"], insts[i]["psi0"], sig[i], bet[i], dts[i],
+                                                       og[offs[i]:offs[i + 1]], info, pole0=int(poff[i]))
+        sj, wj = ost.shifts_and_weights(sig[i], bet[i], dts[i])
+        fl = _floor_iter(g, insts[i]["V"], sj, wj)
+        assert all(gap <= tol for gap, tol in mism), (i, max(mism))
+        # the CPU certificate of the GPU step: within the certified policy's
+        # target, or the attainable FP64 floor where that binds
+        assert cert + comb <= max(1e-10, 3 * fl), (i, g.n, cert, comb, fl)
+        if i in smallest:
+            e = rel(og[offs[i]:offs[i + 1]],
+                    ost.DirectStepper(g.n, g.h, insts[i]["V"], sig[i], bet[i], dts[i]).step(insts[i]["psi0"]))
+            assert e <= cert + comb + 2 * fl, (i, e)
+        res.append((i, g.n, Ks[i], cert, comb, fl))
+    h.close()
+    print("full batch, CPU certificates:", res, "not converged", info["not_converged"])
+    assert info["not_converged"] == 0
