@@ -1110,14 +1110,14 @@ void launch_col(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork& SW
   }
 }
 
-template <int TR, int TC>
+template <int TR, int TC, int NT>
 void launch_tile(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork& SW, int j, bool fused,
                  hipStream_t strm) {
   if (fused) {
     const dim3 g((j < sv.m ? sv.col_total : 0) + sv.S);
-    hipLaunchKernelGGL((rexi::k_lz_step_tile<TR, TC, true>), g, dim3(TPB), 0, strm, W, SW, j);
+    hipLaunchKernelGGL((rexi::k_lz_step_tile<TR, TC, NT, true>), g, dim3(NT), 0, strm, W, SW, j);
   } else {
-    hipLaunchKernelGGL((rexi::k_lz_step_tile<TR, TC, false>), dim3(sv.col_total), dim3(TPB), 0, strm, W, SW, j);
+    hipLaunchKernelGGL((rexi::k_lz_step_tile<TR, TC, NT, false>), dim3(sv.col_total), dim3(NT), 0, strm, W, SW, j);
   }
 }
 
@@ -1127,8 +1127,8 @@ void launch_lz_step(const Solver& sv, const rexi::Work& W, const rexi::ShiftWork
   if (sv.col_kh) {
     switch (sv.col_kh) {
       case 2:
-        if (sv.col_strip) launch_tile<1, rexi::ZS_C>(sv, W, SW, j, fused, strm);
-        else launch_tile<rexi::ZT_R, rexi::ZT_C>(sv, W, SW, j, fused, strm);
+        if (sv.col_strip) launch_tile<1, rexi::ZS_C, rexi::ZS_T>(sv, W, SW, j, fused, strm);
+        else launch_tile<rexi::ZT_R, rexi::ZT_C, rexi::ZT_T>(sv, W, SW, j, fused, strm);
         return;
       case 3: launch_col<3>(sv, W, SW, j, fused, strm); return;
       case 5: launch_col<5>(sv, W, SW, j, fused, strm); return;

@@ -1675,23 +1675,50 @@ __global__ __launch_bounds__(TPB) void k_lz_step_col(Work W, ShiftWork SW, int j
 // range check turns into a zero load or a dropped store. The steps are
 // therefore straight-line code, and the loads issued one step ahead are
 // waited for only where they are used.
-// Tile shapes: 16 x 32 points of the (i1, i2) plane for 3D grids; for 2D
-// grids, relabelled (rows, 1, columns), strips of 253 points of a row (the
-// region is the strip with one column before and two after: 256 slots).
-constexpr int ZT_R = 16, ZT_C = 32;
-constexpr int ZS_C = 253;
-template <int TR, int TC> struct ZTile {
+// Tile shapes: 16 x 32 points of the (i1, i2) plane for 3D grids, in blocks
+// of 768 threads (12 waves, three per SIMD): the 19 x 35 region is one slot
+// per thread, so a SIMD interleaves three waves' stencil arithmetic with the
+// loads in flight (one block per CU at 128^3; with four waves of three slots
+// each, every latency of a wave's chain was exposed). For 2D grids,
+// relabelled (rows, 1, columns), strips of 253 points of a row (the region is
+// the strip with one column before and two after: 256 slots, 256 threads).
+constexpr int ZT_R = 16, ZT_C = 32, ZT_T = 768;
+constexpr int ZS_C = 253, ZS_T = 256;
+template <int TR, int TC, int NT> struct ZTile {
   static constexpr int W = TC + 3;                    // region width
   static constexpr int N = W * (TR > 1 ? TR + 3 : 1);  // region slots (TR = 1: no row halo, n1 = 1)
-  static constexpr int KH = (N + TPB - 1) / TPB;
+  static constexpr int KH = (N + NT - 1) / NT;
 };
+static_assert(ZTile<ZT_R, ZT_C, ZT_T>::KH == 1 && ZTile<1, ZS_C, ZS_T>::KH == 1, "one slot per thread");
+
+// Sum over a block of NW waves; every thread gets the result. lds: NW doubles.
+template <int NW>
+__device__ __forceinline__ double block_sum_w(double v, double* lds) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) s += lds[w];
+  return s;
+}
+
 constexpr uint32_t ZT_OOB = 0x80000000u;    // past the end of every buffer (records < 2^31 bytes)
 
 typedef unsigned int zt_u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t zt_rsrc(const void* p, uint32_t bytes) {
-  // raw buffer (stride 0), 32-bit data format: offsets >= bytes are out of range
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+  // raw buffer (stride 0), 32-bit data format: offsets >= bytes are out of
+  // range. Base and size are uniform; reading them from the first lane puts
+  // the descriptor in scalar registers whatever the compiler can prove (a
+  // descriptor it takes for divergent costs a loop around every access).
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  void* pu = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(pu, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
 }
 __device__ __forceinline__ double2 zt_load2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
@@ -1703,16 +1730,80 @@ __device__ __forceinline__ void zt_store2(__amdgpu_buffer_rsrc_t r, uint32_t off
   __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(zt_u32x4, v), r, off, 0, 0);
 }
 
-template <int TR, int TC, bool FUSED>
-__global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int j) {
-  constexpr int KH = ZTile<TR, TC>::KH;
-  constexpr int ZT_W = ZTile<TR, TC>::W;
-  constexpr int ZT_N = ZTile<TR, TC>::N;
+// lz_col_partials in a block of more than TPB threads, in two parts so that
+// the loads of the partial sums go out before the loads of the planes (a
+// wait for them then waits for nothing else). col_parts_load loads them when
+// the system has at most TPB items (one per lead thread; raw buffer loads, so
+// no branch: other threads read zeros); col_parts_reduce
+// reduces exactly as lz_col_partials does (the same order, so the same
+// values as the end-of-iteration block that reduces the same partial sums;
+// one element per thread is strided_sum2's 0 + element), with every wave at
+// the same two barriers.
+struct ColParts {
+  double2 nn, uz, o;  // elements of the three slots
+};
+__device__ __forceinline__ ColParts col_parts_load(const Work& W, int pbase, int ntiles, int np, int j) {
+  const double2* pp = reinterpret_cast<const double2*>(W.part) + pbase + 3 * (j & 1) * ntiles;
+  const __amdgpu_buffer_rsrc_t r = zt_rsrc(pp, (uint32_t)(3 * ntiles) * 16u);
+  const int t = threadIdx.x;
+  const bool in = np <= TPB && t < np;
+  ColParts q;
+  q.nn = zt_load2(r, in ? (uint32_t)(2 * ntiles + t) * 16u : ZT_OOB);
+  q.uz = zt_load2(r, in ? (uint32_t)t * 16u : ZT_OOB);
+  q.o = zt_load2(r, in ? (uint32_t)(ntiles + t) * 16u : ZT_OOB);
+  return q;
+}
+__device__ __forceinline__ void col_parts_reduce(const ColParts& q, const Work& W, int pbase, int ntiles, int np,
+                                                 int j, double& nn, double& uz, double& oux, double& ouy,
+                                                 double* l4) {
+  const bool lead = threadIdx.x < TPB;  // waves 0 .. NWAVE - 1 (wave-uniform)
+  if (np <= TPB) {  // (threads past np, and every thread past TPB, hold zeros)
+    nn = 0.0 + q.nn.x;
+    uz = 0.0 + q.uz.x;
+    oux = 0.0 + q.o.x;
+    ouy = 0.0 + q.o.y;
+  } else {
+    const double2* pp = reinterpret_cast<const double2*>(W.part) + pbase + 3 * (j & 1) * ntiles;
+    nn = lead ? strided_sum2(pp + 2 * ntiles, np).x : 0.0;
+    uz = lead ? strided_sum2(pp, np).x : 0.0;
+    const double2 o = lead ? strided_sum2(pp + ntiles, np) : make_double2(0.0, 0.0);
+    oux = o.x;
+    ouy = o.y;
+  }
+  oux = wave_sum(oux);
+  ouy = wave_sum(ouy);
+  nn = wave_sum(nn);
+  uz = wave_sum(uz);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lead && lane == 0) {
+    l4[wid] = nn;
+    l4[NWAVE + wid] = uz;
+    l4[2 * NWAVE + wid] = oux;
+    l4[3 * NWAVE + wid] = ouy;
+  }
+  __syncthreads();
+  nn = uz = oux = ouy = 0.0;
+#pragma unroll
+  for (int w = 0; w < NWAVE; ++w) {
+    nn += l4[w];
+    uz += l4[NWAVE + w];
+    oux += l4[2 * NWAVE + w];
+    ouy += l4[3 * NWAVE + w];
+  }
+}
+
+template <int TR, int TC, int NT, bool FUSED>
+__global__ __launch_bounds__(NT) void k_lz_step_tile(Work W, ShiftWork SW, int j) {
+  constexpr int KH = ZTile<TR, TC, NT>::KH;
+  constexpr int ZT_W = ZTile<TR, TC, NT>::W;
+  constexpr int ZT_N = ZTile<TR, TC, NT>::N;
+  constexpr int NW = NT / 64;
   constexpr bool ROWS = TR > 1;  // the region has rows (TR = 1: n1 = 1)
-  __shared__ double lds[NWAVE];
+  __shared__ double lds[NW];
   __shared__ double l4[4 * NWAVE];
-  __shared__ double2 ub[2][KH * TPB];
-  __shared__ double2 wb[2][KH * TPB];
+  __shared__ double2 ub[2][KH * NT];
+  __shared__ double2 wb[2][KH * NT];
   const int m = W.m;
   const int jarg = j;
   j = dev_iter(W, j);
@@ -1723,20 +1814,31 @@ __global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int 
     W.jdev[1] = SW.cap_next - (j + 1);
   }
   if (!FUSED && j >= m) return;
-  const int nitems = FUSED ? (int)gridDim.x - W.S : (int)gridDim.x;
-  if (FUSED && (int)blockIdx.x >= nitems) {
-    lz_end_body(W, SW, (int)blockIdx.x - nitems, j - 1, 1);
+  // FUSED: blocks 0 .. S-1 end iteration j - 1 (one per system), the others
+  // are the items. The end blocks come first so that they are dispatched
+  // first: an item block fills a CU's wave slots, and an end block placed
+  // after all items would wait for one of them to finish.
+  const int iend = FUSED ? W.S : 0;
+  const int nitems = (int)gridDim.x - iend;
+  if (FUSED && (int)blockIdx.x < iend) {
+    // the end of iteration j - 1 takes TPB threads; the other waves leave
+    // (a barrier waits only for the waves of the block that have not ended)
+    if (threadIdx.x >= TPB) return;
+    lz_end_body(W, SW, (int)blockIdx.x, j - 1, 1);
     return;
   }
   if (FUSED && j >= m) return;
   if (paused_before(SW, j)) return;
-  for (int item = blockIdx.x; item < SW.col_total; item += nitems) {
+  for (int item = (int)blockIdx.x - iend; item < SW.col_total; item += nitems) {
     const int s = __builtin_amdgcn_readfirstlane(SW.col_sys ? SW.col_sys[item] : find_sys(SW.col_start, W.S, item));
     if (W.st[s].state != ST_ACTIVE) continue;
     const SysDesc& dref = W.sys[s];
     const int n0 = dref.n0, n1 = dref.n1, n2 = dref.n2;
     const double c0 = dref.c0, c1 = dref.c1, c2 = dref.c2, diag = dref.diag;
     const int cs = dref.col_cs, pbase = dref.pbase;
+    const int np = __builtin_amdgcn_readfirstlane(dref.col_n);
+    ColParts cq{};
+    if (FUSED && NT != TPB) cq = col_parts_load(W, pbase, cs, np, j - 1);
     const int col_nr = dref.col_nr, col_L = dref.col_L;
     const int64_t voff = dref.off, bas = dref.basis;
     const int npts = dref.n;
@@ -1750,20 +1852,7 @@ __global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int 
     const int ia = rng * col_L;
     const int ib = min(n0, ia + col_L);
     const uint32_t plane = (uint32_t)n1 * (uint32_t)n2;
-    double cj, ka, kb;
-    if (FUSED) {
-      double nn, uz, ox, oy;
-      lz_col_partials(W, pbase, cs, dref.col_n, j - 1, nn, uz, ox, oy, l4);
-      const double bj = sqrt(nn);
-      cj = bj > 0.0 ? 1.0 / bj : 0.0;
-      ka = cj * cj * uz * cj;
-      kb = bj * W.cscale[(int64_t)s * (m + 1) + j - 1];
-    } else {
-      cj = W.cscale[(int64_t)s * (m + 1) + j];
-      const double cjm = j > 0 ? W.cscale[(int64_t)s * (m + 1) + j - 1] : 0.0;
-      ka = SW.alpha[(int64_t)s * m + j] * cj;
-      kb = j > 0 ? SW.beta[(int64_t)s * (m + 1) + j] * cjm : 0.0;
-    }
+    double cj = 0.0, ka = 0.0, kb = 0.0;  // set after the first loads are issued
     // u_{j-1} is read at j = 0 too (as u_0, finite), where kb = 0 removes it
     const double2* const bvec = reinterpret_cast<const double2*>(W.basis) + bas;
     const uint32_t vbytes = (uint32_t)npts * 16u;
@@ -1781,7 +1870,7 @@ __global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int 
     int hf[KH], ho[KH];
 #pragma unroll
     for (int q = 0; q < KH; ++q) {
-      const int h = (int)threadIdx.x + q * TPB;
+      const int h = (int)threadIdx.x + q * NT;
       const int rr = ROWS ? h / ZT_W : 1;
       const int cc = ROWS ? h - rr * ZT_W : h;
       const int row = ROWS ? r0 - 1 + rr : 0, col = c0c - 1 + cc;
@@ -1830,7 +1919,7 @@ __global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int 
                     Vec& Wn) {
       const int bu = (p + 1) & 1;
 #pragma unroll
-      for (int q = 0; q < KH; ++q) ub[bu][threadIdx.x + q * TPB] = U1[q];
+      for (int q = 0; q < KH; ++q) ub[bu][threadIdx.x + q * NT] = U1[q];
       fetch_u(U3, p + 3, p + 3 <= ib + 1);
       fetch_mv(My, Vy, p + 2, p + 2 <= ib);
       __syncthreads();  // ub[bu] is written; wb[p & 1] (plane p) is complete
@@ -1862,7 +1951,7 @@ __global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int 
         oux += k ? c.x * w.x + c.y * w.y : 0.0;
         ouy += k ? c.x * w.y - c.y * w.x : 0.0;
         Wn[q] = w;
-        wb[bu][threadIdx.x + q * TPB] = w;
+        wb[bu][threadIdx.x + q * NT] = w;
       }
       if (p >= ia && p < ib) {
         const int bw = p & 1;
@@ -1884,6 +1973,24 @@ __global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int 
     fetch_u(Ub, ia, true);
     fetch_u(Uc, ia + 1, true);
     fetch_mv(Ma, Va, ia, true);
+    // the loads of the first planes are in flight while the coefficients of
+    // the iteration are reduced from the previous pass's partial sums (no
+    // instruction that waits for a load moves above this point)
+    __builtin_amdgcn_sched_barrier(0);
+    if (FUSED) {
+      double nn, uz, ox, oy;
+      if (NT == TPB) lz_col_partials(W, pbase, cs, np, j - 1, nn, uz, ox, oy, l4);
+      else col_parts_reduce(cq, W, pbase, cs, np, j - 1, nn, uz, ox, oy, l4);
+      const double bj = sqrt(nn);
+      cj = bj > 0.0 ? 1.0 / bj : 0.0;
+      ka = cj * cj * uz * cj;
+      kb = bj * W.cscale[(int64_t)s * (m + 1) + j - 1];
+    } else {
+      cj = W.cscale[(int64_t)s * (m + 1) + j];
+      const double cjm = j > 0 ? W.cscale[(int64_t)s * (m + 1) + j - 1] : 0.0;
+      ka = SW.alpha[(int64_t)s * m + j] * cj;
+      kb = j > 0 ? SW.beta[(int64_t)s * (m + 1) + j] * cjm : 0.0;
+    }
 #pragma unroll
     for (int q = 0; q < KH; ++q) Wa[q] = zero;
     step(ia - 1, Ua, Ub, Uc, Ud, Ma, Mb, Va, Vb, Wa, Wb);
@@ -1894,10 +2001,10 @@ __global__ __launch_bounds__(TPB) void k_lz_step_tile(Work W, ShiftWork SW, int 
       step(p + 2, Ud, Ua, Ub, Uc, Mb, Ma, Vb, Va, Wb, Wa);
       step(p + 3, Ua, Ub, Uc, Ud, Ma, Mb, Va, Vb, Wa, Wb);
     }
-    en = block_sum(en, lds);
-    oux = block_sum(oux, lds);
-    ouy = block_sum(ouy, lds);
-    nn = block_sum(nn, lds);
+    en = block_sum_w<NW>(en, lds);
+    oux = block_sum_w<NW>(oux, lds);
+    ouy = block_sum_w<NW>(ouy, lds);
+    nn = block_sum_w<NW>(nn, lds);
     if (threadIdx.x == 0) {
       double2* part = reinterpret_cast<double2*>(W.part) + pbase + 3 * (j & 1) * cs;
       part[t] = make_double2(en, 0.0);
