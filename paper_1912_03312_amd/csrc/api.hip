@@ -76,7 +76,9 @@ struct Prof {
   std::vector<hipEvent_t> ev;      // pool, pairs
   std::vector<int> cls;            // class per recorded pair
   std::vector<double> pbytes;      // bytes per recorded pair
+  std::vector<int> pcount;         // launches per recorded pair
   size_t used = 0;
+  int suspend = 0;                 // > 0: record nothing (a stream is being captured)
 };
 
 }  // namespace
@@ -241,9 +243,10 @@ struct Timed {
   rexi_handle* h;
   int slot = -1;
   hipStream_t st;
-  Timed(rexi_handle* hh, int cls, double bytes, hipStream_t s) : h(hh), st(s) {
+  // count: launches of the class between the two events (a graph of several)
+  Timed(rexi_handle* hh, int cls, double bytes, hipStream_t s, int count = 1) : h(hh), st(s) {
     Prof& P = h->prof;
-    if (!P.on || h->syncfree) return;
+    if (!P.on || h->syncfree || P.suspend) return;
     if (P.used + 2 > P.ev.size()) {
       for (int i = 0; i < 256; ++i) {
         hipEvent_t e;
@@ -255,6 +258,7 @@ struct Timed {
     P.used += 2;
     P.cls.push_back(cls);
     P.pbytes.push_back(bytes);
+    P.pcount.push_back(count);
     (void)hipEventRecord(P.ev[slot], st);
   }
   ~Timed() {
@@ -270,12 +274,13 @@ void prof_collect(rexi_handle* h, hipStream_t st) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, P.ev[2 * k], P.ev[2 * k + 1]) == hipSuccess) {
       P.ms[P.cls[k]] += ms;
-      P.launches[P.cls[k]] += 1;
+      P.launches[P.cls[k]] += P.pcount[k];
       P.bytes[P.cls[k]] += P.pbytes[k];
     }
   }
   P.cls.clear();
   P.pbytes.clear();
+  P.pcount.clear();
   P.used = 0;
 }
 
@@ -1407,8 +1412,11 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
   } else {
     // chunks of iterations between host checks: the first spans as many
     // iterations as the previous solve needed, later ones check_every each;
-    // a chunk is a cached graph (graph_chunks) or plain launches
-    const bool use_graphs = !h->prof.on && h->opt.graph_chunks;
+    // a chunk is a cached graph (graph_chunks) or plain launches. With
+    // profiling, a chunk of fused passes (Lanczos launches only) stays a
+    // graph and is timed as a whole, so that the time per launch is the
+    // kernels' own; other schedules are timed launch by launch
+    const bool use_graphs = h->opt.graph_chunks && (!h->prof.on || fuse);
     auto launch_chunk = [&](int j0, int len) -> rexi_status {
       if (!use_graphs) {
         for (int q = j0; q < j0 + len; ++q) iteration(q, stream);
@@ -1422,7 +1430,9 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
         if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
         HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        ++h->prof.suspend;
         for (int q = j0; q < j0 + len; ++q) iteration(q, h->cap_stream);
+        --h->prof.suspend;
         hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
         if (ec != hipSuccess) return fail(h, REXI_E_HIP, "chunk capture failed: %s", hipGetErrorString(ec));
         hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -1434,6 +1444,9 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
         }
         (*cx.chunks).push_back({j0, len, exec});
       }
+      double cbytes = 0.0;
+      for (int q = j0; q < j0 + len; ++q) cbytes += q + 1 < m ? n * lz_bytes(q + 1) : 0.0;
+      Timed t(h, PC_LANCZOS, cbytes, stream, len);
       HIPCHK(h, hipGraphLaunch(exec, stream));
       return REXI_OK;
     };
