@@ -65,8 +65,21 @@ struct Solver {
   // for at most cap_S systems of cap_pts points in total
   int cap_S = 0;
   int64_t cap_pts = 0;
+  // per-pole finite-difference solves: the basis is stored tile-interleaved
+  // (the points of one work tile of all m + 1 vectors contiguous)
+  bool ilv = false;
   bool ready = false;
 };
+
+// log2 of a power of two
+inline int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+// points of a system's vector in an interleaved basis (room for any tile of
+// at most 8 TPB points)
+inline int64_t ilv_points(int64_t n) { return (n + 8 * rexi::TPB - 1) / (8 * rexi::TPB) * (8 * rexi::TPB); }
 
 struct Prof {
   bool on = false;
@@ -300,9 +313,11 @@ rexi_status dalloc(rexi_handle* h, Solver& sv, X** out, size_t count) {
   return REXI_OK;
 }
 
-size_t solver_bytes(const std::vector<SysDesc>& sys, int m, int prec, int max_cycles, int total_tiles) {
+size_t solver_bytes(const std::vector<SysDesc>& sys, int m, int prec, int max_cycles, int total_tiles,
+                    bool ilv) {
   size_t e = prec ? 8 : 16, tot = 0;
-  for (auto& d : sys) tot += (size_t)(m + 1) * d.n * e + (size_t)d.n * 16 + (size_t)(m + 1) * d.ntiles * 16;
+  for (auto& d : sys)
+    tot += (size_t)(m + 1) * (ilv ? ilv_points(d.n) : d.n) * e + (size_t)d.n * 16 + (size_t)(m + 1) * d.ntiles * 16;
   size_t S = sys.size();
   tot += S * ((size_t)(m + 1) * m * 16 + (m + 1) * 16 * 2 + m * 16 * 3 + (m + 1) * 8 + sizeof(SysState_t));
   tot += (size_t)total_tiles * 8 + (size_t)(max_cycles * (m + 1) + max_cycles + 4) * 4;
@@ -322,7 +337,7 @@ void layout_systems(Solver& sv, int m) {
     d.pbase = pbase;
     sv.htile.push_back(tile0);
     tile0 += d.ntiles;
-    basis += (int64_t)(m + 1) * d.n;
+    basis += (int64_t)(m + 1) * (sv.ilv ? (int64_t)d.ntiles * sv.tile : d.n);
     xo += d.n;
     pbase += (m + 1) * d.ntiles;
   }
@@ -428,7 +443,7 @@ rexi_status build_solver(rexi_handle* h, Solver& sv, hipStream_t stream) {
     npart += (size_t)(m + 1) * nt;
     ntmax += nt;
     nx += d.n;
-    nb += (size_t)(m + 1) * d.n;
+    nb += (size_t)(m + 1) * (sv.ilv ? ilv_points(d.n) : d.n);
   }
   ALLOC(W.part, double, npart * 2);
   ALLOC(W.pnorm, double, ntmax);
@@ -469,6 +484,7 @@ rexi_status build_solver(rexi_handle* h, Solver& sv, hipStream_t stream) {
   W.eta2 = sv.eta * sv.eta;  // DGKS: second pass when ||w - V h|| < eta ||w||
   W.max_cycles = sv.max_cycles;
   W.tile = sv.tile;
+  W.ilv = sv.ilv ? ilog2(sv.tile) : 0;
   if ((st = upload_tile_sys(h, sv, stream)) != REXI_OK) return st;
   sv.ready = true;
   return REXI_OK;
@@ -670,6 +686,11 @@ rexi_status init_solver(rexi_handle* h, Solver& sv, int copies, hipStream_t stre
     }
   }
   for (int c = 0; c < copies; ++c) make_systems(h, sv, c == 1, c);
+  // per-pole finite-difference solves store their bases tile-interleaved
+  // (Q1 element sweeps address whole vectors: they keep the plain layout)
+  sv.ilv = copies > 0;
+  for (auto& d : sv.hsys)
+    if (d.fem) sv.ilv = false;
   sv.prec = h->opt.precision == REXI_PREC_C64_REFINE ? 1 : 0;
   int64_t pts = 0;
   for (auto& d : sv.hsys) pts += d.n;
@@ -692,7 +713,7 @@ rexi_status init_solver(rexi_handle* h, Solver& sv, int copies, hipStream_t stre
   int m = (h->shifted && copies > 0) ? h->opt.fallback_m : h->opt.m;
   for (;;) {
     layout_systems(sv, m);
-    if (solver_bytes(sv.hsys, m, sv.prec, sv.max_cycles, sv.total_tiles) <= budget) break;
+    if (solver_bytes(sv.hsys, m, sv.prec, sv.max_cycles, sv.total_tiles, sv.ilv) <= budget) break;
     if (copies == 0) return fail(h, REXI_E_NO_MEMORY, "shared Krylov basis of dimension %d does not fit", m);
     if (m <= 4) return fail(h, REXI_E_NO_MEMORY, "Krylov workspace does not fit the %zu-byte budget", budget);
     m = std::max(4, m * 3 / 4);
@@ -1836,6 +1857,7 @@ rexi_status apply_tiling(rexi_handle* h, Solver& sv, int ppt, int grid, hipStrea
   sv.grid = grid;
   sv.W.total_tiles = sv.total_tiles;
   sv.W.tile = sv.tile;
+  sv.W.ilv = sv.ilv ? ilog2(sv.tile) : 0;
   HIPCHK(h, hipMemcpyAsync(sv.dsys, sv.hsys.data(), sv.S * sizeof(SysDesc), hipMemcpyHostToDevice, stream));
   HIPCHK(h, hipMemcpyAsync(sv.dtile, sv.htile.data(), (sv.S + 1) * sizeof(int32_t), hipMemcpyHostToDevice, stream));
   HIPCHK(h, hipStreamSynchronize(stream));

@@ -179,6 +179,92 @@ template <typename T> __device__ __forceinline__ T* basis_vec(const Work& W, con
   return reinterpret_cast<T*>(W.basis) + d.basis + (int64_t)i * d.n;
 }
 
+// Per-pole bases may be stored tile-interleaved (W.ilv = log2 of the work
+// tile; 0: vector after vector): the points of work tile t of all m + 1
+// vectors of a system are then one contiguous region, vector i at offset
+// (t (m + 1) + i) * tile. A tile item of the Arnoldi passes reads its tile of
+// all j + 1 vectors; stored vector after vector those are j + 1 concurrent
+// streams into memory, and the bank conflicts between them cost about half
+// of the bandwidth at j ~ 16 (2.3 against 5.5 TB/s for complex64, measured).
+// tile_vec: vector i within tile t (index the tile's points from 0).
+template <typename T> __device__ __forceinline__ T* tile_vec(const Work& W, const SysDesc& d, int t, int i) {
+  T* b = reinterpret_cast<T*>(W.basis) + d.basis;
+  return W.ilv ? b + (((int64_t)t * (W.m + 1) + i) << W.ilv) : b + (int64_t)i * d.n + (int64_t)t * W.tile;
+}
+// Basis vectors whose loads a tile item issues together: eight, or fewer so
+// that they take at most 64 registers per thread.
+template <typename T, int PPT> __device__ constexpr int au_vectors() {
+  return 256 / (PPT * (int)sizeof(T)) < 8 ? 256 / (PPT * (int)sizeof(T)) : 8;
+}
+// Slot q (0 <= q < PPT) of a thread handles point tpt<T>(q) of its work tile.
+// complex64 pairs neighbouring points in a thread (slots 2k and 2k + 1 are
+// adjacent), so that a lane moves 16 bytes per load, as complex128 does with
+// one point: with 8-byte lanes the Arnoldi passes ran at half the bandwidth.
+template <typename T> __device__ __forceinline__ int tpt(int q) {
+  return sizeof(T) == 8 ? ((q >> 1) * TPB + (int)threadIdx.x) * 2 + (q & 1) : q * TPB + (int)threadIdx.x;
+}
+// Slots of a thread in the tile of vector u (its points p0 + tpt(q)), zero
+// past n. full: the tile's region is allocated to its end (tile-interleaved
+// bases), so a complex64 pair is loaded whole and masked.
+template <typename T, int PPT>
+__device__ __forceinline__ void tile_load(const T* __restrict__ u, int p0, int n, bool full, T (&a)[PPT]) {
+  if constexpr (sizeof(T) == 8) {
+#pragma unroll
+    for (int k = 0; k < PPT / 2; ++k) {
+      const int o = tpt<T>(2 * k), p = p0 + o;
+      if (full) {
+        const float4 v = *reinterpret_cast<const float4*>(u + o);
+        a[2 * k] = p < n ? T{v.x, v.y} : T{};
+        a[2 * k + 1] = p + 1 < n ? T{v.z, v.w} : T{};
+      } else {
+        a[2 * k] = p < n ? u[o] : T{};
+        a[2 * k + 1] = p + 1 < n ? u[o + 1] : T{};
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int o = tpt<T>(q);
+      a[q] = p0 + o < n ? u[o] : T{};
+    }
+  }
+}
+// Store the slots of a thread to the tile of vector u (points below n only).
+template <typename T, int PPT>
+__device__ __forceinline__ void tile_store(T* __restrict__ u, int p0, int n, bool full, const T (&a)[PPT]) {
+  if constexpr (sizeof(T) == 8) {
+#pragma unroll
+    for (int k = 0; k < PPT / 2; ++k) {
+      const int o = tpt<T>(2 * k), p = p0 + o;
+      if (full && p + 1 < n) {
+        *reinterpret_cast<float4*>(u + o) = make_float4(a[2 * k].x, a[2 * k].y, a[2 * k + 1].x, a[2 * k + 1].y);
+      } else {
+        if (p < n) u[o] = a[2 * k];
+        if (p + 1 < n) u[o + 1] = a[2 * k + 1];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      const int o = tpt<T>(q);
+      if (p0 + o < n) u[o] = a[q];
+    }
+  }
+}
+// Point q of a vector in either layout: map_vec(i)[BMap(q)] (for stencils,
+// whose neighbours lie in other tiles).
+struct BMap {
+  int lt, vs;  // log2 of the tile (0: plain), vectors per tile
+  __device__ __forceinline__ int64_t operator()(uint32_t q) const {
+    return lt ? ((((int64_t)(q >> lt)) * vs) << lt) + (int64_t)(q & ((1u << lt) - 1u)) : (int64_t)q;
+  }
+};
+__device__ __forceinline__ BMap bmap(const Work& W) { return BMap{W.ilv, W.m + 1}; }
+template <typename T> __device__ __forceinline__ T* map_vec(const Work& W, const SysDesc& d, int i) {
+  T* b = reinterpret_cast<T*>(W.basis) + d.basis;
+  return W.ilv ? b + ((int64_t)i << W.ilv) : b + (int64_t)i * d.n;
+}
+
 // Iteration indices of captured schedules. A launch's iteration is its
 // argument when that is >= 0. A captured schedule cannot read anything on the
 // host, so its launches take the index from the device instead: JD_REC is
@@ -198,24 +284,24 @@ __device__ __forceinline__ int dev_iter(const Work& W, int j) {
 // (H - s) u at point p, for storage type T, in the arithmetic of T.
 template <typename T>
 __device__ __forceinline__ double2 stencil_point(const T* __restrict__ u, const SysDesc& d,
-                                                 double vp, uint32_t p);
+                                                 double vp, uint32_t p, BMap mp = BMap{0, 0});
 
 template <>
 __device__ __forceinline__ double2 stencil_point<double2>(const double2* __restrict__ u, const SysDesc& d,
-                                                          double vp, uint32_t p) {
+                                                          double vp, uint32_t p, BMap mp) {
   const uint32_t r = fdiv(p, d.d2);
   const uint32_t k = p - r * (uint32_t)d.n2;
   const uint32_t i0 = fdiv(r, d.d1);
   const uint32_t j = r - i0 * (uint32_t)d.n1;
   const uint32_t plane = (uint32_t)d.n1 * (uint32_t)d.n2;
-  const double2 c = u[p];
+  const double2 c = u[mp(p)];
   double2 nb2 = make_double2(0.0, 0.0), nb1 = nb2, nb0 = nb2;
-  if (k > 0) { double2 t = u[p - 1]; nb2.x += t.x; nb2.y += t.y; }
-  if (k + 1 < (uint32_t)d.n2) { double2 t = u[p + 1]; nb2.x += t.x; nb2.y += t.y; }
-  if (j > 0) { double2 t = u[p - d.n2]; nb1.x += t.x; nb1.y += t.y; }
-  if (j + 1 < (uint32_t)d.n1) { double2 t = u[p + d.n2]; nb1.x += t.x; nb1.y += t.y; }
-  if (i0 > 0) { double2 t = u[p - plane]; nb0.x += t.x; nb0.y += t.y; }
-  if (i0 + 1 < (uint32_t)d.n0) { double2 t = u[p + plane]; nb0.x += t.x; nb0.y += t.y; }
+  if (k > 0) { double2 t = u[mp(p - 1)]; nb2.x += t.x; nb2.y += t.y; }
+  if (k + 1 < (uint32_t)d.n2) { double2 t = u[mp(p + 1)]; nb2.x += t.x; nb2.y += t.y; }
+  if (j > 0) { double2 t = u[mp(p - d.n2)]; nb1.x += t.x; nb1.y += t.y; }
+  if (j + 1 < (uint32_t)d.n1) { double2 t = u[mp(p + d.n2)]; nb1.x += t.x; nb1.y += t.y; }
+  if (i0 > 0) { double2 t = u[mp(p - plane)]; nb0.x += t.x; nb0.y += t.y; }
+  if (i0 + 1 < (uint32_t)d.n0) { double2 t = u[mp(p + plane)]; nb0.x += t.x; nb0.y += t.y; }
   const double a = d.diag + vp - d.sre;
   double2 o;
   o.x = a * c.x + d.sim * c.y - (d.c2 * nb2.x + d.c1 * nb1.x + d.c0 * nb0.x);
@@ -225,26 +311,75 @@ __device__ __forceinline__ double2 stencil_point<double2>(const double2* __restr
 
 template <>
 __device__ __forceinline__ double2 stencil_point<float2>(const float2* __restrict__ u, const SysDesc& d,
-                                                         double vp, uint32_t p) {
+                                                         double vp, uint32_t p, BMap mp) {
   const uint32_t r = fdiv(p, d.d2);
   const uint32_t k = p - r * (uint32_t)d.n2;
   const uint32_t i0 = fdiv(r, d.d1);
   const uint32_t j = r - i0 * (uint32_t)d.n1;
   const uint32_t plane = (uint32_t)d.n1 * (uint32_t)d.n2;
-  const float2 c = u[p];
+  const float2 c = u[mp(p)];
   float2 nb2 = make_float2(0.f, 0.f), nb1 = nb2, nb0 = nb2;
-  if (k > 0) { float2 t = u[p - 1]; nb2.x += t.x; nb2.y += t.y; }
-  if (k + 1 < (uint32_t)d.n2) { float2 t = u[p + 1]; nb2.x += t.x; nb2.y += t.y; }
-  if (j > 0) { float2 t = u[p - d.n2]; nb1.x += t.x; nb1.y += t.y; }
-  if (j + 1 < (uint32_t)d.n1) { float2 t = u[p + d.n2]; nb1.x += t.x; nb1.y += t.y; }
-  if (i0 > 0) { float2 t = u[p - plane]; nb0.x += t.x; nb0.y += t.y; }
-  if (i0 + 1 < (uint32_t)d.n0) { float2 t = u[p + plane]; nb0.x += t.x; nb0.y += t.y; }
+  if (k > 0) { float2 t = u[mp(p - 1)]; nb2.x += t.x; nb2.y += t.y; }
+  if (k + 1 < (uint32_t)d.n2) { float2 t = u[mp(p + 1)]; nb2.x += t.x; nb2.y += t.y; }
+  if (j > 0) { float2 t = u[mp(p - d.n2)]; nb1.x += t.x; nb1.y += t.y; }
+  if (j + 1 < (uint32_t)d.n1) { float2 t = u[mp(p + d.n2)]; nb1.x += t.x; nb1.y += t.y; }
+  if (i0 > 0) { float2 t = u[mp(p - plane)]; nb0.x += t.x; nb0.y += t.y; }
+  if (i0 + 1 < (uint32_t)d.n0) { float2 t = u[mp(p + plane)]; nb0.x += t.x; nb0.y += t.y; }
   const float a = (float)(d.diag - d.sre) + (float)vp;
   const float sim = (float)d.sim;
   const float c2 = (float)d.c2, c1 = (float)d.c1, c0 = (float)d.c0;
   float ox = a * c.x + sim * c.y - (c2 * nb2.x + c1 * nb1.x + c0 * nb0.x);
   float oy = a * c.y - sim * c.x - (c2 * nb2.y + c1 * nb1.y + c0 * nb0.y);
   return make_double2((double)ox, (double)oy);
+}
+
+// (H - s) u at the adjacent points p and p + 1 of a complex64 vector of a
+// tile-interleaved basis (p even and n2 even: both points lie in one row and
+// one tile, and every pair below is one aligned 16-byte load). Each point's
+// arithmetic is stencil_point<float2>'s, term by term.
+__device__ __forceinline__ void stencil_pair_c64(const float2* __restrict__ u, const float* __restrict__ V,
+                                                 const SysDesc& d, uint32_t p, BMap mp, double2& o0,
+                                                 double2& o1) {
+  const uint32_t r = fdiv(p, d.d2);
+  const uint32_t k = p - r * (uint32_t)d.n2;
+  const uint32_t i0 = fdiv(r, d.d1);
+  const uint32_t jr = r - i0 * (uint32_t)d.n1;
+  const uint32_t plane = (uint32_t)d.n1 * (uint32_t)d.n2;
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  auto pair = [&](uint32_t q) { return *reinterpret_cast<const float4*>(u + mp(q)); };
+  const float4 c = pair(p);
+  const float2 l = k > 0 ? u[mp(p - 1)] : make_float2(0.f, 0.f);
+  const bool hr = k + 2 < (uint32_t)d.n2;
+  const float2 rr = hr ? u[mp(p + 2)] : make_float2(0.f, 0.f);
+  const bool hd = jr > 0, hu = jr + 1 < (uint32_t)d.n1, hb = i0 > 0, hf = i0 + 1 < (uint32_t)d.n0;
+  const float4 dn = hd ? pair(p - d.n2) : z4, up = hu ? pair(p + d.n2) : z4;
+  const float4 bk = hb ? pair(p - plane) : z4, fr = hf ? pair(p + plane) : z4;
+  const float2 vv = *reinterpret_cast<const float2*>(V + d.off + p);
+  const float sim = (float)d.sim;
+  const float c2 = (float)d.c2, c1 = (float)d.c1, c0 = (float)d.c0;
+  const float a0 = (float)(d.diag - d.sre) + vv.x, a1 = (float)(d.diag - d.sre) + vv.y;
+  // point p: left neighbour if any, right neighbour p + 1
+  float2 nb2 = make_float2(0.f, 0.f), nb1 = nb2, nb0 = nb2;
+  if (k > 0) { nb2.x += l.x; nb2.y += l.y; }
+  nb2.x += c.z; nb2.y += c.w;
+  if (hd) { nb1.x += dn.x; nb1.y += dn.y; }
+  if (hu) { nb1.x += up.x; nb1.y += up.y; }
+  if (hb) { nb0.x += bk.x; nb0.y += bk.y; }
+  if (hf) { nb0.x += fr.x; nb0.y += fr.y; }
+  float ox = a0 * c.x + sim * c.y - (c2 * nb2.x + c1 * nb1.x + c0 * nb0.x);
+  float oy = a0 * c.y - sim * c.x - (c2 * nb2.y + c1 * nb1.y + c0 * nb0.y);
+  o0 = make_double2((double)ox, (double)oy);
+  // point p + 1: left neighbour p, right neighbour if any
+  nb2 = make_float2(0.f, 0.f); nb1 = nb2; nb0 = nb2;
+  nb2.x += c.x; nb2.y += c.y;
+  if (hr) { nb2.x += rr.x; nb2.y += rr.y; }
+  if (hd) { nb1.x += dn.z; nb1.y += dn.w; }
+  if (hu) { nb1.x += up.z; nb1.y += up.w; }
+  if (hb) { nb0.x += bk.z; nb0.y += bk.w; }
+  if (hf) { nb0.x += fr.z; nb0.y += fr.w; }
+  ox = a1 * c.z + sim * c.w - (c2 * nb2.x + c1 * nb1.x + c0 * nb0.x);
+  oy = a1 * c.w - sim * c.z - (c2 * nb2.y + c1 * nb1.y + c0 * nb0.y);
+  o1 = make_double2((double)ox, (double)oy);
 }
 
 // FP64 stencil on an FP64 vector: (H - s) x at p.
@@ -513,14 +648,14 @@ __global__ __launch_bounds__(TPB) void k_start(Work W, const double2* __restrict
     const SysDesc& d = W.sys[s];
     const int t = item - d.tile0;
     const double2* __restrict__ b = (d.rhs_sel ? rhs1 : rhs0) + d.off;
-    T* __restrict__ u0 = basis_vec<T>(W, d, 0);
+    T* __restrict__ u0 = tile_vec<T>(W, d, t, 0);
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
       const int p = t * W.tile + q * TPB + threadIdx.x;
       if (p < d.n) {
         double2 v = b[p];
-        u0[p] = from_d2<T>(v);
+        u0[q * TPB + threadIdx.x] = from_d2<T>(v);
         acc += v.x * v.x + v.y * v.y;
       }
     }
@@ -701,33 +836,71 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
     const SysDesc& d = W.sys[s];
     const int t = item - d.tile0;
     const double cj = W.cscale[(int64_t)s * (W.m + 1) + j];
-    T* __restrict__ unew = basis_vec<T>(W, d, j + 1);
+    T* __restrict__ unew = tile_vec<T>(W, d, t, j + 1);
     double2 w[PPT];
     double wn = 0.0;
+    // complex64 in a tile-interleaved basis: point pairs with 16-byte accesses
+    // (the matvec when the pairs stay in rows: n2 even, V's pairs aligned)
+    bool paired = false;
+    if constexpr (sizeof(T) == 8) {
+      if (W.ilv && (!MATVEC || (!d.fem && (d.n2 & 1) == 0 && (d.off & 1) == 0))) {
+        paired = true;
+        T wv[PPT];
+        if (!MATVEC) tile_load<T, PPT>(unew, t * W.tile, d.n, true, wv);
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-      const int p = t * W.tile + q * TPB + threadIdx.x;
+        for (int k = 0; k < PPT / 2; ++k) {
+          const int o = tpt<T>(2 * k);
+          const int p = t * W.tile + o;
+          double2 v0 = make_double2(0.0, 0.0), v1 = v0;
+          if (MATVEC) {
+            if (p < d.n) stencil_pair_c64(reinterpret_cast<const float2*>(map_vec<T>(W, d, j)), W.V32, d,
+                                          (uint32_t)p, bmap(W), v0, v1);
+          } else {
+            v0 = to_d2(wv[2 * k]);
+            v1 = to_d2(wv[2 * k + 1]);
+          }
+          if (MATVEC || pre) {
+            v0.x *= cj;
+            v0.y *= cj;
+            v1.x *= cj;
+            v1.y *= cj;
+          }
+          wv[2 * k] = from_d2<T>(v0);
+          wv[2 * k + 1] = from_d2<T>(v1);
+          // (n even here when MATVEC; otherwise the second point may be past n)
+          w[2 * k] = p < d.n ? to_d2(wv[2 * k]) : make_double2(0.0, 0.0);
+          w[2 * k + 1] = p + 1 < d.n ? to_d2(wv[2 * k + 1]) : make_double2(0.0, 0.0);
+          if (p < d.n) wn += w[2 * k].x * w[2 * k].x + w[2 * k].y * w[2 * k].y;
+          if (p + 1 < d.n) wn += w[2 * k + 1].x * w[2 * k + 1].x + w[2 * k + 1].y * w[2 * k + 1].y;
+        }
+        if (MATVEC || pre) tile_store<T, PPT>(unew, t * W.tile, d.n, true, wv);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PPT && !paired; ++q) {
+      const int o = tpt<T>(q);  // the point within the tile
+      const int p = t * W.tile + o;
       w[q] = make_double2(0.0, 0.0);
       if (p < d.n) {
         if (MATVEC) {
-          const T* __restrict__ uj = basis_vec<T>(W, d, j);
-          double2 v = d.fem ? fem_point<T>(uj, d.n0, d.n1, d.n2, d.d2, d.d1, d.fmd, d.fmo, d.fkd, d.fko, d.fvol,
-                                           vpot<T>(W, d.off + p), d.sre, d.sim, (uint32_t)p)
-                            : stencil_point<T>(uj, d, vpot<T>(W, d.off + p), (uint32_t)p);
+          // (Q1 elements keep the plain layout: W.ilv = 0)
+          double2 v = d.fem ? fem_point<T>(basis_vec<T>(W, d, j), d.n0, d.n1, d.n2, d.d2, d.d1, d.fmd, d.fmo,
+                                           d.fkd, d.fko, d.fvol, vpot<T>(W, d.off + p), d.sre, d.sim, (uint32_t)p)
+                            : stencil_point<T>(map_vec<T>(W, d, j), d, vpot<T>(W, d.off + p), (uint32_t)p, bmap(W));
           v.x *= cj;
           v.y *= cj;
           T vs = from_d2<T>(v);
-          unew[p] = vs;
+          unew[o] = vs;
           w[q] = to_d2(vs);
         } else if (pre) {
-          double2 v = to_d2(unew[p]);
+          double2 v = to_d2(unew[o]);
           v.x *= cj;
           v.y *= cj;
           T vs = from_d2<T>(v);
-          unew[p] = vs;
+          unew[o] = vs;
           w[q] = to_d2(vs);
         } else {
-          w[q] = to_d2(unew[p]);
+          w[q] = to_d2(unew[o]);
         }
         wn += w[q].x * w[q].x + w[q].y * w[q].y;
       }
@@ -737,26 +910,19 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
     // are issued together (a tall-skinny matrix-vector product), then AU
     // independent wave reductions; each dot is summed in the same order as
     // one vector at a time
-    constexpr int AU = 8;
+    constexpr int AU = au_vectors<T, PPT>();
     int i = lo;
     for (; i + AU <= j + 1; i += AU) {
       T a[AU][PPT];
 #pragma unroll
-      for (int r = 0; r < AU; ++r) {
-        const T* __restrict__ ui = basis_vec<T>(W, d, i + r);
-#pragma unroll
-        for (int q = 0; q < PPT; ++q) {
-          const int p = t * W.tile + q * TPB + threadIdx.x;
-          a[r][q] = p < d.n ? ui[p] : T{};
-        }
-      }
+      for (int r = 0; r < AU; ++r) tile_load<T, PPT>(tile_vec<T>(W, d, t, i + r), t * W.tile, d.n, W.ilv != 0, a[r]);
       double2 acc[AU];
 #pragma unroll
       for (int r = 0; r < AU; ++r) {
         acc[r] = make_double2(0.0, 0.0);
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
-          const int p = t * W.tile + q * TPB + threadIdx.x;
+          const int p = t * W.tile + tpt<T>(q);
           if (p < d.n) {
             const double2 c = cjmul(to_d2(a[r][q]), w[q]);
             acc[r].x += c.x;
@@ -772,13 +938,14 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
       }
     }
     for (; i <= j; ++i) {
-      const T* __restrict__ ui = basis_vec<T>(W, d, i);
+      T av[PPT];
+      tile_load<T, PPT>(tile_vec<T>(W, d, t, i), t * W.tile, d.n, W.ilv != 0, av);
       double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
-        const int p = t * W.tile + q * TPB + threadIdx.x;
+        const int p = t * W.tile + tpt<T>(q);
         if (p < d.n) {
-          double2 a = to_d2(ui[p]);
+          double2 a = to_d2(av[q]);
           double2 c = cjmul(a, w[q]);
           acc.x += c.x;
           acc.y += c.y;
@@ -1100,37 +1267,61 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second, in
       W.st[s].reorth = reo ? 1 : 0;
       if (reo && W.reo_any) W.reo_any[j] = 1;
     }
-    T* __restrict__ unew = basis_vec<T>(W, d, j + 1);
+    T* __restrict__ unew = tile_vec<T>(W, d, t, j + 1);
     double2 w[PPT];
+    {
+      T wv[PPT];
+      tile_load<T, PPT>(unew, t * W.tile, d.n, W.ilv != 0, wv);
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-      const int p = t * W.tile + q * TPB + threadIdx.x;
-      w[q] = p < d.n ? to_d2(unew[p]) : make_double2(0.0, 0.0);
+      for (int q = 0; q < PPT; ++q) w[q] = to_d2(wv[q]);
     }
-    for (int i = lo; i <= j; ++i) {
-      const T* __restrict__ ui = basis_vec<T>(W, d, i);
+    // the loads of AU vectors are issued together; the updates keep the order i = lo .. j
+    constexpr int AU = au_vectors<T, PPT>();
+    int i = lo;
+    for (; i + AU <= j + 1; i += AU) {
+      T a[AU][PPT];
+#pragma unroll
+      for (int r = 0; r < AU; ++r) tile_load<T, PPT>(tile_vec<T>(W, d, t, i + r), t * W.tile, d.n, W.ilv != 0, a[r]);
+#pragma unroll
+      for (int r = 0; r < AU; ++r) {
+        const double2 c = coef[i + r];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+          const int p = t * W.tile + tpt<T>(q);
+          if (p < d.n) {
+            const double2 av = to_d2(a[r][q]);
+            w[q].x -= c.x * av.x - c.y * av.y;
+            w[q].y -= c.x * av.y + c.y * av.x;
+          }
+        }
+      }
+    }
+    for (; i <= j; ++i) {
+      T av[PPT];
+      tile_load<T, PPT>(tile_vec<T>(W, d, t, i), t * W.tile, d.n, W.ilv != 0, av);
       const double2 c = coef[i];
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
-        const int p = t * W.tile + q * TPB + threadIdx.x;
+        const int p = t * W.tile + tpt<T>(q);
         if (p < d.n) {
-          double2 a = to_d2(ui[p]);
+          double2 a = to_d2(av[q]);
           w[q].x -= c.x * a.x - c.y * a.y;
           w[q].y -= c.x * a.y + c.y * a.x;
         }
       }
     }
     double wn = 0.0;
+    T wo[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-      const int p = t * W.tile + q * TPB + threadIdx.x;
+      const int p = t * W.tile + tpt<T>(q);
+      wo[q] = from_d2<T>(w[q]);
       if (p < d.n) {
-        T v = from_d2<T>(w[q]);
-        unew[p] = v;
-        double2 vd = to_d2(v);
+        double2 vd = to_d2(wo[q]);
         wn += vd.x * vd.x + vd.y * vd.y;
       }
     }
+    tile_store<T, PPT>(unew, t * W.tile, d.n, W.ilv != 0, wo);
     wn = block_sum(wn, lds);
     if (threadIdx.x == 0) W.pnorm[item] = wn;
   }
@@ -2544,17 +2735,39 @@ __global__ __launch_bounds__(TPB) void k_update_x(Work W) {
     double2 acc[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-      const int p = t * W.tile + q * TPB + threadIdx.x;
+      const int p = t * W.tile + tpt<T>(q);
       acc[q] = (p < d.n && !st.first) ? x[p] : make_double2(0.0, 0.0);
     }
-    for (int i = 0; i < k; ++i) {
-      const T* __restrict__ ui = basis_vec<T>(W, d, i);
+    // the loads of AU vectors are issued together; the sums keep the order i = 0 .. k - 1
+    constexpr int AU = au_vectors<T, PPT>();
+    int i = 0;
+    for (; i + AU <= k; i += AU) {
+      T a[AU][PPT];
+#pragma unroll
+      for (int r = 0; r < AU; ++r) tile_load<T, PPT>(tile_vec<T>(W, d, t, i + r), t * W.tile, d.n, W.ilv != 0, a[r]);
+#pragma unroll
+      for (int r = 0; r < AU; ++r) {
+        const double2 c = coef[i + r];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+          const int p = t * W.tile + tpt<T>(q);
+          if (p < d.n) {
+            const double2 av = to_d2(a[r][q]);
+            acc[q].x += c.x * av.x - c.y * av.y;
+            acc[q].y += c.x * av.y + c.y * av.x;
+          }
+        }
+      }
+    }
+    for (; i < k; ++i) {
+      T av[PPT];
+      tile_load<T, PPT>(tile_vec<T>(W, d, t, i), t * W.tile, d.n, W.ilv != 0, av);
       const double2 c = coef[i];
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
-        const int p = t * W.tile + q * TPB + threadIdx.x;
+        const int p = t * W.tile + tpt<T>(q);
         if (p < d.n) {
-          const double2 a = to_d2(ui[p]);
+          const double2 a = to_d2(av[q]);
           acc[q].x += c.x * a.x - c.y * a.y;
           acc[q].y += c.x * a.y + c.y * a.x;
         }
@@ -2562,7 +2775,7 @@ __global__ __launch_bounds__(TPB) void k_update_x(Work W) {
     }
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
-      const int p = t * W.tile + q * TPB + threadIdx.x;
+      const int p = t * W.tile + tpt<T>(q);
       if (p < d.n) x[p] = acc[q];
     }
   }
@@ -2581,7 +2794,7 @@ __global__ __launch_bounds__(TPB) void k_residual(Work W, const double2* __restr
     const int t = item - d.tile0;
     const double2* __restrict__ b = (d.rhs_sel ? rhs1 : rhs0) + d.off;
     const double2* __restrict__ x = reinterpret_cast<const double2*>(W.x) + d.xoff;
-    T* __restrict__ u0 = basis_vec<T>(W, d, 0);
+    T* __restrict__ u0 = tile_vec<T>(W, d, t, 0);
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
@@ -2594,7 +2807,7 @@ __global__ __launch_bounds__(TPB) void k_residual(Work W, const double2* __restr
                                       d.sre, d.sim, (uint32_t)p);
         const double2 bp = b[p];
         const double2 r = make_double2(bp.x - hx.x, bp.y - hx.y);
-        u0[p] = from_d2<T>(r);
+        u0[q * TPB + threadIdx.x] = from_d2<T>(r);
         acc += r.x * r.x + r.y * r.y;
       }
     }

@@ -132,6 +132,7 @@ struct Work {
   double eta2;      // DGKS threshold squared
   int32_t max_cycles;
   int32_t tile;     // points per tile
+  int32_t ilv;      // per-pole bases stored tile-interleaved: log2(tile) (0: vector after vector)
   const int32_t* tile_sys;  // [total_tiles] system of each tile (null: search tile_start)
   int32_t* reo_any; // [m + 1] shared basis: 1 if any system takes a second pass at
                     // iteration j (null: per-system flags only)
