@@ -23,8 +23,9 @@ Prints one JSON line:
                 pole solutions with the oracle's sparse H (a certificate of the
                 error against the exact step), and the sampled poles' solutions
                 against the oracle's solves;
-  variants      the same workload at the per-pole relative residual 1e-10, and
-                per pole in complex128 and in complex64 + FP64 refinement;
+  variants      the same workload as one captured HIP graph per step, at the
+                per-pole relative residual 1e-10, and per pole in complex128
+                and in complex64 + FP64 refinement;
   configs       the other workloads (1D harmonic, 2D double well at 512^2,
                 the differentiation workload, the uneven batch) with their
                 rates and errors against the oracle.
@@ -601,6 +602,26 @@ def main():
                                       "max_rel_residual": vi["max_rel_residual"],
                                       "certified_rel_error_bound": vi["certified_bound"]}
         log(f"# variant shared_relres_1e-10: {vms:.3f} ms/step")
+        # the headline as one captured HIP graph per step (fixed launch
+        # schedule, iteration indices on the device)
+        hv = rexi.setup(g.n, g.lo, g.hi, V, wl.hbar, wl.mass, wl.dt, sigma, beta, capture_safe=1, **opts)
+        a = psi.clone()
+        for _ in range(3):  # the graphs of both buffer orders are recorded
+            hv.step(a, out, 1, info=False)
+            a, out = out, a
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            hv.step(a, out, 1, info=False)
+            a, out = out, a
+        torch.cuda.synchronize()
+        vms = (time.perf_counter() - t0) * 1e3 / args.steps
+        vi = hv.step(a, out, 1, info=True, raise_on_nc=False)
+        hv.close()
+        var["captured"] = {"value": round(1e3 / vms, 4), "ms_per_step": round(vms, 4), "graph_replay": True,
+                           "vs_eager": round(ms / vms, 3), "not_converged": int(vi["not_converged"]),
+                           "certified_rel_error_bound": vi["certified_bound"]}
+        log(f"# variant captured: {vms:.3f} ms/step")
         # per pole: plain FP64 and the mixed form (complex64 inner solves, FP64
         # refinement), both to the headline's per-pole targets, a few steps each
         for name, prec in (("per_pole_c128", "c128"), ("per_pole_c64_refine", "c64")):

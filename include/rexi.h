@@ -238,11 +238,13 @@ typedef struct {
                            Default 0                                          */
   int32_t capture_pauses; /* capture_safe, shared basis with the tiled pass:
                            second Gram-Schmidt passes per cycle the captured
-                           schedule makes room for (each takes up to 15
-                           launches of it); 0 (default): 2 for a single
-                           instance, max(2, m / 32) for a batch (whose
-                           instances all pause when one needs a pass). A
-                           cycle that pauses more stops below m vectors    */
+                           schedule makes room for (each takes up to 31
+                           launches of it for a single instance, 15 for a
+                           batch); 0 (default): 1 for a single instance,
+                           max(2, m / 32) for a batch (whose instances all
+                           pause when one needs a pass). A cycle whose
+                           pauses take more launches than that room stops
+                           below m vectors                                 */
   int32_t reserved_opt2_;
 } rexi_options;
 

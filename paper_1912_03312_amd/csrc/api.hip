@@ -1383,9 +1383,12 @@ rexi_status shifted_pass(rexi_handle* h, ShiftCtx cx, const double2* b, hipStrea
   // pauses shorten the largest Krylov dimension a captured solve reaches).
   const bool capfuse = h->syncfree && pipe && lz && sv.col_kh == 2 && h->jdev;
   if (capfuse) {
-    constexpr int QB = 16;
-    // (a batch pauses all its instances whenever one needs a pass)
-    const int QR = h->opt.capture_pauses > 0 ? h->opt.capture_pauses : S == 1 ? 2 : std::max(2, m / 32);
+    // a single instance: groups of 32 (a recovery is seven launches, which
+    // cost about as much as the launches of a converged solve), room for one
+    // pause; a batch pauses all its instances whenever one needs a pass:
+    // groups of 16, room for max(2, m / 32) pauses
+    const int QB = S == 1 ? 32 : 16;
+    const int QR = h->opt.capture_pauses > 0 ? h->opt.capture_pauses : S == 1 ? 1 : std::max(2, m / 32);
     Work Wd = W;
     Wd.jdev = h->jdev;
     rexi::ShiftWork SWd = SWc;

@@ -1997,6 +1997,10 @@ __global__ __launch_bounds__(NT) void k_lz_step_tile(Work W, ShiftWork SW, int j
   __shared__ double2 wb[2][KH * NT];
   const int m = W.m;
   const int jarg = j;
+  // one instance: its state is read with the iteration index (one round
+  // trip), so that the launches of a captured schedule past convergence
+  // return at once
+  const int st1 = FUSED && W.S == 1 ? W.st[0].state : (int)ST_ACTIVE;
   j = dev_iter(W, j);
   if (j < 0) return;
   if (!FUSED && jarg == JD_REC1 && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -2011,6 +2015,7 @@ __global__ __launch_bounds__(NT) void k_lz_step_tile(Work W, ShiftWork SW, int j
   // after all items would wait for one of them to finish.
   const int iend = FUSED ? W.S : 0;
   const int nitems = (int)gridDim.x - iend;
+  if (st1 != ST_ACTIVE) return;  // (the end block would return too)
   if (FUSED && (int)blockIdx.x < iend) {
     // the end of iteration j - 1 takes TPB threads; the other waves leave
     // (a barrier waits only for the waves of the block that have not ended)
