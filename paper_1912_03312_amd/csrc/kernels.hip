@@ -916,18 +916,16 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
       T a[AU][PPT];
 #pragma unroll
       for (int r = 0; r < AU; ++r) tile_load<T, PPT>(tile_vec<T>(W, d, t, i + r), t * W.tile, d.n, W.ilv != 0, a[r]);
+      // (slots past n hold zeros in a and w: no guard, so the loop has no branch)
       double2 acc[AU];
 #pragma unroll
       for (int r = 0; r < AU; ++r) {
         acc[r] = make_double2(0.0, 0.0);
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
-          const int p = t * W.tile + tpt<T>(q);
-          if (p < d.n) {
-            const double2 c = cjmul(to_d2(a[r][q]), w[q]);
-            acc[r].x += c.x;
-            acc[r].y += c.y;
-          }
+          const double2 c = cjmul(to_d2(a[r][q]), w[q]);
+          acc[r].x += c.x;
+          acc[r].y += c.y;
         }
       }
 #pragma unroll
@@ -943,13 +941,10 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
       double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
-        const int p = t * W.tile + tpt<T>(q);
-        if (p < d.n) {
-          double2 a = to_d2(av[q]);
-          double2 c = cjmul(a, w[q]);
-          acc.x += c.x;
-          acc.y += c.y;
-        }
+        double2 a = to_d2(av[q]);
+        double2 c = cjmul(a, w[q]);
+        acc.x += c.x;
+        acc.y += c.y;
       }
       acc.x = wave_sum(acc.x);
       acc.y = wave_sum(acc.y);
@@ -1282,17 +1277,15 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second, in
       T a[AU][PPT];
 #pragma unroll
       for (int r = 0; r < AU; ++r) tile_load<T, PPT>(tile_vec<T>(W, d, t, i + r), t * W.tile, d.n, W.ilv != 0, a[r]);
+      // (slots past n hold zeros and are not stored: no guard, no branch)
 #pragma unroll
       for (int r = 0; r < AU; ++r) {
         const double2 c = coef[i + r];
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
-          const int p = t * W.tile + tpt<T>(q);
-          if (p < d.n) {
-            const double2 av = to_d2(a[r][q]);
-            w[q].x -= c.x * av.x - c.y * av.y;
-            w[q].y -= c.x * av.y + c.y * av.x;
-          }
+          const double2 av = to_d2(a[r][q]);
+          w[q].x -= c.x * av.x - c.y * av.y;
+          w[q].y -= c.x * av.y + c.y * av.x;
         }
       }
     }
@@ -1302,12 +1295,9 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second, in
       const double2 c = coef[i];
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
-        const int p = t * W.tile + tpt<T>(q);
-        if (p < d.n) {
-          double2 a = to_d2(av[q]);
-          w[q].x -= c.x * a.x - c.y * a.y;
-          w[q].y -= c.x * a.y + c.y * a.x;
-        }
+        double2 a = to_d2(av[q]);
+        w[q].x -= c.x * a.x - c.y * a.y;
+        w[q].y -= c.x * a.y + c.y * a.x;
       }
     }
     double wn = 0.0;
@@ -2750,17 +2740,15 @@ __global__ __launch_bounds__(TPB) void k_update_x(Work W) {
       T a[AU][PPT];
 #pragma unroll
       for (int r = 0; r < AU; ++r) tile_load<T, PPT>(tile_vec<T>(W, d, t, i + r), t * W.tile, d.n, W.ilv != 0, a[r]);
+      // (slots past n hold zeros and are not stored: no guard, no branch)
 #pragma unroll
       for (int r = 0; r < AU; ++r) {
         const double2 c = coef[i + r];
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
-          const int p = t * W.tile + tpt<T>(q);
-          if (p < d.n) {
-            const double2 av = to_d2(a[r][q]);
-            acc[q].x += c.x * av.x - c.y * av.y;
-            acc[q].y += c.x * av.y + c.y * av.x;
-          }
+          const double2 av = to_d2(a[r][q]);
+          acc[q].x += c.x * av.x - c.y * av.y;
+          acc[q].y += c.x * av.y + c.y * av.x;
         }
       }
     }
@@ -2770,12 +2758,9 @@ __global__ __launch_bounds__(TPB) void k_update_x(Work W) {
       const double2 c = coef[i];
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
-        const int p = t * W.tile + tpt<T>(q);
-        if (p < d.n) {
-          const double2 a = to_d2(av[q]);
-          acc[q].x += c.x * a.x - c.y * a.y;
-          acc[q].y += c.x * a.y + c.y * a.x;
-        }
+        const double2 a = to_d2(av[q]);
+        acc[q].x += c.x * a.x - c.y * a.y;
+        acc[q].y += c.x * a.y + c.y * a.x;
       }
     }
 #pragma unroll
