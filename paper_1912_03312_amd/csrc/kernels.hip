@@ -28,6 +28,8 @@
 // residuals and the pole sum are FP64 for both.
 #include "rexi_internal.h"
 
+#include <type_traits>
+
 namespace rexi {
 
 constexpr int TPB = 256;
@@ -204,15 +206,17 @@ template <typename T> __device__ __forceinline__ int tpt(int q) {
   return sizeof(T) == 8 ? ((q >> 1) * TPB + (int)threadIdx.x) * 2 + (q & 1) : q * TPB + (int)threadIdx.x;
 }
 // Slots of a thread in the tile of vector u (its points p0 + tpt(q)), zero
-// past n. full: the tile's region is allocated to its end (tile-interleaved
-// bases), so a complex64 pair is loaded whole and masked.
-template <typename T, int PPT>
-__device__ __forceinline__ void tile_load(const T* __restrict__ u, int p0, int n, bool full, T (&a)[PPT]) {
+// past n. FULL: the tile's region is allocated to its end (tile-interleaved
+// bases), so a complex64 pair is loaded whole and masked. FULL is a template
+// parameter: a runtime choice put every load in a branch of its own, and the
+// compiler then waited for each load before issuing the next.
+template <typename T, int PPT, bool FULL>
+__device__ __forceinline__ void tile_load(const T* __restrict__ u, int p0, int n, T (&a)[PPT]) {
   if constexpr (sizeof(T) == 8) {
 #pragma unroll
     for (int k = 0; k < PPT / 2; ++k) {
       const int o = tpt<T>(2 * k), p = p0 + o;
-      if (full) {
+      if constexpr (FULL) {
         const float4 v = *reinterpret_cast<const float4*>(u + o);
         a[2 * k] = p < n ? T{v.x, v.y} : T{};
         a[2 * k + 1] = p + 1 < n ? T{v.z, v.w} : T{};
@@ -230,13 +234,13 @@ __device__ __forceinline__ void tile_load(const T* __restrict__ u, int p0, int n
   }
 }
 // Store the slots of a thread to the tile of vector u (points below n only).
-template <typename T, int PPT>
-__device__ __forceinline__ void tile_store(T* __restrict__ u, int p0, int n, bool full, const T (&a)[PPT]) {
+template <typename T, int PPT, bool FULL>
+__device__ __forceinline__ void tile_store(T* __restrict__ u, int p0, int n, const T (&a)[PPT]) {
   if constexpr (sizeof(T) == 8) {
 #pragma unroll
     for (int k = 0; k < PPT / 2; ++k) {
       const int o = tpt<T>(2 * k), p = p0 + o;
-      if (full && p + 1 < n) {
+      if (FULL && p + 1 < n) {
         *reinterpret_cast<float4*>(u + o) = make_float4(a[2 * k].x, a[2 * k].y, a[2 * k + 1].x, a[2 * k + 1].y);
       } else {
         if (p < n) u[o] = a[2 * k];
@@ -846,7 +850,7 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
       if (W.ilv && (!MATVEC || (!d.fem && (d.n2 & 1) == 0 && (d.off & 1) == 0))) {
         paired = true;
         T wv[PPT];
-        if (!MATVEC) tile_load<T, PPT>(unew, t * W.tile, d.n, true, wv);
+        if (!MATVEC) tile_load<T, PPT, true>(unew, t * W.tile, d.n, wv);
 #pragma unroll
         for (int k = 0; k < PPT / 2; ++k) {
           const int o = tpt<T>(2 * k);
@@ -873,7 +877,7 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
           if (p < d.n) wn += w[2 * k].x * w[2 * k].x + w[2 * k].y * w[2 * k].y;
           if (p + 1 < d.n) wn += w[2 * k + 1].x * w[2 * k + 1].x + w[2 * k + 1].y * w[2 * k + 1].y;
         }
-        if (MATVEC || pre) tile_store<T, PPT>(unew, t * W.tile, d.n, true, wv);
+        if (MATVEC || pre) tile_store<T, PPT, true>(unew, t * W.tile, d.n, wv);
       }
     }
 #pragma unroll
@@ -911,11 +915,13 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
     // independent wave reductions; each dot is summed in the same order as
     // one vector at a time
     constexpr int AU = au_vectors<T, PPT>();
+    auto project = [&](auto fullc) {
+    constexpr bool FULL = decltype(fullc)::value;
     int i = lo;
     for (; i + AU <= j + 1; i += AU) {
       T a[AU][PPT];
 #pragma unroll
-      for (int r = 0; r < AU; ++r) tile_load<T, PPT>(tile_vec<T>(W, d, t, i + r), t * W.tile, d.n, W.ilv != 0, a[r]);
+      for (int r = 0; r < AU; ++r) tile_load<T, PPT, FULL>(tile_vec<T>(W, d, t, i + r), t * W.tile, d.n, a[r]);
       // (slots past n hold zeros in a and w: no guard, so the loop has no branch)
       double2 acc[AU];
 #pragma unroll
@@ -937,7 +943,7 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
     }
     for (; i <= j; ++i) {
       T av[PPT];
-      tile_load<T, PPT>(tile_vec<T>(W, d, t, i), t * W.tile, d.n, W.ilv != 0, av);
+      tile_load<T, PPT, FULL>(tile_vec<T>(W, d, t, i), t * W.tile, d.n, av);
       double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
@@ -950,6 +956,9 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
       acc.y = wave_sum(acc.y);
       if (lane == 0) red[wid][i] = acc;
     }
+    };
+    if (W.ilv) project(std::true_type{});
+    else project(std::false_type{});
     wn = wave_sum(wn);
     if (lane == 0) red[wid][MAXM] = make_double2(wn, 0.0);
     __syncthreads();
@@ -1263,10 +1272,13 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second, in
       if (reo && W.reo_any) W.reo_any[j] = 1;
     }
     T* __restrict__ unew = tile_vec<T>(W, d, t, j + 1);
+    double wn = 0.0;
+    auto update = [&](auto fullc) {
+    constexpr bool FULL = decltype(fullc)::value;
     double2 w[PPT];
     {
       T wv[PPT];
-      tile_load<T, PPT>(unew, t * W.tile, d.n, W.ilv != 0, wv);
+      tile_load<T, PPT, FULL>(unew, t * W.tile, d.n, wv);
 #pragma unroll
       for (int q = 0; q < PPT; ++q) w[q] = to_d2(wv[q]);
     }
@@ -1276,7 +1288,7 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second, in
     for (; i + AU <= j + 1; i += AU) {
       T a[AU][PPT];
 #pragma unroll
-      for (int r = 0; r < AU; ++r) tile_load<T, PPT>(tile_vec<T>(W, d, t, i + r), t * W.tile, d.n, W.ilv != 0, a[r]);
+      for (int r = 0; r < AU; ++r) tile_load<T, PPT, FULL>(tile_vec<T>(W, d, t, i + r), t * W.tile, d.n, a[r]);
       // (slots past n hold zeros and are not stored: no guard, no branch)
 #pragma unroll
       for (int r = 0; r < AU; ++r) {
@@ -1291,7 +1303,7 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second, in
     }
     for (; i <= j; ++i) {
       T av[PPT];
-      tile_load<T, PPT>(tile_vec<T>(W, d, t, i), t * W.tile, d.n, W.ilv != 0, av);
+      tile_load<T, PPT, FULL>(tile_vec<T>(W, d, t, i), t * W.tile, d.n, av);
       const double2 c = coef[i];
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
@@ -1300,7 +1312,6 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second, in
         w[q].y -= c.x * a.y + c.y * a.x;
       }
     }
-    double wn = 0.0;
     T wo[PPT];
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
@@ -1311,7 +1322,10 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_b(Work W, int j, int second, in
         wn += vd.x * vd.x + vd.y * vd.y;
       }
     }
-    tile_store<T, PPT>(unew, t * W.tile, d.n, W.ilv != 0, wo);
+    tile_store<T, PPT, FULL>(unew, t * W.tile, d.n, wo);
+    };
+    if (W.ilv) update(std::true_type{});
+    else update(std::false_type{});
     wn = block_sum(wn, lds);
     if (threadIdx.x == 0) W.pnorm[item] = wn;
   }
@@ -2735,11 +2749,13 @@ __global__ __launch_bounds__(TPB) void k_update_x(Work W) {
     }
     // the loads of AU vectors are issued together; the sums keep the order i = 0 .. k - 1
     constexpr int AU = au_vectors<T, PPT>();
+    auto accumulate = [&](auto fullc) {
+    constexpr bool FULL = decltype(fullc)::value;
     int i = 0;
     for (; i + AU <= k; i += AU) {
       T a[AU][PPT];
 #pragma unroll
-      for (int r = 0; r < AU; ++r) tile_load<T, PPT>(tile_vec<T>(W, d, t, i + r), t * W.tile, d.n, W.ilv != 0, a[r]);
+      for (int r = 0; r < AU; ++r) tile_load<T, PPT, FULL>(tile_vec<T>(W, d, t, i + r), t * W.tile, d.n, a[r]);
       // (slots past n hold zeros and are not stored: no guard, no branch)
 #pragma unroll
       for (int r = 0; r < AU; ++r) {
@@ -2754,7 +2770,7 @@ __global__ __launch_bounds__(TPB) void k_update_x(Work W) {
     }
     for (; i < k; ++i) {
       T av[PPT];
-      tile_load<T, PPT>(tile_vec<T>(W, d, t, i), t * W.tile, d.n, W.ilv != 0, av);
+      tile_load<T, PPT, FULL>(tile_vec<T>(W, d, t, i), t * W.tile, d.n, av);
       const double2 c = coef[i];
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
@@ -2763,6 +2779,9 @@ __global__ __launch_bounds__(TPB) void k_update_x(Work W) {
         acc[q].y += c.x * a.y + c.y * a.x;
       }
     }
+    };
+    if (W.ilv) accumulate(std::true_type{});
+    else accumulate(std::false_type{});
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
       const int p = t * W.tile + tpt<T>(q);
