@@ -285,56 +285,80 @@ __device__ __forceinline__ int dev_iter(const Work& W, int j) {
   return (JD_LAUNCH - j) - W.jdev[1];
 }
 
-// (H - s) u at point p, for storage type T, in the arithmetic of T.
-template <typename T>
-__device__ __forceinline__ double2 stencil_point(const T* __restrict__ u, const SysDesc& d,
-                                                 double vp, uint32_t p, BMap mp = BMap{0, 0});
-
-template <>
-__device__ __forceinline__ double2 stencil_point<double2>(const double2* __restrict__ u, const SysDesc& d,
-                                                          double vp, uint32_t p, BMap mp) {
-  const uint32_t r = fdiv(p, d.d2);
-  const uint32_t k = p - r * (uint32_t)d.n2;
-  const uint32_t i0 = fdiv(r, d.d1);
-  const uint32_t j = r - i0 * (uint32_t)d.n1;
-  const uint32_t plane = (uint32_t)d.n1 * (uint32_t)d.n2;
-  const double2 c = u[mp(p)];
-  double2 nb2 = make_double2(0.0, 0.0), nb1 = nb2, nb0 = nb2;
-  if (k > 0) { double2 t = u[mp(p - 1)]; nb2.x += t.x; nb2.y += t.y; }
-  if (k + 1 < (uint32_t)d.n2) { double2 t = u[mp(p + 1)]; nb2.x += t.x; nb2.y += t.y; }
-  if (j > 0) { double2 t = u[mp(p - d.n2)]; nb1.x += t.x; nb1.y += t.y; }
-  if (j + 1 < (uint32_t)d.n1) { double2 t = u[mp(p + d.n2)]; nb1.x += t.x; nb1.y += t.y; }
-  if (i0 > 0) { double2 t = u[mp(p - plane)]; nb0.x += t.x; nb0.y += t.y; }
-  if (i0 + 1 < (uint32_t)d.n0) { double2 t = u[mp(p + plane)]; nb0.x += t.x; nb0.y += t.y; }
-  const double a = d.diag + vp - d.sre;
-  double2 o;
-  o.x = a * c.x + d.sim * c.y - (d.c2 * nb2.x + d.c1 * nb1.x + d.c0 * nb0.x);
-  o.y = a * c.y - d.sim * c.x - (d.c2 * nb2.y + d.c1 * nb1.y + d.c0 * nb0.y);
-  return o;
+// The stencil's geometry and coefficients of a system held in registers (a
+// SysDesc reference into global memory is re-read after every store the
+// compiler cannot prove apart from it, and each re-read waits for the loads
+// in flight).
+struct SGeo {
+  FastDiv d2, d1;
+  int n0, n1, n2;
+  double c0, c1, c2, diag, sre, sim;
+  int64_t off;
+};
+__device__ __forceinline__ SGeo sgeo(const SysDesc& d) {
+  return SGeo{d.d2, d.d1, d.n0, d.n1, d.n2, d.c0, d.c1, d.c2, d.diag, d.sre, d.sim, d.off};
 }
 
-template <>
-__device__ __forceinline__ double2 stencil_point<float2>(const float2* __restrict__ u, const SysDesc& d,
-                                                         double vp, uint32_t p, BMap mp) {
+// (H - s) u at point p, for storage type T, in the arithmetic of T. D is a
+// SysDesc or an SGeo.
+template <typename T, typename D>
+__device__ __forceinline__ double2 stencil_point(const T* __restrict__ u, const D& d, double vp, uint32_t p,
+                                                 BMap mp = BMap{0, 0}) {
   const uint32_t r = fdiv(p, d.d2);
   const uint32_t k = p - r * (uint32_t)d.n2;
   const uint32_t i0 = fdiv(r, d.d1);
   const uint32_t j = r - i0 * (uint32_t)d.n1;
   const uint32_t plane = (uint32_t)d.n1 * (uint32_t)d.n2;
-  const float2 c = u[mp(p)];
-  float2 nb2 = make_float2(0.f, 0.f), nb1 = nb2, nb0 = nb2;
-  if (k > 0) { float2 t = u[mp(p - 1)]; nb2.x += t.x; nb2.y += t.y; }
-  if (k + 1 < (uint32_t)d.n2) { float2 t = u[mp(p + 1)]; nb2.x += t.x; nb2.y += t.y; }
-  if (j > 0) { float2 t = u[mp(p - d.n2)]; nb1.x += t.x; nb1.y += t.y; }
-  if (j + 1 < (uint32_t)d.n1) { float2 t = u[mp(p + d.n2)]; nb1.x += t.x; nb1.y += t.y; }
-  if (i0 > 0) { float2 t = u[mp(p - plane)]; nb0.x += t.x; nb0.y += t.y; }
-  if (i0 + 1 < (uint32_t)d.n0) { float2 t = u[mp(p + plane)]; nb0.x += t.x; nb0.y += t.y; }
-  const float a = (float)(d.diag - d.sre) + (float)vp;
-  const float sim = (float)d.sim;
-  const float c2 = (float)d.c2, c1 = (float)d.c1, c0 = (float)d.c0;
-  float ox = a * c.x + sim * c.y - (c2 * nb2.x + c1 * nb1.x + c0 * nb0.x);
-  float oy = a * c.y - sim * c.x - (c2 * nb2.y + c1 * nb1.y + c0 * nb0.y);
-  return make_double2((double)ox, (double)oy);
+  if constexpr (std::is_same<T, double2>::value) {
+    const double2 c = u[mp(p)];
+    double2 nb2 = make_double2(0.0, 0.0), nb1 = nb2, nb0 = nb2;
+    // every neighbour load is issued (a missing neighbour reads p itself) and
+    // a missing one is added as zero: no branch between the loads
+    const bool hl = k > 0, hr = k + 1 < (uint32_t)d.n2, hd = j > 0, hu = j + 1 < (uint32_t)d.n1;
+    const bool hb = i0 > 0, hf = i0 + 1 < (uint32_t)d.n0;
+    const double2 tl = u[mp(hl ? p - 1 : p)], tr = u[mp(hr ? p + 1 : p)];
+    const double2 td = u[mp(hd ? p - d.n2 : p)], tu = u[mp(hu ? p + d.n2 : p)];
+    const double2 tb = u[mp(hb ? p - plane : p)], tf = u[mp(hf ? p + plane : p)];
+    const double2 z = make_double2(0.0, 0.0);
+    const double2 al = hl ? tl : z, ar = hr ? tr : z, ad = hd ? td : z, au = hu ? tu : z, ab = hb ? tb : z,
+              af = hf ? tf : z;
+    nb2.x += al.x; nb2.y += al.y;
+    nb2.x += ar.x; nb2.y += ar.y;
+    nb1.x += ad.x; nb1.y += ad.y;
+    nb1.x += au.x; nb1.y += au.y;
+    nb0.x += ab.x; nb0.y += ab.y;
+    nb0.x += af.x; nb0.y += af.y;
+    const double a = d.diag + vp - d.sre;
+    double2 o;
+    o.x = a * c.x + d.sim * c.y - (d.c2 * nb2.x + d.c1 * nb1.x + d.c0 * nb0.x);
+    o.y = a * c.y - d.sim * c.x - (d.c2 * nb2.y + d.c1 * nb1.y + d.c0 * nb0.y);
+    return o;
+  } else {
+    const float2 c = u[mp(p)];
+    float2 nb2 = make_float2(0.f, 0.f), nb1 = nb2, nb0 = nb2;
+    // every neighbour load is issued (a missing neighbour reads p itself) and
+    // a missing one is added as zero: no branch between the loads
+    const bool hl = k > 0, hr = k + 1 < (uint32_t)d.n2, hd = j > 0, hu = j + 1 < (uint32_t)d.n1;
+    const bool hb = i0 > 0, hf = i0 + 1 < (uint32_t)d.n0;
+    const float2 tl = u[mp(hl ? p - 1 : p)], tr = u[mp(hr ? p + 1 : p)];
+    const float2 td = u[mp(hd ? p - d.n2 : p)], tu = u[mp(hu ? p + d.n2 : p)];
+    const float2 tb = u[mp(hb ? p - plane : p)], tf = u[mp(hf ? p + plane : p)];
+    const float2 z = make_float2(0.f, 0.f);
+    const float2 al = hl ? tl : z, ar = hr ? tr : z, ad = hd ? td : z, au = hu ? tu : z, ab = hb ? tb : z,
+              af = hf ? tf : z;
+    nb2.x += al.x; nb2.y += al.y;
+    nb2.x += ar.x; nb2.y += ar.y;
+    nb1.x += ad.x; nb1.y += ad.y;
+    nb1.x += au.x; nb1.y += au.y;
+    nb0.x += ab.x; nb0.y += ab.y;
+    nb0.x += af.x; nb0.y += af.y;
+    const float a = (float)(d.diag - d.sre) + (float)vp;
+    const float sim = (float)d.sim;
+    const float c2 = (float)d.c2, c1 = (float)d.c1, c0 = (float)d.c0;
+    float ox = a * c.x + sim * c.y - (c2 * nb2.x + c1 * nb1.x + c0 * nb0.x);
+    float oy = a * c.y - sim * c.x - (c2 * nb2.y + c1 * nb1.y + c0 * nb0.y);
+    return make_double2((double)ox, (double)oy);
+  }
 }
 
 // (H - s) u at the adjacent points p and p + 1 of a complex64 vector of a
@@ -342,7 +366,7 @@ __device__ __forceinline__ double2 stencil_point<float2>(const float2* __restric
 // one tile, and every pair below is one aligned 16-byte load). Each point's
 // arithmetic is stencil_point<float2>'s, term by term.
 __device__ __forceinline__ void stencil_pair_c64(const float2* __restrict__ u, const float* __restrict__ V,
-                                                 const SysDesc& d, uint32_t p, BMap mp, double2& o0,
+                                                 const SGeo& d, uint32_t p, BMap mp, double2& o0,
                                                  double2& o1) {
   const uint32_t r = fdiv(p, d.d2);
   const uint32_t k = p - r * (uint32_t)d.n2;
@@ -352,12 +376,15 @@ __device__ __forceinline__ void stencil_pair_c64(const float2* __restrict__ u, c
   const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
   auto pair = [&](uint32_t q) { return *reinterpret_cast<const float4*>(u + mp(q)); };
   const float4 c = pair(p);
-  const float2 l = k > 0 ? u[mp(p - 1)] : make_float2(0.f, 0.f);
-  const bool hr = k + 2 < (uint32_t)d.n2;
-  const float2 rr = hr ? u[mp(p + 2)] : make_float2(0.f, 0.f);
+  // every load is issued (a missing neighbour reads p itself) and masked:
+  // no branch between the loads
+  const bool hl = k > 0, hr = k + 2 < (uint32_t)d.n2;
   const bool hd = jr > 0, hu = jr + 1 < (uint32_t)d.n1, hb = i0 > 0, hf = i0 + 1 < (uint32_t)d.n0;
-  const float4 dn = hd ? pair(p - d.n2) : z4, up = hu ? pair(p + d.n2) : z4;
-  const float4 bk = hb ? pair(p - plane) : z4, fr = hf ? pair(p + plane) : z4;
+  const float2 l0 = u[mp(hl ? p - 1 : p)], r0 = u[mp(hr ? p + 2 : p)];
+  const float4 dn0 = pair(hd ? p - d.n2 : p), up0 = pair(hu ? p + d.n2 : p);
+  const float4 bk0 = pair(hb ? p - plane : p), fr0 = pair(hf ? p + plane : p);
+  const float2 l = hl ? l0 : make_float2(0.f, 0.f), rr = hr ? r0 : make_float2(0.f, 0.f);
+  const float4 dn = hd ? dn0 : z4, up = hu ? up0 : z4, bk = hb ? bk0 : z4, fr = hf ? fr0 : z4;
   const float2 vv = *reinterpret_cast<const float2*>(V + d.off + p);
   const float sim = (float)d.sim;
   const float c2 = (float)d.c2, c1 = (float)d.c1, c0 = (float)d.c0;
@@ -398,12 +425,21 @@ __device__ __forceinline__ double2 stencil_point_f64(const double2* __restrict__
   const uint32_t plane = (uint32_t)n1 * (uint32_t)n2;
   const double2 c = u[p];
   double2 nb2 = make_double2(0.0, 0.0), nb1 = nb2, nb0 = nb2;
-  if (k > 0) { double2 t = u[p - 1]; nb2.x += t.x; nb2.y += t.y; }
-  if (k + 1 < (uint32_t)n2) { double2 t = u[p + 1]; nb2.x += t.x; nb2.y += t.y; }
-  if (j > 0) { double2 t = u[p - n2]; nb1.x += t.x; nb1.y += t.y; }
-  if (j + 1 < (uint32_t)n1) { double2 t = u[p + n2]; nb1.x += t.x; nb1.y += t.y; }
-  if (i0 > 0) { double2 t = u[p - plane]; nb0.x += t.x; nb0.y += t.y; }
-  if (i0 + 1 < (uint32_t)n0) { double2 t = u[p + plane]; nb0.x += t.x; nb0.y += t.y; }
+  // every neighbour load is issued (a missing neighbour reads p itself) and a
+  // missing one is added as zero: no branch between the loads
+  const bool hl = k > 0, hr = k + 1 < (uint32_t)n2, hd = j > 0, hu = j + 1 < (uint32_t)n1;
+  const bool hb = i0 > 0, hf = i0 + 1 < (uint32_t)n0;
+  const double2 tl = u[hl ? p - 1 : p], tr = u[hr ? p + 1 : p], td = u[hd ? p - n2 : p], tu = u[hu ? p + n2 : p];
+  const double2 tb = u[hb ? p - plane : p], tf = u[hf ? p + plane : p];
+  const double2 z = make_double2(0.0, 0.0);
+  const double2 al = hl ? tl : z, ar = hr ? tr : z, ad = hd ? td : z, au = hu ? tu : z, ab = hb ? tb : z,
+                af = hf ? tf : z;
+  nb2.x += al.x; nb2.y += al.y;
+  nb2.x += ar.x; nb2.y += ar.y;
+  nb1.x += ad.x; nb1.y += ad.y;
+  nb1.x += au.x; nb1.y += au.y;
+  nb0.x += ab.x; nb0.y += ab.y;
+  nb0.x += af.x; nb0.y += af.y;
   const double a = diag + vp - sre;
   double2 o;
   o.x = a * c.x + sim * c.y - (c2 * nb2.x + c1 * nb1.x + c0 * nb0.x);
@@ -841,6 +877,8 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
     const int t = item - d.tile0;
     const double cj = W.cscale[(int64_t)s * (W.m + 1) + j];
     T* __restrict__ unew = tile_vec<T>(W, d, t, j + 1);
+    const SGeo g = sgeo(d);
+    const int dn = d.n;
     double2 w[PPT];
     double wn = 0.0;
     // complex64 in a tile-interleaved basis: point pairs with 16-byte accesses
@@ -850,15 +888,17 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
       if (W.ilv && (!MATVEC || (!d.fem && (d.n2 & 1) == 0 && (d.off & 1) == 0))) {
         paired = true;
         T wv[PPT];
-        if (!MATVEC) tile_load<T, PPT, true>(unew, t * W.tile, d.n, wv);
+        if (!MATVEC) tile_load<T, PPT, true>(unew, t * W.tile, dn, wv);
 #pragma unroll
         for (int k = 0; k < PPT / 2; ++k) {
           const int o = tpt<T>(2 * k);
           const int p = t * W.tile + o;
           double2 v0 = make_double2(0.0, 0.0), v1 = v0;
           if (MATVEC) {
-            if (p < d.n) stencil_pair_c64(reinterpret_cast<const float2*>(map_vec<T>(W, d, j)), W.V32, d,
-                                          (uint32_t)p, bmap(W), v0, v1);
+            // (a pair past n computes point 0's stencil and is masked: no branch)
+            stencil_pair_c64(reinterpret_cast<const float2*>(map_vec<T>(W, d, j)), W.V32, g,
+                             (uint32_t)(p < dn ? p : 0), bmap(W), v0, v1);
+            if (p >= dn) v0 = v1 = make_double2(0.0, 0.0);
           } else {
             v0 = to_d2(wv[2 * k]);
             v1 = to_d2(wv[2 * k + 1]);
@@ -872,12 +912,12 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
           wv[2 * k] = from_d2<T>(v0);
           wv[2 * k + 1] = from_d2<T>(v1);
           // (n even here when MATVEC; otherwise the second point may be past n)
-          w[2 * k] = p < d.n ? to_d2(wv[2 * k]) : make_double2(0.0, 0.0);
-          w[2 * k + 1] = p + 1 < d.n ? to_d2(wv[2 * k + 1]) : make_double2(0.0, 0.0);
-          if (p < d.n) wn += w[2 * k].x * w[2 * k].x + w[2 * k].y * w[2 * k].y;
-          if (p + 1 < d.n) wn += w[2 * k + 1].x * w[2 * k + 1].x + w[2 * k + 1].y * w[2 * k + 1].y;
+          w[2 * k] = p < dn ? to_d2(wv[2 * k]) : make_double2(0.0, 0.0);
+          w[2 * k + 1] = p + 1 < dn ? to_d2(wv[2 * k + 1]) : make_double2(0.0, 0.0);
+          if (p < dn) wn += w[2 * k].x * w[2 * k].x + w[2 * k].y * w[2 * k].y;
+          if (p + 1 < dn) wn += w[2 * k + 1].x * w[2 * k + 1].x + w[2 * k + 1].y * w[2 * k + 1].y;
         }
-        if (MATVEC || pre) tile_store<T, PPT, true>(unew, t * W.tile, d.n, wv);
+        if (MATVEC || pre) tile_store<T, PPT, true>(unew, t * W.tile, dn, wv);
       }
     }
 #pragma unroll
@@ -885,12 +925,12 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
       const int o = tpt<T>(q);  // the point within the tile
       const int p = t * W.tile + o;
       w[q] = make_double2(0.0, 0.0);
-      if (p < d.n) {
+      if (p < dn) {
         if (MATVEC) {
           // (Q1 elements keep the plain layout: W.ilv = 0)
           double2 v = d.fem ? fem_point<T>(basis_vec<T>(W, d, j), d.n0, d.n1, d.n2, d.d2, d.d1, d.fmd, d.fmo,
                                            d.fkd, d.fko, d.fvol, vpot<T>(W, d.off + p), d.sre, d.sim, (uint32_t)p)
-                            : stencil_point<T>(map_vec<T>(W, d, j), d, vpot<T>(W, d.off + p), (uint32_t)p, bmap(W));
+                            : stencil_point<T>(map_vec<T>(W, d, j), g, vpot<T>(W, g.off + p), (uint32_t)p, bmap(W));
           v.x *= cj;
           v.y *= cj;
           T vs = from_d2<T>(v);
@@ -921,7 +961,7 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
     for (; i + AU <= j + 1; i += AU) {
       T a[AU][PPT];
 #pragma unroll
-      for (int r = 0; r < AU; ++r) tile_load<T, PPT, FULL>(tile_vec<T>(W, d, t, i + r), t * W.tile, d.n, a[r]);
+      for (int r = 0; r < AU; ++r) tile_load<T, PPT, FULL>(tile_vec<T>(W, d, t, i + r), t * W.tile, dn, a[r]);
       // (slots past n hold zeros in a and w: no guard, so the loop has no branch)
       double2 acc[AU];
 #pragma unroll
@@ -943,7 +983,7 @@ __global__ __launch_bounds__(TPB) void k_arnoldi_a(Work W, int j, int i0, int pr
     }
     for (; i <= j; ++i) {
       T av[PPT];
-      tile_load<T, PPT, FULL>(tile_vec<T>(W, d, t, i), t * W.tile, d.n, av);
+      tile_load<T, PPT, FULL>(tile_vec<T>(W, d, t, i), t * W.tile, dn, av);
       double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
       for (int q = 0; q < PPT; ++q) {
