@@ -2844,16 +2844,18 @@ __global__ __launch_bounds__(TPB) void k_residual(Work W, const double2* __restr
     const double2* __restrict__ b = (d.rhs_sel ? rhs1 : rhs0) + d.off;
     const double2* __restrict__ x = reinterpret_cast<const double2*>(W.x) + d.xoff;
     T* __restrict__ u0 = tile_vec<T>(W, d, t, 0);
+    const SGeo g = sgeo(d);  // (in registers: d would be re-read after each store)
+    const int dn = d.n, fem = d.fem;
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < PPT; ++q) {
       const int p = t * W.tile + q * TPB + threadIdx.x;
-      if (p < d.n) {
+      if (p < dn) {
         const double2 hx =
-            d.fem ? fem_point<double2>(x, d.n0, d.n1, d.n2, d.d2, d.d1, d.fmd, d.fmo, d.fkd, d.fko, d.fvol,
-                                       W.V64[d.off + p], d.sre, d.sim, (uint32_t)p)
-                  : stencil_point_f64(x, d.n0, d.n1, d.n2, d.d2, d.d1, d.c0, d.c1, d.c2, d.diag, W.V64[d.off + p],
-                                      d.sre, d.sim, (uint32_t)p);
+            fem ? fem_point<double2>(x, d.n0, d.n1, d.n2, d.d2, d.d1, d.fmd, d.fmo, d.fkd, d.fko, d.fvol,
+                                     W.V64[g.off + p], d.sre, d.sim, (uint32_t)p)
+                : stencil_point_f64(x, g.n0, g.n1, g.n2, g.d2, g.d1, g.c0, g.c1, g.c2, g.diag, W.V64[g.off + p],
+                                    g.sre, g.sim, (uint32_t)p);
         const double2 bp = b[p];
         const double2 r = make_double2(bp.x - hx.x, bp.y - hx.y);
         u0[q * TPB + threadIdx.x] = from_d2<T>(r);
