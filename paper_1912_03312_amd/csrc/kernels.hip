@@ -2028,8 +2028,67 @@ __device__ __forceinline__ void col_parts_reduce(const ColParts& q, const Work& 
   }
 }
 
+// The fields of a system's descriptor that the tiled pass reads, in registers.
+struct TileSys {
+  int32_t n, n0, n1, n2, col_cs, pbase, col_n, col_nr, col_L;
+  int64_t off, basis;
+  double c0, c1, c2, diag;
+};
+__device__ __forceinline__ TileSys tile_sys(const SysDesc& d) {
+  return TileSys{d.n, d.n0, d.n1, d.n2, d.col_cs, d.pbase, d.col_n, d.col_nr, d.col_L,
+                 d.off, d.basis, d.c0, d.c1, d.c2, d.diag};
+}
+// The same fields of the first system read with vector memory loads: their
+// waits are counted in order with the other vector loads (a scalar load is
+// waited for together with every scalar load in flight, the kernel arguments
+// included), so they go out at the start of a launch with the state and the
+// pause mark and are waited for where they are used: one round trip before
+// the first loads of an item.
+__device__ __forceinline__ uint32_t zt_ld4(const void* p) {
+  return __builtin_amdgcn_raw_buffer_load_b32(zt_rsrc(p, 4u), 0, 0, 0);
+}
+__device__ __forceinline__ zt_u32x4 zt_ld16(const void* p) {
+  return __builtin_amdgcn_raw_buffer_load_b128(zt_rsrc(p, 16u), 0, 0, 0);
+}
+struct SysChunks {
+  zt_u32x4 a, b, c, d, e, f;  // (off, basis), (n, n0, n1, n2), (c0, c1), (c2, diag), (pbase, .., col_L, col_nr),
+                              // (col_n, col_cs, ..)
+};
+static_assert(offsetof(SysDesc, basis) == offsetof(SysDesc, off) + 8, "SysDesc layout");
+static_assert(offsetof(SysDesc, n0) == offsetof(SysDesc, n) + 4 && offsetof(SysDesc, n1) == offsetof(SysDesc, n) + 8 &&
+                  offsetof(SysDesc, n2) == offsetof(SysDesc, n) + 12, "SysDesc layout");
+static_assert(offsetof(SysDesc, c1) == offsetof(SysDesc, c0) + 8 && offsetof(SysDesc, diag) == offsetof(SysDesc, c2) + 8,
+              "SysDesc layout");
+static_assert(offsetof(SysDesc, col_L) == offsetof(SysDesc, pbase) + 8 &&
+                  offsetof(SysDesc, col_nr) == offsetof(SysDesc, pbase) + 12 &&
+                  offsetof(SysDesc, col_cs) == offsetof(SysDesc, col_n) + 4 &&
+                  offsetof(SysDesc, col_n) + 16 <= sizeof(SysDesc),
+              "SysDesc layout");
+__device__ __forceinline__ SysChunks sys_chunks(const SysDesc* d) {
+  const char* b = reinterpret_cast<const char*>(d);
+  return SysChunks{zt_ld16(b + offsetof(SysDesc, off)), zt_ld16(b + offsetof(SysDesc, n)),
+                   zt_ld16(b + offsetof(SysDesc, c0)), zt_ld16(b + offsetof(SysDesc, c2)),
+                   zt_ld16(b + offsetof(SysDesc, pbase)), zt_ld16(b + offsetof(SysDesc, col_n))};
+}
+__device__ __forceinline__ uint32_t zt_rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t zt_rfl64(uint32_t lo, uint32_t hi) {
+  return (uint64_t)zt_rfl(hi) << 32 | zt_rfl(lo);
+}
+__device__ __forceinline__ TileSys tile_sys(const SysChunks& c) {
+  return TileSys{(int32_t)zt_rfl(c.b[0]), (int32_t)zt_rfl(c.b[1]), (int32_t)zt_rfl(c.b[2]), (int32_t)zt_rfl(c.b[3]),
+                 (int32_t)zt_rfl(c.f[1]), (int32_t)zt_rfl(c.e[0]), (int32_t)zt_rfl(c.f[0]), (int32_t)zt_rfl(c.e[3]),
+                 (int32_t)zt_rfl(c.e[2]), (int64_t)zt_rfl64(c.a[0], c.a[1]), (int64_t)zt_rfl64(c.a[2], c.a[3]),
+                 __builtin_bit_cast(double, zt_rfl64(c.c[0], c.c[1])),
+                 __builtin_bit_cast(double, zt_rfl64(c.c[2], c.c[3])),
+                 __builtin_bit_cast(double, zt_rfl64(c.d[0], c.d[1])),
+                 __builtin_bit_cast(double, zt_rfl64(c.d[2], c.d[3]))};
+}
+
+// At most 128 registers a lane (four waves per SIMD): a block that ends the
+// previous iteration then shares a compute unit with an item (at 128^3, 257
+// blocks on 256 units); with 150 registers one item waited until it had ended.
 template <int TR, int TC, int NT, bool FUSED>
-__global__ __launch_bounds__(NT) void k_lz_step_tile(Work W, ShiftWork SW, int j) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_lz_step_tile(Work W, ShiftWork SW, int j) {
   constexpr int KH = ZTile<TR, TC, NT>::KH;
   constexpr int ZT_W = ZTile<TR, TC, NT>::W;
   constexpr int ZT_N = ZTile<TR, TC, NT>::N;
@@ -2041,10 +2100,14 @@ __global__ __launch_bounds__(NT) void k_lz_step_tile(Work W, ShiftWork SW, int j
   __shared__ double2 wb[2][KH * NT];
   const int m = W.m;
   const int jarg = j;
-  // one instance: its state is read with the iteration index (one round
-  // trip), so that the launches of a captured schedule past convergence
-  // return at once
-  const int st1 = FUSED && W.S == 1 ? W.st[0].state : (int)ST_ACTIVE;
+  // one instance: its state, the pause mark and the fields of its descriptor
+  // are loaded together at the start (one round trip before the item's first
+  // loads; the launches of a captured schedule past convergence still return
+  // after it)
+  const bool S1 = W.S == 1;
+  const uint32_t st0v = zt_ld4(&W.st[0].state);
+  const uint32_t gpv = zt_ld4(SW.gpause);
+  const SysChunks c0v = sys_chunks(W.sys);
   j = dev_iter(W, j);
   if (j < 0) return;
   if (!FUSED && jarg == JD_REC1 && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -2059,7 +2122,7 @@ __global__ __launch_bounds__(NT) void k_lz_step_tile(Work W, ShiftWork SW, int j
   // after all items would wait for one of them to finish.
   const int iend = FUSED ? W.S : 0;
   const int nitems = (int)gridDim.x - iend;
-  if (st1 != ST_ACTIVE) return;  // (the end block would return too)
+  if (S1 && (int)__builtin_amdgcn_readfirstlane(st0v) != (int)ST_ACTIVE) return;  // (the end block would return too)
   if (FUSED && (int)blockIdx.x < iend) {
     // the end of iteration j - 1 takes TPB threads; the other waves leave
     // (a barrier waits only for the waves of the block that have not ended)
@@ -2068,21 +2131,29 @@ __global__ __launch_bounds__(NT) void k_lz_step_tile(Work W, ShiftWork SW, int j
     return;
   }
   if (FUSED && j >= m) return;
-  if (paused_before(SW, j)) return;
+  if (SW.pause_mode) {  // the solve paused at an earlier iteration
+    const int gp = (int)__builtin_amdgcn_readfirstlane(gpv);
+    if (gp >= 0 && gp < j) return;
+  }
+  const TileSys g0 = tile_sys(c0v);  // (scalar registers from here on)
   for (int item = (int)blockIdx.x - iend; item < SW.col_total; item += nitems) {
-    const int s = __builtin_amdgcn_readfirstlane(SW.col_sys ? SW.col_sys[item] : find_sys(SW.col_start, W.S, item));
-    if (W.st[s].state != ST_ACTIVE) continue;
-    const SysDesc& dref = W.sys[s];
-    const int n0 = dref.n0, n1 = dref.n1, n2 = dref.n2;
-    const double c0 = dref.c0, c1 = dref.c1, c2 = dref.c2, diag = dref.diag;
-    const int cs = dref.col_cs, pbase = dref.pbase;
-    const int np = __builtin_amdgcn_readfirstlane(dref.col_n);
+    int s = 0, t = item;
+    TileSys g = g0;
+    if (!S1) {
+      s = __builtin_amdgcn_readfirstlane(SW.col_sys ? SW.col_sys[item] : find_sys(SW.col_start, W.S, item));
+      if (W.st[s].state != ST_ACTIVE) continue;
+      g = tile_sys(W.sys[s]);
+      t = item - SW.col_start[s];
+    }
+    const int n0 = g.n0, n1 = g.n1, n2 = g.n2;
+    const double c0 = g.c0, c1 = g.c1, c2 = g.c2, diag = g.diag;
+    const int cs = g.col_cs, pbase = g.pbase;
+    const int np = __builtin_amdgcn_readfirstlane(g.col_n);
     ColParts cq{};
     if (FUSED && NT != TPB) cq = col_parts_load(W, pbase, cs, np, j - 1);
-    const int col_nr = dref.col_nr, col_L = dref.col_L;
-    const int64_t voff = dref.off, bas = dref.basis;
-    const int npts = dref.n;
-    const int t = item - SW.col_start[s];
+    const int col_nr = g.col_nr, col_L = g.col_L;
+    const int64_t voff = g.off, bas = g.basis;
+    const int npts = g.n;
     const int tile = t / col_nr;
     const int rng = t - tile * col_nr;
     const int ntc = (n2 + TC - 1) / TC;
