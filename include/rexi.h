@@ -127,14 +127,16 @@ typedef struct {
                           at most 256. For the shared-basis solver the
                           largest basis of one cycle (poles that need more
                           restart on a new shared basis, option fallback)   */
-  int32_t max_cycles;  /* restarts / refinement sweeps per solve, 20         */
+  int32_t max_cycles;  /* restarts / refinement sweeps per solve, 40         */
   double tol;          /* see tol_policy, default 1e-10                      */
   int32_t tol_policy;  /* rexi_tol_policy, default REXI_TOL_RELRES           */
   int32_t reorth;      /* 0 classical Gram-Schmidt, 1 DGKS when cancellation
                           is detected (default), 2 always twice              */
   double reorth_eta;   /* DGKS threshold: a second pass when the projected
                           vector keeps less than eta of its norm, 1e-2       */
-  double inner_rtol;   /* C64_REFINE: residual reduction per sweep, 1e-5     */
+  double inner_rtol;   /* C64_REFINE: a complex64 sweep stops when it has
+                          reduced its FP64 starting residual by this factor
+                          (or met the pole's target), 0.1                   */
   int32_t check_every; /* shared-basis solver: iterations between host reads
                           of the convergence flag, default 4                 */
   int32_t lanczos;     /* shared-basis solver: H is Hermitian, so the basis
@@ -156,8 +158,9 @@ typedef struct {
                           2) takes one launch per iteration, with room for
                           capture_pauses second Gram-Schmidt passes        */
   int32_t capture_cycles; /* capture_safe: cycles of a captured solve, the
-                          first included: per-pole solver 4, shared basis
-                          1 (no restarts) when 0 (the default); shared basis
+                          first included: per-pole solver 4 (C64_REFINE:
+                          16), shared basis 1 (no restarts) when 0 (the
+                          default); shared basis
                           with fallback 1: capture_cycles - 1 restart cycles
                           on the shared basis                               */
   int32_t graph_chunks;   /* shared-basis solver: replay cached HIP graphs of

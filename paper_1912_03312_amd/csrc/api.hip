@@ -571,7 +571,7 @@ rexi_status run_cycles(rexi_handle* h, Solver& sv, const double2* r0, const doub
     }
     HIPCHK(h, hipGetLastError());
     if (h->syncfree) {
-      if (c + 1 >= (h->opt.capture_cycles > 0 ? h->opt.capture_cycles : 4)) break;
+      if (c + 1 >= (h->opt.capture_cycles > 0 ? h->opt.capture_cycles : sv.prec ? 16 : 4)) break;
       continue;
     }
     // restarted count of this cycle: counters[max_cycles*(m+1)] accumulates; read the total
@@ -2575,12 +2575,12 @@ void rexi_default_options(rexi_options* o) {
   o->precision = REXI_PREC_C128;
   o->solver = REXI_SOLVER_PER_POLE;
   o->m = 30;
-  o->max_cycles = 20;
+  o->max_cycles = 40;
   o->tol = 1e-10;
   o->tol_policy = REXI_TOL_RELRES;
   o->reorth = 1;
   o->reorth_eta = 1e-2;
-  o->inner_rtol = 1e-5;
+  o->inner_rtol = 0.1;
   o->check_every = 4;
   o->lanczos = 1;
   o->capture_cycles = 0;

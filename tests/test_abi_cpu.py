@@ -43,7 +43,7 @@ def test_status_strings_and_defaults(rx):
     assert rx.status_string(0) == "REXI_OK"
     assert rx.status_string(4) == "REXI_E_NOT_CONVERGED"
     o = rx.default_options()
-    assert o.m == 30 and o.max_cycles == 20 and o.tol == 1e-10 and o.reorth == 1
+    assert o.m == 30 and o.max_cycles == 40 and o.tol == 1e-10 and o.reorth == 1 and o.inner_rtol == 0.1
     assert o.precision == rx.PREC_C128 and o.solver == rx.SOLVER_PER_POLE
 
 

@@ -439,10 +439,13 @@ def test_graph_replays_match_eager(rexi, solver, prec):
     Vd = to_dev(wl.V.ravel())
     kw = dict(solver=solver, precision=prec, tol=1e-10, m=100 if solver == "shifted" else 30)
     he = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, wl.dt, s, b, **kw)
-    hg = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, wl.dt, s, b, capture_safe=1, capture_cycles=6, **kw)
     p0 = to_dev(wl.psi0.ravel())
     ref = torch.empty_like(p0)
-    he.step(p0, ref, 1)
+    ie = he.step(p0, ref, 1)
+    # the captured schedule runs a fixed number of cycles: two more than the
+    # eager solve needed
+    hg = r.setup(g.n, g.lo, g.hi, Vd, 1.0, 1.0, wl.dt, s, b, capture_safe=1,
+                 capture_cycles=ie["max_cycles_used"] + 2, **kw)
     out = torch.empty_like(p0)
     for rep in range(4):
         out.zero_()
