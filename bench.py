@@ -72,8 +72,13 @@ def load_traffic(kernel: str, precision: str, tiling=None):
     ent = d.get("kernels", {}).get(f"{kernel}:{precision}")
     if ent is None:
         return None
-    if tiling is not None and ent.get("tiling", d.get("tiling")) != tiling:
-        return None
+    if tiling is not None:
+        # the fused pass's own plan decides its bytes (the grid-stride tiling of
+        # the other kernels does not)
+        keys = ("march_slots", "march_planes", "march_items")
+        prof = ent.get("tiling", d.get("tiling")) or {}
+        if any(prof.get(k) != tiling.get(k) for k in keys):
+            return None
     return ent.get("hbm_bytes_per_launch")
 
 
