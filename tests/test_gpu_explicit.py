@@ -302,6 +302,67 @@ def test_bench_configuration_full_scale_against_oracle(rexi):
     h.close()
 
 
+@pytest.mark.timeout(400)
+def test_mixed_precision_full_scale_against_oracle(rexi):
+    # the per-pole complex64 + FP64 refinement form (default inner tolerance)
+    # on the benchmarked 128^3 workload at the certified policy: the CPU
+    # certificate of its pole solutions bounds its distance to the exact
+    # step, and sampled poles are compared element by element with the
+    # oracle's FP64 GMRES solves
+    import time
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+    from threadpoolctl import threadpool_limits
+    wl = inputs.workload("3d_bumps")
+    g = wl.grid
+    s, b = poles(wl.K, wl.R1)
+    h = rexi.setup(g.n, g.lo, g.hi, to_dev(wl.V.ravel()), 1.0, 1.0, wl.dt, s, b, precision="c64", m=30,
+                   tol=1e-10, tol_policy="certified", max_cycles=200)
+    p0 = to_dev(wl.psi0.ravel())
+    out = torch.empty_like(p0)
+    info = h.step(p0, out, 1)
+    torch.cuda.synchronize()
+    og = out.cpu().numpy()
+    cert, comb, mism, slack, amp = cpu_certificate(h, g, wl.V, wl.psi0, s, b, wl.dt, og, info)
+    sj, wj = ost.shifts_and_weights(s, b, wl.dt)
+    floor = _floor_iter(g, wl.V, sj, wj)
+    bar = max(1e-10, 3 * floor)
+    print(f"mixed 128^3: its {info['total_iterations']}, cycles {info['max_cycles_used']}, library bound "
+          f"{info['certified_bound']:.3e}, CPU certificate {cert:.3e} + combination {comb:.3e}, bar {bar:.3e}",
+          flush=True)
+    assert info["explicit_residuals"] and info["not_converged"] == 0
+    assert all(gap <= tol for gap, tol in mism), max(mism)
+    assert cert + comb <= bar
+    lo, hi = ham.gershgorin(g.n, g.h, wl.V)
+    dist = _dist(sj, lo, hi)
+    weight = np.abs(wj) / dist
+    order = [int(j) for j in np.argsort(-weight)]
+    sample = sorted({order[0], order[len(order) // 2], order[-1]})
+    H = ham.hamiltonian(g.n, g.h, wl.V).astype(np.complex128)
+    psi = wl.psi0.ravel().astype(np.complex128)
+
+    def solve(j):
+        tol = max(1e-14, 4 * EPS * (1.0 + (hi + abs(sj[j])) / dist[j]))
+        return okr.gmres(lambda x: H @ x - sj[j] * x, psi, tol, 60)
+
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        with ThreadPoolExecutor(max_workers=min(len(sample), okr.host_threads())) as ex:
+            ref = dict(zip(sample, ex.map(solve, sample)))
+    xd = torch.empty_like(p0)
+    for j in sample:
+        h.solution(int(j), xd)
+        torch.cuda.synchronize()
+        xo, its, rho_o = ref[j]
+        e = rel(xd.cpu().numpy(), xo)
+        bnd = (info["rel_residual"][j] + rho_o) * np.linalg.norm(psi) / dist[j] / np.linalg.norm(xo)
+        print(f"pole {j}: |w|/dist {weight[j]:.2e}, rel diff {e:.2e}, bound {bnd:.2e}", flush=True)
+        assert e <= bnd * (1 + 1e-6) + 1e-13
+    print(f"oracle solves of {len(sample)} poles: {time.perf_counter() - t0:.1f} s", flush=True)
+    h.close()
+
+
 @pytest.mark.timeout(300)
 def test_double_well_full_size_against_exact_separable_step(rexi):
     # the 512^2 double well (its potential is separable, so the oracle's
