@@ -4,7 +4,7 @@ Every test calls the library through its C ABI (ctypes binding) and
 compares, element by element, with the oracle on the same seeded inputs.
 Bars: FP64 path relative L2 error <= max(1e-10, 10 F) with F the oracle's
 own two-method floor (direct solve vs eigendecomposition) measured in the
-test; complex64 + FP64 refinement <= 1e-6; the stencil to FP64 roundoff.
+test; complex64 + FP64 refinement within its certified bound; the stencil to FP64 roundoff.
 """
 import numpy as np
 import pytest
@@ -153,8 +153,14 @@ def test_step_mixed_precision(rexi, name, scale):
     out, infos = gpu_steps(g, wl.V, wl.psi0, s, b, wl.dt, 2, precision="c64", tol=1e-8, tol_policy="certified",
                            max_cycles=200)
     errs = [rel(o, r) for o, r in zip(out, ref)]
-    print("mixed errs", name, errs, [i["max_cycles_used"] for i in infos])
-    assert max(errs) <= 1e-6
+    # FP64 refinement: each step within its certified bound of the exact one
+    # (the REXI step nearly preserves the norm, so the first step's error
+    # carries over into the second) plus the FP64 floor of the residuals
+    fl = 3 * iterative_floor(g, wl.V, s, b, wl.dt)
+    bars = [1.01 * infos[0]["certified_bound"] + fl,
+            1.01 * (infos[0]["certified_bound"] + infos[1]["certified_bound"]) + 2 * fl]
+    print("mixed errs", name, errs, bars, [i["max_cycles_used"] for i in infos])
+    assert all(e <= bar for e, bar in zip(errs, bars)), (errs, bars)
     assert infos[0]["certified_bound"] <= 1.01e-8
 
 
@@ -174,7 +180,7 @@ def test_full_size_3d_separable(rexi):
     out64, infos64 = gpu_steps(g, V, psi0, s, b, 1.0, 1, tol=1e-12, tol_policy="certified")
     e64 = rel(out64[0], ref)
     print("full 3d separable: mixed", e_mixed, "fp64", e64, infos[0]["total_iterations"], infos64[0]["total_iterations"])
-    assert e_mixed <= 1e-6
+    assert e_mixed <= 1.01 * infos[0]["certified_bound"] + 3 * iterative_floor(g, V, s, b, 1.0)
     assert e64 <= max(1e-10, 10 * d["amplification"] * EPS)
 
 
@@ -358,7 +364,7 @@ def test_shifted_full_size_3d_separable(rexi):
     out2, infos2 = gpu_steps(g, V, psi0, s, b, 1.0, 1, solver="shifted", m=100, tol=1e-12, tol_policy="certified")
     e2 = rel(out2[0], ref)
     print("shifted full 3d separable", e1, e2, infos[0]["total_iterations"], infos2[0]["total_iterations"])
-    assert e1 <= max(1e-6, infos[0]["certified_bound"])
+    assert e1 <= 1.01 * infos[0]["certified_bound"] + 3 * iterative_floor(g, V, s, b, 1.0)
     assert e2 <= max(1e-10, 10 * d["amplification"] * EPS)
 
 
@@ -570,7 +576,8 @@ def test_uneven_batch_matches_oracle_per_instance(rexi, solver, prec):
         g = it["grid"]
         ref = ost.DirectStepper(g.n, g.h, it["V"], sig[i], bet[i], dts[i]).step(it["psi0"]).ravel()
         e = rel(res[off:off + g.size], ref)
-        bar = 1e-6 if prec == "c64" else max(1e-10, 3 * iterative_floor(g, it["V"], sig[i], bet[i], dts[i]))
+        fl = 3 * iterative_floor(g, it["V"], sig[i], bet[i], dts[i])
+        bar = 1.01 * info["certified_bound"] + fl if prec == "c64" else max(1e-10, fl)
         errs.append((g.n[0], it["K"], round(dts[i], 3), e, bar))
         assert e <= bar, errs[-1]
         off += g.size
